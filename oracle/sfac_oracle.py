@@ -1,0 +1,288 @@
+"""Plain FP64 CPU oracle for the two-level Strang splitting of the spatial fractional
+Allen-Cahn equation (Cai, Fang, Chen, Sun, arXiv 2209.08437).
+
+TEST INFRASTRUCTURE ONLY. This module exists to check the GPU library; it is not part of
+the product. Only the test suite, the package's smoke check and the benchmark's CPU
+baseline leg may import it. It shares no code, table or constant with the GPU path.
+
+What it computes, in the paper's order and notation (Sec. 2):
+
+* eq. (g_coe) and eq. (omega_coe): the weights g_k and omega_k;
+* eq. (B) with the matrix D_alpha of Sec. 2.1: the symmetric Toeplitz matrix
+  B_alpha = kappa (D_alpha + D_alpha^T), kappa = -eps^2 / (2 h^alpha cos(alpha pi / 2));
+* eqs. (C) and (S): the circulant C_alpha and skew-circulant S_alpha with B = C + S;
+* Remark 1: their spectra through the Fourier matrix F and the diagonal Psi, and from them
+  the dense matrices exp(t C) = F* diag(e^{t lambda}) F and exp(t S) = Psi* F* diag(e^{t mu}) F Psi;
+* eq. (nonlinear_operator): the closed-form nonlinear flow J^Q_t;
+* eq. (hatv) and eq. (finalstrang): one step of the two-level scheme,
+  J^Q_{tau/2} e^{tau/2 C_a} e^{tau S_a} e^{tau/2 C_a} J^Q_{tau/2}, where C_a and S_a are the
+  Kronecker sums of eq. (2DA) / (3DA) form, so each exponential is the product of the
+  per-axis exponentials (all axes' C factors, then all S factors, then all C factors);
+* eq. (strang) with eq. (linear_operator): the one-level scheme with the exact exponential
+  e^{tau A}, used only to reproduce the paper's "Strang splitting" table columns.
+
+Every linear factor is a dense N x N matrix applied by a dense product along one axis of
+the state; there is no FFT, blocking or fusion. Arrays are C-order with axis 1 (the paper's
+x^(1), index i) fastest, i.e. shape (N2, N1) in 2D and (N3, N2, N1) in 3D, as the state
+vector ordering of Sec. 2.1 prescribes.
+
+Index convention: the paper's m is the number of mesh intervals; the unknowns are the
+N = m - 1 interior nodes, and every matrix here is N x N.
+"""
+
+import numpy as np
+
+__all__ = [
+    "g_coefficients", "omega_weights", "riesz_factor", "matrix_D", "matrix_B",
+    "toeplitz_column", "circulant_skew_split", "fourier_matrix", "skew_diagonal",
+    "circulant_spectrum", "skew_spectrum", "exp_circulant", "exp_skew",
+    "exp_symmetric", "nonlinear_flow", "AxisOperators", "axis_operators",
+    "apply_along_axis", "two_level_step", "two_level_solve", "strang_step",
+    "strang_solve", "discrete_energy",
+]
+
+
+# ----------------------------------------------------------------------------- weights
+def g_coefficients(alpha, count):
+    """g_0 .. g_{count-1} by the recursion of eq. (g_coe), Sec. 2.1:
+    g_0 = 1, g_{k+1} = (1 - (alpha + 1)/(k + 1)) g_k."""
+    g = np.empty(count, dtype=np.float64)
+    g[0] = 1.0
+    for k in range(count - 1):
+        g[k + 1] = (1.0 - (alpha + 1.0) / (k + 1.0)) * g[k]
+    return g
+
+
+def omega_weights(alpha, count):
+    """omega_0 .. omega_{count-1} of eq. (omega_coe), Sec. 2.1:
+    omega_0 = (alpha/2) g_0, omega_{k+1} = (alpha/2) g_{k+1} + ((2 - alpha)/2) g_k."""
+    g = g_coefficients(alpha, count)
+    w = np.empty(count, dtype=np.float64)
+    w[0] = 0.5 * alpha * g[0]
+    for k in range(count - 1):
+        w[k + 1] = 0.5 * alpha * g[k + 1] + 0.5 * (2.0 - alpha) * g[k]
+    return w
+
+
+def riesz_factor(alpha, eps, h):
+    """The scalar -eps^2 / (2 h^alpha cos(alpha pi / 2)) that multiplies D + D^T in eq. (B)
+    (it is the factor of both sums in eq. (disFAC))."""
+    return -(eps * eps) / (2.0 * h ** alpha * np.cos(alpha * np.pi / 2.0))
+
+
+# ---------------------------------------------------------------------- Toeplitz matrix
+def matrix_D(alpha, N):
+    """D_alpha of Sec. 2.1 as an N x N dense matrix (N = m - 1 interior nodes):
+    entry (i, j) is omega_{i - j + 1} when i - j + 1 >= 0 and zero otherwise, i.e.
+    omega_1 on the diagonal, omega_0 on the superdiagonal, omega_2, omega_3, ... below."""
+    w = omega_weights(alpha, N + 1)
+    i = np.arange(N)[:, None]
+    j = np.arange(N)[None, :]
+    k = i - j + 1
+    D = np.where(k >= 0, w[np.clip(k, 0, N)], 0.0)
+    return D
+
+
+def matrix_B(alpha, eps, h, N):
+    """B_alpha = kappa (D_alpha + D_alpha^T), eq. (B) of Sec. 2.1 (symmetric Toeplitz)."""
+    D = matrix_D(alpha, N)
+    return riesz_factor(alpha, eps, h) * (D + D.T)
+
+
+def toeplitz_column(B):
+    """Diagonal values b_k = B[i, j] for k = i - j, k = -(N-1) .. N-1, as a function."""
+    N = B.shape[0]
+
+    def b(k):
+        if k >= 0:
+            return B[k, 0]
+        return B[0, -k]
+
+    return b, N
+
+
+def circulant_skew_split(B):
+    """Dense C_alpha and S_alpha of eqs. (C) and (S): the k-th diagonal of C is
+    (b_k + b_{k-N})/2 for k > 0, b_0/2 for k = 0, (b_k + b_{k+N})/2 for k < 0; S takes the
+    differences instead. (The paper writes k - m + 1 with m - 1 = N.)"""
+    b, N = toeplitz_column(B)
+    cdiag = {}
+    sdiag = {}
+    for k in range(-(N - 1), N):
+        if k == 0:
+            cdiag[k] = 0.5 * b(0)
+            sdiag[k] = 0.5 * b(0)
+        elif k > 0:
+            cdiag[k] = 0.5 * (b(k) + b(k - N))
+            sdiag[k] = 0.5 * (b(k) - b(k - N))
+        else:
+            cdiag[k] = 0.5 * (b(k) + b(k + N))
+            sdiag[k] = 0.5 * (b(k) - b(k + N))
+    i = np.arange(N)[:, None]
+    j = np.arange(N)[None, :]
+    kk = i - j
+    cvals = np.array([cdiag[k] for k in range(-(N - 1), N)])
+    svals = np.array([sdiag[k] for k in range(-(N - 1), N)])
+    C = cvals[kk + (N - 1)]
+    S = svals[kk + (N - 1)]
+    return C, S
+
+
+# -------------------------------------------------------------------------- Remark 1
+def fourier_matrix(N):
+    """The unitary Fourier matrix of Remark 1: F[j, k] = exp(2 pi i j k / N) / sqrt(N).
+    The angle is reduced exactly in integers (j k mod N) before the trigonometric call."""
+    j = np.arange(N, dtype=np.int64)[:, None]
+    k = np.arange(N, dtype=np.int64)[None, :]
+    r = (j * k) % N
+    ang = 2.0 * np.pi * r.astype(np.float64) / N
+    return (np.cos(ang) + 1j * np.sin(ang)) / np.sqrt(N)
+
+
+def skew_diagonal(N):
+    """Psi = diag(1, e^{-i pi/N}, ..., e^{-i pi (N-1)/N}) of Remark 1, as a vector."""
+    k = np.arange(N, dtype=np.float64)
+    ang = -np.pi * k / N
+    return np.cos(ang) + 1j * np.sin(ang)
+
+
+def circulant_spectrum(C):
+    """Eigenvalues of the circulant C by Remark 1: F C e_1 = Lambda_C 1 / sqrt(N), so
+    lambda = sqrt(N) F (C e_1). C is symmetric, so lambda is real."""
+    N = C.shape[0]
+    lam = np.sqrt(N) * (fourier_matrix(N) @ C[:, 0])
+    return lam.real
+
+
+def skew_spectrum(S):
+    """Eigenvalues of the skew-circulant S by Remark 1: F Psi S e_1 = Lambda_S 1 / sqrt(N)."""
+    N = S.shape[0]
+    mu = np.sqrt(N) * (fourier_matrix(N) @ (skew_diagonal(N) * S[:, 0]))
+    return mu.real
+
+
+def exp_circulant(C, t):
+    """exp(t C) = F* diag(e^{t lambda}) F (Remark 1), a dense real N x N matrix."""
+    N = C.shape[0]
+    F = fourier_matrix(N)
+    lam = circulant_spectrum(C)
+    E = F.conj().T @ (np.exp(t * lam)[:, None] * F)
+    return E.real
+
+
+def exp_skew(S, t):
+    """exp(t S) = Psi* F* diag(e^{t mu}) F Psi (Remark 1), a dense real N x N matrix."""
+    N = S.shape[0]
+    F = fourier_matrix(N)
+    psi = skew_diagonal(N)
+    mu = skew_spectrum(S)
+    G = F * psi[None, :]                      # F Psi
+    E = G.conj().T @ (np.exp(t * mu)[:, None] * G)
+    return E.real
+
+
+def exp_symmetric(B, t):
+    """exp(t B) for a real symmetric B through its eigendecomposition (numpy eigh), used
+    for the exact linear flow e^{tau A} of eq. (linear_operator) in the one-level scheme."""
+    w, V = np.linalg.eigh(B)
+    return (V * np.exp(t * w)[None, :]) @ V.T
+
+
+# ------------------------------------------------------------------------ nonlinear part
+def nonlinear_flow(v, t):
+    """J^Q_t of eq. (nonlinear_operator): v / sqrt(v^2 + (1 - v^2) e^{-2t}), the exact flow
+    of the Bernoulli equation v' = v - v^3, applied pointwise."""
+    v = np.asarray(v, dtype=np.float64)
+    return v / np.sqrt(v * v + (1.0 - v * v) * np.exp(-2.0 * t))
+
+
+# ---------------------------------------------------------------------- per-axis factors
+class AxisOperators:
+    """Dense per-axis matrices for one axis: B, C, S and the factors exp(tau/2 C), exp(tau S),
+    plus the exact exp(tau B) on request."""
+
+    def __init__(self, N, alpha, eps, h, tau):
+        self.N, self.alpha, self.eps, self.h, self.tau = N, alpha, eps, h, tau
+        self.B = matrix_B(alpha, eps, h, N)
+        self.C, self.S = circulant_skew_split(self.B)
+        self.EC = exp_circulant(self.C, 0.5 * tau)
+        self.ES = exp_skew(self.S, tau)
+        self._EB = None
+
+    @property
+    def EB(self):
+        if self._EB is None:
+            self._EB = exp_symmetric(self.B, self.tau)
+        return self._EB
+
+
+def axis_operators(ns, alphas, eps, hs, tau):
+    """AxisOperators for axes 1..d (ns, alphas, hs are per-axis sequences, axis 1 first)."""
+    return [AxisOperators(int(n), float(a), float(eps), float(h), float(tau))
+            for n, a, h in zip(ns, alphas, hs)]
+
+
+def apply_along_axis(M, u, axis):
+    """Apply the N x N matrix M to every line of u along the paper's axis `axis` (1-based,
+    axis 1 = last array dimension), i.e. the Kronecker factor I x .. x M x .. x I."""
+    d = u.ndim
+    ax = d - axis
+    out = np.tensordot(M, u, axes=([1], [ax]))
+    return np.moveaxis(out, 0, ax)
+
+
+def two_level_step(u, ops, tau):
+    """One step of eq. (finalstrang): J^Q_{tau/2} (e^{tau/2 C_a} e^{tau S_a} e^{tau/2 C_a}) J^Q_{tau/2}.
+    Each Kronecker-sum exponential is applied as the product of its per-axis factors."""
+    d = u.ndim
+    u = nonlinear_flow(u, 0.5 * tau)
+    for ax in range(1, d + 1):
+        u = apply_along_axis(ops[ax - 1].EC, u, ax)
+    for ax in range(1, d + 1):
+        u = apply_along_axis(ops[ax - 1].ES, u, ax)
+    for ax in range(1, d + 1):
+        u = apply_along_axis(ops[ax - 1].EC, u, ax)
+    u = nonlinear_flow(u, 0.5 * tau)
+    return u
+
+
+def two_level_solve(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, observe=None):
+    """nsteps steps of the two-level scheme from u0 (shape (N_d, .., N_1)). `observe`, if
+    given, is called with (step index, state) after every step."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    if ops is None:
+        ops = axis_operators(ns, alphas, eps, hs, tau)
+    for n in range(nsteps):
+        u = two_level_step(u, ops, tau)
+        if observe is not None:
+            observe(n + 1, u)
+    return u
+
+
+def strang_step(u, ops, tau):
+    """One step of eq. (strang): J^Q_{tau/2} e^{tau A} J^Q_{tau/2}, with e^{tau A} the product of
+    the exact per-axis exponentials exp(tau B_l) (A is a Kronecker sum, eq. (2DA)/(3DA))."""
+    d = u.ndim
+    u = nonlinear_flow(u, 0.5 * tau)
+    for ax in range(1, d + 1):
+        u = apply_along_axis(ops[ax - 1].EB, u, ax)
+    return nonlinear_flow(u, 0.5 * tau)
+
+
+def strang_solve(u0, ns, alphas, eps, hs, tau, nsteps, ops=None):
+    u = np.array(u0, dtype=np.float64, copy=True)
+    if ops is None:
+        ops = axis_operators(ns, alphas, eps, hs, tau)
+    for _ in range(nsteps):
+        u = strang_step(u, ops, tau)
+    return u
+
+
+def discrete_energy(u, ops, hs):
+    """Discrete free energy of Example 5 (Sec. 5): prod(h) (1/4 |u^2 - 1|^2 - 1/2 u^T A u),
+    with A the Kronecker sum of the per-axis B matrices."""
+    Au = np.zeros_like(u)
+    for ax in range(1, u.ndim + 1):
+        Au = Au + apply_along_axis(ops[ax - 1].B, u, ax)
+    q = u * u - 1.0
+    return float(np.prod(hs)) * (0.25 * np.sum(q * q) - 0.5 * np.sum(u * Au))
