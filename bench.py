@@ -1,0 +1,178 @@
+"""Throughput of the two-level Strang step on one MI355X: grid-point-steps per second.
+
+A bench step is one time step of the solver (J^Q_{tau/2}, e^{tau/2 C} e^{tau S} e^{tau/2 C}
+along every axis, J^Q_{tau/2}) over the whole grid of the workload. The default workload is
+the 2D single large instance (N = 1023 per axis, alpha = (1.3, 1.7), eps = 0.05, tau = 1e-3,
+FP64) and the default K = 1000 timed steps is its full run. The state is resident in HBM before
+the timed region starts; the timed region is one sfac_step call of K steps (HIP graph replays)
+bracketed by device synchronizations.
+
+Besides the headline value the JSON line carries: the FP32 rate of the same workload, the
+roofline of the axis-pass kernel (algorithmic bytes per launch over its mean duration, timed
+with HIP events on the plan's stream), and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-point-steps/s (N^d·steps/s) FP64 vs FP32 + HBM GB/s; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2209_08437_amd import workloads as W
+    if name == "large_2d_1023":
+        return W.large_2d_1023(), "2D single large instance: [-1,1]^2, N=1023 per axis, alpha=(1.3,1.7), eps=0.05, tau=1e-3, 1000 steps, u0 = 0.9 tanh of a smoothed seeded normal field"
+    if name == "large_3d_255":
+        return W.large_3d_255(), "3D single instance: [-1,1]^3, N=255 per axis, alpha=(1.2,1.5,1.8), eps=0.08, tau=5e-3, 200 steps, u0 uniform in [-0.5,0.5]"
+    if name == "plain_2d_63":
+        return W.plain_2d_63(), "2D plain method: [-1,1]^2, N=63 per axis, alpha=(1.5,1.5), eps=0.1, tau=0.01, 100 steps, u0 uniform in [-0.9,0.9]"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def gpu_rate(inst, dtype, steps, warmup, pass_reps):
+    import numpy as np
+    import torch
+    from paper_2209_08437_amd import sfac
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    u0 = torch.tensor(inst.u0, dtype=tdt, device="cuda")
+    u = u0.clone()
+    plan = sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype)
+    methods = [plan.method(a + 1) for a in range(inst.dims)]
+    log(f"[bench] {dtype}: methods per axis {methods}; warmup {warmup} steps")
+    plan.step(u, warmup)
+    torch.cuda.synchronize()
+    u.copy_(u0)
+    plan.reset_flags()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    plan.step(u, steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    flags, vmax = plan.flags()
+    log(f"[bench] {dtype}: {steps} steps in {wall * 1e3:.2f} ms wall ({gpu_ms:.2f} ms events), "
+        f"max|u| {vmax:.6f}, flags {flags}")
+    # per-pass kernel durations (HIP events on the plan's stream around each launch)
+    uu = u0.clone()
+    pass_ms = plan.time_passes(uu, pass_reps)
+    torch.cuda.synchronize()
+    result = {
+        "wall_s": wall, "gpu_ms": gpu_ms, "flags": flags, "max_abs": vmax,
+        "pass_ms": pass_ms, "methods": methods, "state": u.double().cpu().numpy(),
+    }
+    plan.close()
+    return result
+
+
+def cpu_baseline(inst, seconds):
+    """The CPU oracle as it stands, on a bounded sample of the same workload: table set-up
+    (dense per-axis exponentials) timed apart, then as many whole steps as fit the budget."""
+    import numpy as np
+    from oracle import sfac_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    ops = O.axis_operators(inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau)
+    setup = time.perf_counter() - t0
+    u = np.array(inst.u0, dtype=np.float64)
+    t0 = time.perf_counter()
+    u = O.two_level_step(u, ops, inst.tau)
+    one = time.perf_counter() - t0
+    k = max(1, min(inst.steps - 1, int(seconds / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    for _ in range(k):
+        u = O.two_level_step(u, ops, inst.tau)
+    dt = time.perf_counter() - t0
+    pts = inst.points
+    return {
+        "value": pts * k / dt, "unit": "grid-point-steps/s", "cores": int(threads), "kind": "oracle",
+        "sample": f"{k} steps of the same {'x'.join(map(str, inst.ns))} workload after 1 untimed step "
+                  f"(dense per-axis exponentials, numpy/OpenBLAS FP64); table set-up {setup:.2f} s not included",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="large_2d_1023")
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--pass-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design note, not part of this build)", flush=True)
+        sys.exit(2)
+    import torch
+    from paper_2209_08437_amd import sfac, build_lib
+    if not os.path.exists(sfac.LIB_PATH):
+        build_lib.build()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    inst, desc = workload(args.workload)
+    steps = args.steps if args.steps is not None else inst.steps
+    esize = 8 if args.dtype == "f64" else 4
+    pts = inst.points
+    main_r = gpu_rate(inst, args.dtype, steps, args.warmup, args.pass_reps)
+    value = pts * steps / main_r["wall_s"]
+    # roofline of the dominant kernel: the axis pass with the largest mean duration
+    pass_ms = main_r["pass_ms"]
+    a_dom = max(range(len(pass_ms)), key=lambda a: pass_ms[a])
+    bytes_per_launch = 2 * pts * esize           # one read and one write of the state
+    achieved = bytes_per_launch / (pass_ms[a_dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"axis_pass_single<{'double' if esize == 8 else 'float'}> axis {a_dom + 1}",
+            "pass_ms": [round(x, 5) for x in pass_ms], "bytes_per_launch": bytes_per_launch}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "grid-point-steps/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(main_r["wall_s"] * 1e3 / steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": desc, "grid": list(inst.ns), "points": pts,
+                   "methods": [m for m, _ in main_r["methods"]],
+                   "effective_GBps": round(value * 2 * inst.dims * esize / 1e9, 2)},
+        "roofline": roof,
+    }
+    if not args.no_fp32 and args.dtype == "f64":
+        r32 = gpu_rate(inst, "f32", steps, args.warmup, args.pass_reps)
+        import numpy as np
+        ref = main_r["state"]
+        out["fp32"] = {"value": round(pts * steps / r32["wall_s"], 1), "unit": "grid-point-steps/s",
+                       "ms_per_step": round(r32["wall_s"] * 1e3 / steps, 5),
+                       "rel_err_vs_fp64_gpu": float(np.abs(r32["state"] - ref).max() / np.abs(ref).max()),
+                       "max_abs": r32["max_abs"], "flags": r32["flags"],
+                       "pass_ms": [round(x, 5) for x in r32["pass_ms"]]}
+    out["max_abs"] = main_r["max_abs"]
+    out["flags"] = main_r["flags"]
+    if not args.no_cpu:
+        log(f"[bench] timing the CPU oracle for about {args.cpu_seconds:.0f} s")
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * sfac.h - C ABI of the MI355X (gfx950) library for the two-level Strang splitting of the
+ * 2D/3D spatial fractional Allen-Cahn equation
+ *
+ *     u_t = eps^2 L^alpha u + u - u^3   on [a,b]^d, homogeneous Dirichlet boundary,
+ *
+ * (Cai, Fang, Chen, Sun, arXiv 2209.08437). One step of the method, eq. (finalstrang):
+ *
+ *     u <- J^Q_{tau/2} ( e^{tau/2 C_a} e^{tau S_a} e^{tau/2 C_a} ) J^Q_{tau/2} u,
+ *
+ * where J^Q_t v = v / sqrt(v^2 + (1 - v^2) e^{-2t}) is the closed-form nonlinear flow of
+ * eq. (nonlinear_operator), and C_a, S_a are the Kronecker sums of the per-axis circulant and
+ * skew-circulant parts of the symmetric Toeplitz matrix B_alpha (eqs. (B), (C), (S), Sec. 2.1-2.2).
+ * Each exponential is applied along every axis with fast Fourier transforms (Remark 1).
+ *
+ * Conventions shared by every entry point
+ *  - Axis 1 is the paper's x^(1) (index i), the fastest-varying index of the state vector
+ *    (Sec. 2.1). A state of d axes is a dense C-order array of shape (N_d, ..., N_1) holding
+ *    the interior nodes only; the Dirichlet zeros are implicit.
+ *  - N_l is the number of interior nodes on axis l (the paper's m_l - 1); h_l its mesh width.
+ *  - Device pointers are HIP device addresses owned by the caller; the library never frees
+ *    them. Host pointers are read during the call only.
+ *  - Every call returns a status; nothing throws across the ABI. On a non-OK status
+ *    sfac_last_error() returns a thread-local message describing it.
+ *  - A plan or batch is not reentrant: calls on one handle must not overlap. Distinct
+ *    handles may be used from different threads.
+ */
+#ifndef SFAC_H
+#define SFAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SFAC_OK = 0,
+    SFAC_EINVAL = 1,       /* an argument is outside its documented range */
+    SFAC_EUNSUPPORTED = 2, /* valid, but beyond what this build implements (e.g. N too large) */
+    SFAC_ENOMEM = 3,       /* a device or host allocation failed */
+    SFAC_EDEVICE = 4,      /* a HIP runtime call failed; the message carries its text */
+    SFAC_EBUDGET = 5       /* a request does not fit the caller's device-memory budget */
+} sfac_status;
+
+typedef enum { SFAC_FP64 = 0, SFAC_FP32 = 1 } sfac_dtype;
+
+/* How one axis applies its circulant / skew-circulant exponentials (both exact, they differ
+ * only in rounding):
+ *  SFAC_METHOD_DIAG:  Remark 1 literally. e^{tC} x = F^-1 diag(e^{t lambda}) F x and
+ *                     e^{tS} x = conj(psi) . F^-1 diag(e^{t mu}) F (psi . x) with length-N
+ *                     mixed-radix transforms and psi_k = e^{-i pi k / N}. Needs every prime
+ *                     factor of N to be at most 31.
+ *  SFAC_METHOD_EMBED: the same circulant and skew-circulant matrices are symmetric Toeplitz;
+ *                     each is applied as a linear convolution by its first column, computed
+ *                     with one forward and one inverse length-M transform, M = 2^k >= 2N - 1.
+ *                     Works for every N.
+ *  SFAC_METHOD_AUTO:  the library picks per axis (the faster of the two for N and dtype). */
+typedef enum { SFAC_METHOD_AUTO = 0, SFAC_METHOD_DIAG = 1, SFAC_METHOD_EMBED = 2 } sfac_method;
+
+typedef struct sfac_plan_s* sfac_plan;
+typedef struct sfac_batch_s* sfac_batch;
+
+/* Optional plan settings; pass NULL for the defaults. */
+typedef struct {
+    int32_t method[3];    /* sfac_method per axis (axis 1 first); default SFAC_METHOD_AUTO */
+    int32_t use_graph;    /* 1 (default): replay steps from captured HIP graphs; 0: plain launches */
+    int32_t graph_chunk;  /* steps captured per graph replay (default 32, 1..1024) */
+} sfac_options;
+
+/* Per-plan sticky status, read with sfac_plan_flags. */
+#define SFAC_FLAG_NONFINITE 1u  /* a NaN or infinity was stored */
+#define SFAC_FLAG_ABOVE_ONE 2u  /* some |u| > 1 was stored (the discrete maximum principle,
+                                   Theorem 1, says this does not happen when |u0| <= 1) */
+
+/*
+ * sfac_plan_create - build the per-axis tables of eqs. (g_coe), (omega_coe), (B), (C), (S)
+ * and Remark 1 in FP64 on the host, upload them, and prepare the step launches.
+ *   out        : receives the plan; *out = NULL on failure.
+ *   dims       : number of axes, 1, 2 or 3 (the paper treats 2 and 3; 1 is accepted).
+ *   n_axis     : dims values N_l >= 1, axis 1 first.
+ *   alpha_axis : dims fractional orders, each in (1, 2] (alpha = 1 makes cos(alpha pi/2) = 0;
+ *                the paper uses (1, 2), alpha = 2 is the three-point Laplacian).
+ *   eps        : interface parameter, >= 0 (the paper uses eps > 0; 0 gives the pure ODE).
+ *   tau        : time step, > 0.
+ *   h_axis     : dims mesh widths h_l = (b - a)/(N_l + 1) > 0.
+ *   dt         : arithmetic of the state and of every kernel (tables are always built in FP64
+ *                and rounded once for SFAC_FP32).
+ *   hip_stream : hipStream_t the steps are ordered on; NULL means the legacy default stream.
+ *   opt        : NULL or settings as above.
+ * Errors: SFAC_EINVAL for arguments out of range, SFAC_EUNSUPPORTED for N_l above 4096
+ * (diagonal method) or 2048 (embedded method), SFAC_ENOMEM, SFAC_EDEVICE.
+ */
+sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis,
+                             const double* alpha_axis, double eps, double tau,
+                             const double* h_axis, sfac_dtype dt, void* hip_stream,
+                             const sfac_options* opt);
+
+/*
+ * sfac_step - advance the state by nsteps steps of eq. (finalstrang), in place.
+ *   u_dev  : device pointer to prod(N_l) values of the plan's dtype, C-order (N_d, .., N_1),
+ *            aligned to the element size.
+ *   nsteps : >= 0; 0 returns at once.
+ * Asynchronous on the plan's stream: it returns once the work is queued. Splitting a run
+ * into several calls gives bitwise the same result (no step is fused across calls or steps).
+ * Errors: SFAC_EINVAL (NULL plan or pointer, misaligned pointer, nsteps < 0), SFAC_EDEVICE.
+ */
+sfac_status sfac_step(sfac_plan p, void* u_dev, int64_t nsteps);
+
+/* sfac_plan_destroy - release the plan's device tables, graphs and streams; NULL is accepted.
+ * Waits for the plan's queued work first. */
+sfac_status sfac_plan_destroy(sfac_plan p);
+
+/* sfac_plan_device_bytes - device memory the plan holds (tables, flags), excluding the
+ * caller's state; 0 for NULL. */
+size_t sfac_plan_device_bytes(sfac_plan p);
+
+/* sfac_plan_flags - synchronize the plan's stream and read its sticky status: *flags gets
+ * SFAC_FLAG_* bits, *max_abs the largest |u| stored since the last reset (either pointer may
+ * be NULL). Errors: SFAC_EINVAL for a NULL plan, SFAC_EDEVICE. */
+sfac_status sfac_plan_flags(sfac_plan p, uint32_t* flags, double* max_abs);
+
+/* sfac_plan_reset_flags - clear the sticky status (queued on the plan's stream). */
+sfac_status sfac_plan_reset_flags(sfac_plan p);
+
+/*
+ * sfac_plan_time_passes - measure the axis-pass kernels: run `reps` >= 1 steps on u_dev with
+ * plain launches, a HIP event pair recorded on the plan's stream around every pass, and write
+ * the mean duration of each axis' pass in milliseconds to ms[0 .. dims-1]. The state advances
+ * by `reps` steps exactly as sfac_step would advance it. Synchronizes the plan's stream.
+ * Errors: SFAC_EINVAL, SFAC_EDEVICE.
+ */
+sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float* ms);
+
+/* sfac_plan_method - the method (SFAC_METHOD_DIAG or SFAC_METHOD_EMBED) and transform length
+ * the plan uses on axis `axis` (1-based). Errors: SFAC_EINVAL. */
+sfac_status sfac_plan_method(sfac_plan p, int32_t axis, int32_t* method, int32_t* length);
+
+/*
+ * sfac_axis_tables - host-only introspection of the tables one axis of a plan would use (no
+ * device call). For N, alpha, eps, tau, h and method (SFAC_METHOD_DIAG or SFAC_METHOD_EMBED;
+ * AUTO resolves as sfac_plan_create does):
+ *   *length   : transform length L (N for DIAG, M = 2^k >= 2N - 1 for EMBED);
+ *   scale_c   : if not NULL, L doubles: DIAG e^{tau/2 lambda_j}/N (lambda_j = sum_k c_k
+ *               e^{-2 pi i j k/N}); EMBED the length-M spectrum of the first column of
+ *               e^{tau/2 C} placed as a symmetric circular kernel, divided by M;
+ *   scale_s   : likewise for e^{tau S} (DIAG: mu_j = sum_k s_k e^{-i pi k (2j+1)/N});
+ *   radices   : if not NULL, up to 12 stage radices, *nstages their count.
+ * Call it once with NULL arrays to learn L. Errors as sfac_plan_create.
+ */
+sfac_status sfac_axis_tables(int32_t n, double alpha, double eps, double tau, double h, int32_t method,
+                             int32_t* length, double* scale_c, double* scale_s, int32_t* radices,
+                             int32_t* nstages);
+
+/* sfac_last_error - message for the last non-OK status returned on this thread ("" if none).
+ * The string stays valid until the next library call on the same thread. */
+const char* sfac_last_error(void);
+
+/* ---------------------------------------------------------------- batched form
+ * Many independent instances (each its own dims, N, alpha, eps, tau, h) stepped together:
+ * every axis pass of every instance in the batch is one launch over all instances' lines. */
+typedef struct {
+    int32_t dims;       /* 1, 2 or 3 */
+    int32_t n[3];       /* N_l, axis 1 first; unused entries ignored */
+    double alpha[3];
+    double eps;
+    double tau;
+    double h[3];
+} sfac_instance_desc;
+
+/*
+ * sfac_batch_create - plan `count` instances (count >= 1) for arithmetic dt on hip_stream.
+ * Every instance is validated as by sfac_plan_create; the first invalid one fails the call
+ * with its index in the message. Errors as sfac_plan_create.
+ */
+sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instance_desc* desc,
+                              sfac_dtype dt, void* hip_stream);
+
+/*
+ * sfac_batch_step - advance instance i by nsteps[i] steps (>= 0) in place; u_dev[i] is its
+ * state as for sfac_step. Instances with fewer steps drop out of the launches once done.
+ * An instance's result is bitwise the same as stepping it alone with sfac_step.
+ * Asynchronous on the batch's stream. Errors: SFAC_EINVAL, SFAC_EDEVICE.
+ */
+sfac_status sfac_batch_step(sfac_batch b, void* const* u_dev, const int64_t* nsteps);
+
+/* sfac_batch_destroy - release the batch; NULL is accepted. */
+sfac_status sfac_batch_destroy(sfac_batch b);
+
+/* sfac_batch_device_bytes - device memory the batch holds, excluding the states. */
+size_t sfac_batch_device_bytes(sfac_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFAC_H */

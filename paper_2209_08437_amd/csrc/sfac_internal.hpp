@@ -1,0 +1,54 @@
+// Internal declarations shared by the host table builder, the kernels and the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sfac.h"
+
+namespace sfac {
+
+constexpr int kMaxStages = 12;
+constexpr int kMaxDiagLength = 4096;   // largest N for the length-N (diagonal) method
+constexpr int kMaxEmbedLength = 4096;  // largest M for the embedded method (N <= 2048)
+constexpr int kMaxPrimeRadix = 31;     // largest prime factor the mixed-radix transform handles
+
+// One axis of one instance, as the host builds it (FP64 values).
+struct AxisTables {
+    int n = 0;                  // interior nodes N on this axis
+    int method = 0;             // SFAC_METHOD_DIAG or SFAC_METHOD_EMBED
+    int length = 0;             // transform length: N (diag) or M (embed)
+    std::vector<int> radices;   // stage radices, product == length
+    // twiddles e^{-2 pi i m / length}, m < length
+    std::vector<double> tw_re, tw_im;
+    // diag: e^{tau/2 lambda_j}/N and e^{tau mu_j}/N (length N)
+    // embed: spectra of the Toeplitz kernels of e^{tau/2 C} and e^{tau S}, divided by M (length M)
+    std::vector<double> scale_c, scale_s;
+    // diag only: psi_k = e^{-i pi k / N}
+    std::vector<double> psi_re, psi_im;
+};
+
+// Per-axis parameters of the method.
+struct AxisParams {
+    int n;
+    double alpha, eps, tau, h;
+};
+
+// Builds the tables for one axis. Returns an empty string on success, else an error message.
+// `method` is SFAC_METHOD_DIAG or SFAC_METHOD_EMBED (AUTO is resolved by the caller).
+std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out);
+
+// Factorisation of n into the supported radices (largest first); empty if n has a prime
+// factor above kMaxPrimeRadix. n == 1 yields an empty list and returns true.
+bool factor_radices(int n, std::vector<int>* radices);
+
+// Default method for (n, dtype): the choice the library makes for SFAC_METHOD_AUTO.
+int auto_method(int n, sfac_dtype dt);
+
+// Smallest power of two >= 2n - 1 (at least 2).
+int embed_length(int n);
+
+}  // namespace sfac

@@ -1,0 +1,289 @@
+// Axis-pass kernels of the two-level Strang step (eqs. (hatv), (finalstrang), Remark 1).
+//
+// One pass handles every line of the state along one axis: it loads a tile of lines, packs
+// two real lines into one complex line (the per-axis operator is real, so the real and
+// imaginary parts are transformed independently), applies e^{tau/2 C} e^{tau S} e^{tau/2 C}
+// by transforms in LDS, and stores the lines back in place. The first pass of a step applies
+// the nonlinear half-step J^Q_{tau/2} (eq. (nonlinear_operator)) on load, the last pass applies
+// it on store and records max |u| and non-finite values.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sfac_fft.hpp"
+#include "sfac_kernels.hpp"
+
+namespace sfac {
+
+namespace {
+
+// J^Q_{tau/2} v = v / sqrt(v^2 + (1 - v^2) e^{-tau}), with 1 - v^2 formed as (1 - v)(1 + v)
+template <typename T>
+__device__ __forceinline__ T nonlinear_half_step(T v, T decay) {
+    const T one = (T)1;
+    const T q = (one - v) * (one + v);
+    return v / sqrt(v * v + q * decay);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void run_stage(int R, const cplx<T>* src, cplx<T>* dst, int L, int Ns,
+                                          int lines, const cplx<T>* tw) {
+    switch (R) {
+        case 2: stockham_stage<2, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 3: stockham_stage<3, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 4: stockham_stage<4, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 5: stockham_stage<5, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 7: stockham_stage<7, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 8: stockham_stage<8, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 9: stockham_stage<9, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 11: stockham_stage<11, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 13: stockham_stage<13, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 16: stockham_stage<16, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 17: stockham_stage<17, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 19: stockham_stage<19, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 23: stockham_stage<23, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 29: stockham_stage<29, DIR>(src, dst, L, Ns, lines, tw); break;
+        case 31: stockham_stage<31, DIR>(src, dst, L, Ns, lines, tw); break;
+        default: break;  // the host only plans the radices above
+    }
+}
+
+// Full transform of `lines` lines; returns the buffer holding the result.
+template <int DIR, typename T>
+__device__ cplx<T>* transform(const PassDesc<T>& d, cplx<T>* cur, cplx<T>* other, int lines) {
+    int Ns = 1;
+    for (int s = 0; s < d.nst; ++s) {
+        const int R = d.radix[s];
+        run_stage<DIR>(R, cur, other, d.L, Ns, lines, d.tw);
+        __syncthreads();
+        cplx<T>* t = cur;
+        cur = other;
+        other = t;
+        Ns *= R;
+    }
+    return cur;
+}
+
+template <typename T>
+__device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>* buf1) {
+    const int N = d.N, L = d.L, lpb = d.lpb;
+    const bool contiguous = d.inner == 1;
+    long long first;       // first real line (row) or column of the tile
+    long long avail;       // real lines available from `first`
+    T* base;               // address of element 0 of real line `first`
+    long long lstride;     // distance between adjacent real lines
+    long long kstride;     // distance between adjacent elements of a line
+    if (contiguous) {
+        first = (long long)tile * 2 * lpb;
+        avail = d.outer - first;
+        base = d.u + first * N;
+        lstride = N;
+        kstride = 1;
+    } else {
+        const long long o = tile / d.tiles_per_outer;
+        first = (long long)(tile % d.tiles_per_outer) * 2 * lpb;
+        avail = d.inner - first;
+        base = d.u + o * (long long)N * d.inner + first;
+        lstride = 1;
+        kstride = d.inner;
+    }
+    const int nreal = (int)(avail < 2 * lpb ? avail : 2 * lpb);
+    const int lines = (nreal + 1) >> 1;
+    const bool nl_in = d.nl_in != 0;
+    const T decay = d.decay;
+
+    // load (with zero padding to the transform length and a zero partner for an odd line)
+    const int total = lines * L;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int b, k;
+        if (contiguous) {
+            b = idx / L;
+            k = idx - b * L;
+        } else {
+            k = idx / lines;
+            b = idx - k * lines;
+        }
+        cplx<T> z = {(T)0, (T)0};
+        if (k < N) {
+            const T* p = base + (long long)(2 * b) * lstride + (long long)k * kstride;
+            z.x = p[0];
+            if (2 * b + 1 < nreal) z.y = p[lstride];
+            if (nl_in) {
+                z.x = nonlinear_half_step(z.x, decay);
+                z.y = nonlinear_half_step(z.y, decay);
+            }
+        }
+        buf0[b * L + k] = z;
+    }
+    __syncthreads();
+
+    cplx<T>* cur = buf0;
+    cplx<T>* other = buf1;
+    const bool diag = d.method == 1;
+    for (int f = 0; f < 3; ++f) {
+        const T* scale = f == 1 ? d.scale_s : d.scale_c;
+        const bool skew = f == 1;
+        if (diag && skew) {  // x <- psi . x
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+                const int k = idx % L;
+                cur[idx] = cmul(cur[idx], d.psi[k]);
+            }
+            __syncthreads();
+        }
+        cur = transform<-1>(d, cur, other, lines);
+        other = cur == buf0 ? buf1 : buf0;
+        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+            const int k = idx % L;
+            const T sc = scale[k];
+            cur[idx].x *= sc;
+            cur[idx].y *= sc;
+        }
+        __syncthreads();
+        cur = transform<+1>(d, cur, other, lines);
+        other = cur == buf0 ? buf1 : buf0;
+        if (diag && skew) {  // x <- conj(psi) . x
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+                const int k = idx % L;
+                cur[idx] = cmulc(cur[idx], d.psi[k]);
+            }
+            __syncthreads();
+        } else if (!diag) {  // embedded: keep the first N entries of the circular result
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+                const int k = idx % L;
+                if (k >= N) cur[idx] = {(T)0, (T)0};
+            }
+            __syncthreads();
+        }
+    }
+
+    // store
+    const bool nl_out = d.nl_out != 0;
+    double vmax = 0.0;
+    unsigned int bad = 0;
+    const int stotal = lines * N;
+    for (int idx = threadIdx.x; idx < stotal; idx += blockDim.x) {
+        int b, k;
+        if (contiguous) {
+            b = idx / N;
+            k = idx - b * N;
+        } else {
+            k = idx / lines;
+            b = idx - k * lines;
+        }
+        cplx<T> z = cur[b * L + k];
+        if (nl_out) {
+            z.x = nonlinear_half_step(z.x, decay);
+            z.y = nonlinear_half_step(z.y, decay);
+        }
+        T* p = base + (long long)(2 * b) * lstride + (long long)k * kstride;
+        p[0] = z.x;
+        const bool two = 2 * b + 1 < nreal;
+        if (two) p[lstride] = z.y;
+        if (nl_out) {
+            const double ax = fabs((double)z.x), ay = two ? fabs((double)z.y) : 0.0;
+            if (!(ax <= 1.7976931348623157e308) || !(ay <= 1.7976931348623157e308))
+                bad |= SFAC_FLAG_NONFINITE;
+            else
+                vmax = fmax(vmax, fmax(ax, ay));
+        }
+    }
+    if (nl_out) {
+        // wave reduction, then one atomic per wave
+        for (int off = 32; off > 0; off >>= 1) {
+            vmax = fmax(vmax, __shfl_xor(vmax, off));
+            bad |= __shfl_xor(bad, off);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (vmax > 1.0) bad |= SFAC_FLAG_ABOVE_ONE;
+            if (bad) atomicOr(d.stat_flags, bad);
+            atomicMax(d.stat_max, (unsigned long long)__double_as_longlong(vmax));
+        }
+    }
+}
+
+// blockIdx -> tile, grouping neighbouring tiles on one XCD (blocks are dealt round-robin to
+// the 8 XCDs, so block b runs on XCD b % 8): tiles that share cache lines then share an L2.
+__device__ __forceinline__ int xcd_tile(int block, int ntiles) {
+    const int per = (ntiles + 7) >> 3;
+    return (block & 7) * per + (block >> 3);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) axis_pass_single(PassDesc<T> d) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* buf1 = buf0 + d.lpb * d.L;
+    const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
+    if (tile >= d.ntiles) return;
+    run_tile(d, tile, buf0, buf1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockThreads) axis_pass_multi(const PassDesc<T>* __restrict__ descs,
+                                                                 const int* __restrict__ block_start,
+                                                                 int ndesc) {
+    extern __shared__ unsigned char smem_raw[];
+    // find the descriptor whose block range holds this block (block_start has ndesc + 1 entries)
+    int lo = 0, hi = ndesc;
+    const int b = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (block_start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const PassDesc<T> d = descs[lo];
+    const int local = b - block_start[lo];
+    const int tile = d.xcd_remap ? xcd_tile(local, d.ntiles) : local;
+    if (tile >= d.ntiles) return;
+    cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* buf1 = buf0 + d.lpb * d.L;
+    run_tile(d, tile, buf0, buf1);
+}
+
+}  // namespace
+
+template <typename T>
+int pass_blocks(const PassDesc<T>& d) {
+    return d.xcd_remap ? 8 * ((d.ntiles + 7) / 8) : d.ntiles;
+}
+
+template <typename T>
+hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream) {
+    const int blocks = pass_blocks(d);
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(axis_pass_single<T>, dim3(blocks), dim3(kBlockThreads), lds_bytes, stream, d);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axis_pass_multi(const PassDesc<T>* descs_dev, const int* block_start_dev, int ndesc,
+                                  int total_blocks, size_t lds_bytes, hipStream_t stream) {
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(axis_pass_multi<T>, dim3(total_blocks), dim3(kBlockThreads), lds_bytes, stream,
+                       descs_dev, block_start_dev, ndesc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t allow_lds(size_t lds_bytes) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_single<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_multi<T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
+template int pass_blocks<double>(const PassDesc<double>&);
+template int pass_blocks<float>(const PassDesc<float>&);
+template hipError_t launch_axis_pass<double>(const PassDesc<double>&, size_t, hipStream_t);
+template hipError_t launch_axis_pass<float>(const PassDesc<float>&, size_t, hipStream_t);
+template hipError_t launch_axis_pass_multi<double>(const PassDesc<double>*, const int*, int, int, size_t,
+                                                   hipStream_t);
+template hipError_t launch_axis_pass_multi<float>(const PassDesc<float>*, const int*, int, int, size_t,
+                                                  hipStream_t);
+template hipError_t allow_lds<double>(size_t);
+template hipError_t allow_lds<float>(size_t);
+
+}  // namespace sfac

@@ -1,0 +1,55 @@
+// Launch interface of the axis-pass kernels (host and device share these types).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sfac_fft.hpp"
+#include "sfac_internal.hpp"
+
+namespace sfac {
+
+constexpr int kBlockThreads = 256;
+
+// Everything one axis pass of one instance needs. Lines along the axis are addressed as
+// u[o * N * inner + k * inner + i]: o < outer indexes the slower axes, i < inner the faster
+// ones, k < N the position on the line. inner == 1 is the contiguous axis (axis 1).
+template <typename T>
+struct PassDesc {
+    T* u;                            // state, device
+    const cplx<T>* tw;               // e^{-2 pi i m / L}, m < L
+    const T* scale_c;                // diag: e^{tau/2 lambda}/N; embed: kernel spectrum / M
+    const T* scale_s;                // diag: e^{tau mu}/N;       embed: kernel spectrum / M
+    const cplx<T>* psi;              // diag: e^{-i pi k / N}, k < N
+    unsigned long long* stat_max;    // bits of the largest |u| stored (non-negative double)
+    unsigned int* stat_flags;        // SFAC_FLAG_* bits
+    long long inner, outer;
+    int N;                           // points per line
+    int L;                           // transform length (N or M)
+    int method;                      // 1 diag, 2 embed
+    int nst;                         // number of stages
+    int radix[kMaxStages];
+    int lpb;                         // complex lines (pairs of real lines) per block
+    int tiles_per_outer;             // strided passes: ceil(inner / (2 lpb))
+    int ntiles;                      // tiles in this pass
+    int nl_in, nl_out;               // apply J^Q_{tau/2} on load / on store (+ statistics)
+    int xcd_remap;                   // group neighbouring tiles per XCD
+    T decay;                         // e^{-tau}
+};
+
+template <typename T>
+int pass_blocks(const PassDesc<T>& d);
+
+template <typename T>
+hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream);
+
+template <typename T>
+hipError_t launch_axis_pass_multi(const PassDesc<T>* descs_dev, const int* block_start_dev, int ndesc,
+                                  int total_blocks, size_t lds_bytes, hipStream_t stream);
+
+// Raise the dynamic-LDS limit of the pass kernels to lds_bytes (needed above 64 KiB).
+template <typename T>
+hipError_t allow_lds(size_t lds_bytes);
+
+}  // namespace sfac

@@ -1,0 +1,678 @@
+// C ABI of the library: plans, batches, the step loop (HIP graphs of captured launches),
+// sticky status and error reporting. The arithmetic lives in the kernels (sfac_kernels.hip)
+// and the FP64 host tables (sfac_tables.cpp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sfac_internal.hpp"
+#include "sfac_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_error;
+
+sfac_status fail(sfac_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+sfac_status hip_fail(hipError_t e, const char* what) {
+    return fail(SFAC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kLdsBudget = 64 * 1024;        // per block when more than one line fits
+constexpr size_t kLdsMax = 160 * 1024;          // gfx950 LDS per CU
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Device copy of one axis' tables in the plan's arithmetic type.
+struct AxisDevice {
+    sfac::AxisTables host;
+    size_t off_tw = 0, off_sc = 0, off_ss = 0, off_psi = 0;
+    int lpb = 1;
+    size_t lds = 0;
+};
+
+template <typename T>
+size_t axis_table_bytes(const sfac::AxisTables& t, size_t base, AxisDevice* ad) {
+    size_t off = base;
+    ad->off_tw = off;
+    off = align_up(off + sizeof(sfac::cplx<T>) * t.length, 256);
+    ad->off_sc = off;
+    off = align_up(off + sizeof(T) * t.scale_c.size(), 256);
+    ad->off_ss = off;
+    off = align_up(off + sizeof(T) * t.scale_s.size(), 256);
+    ad->off_psi = off;
+    off = align_up(off + sizeof(sfac::cplx<T>) * t.psi_re.size(), 256);
+    return off;
+}
+
+template <typename T>
+void axis_table_fill(const sfac::AxisTables& t, const AxisDevice& ad, unsigned char* host) {
+    auto* tw = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_tw);
+    for (int m = 0; m < t.length; ++m) tw[m] = {(T)t.tw_re[m], (T)t.tw_im[m]};
+    auto* sc = reinterpret_cast<T*>(host + ad.off_sc);
+    for (size_t m = 0; m < t.scale_c.size(); ++m) sc[m] = (T)t.scale_c[m];
+    auto* ss = reinterpret_cast<T*>(host + ad.off_ss);
+    for (size_t m = 0; m < t.scale_s.size(); ++m) ss[m] = (T)t.scale_s[m];
+    auto* ps = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_psi);
+    for (size_t m = 0; m < t.psi_re.size(); ++m) ps[m] = {(T)t.psi_re[m], (T)t.psi_im[m]};
+}
+
+// One instance's geometry and tables: the part a plan and a batch entry share.
+struct Instance {
+    int dims = 0;
+    int n[3] = {1, 1, 1};
+    double alpha[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    double eps = 0, tau = 0;
+    sfac_dtype dt = SFAC_FP64;
+    AxisDevice ax[3];
+    size_t table_bytes = 0;   // tables only
+    size_t lds_max = 0;
+    long long points() const {
+        long long p = 1;
+        for (int a = 0; a < dims; ++a) p *= n[a];
+        return p;
+    }
+};
+
+sfac_status validate_instance(int dims, const int32_t* n, const double* alpha, double eps, double tau,
+                              const double* h, const char* who) {
+    if (dims < 1 || dims > 3) return fail(SFAC_EINVAL, "%sdims = %d, expected 1, 2 or 3", who, dims);
+    if (!n || !alpha || !h) return fail(SFAC_EINVAL, "%sNULL n_axis, alpha_axis or h_axis", who);
+    for (int a = 0; a < dims; ++a) {
+        if (n[a] < 1) return fail(SFAC_EINVAL, "%sN_%d = %d, expected >= 1", who, a + 1, n[a]);
+        if (!(alpha[a] > 1.0 && alpha[a] <= 2.0))
+            return fail(SFAC_EINVAL, "%salpha_%d = %g is outside (1, 2]", who, a + 1, alpha[a]);
+        if (!(h[a] > 0.0) || !std::isfinite(h[a]))
+            return fail(SFAC_EINVAL, "%sh_%d = %g, expected finite > 0", who, a + 1, h[a]);
+    }
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SFAC_EINVAL, "%seps = %g, expected finite >= 0", who, eps);
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(SFAC_EINVAL, "%stau = %g, expected finite > 0", who, tau);
+    long long pts = 1;
+    for (int a = 0; a < dims; ++a) {
+        pts *= n[a];
+        if (pts > (1LL << 40)) return fail(SFAC_EINVAL, "%sgrid too large", who);
+    }
+    return SFAC_OK;
+}
+
+// Tables for every axis of one instance (host side); methods[a] may be AUTO.
+sfac_status build_instance(Instance* in, int dims, const int32_t* n, const double* alpha, double eps,
+                           double tau, const double* h, sfac_dtype dt, const int32_t* methods,
+                           const char* who) {
+    sfac_status st = validate_instance(dims, n, alpha, eps, tau, h, who);
+    if (st != SFAC_OK) return st;
+    in->dims = dims;
+    in->eps = eps;
+    in->tau = tau;
+    in->dt = dt;
+    const size_t elem = dt == SFAC_FP64 ? sizeof(sfac::cplx<double>) : sizeof(sfac::cplx<float>);
+    size_t off = 0;
+    for (int a = 0; a < dims; ++a) {
+        in->n[a] = n[a];
+        in->alpha[a] = alpha[a];
+        in->h[a] = h[a];
+        int m = methods ? methods[a] : SFAC_METHOD_AUTO;
+        if (m == SFAC_METHOD_AUTO) m = sfac::auto_method(n[a], dt);
+        if (m != SFAC_METHOD_DIAG && m != SFAC_METHOD_EMBED)
+            return fail(SFAC_EUNSUPPORTED, "%saxis %d: no method supports N = %d", who, a + 1, n[a]);
+        sfac::AxisParams p{n[a], alpha[a], eps, tau, h[a]};
+        std::string err = sfac::build_axis_tables(p, m, &in->ax[a].host);
+        if (!err.empty()) {
+            const bool range = err.find("exceeds") != std::string::npos || err.find("prime factor") != std::string::npos;
+            return fail(range ? SFAC_EUNSUPPORTED : SFAC_EINVAL, "%saxis %d: %s", who, a + 1, err.c_str());
+        }
+        off = dt == SFAC_FP64 ? axis_table_bytes<double>(in->ax[a].host, off, &in->ax[a])
+                              : axis_table_bytes<float>(in->ax[a].host, off, &in->ax[a]);
+        // lines per block: as many as fit the LDS budget (two buffers), at most the lines there are
+        const int L = in->ax[a].host.length;
+        const size_t per_line = 2 * elem * (size_t)L;
+        long long inner = 1, outer = 1;
+        for (int b = 0; b < a; ++b) inner *= n[b];
+        for (int b = a + 1; b < dims; ++b) outer *= n[b];
+        const long long avail = (inner == 1 ? outer : inner);
+        int lpb = (int)std::max<size_t>(1, kLdsBudget / per_line);
+        lpb = (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2));
+        lpb = std::min(lpb, 64);
+        in->ax[a].lpb = lpb;
+        in->ax[a].lds = per_line * lpb;
+        if (in->ax[a].lds > kLdsMax)
+            return fail(SFAC_EUNSUPPORTED, "%saxis %d: transform length %d needs %zu bytes of LDS", who, a + 1, L,
+                        in->ax[a].lds);
+        in->lds_max = std::max(in->lds_max, in->ax[a].lds);
+    }
+    in->table_bytes = off;
+    return SFAC_OK;
+}
+
+template <typename T>
+sfac::PassDesc<T> make_desc(const Instance& in, int a, unsigned char* dev_tables, T* u,
+                            unsigned long long* stat_max, unsigned int* stat_flags) {
+    const AxisDevice& ad = in.ax[a];
+    const sfac::AxisTables& t = ad.host;
+    sfac::PassDesc<T> d{};
+    d.u = u;
+    d.tw = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_tw);
+    d.scale_c = reinterpret_cast<const T*>(dev_tables + ad.off_sc);
+    d.scale_s = reinterpret_cast<const T*>(dev_tables + ad.off_ss);
+    d.psi = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_psi);
+    d.stat_max = stat_max;
+    d.stat_flags = stat_flags;
+    long long inner = 1, outer = 1;
+    for (int b = 0; b < a; ++b) inner *= in.n[b];
+    for (int b = a + 1; b < in.dims; ++b) outer *= in.n[b];
+    d.inner = inner;
+    d.outer = outer;
+    d.N = t.n;
+    d.L = t.length;
+    d.method = t.method;
+    d.nst = (int)t.radices.size();
+    for (int s = 0; s < d.nst; ++s) d.radix[s] = t.radices[s];
+    d.lpb = ad.lpb;
+    if (inner == 1) {
+        d.tiles_per_outer = 0;
+        d.ntiles = (int)((outer + 2LL * d.lpb - 1) / (2LL * d.lpb));
+    } else {
+        d.tiles_per_outer = (int)((inner + 2LL * d.lpb - 1) / (2LL * d.lpb));
+        d.ntiles = (int)(outer * d.tiles_per_outer);
+    }
+    d.nl_in = a == 0;
+    d.nl_out = a == in.dims - 1;
+    d.xcd_remap = inner > 1 ? 1 : 0;
+    d.decay = (T)std::exp(-in.tau);
+    return d;
+}
+
+template <typename T>
+hipError_t launch_pass(const sfac::PassDesc<T>& d, size_t lds, hipStream_t s) {
+    return sfac::launch_axis_pass<T>(d, lds, s);
+}
+
+}  // namespace
+
+// ===================================================================== plans
+struct sfac_plan_s {
+    Instance in;
+    hipStream_t stream = nullptr;      // caller's stream (may be the legacy default stream)
+    hipStream_t capture = nullptr;     // private stream used only to capture graphs
+    unsigned char* dev = nullptr;      // tables + status words
+    size_t dev_bytes = 0;
+    size_t off_stat = 0;
+    sfac::PassDesc<double> d64[3];
+    sfac::PassDesc<float> d32[3];
+    int use_graph = 1;
+    int chunk = 32;
+    void* graph_u = nullptr;           // state pointer the graphs were captured for
+    hipGraphExec_t exec_chunk = nullptr, exec_one = nullptr;
+    hipGraph_t graph_chunk = nullptr, graph_one = nullptr;
+
+    unsigned long long* stat_max() { return reinterpret_cast<unsigned long long*>(dev + off_stat); }
+    unsigned int* stat_flags() { return reinterpret_cast<unsigned int*>(dev + off_stat + 8); }
+
+    void drop_graphs() {
+        if (exec_chunk) hipGraphExecDestroy(exec_chunk);
+        if (exec_one) hipGraphExecDestroy(exec_one);
+        if (graph_chunk) hipGraphDestroy(graph_chunk);
+        if (graph_one) hipGraphDestroy(graph_one);
+        exec_chunk = exec_one = nullptr;
+        graph_chunk = graph_one = nullptr;
+        graph_u = nullptr;
+    }
+
+    hipError_t launch_steps(hipStream_t s, int64_t nsteps) {
+        for (int64_t k = 0; k < nsteps; ++k) {
+            for (int a = 0; a < in.dims; ++a) {
+                hipError_t e = in.dt == SFAC_FP64 ? launch_pass(d64[a], in.ax[a].lds, s)
+                                                  : launch_pass(d32[a], in.ax[a].lds, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+        return hipSuccess;
+    }
+
+    void set_u(void* u) {
+        for (int a = 0; a < in.dims; ++a) {
+            d64[a].u = static_cast<double*>(u);
+            d32[a].u = static_cast<float*>(u);
+        }
+    }
+
+    sfac_status capture_graph(int64_t steps, hipGraph_t* g, hipGraphExec_t* x) {
+        hipError_t e = hipStreamBeginCapture(capture, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = launch_steps(capture, steps);
+        e = hipStreamEndCapture(capture, g);
+        if (le != hipSuccess) return hip_fail(le, "kernel launch during capture");
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(x, *g, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        return SFAC_OK;
+    }
+};
+
+extern "C" {
+
+const char* sfac_last_error(void) { return g_error.c_str(); }
+
+sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis, const double* alpha_axis,
+                             double eps, double tau, const double* h_axis, sfac_dtype dt, void* hip_stream,
+                             const sfac_options* opt) {
+    g_error.clear();
+    if (!out) return fail(SFAC_EINVAL, "NULL output handle");
+    *out = nullptr;
+    if (dt != SFAC_FP64 && dt != SFAC_FP32) return fail(SFAC_EINVAL, "unknown dtype %d", (int)dt);
+    if (opt) {
+        if (opt->graph_chunk < 0 || opt->graph_chunk > 1024)
+            return fail(SFAC_EINVAL, "graph_chunk = %d, expected 1..1024 (0 = default)", opt->graph_chunk);
+        for (int a = 0; a < 3; ++a)
+            if (opt->method[a] < SFAC_METHOD_AUTO || opt->method[a] > SFAC_METHOD_EMBED)
+                return fail(SFAC_EINVAL, "unknown method %d for axis %d", opt->method[a], a + 1);
+    }
+    std::unique_ptr<sfac_plan_s> p(new (std::nothrow) sfac_plan_s());
+    if (!p) return fail(SFAC_ENOMEM, "host allocation failed");
+    sfac_status st = build_instance(&p->in, dims, n_axis, alpha_axis, eps, tau, h_axis, dt,
+                                    opt ? opt->method : nullptr, "");
+    if (st != SFAC_OK) return st;
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    if (opt) {
+        p->use_graph = opt->use_graph ? 1 : 0;
+        if (opt->graph_chunk > 0) p->chunk = opt->graph_chunk;
+    }
+    p->off_stat = align_up(p->in.table_bytes, 256);
+    p->dev_bytes = p->off_stat + 256;
+    std::vector<unsigned char> host(p->dev_bytes, 0);
+    for (int a = 0; a < p->in.dims; ++a) {
+        if (dt == SFAC_FP64)
+            axis_table_fill<double>(p->in.ax[a].host, p->in.ax[a], host.data());
+        else
+            axis_table_fill<float>(p->in.ax[a].host, p->in.ax[a], host.data());
+    }
+    hipError_t e = hipMalloc(&p->dev, p->dev_bytes);
+    if (e != hipSuccess) {
+        p->dev = nullptr;
+        return e == hipErrorOutOfMemory ? fail(SFAC_ENOMEM, "hipMalloc(%zu): %s", p->dev_bytes, hipGetErrorString(e))
+                                        : hip_fail(e, "hipMalloc");
+    }
+    e = hipMemcpy(p->dev, host.data(), p->dev_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(p->dev);
+        return hip_fail(e, "hipMemcpy tables");
+    }
+    if (p->in.lds_max > 64 * 1024) {
+        e = dt == SFAC_FP64 ? sfac::allow_lds<double>(p->in.lds_max) : sfac::allow_lds<float>(p->in.lds_max);
+        if (e != hipSuccess) {
+            hipFree(p->dev);
+            return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
+        }
+    }
+    e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        hipFree(p->dev);
+        return hip_fail(e, "hipStreamCreate");
+    }
+    for (int a = 0; a < p->in.dims; ++a) {
+        p->d64[a] = make_desc<double>(p->in, a, p->dev, nullptr, p->stat_max(), p->stat_flags());
+        p->d32[a] = make_desc<float>(p->in, a, p->dev, nullptr, p->stat_max(), p->stat_flags());
+    }
+    *out = p.release();
+    return SFAC_OK;
+}
+
+sfac_status sfac_step(sfac_plan p, void* u_dev, int64_t nsteps) {
+    g_error.clear();
+    if (!p) return fail(SFAC_EINVAL, "NULL plan");
+    if (nsteps < 0) return fail(SFAC_EINVAL, "nsteps = %lld, expected >= 0", (long long)nsteps);
+    if (!u_dev) return fail(SFAC_EINVAL, "NULL state pointer");
+    const size_t es = p->in.dt == SFAC_FP64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(u_dev) % es) return fail(SFAC_EINVAL, "state pointer not aligned to %zu bytes", es);
+    if (nsteps == 0) return SFAC_OK;
+    if (!p->use_graph) {
+        p->set_u(u_dev);
+        hipError_t e = p->launch_steps(p->stream, nsteps);
+        return e == hipSuccess ? SFAC_OK : hip_fail(e, "kernel launch");
+    }
+    if (p->graph_u != u_dev) {
+        p->drop_graphs();
+        p->set_u(u_dev);
+        sfac_status st = p->capture_graph(p->chunk, &p->graph_chunk, &p->exec_chunk);
+        if (st == SFAC_OK) st = p->capture_graph(1, &p->graph_one, &p->exec_one);
+        if (st != SFAC_OK) {
+            p->drop_graphs();
+            return st;
+        }
+        p->graph_u = u_dev;
+    }
+    const int64_t full = nsteps / p->chunk, rest = nsteps % p->chunk;
+    for (int64_t k = 0; k < full; ++k) {
+        hipError_t e = hipGraphLaunch(p->exec_chunk, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    for (int64_t k = 0; k < rest; ++k) {
+        hipError_t e = hipGraphLaunch(p->exec_one, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    return SFAC_OK;
+}
+
+sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float* ms) {
+    g_error.clear();
+    if (!p) return fail(SFAC_EINVAL, "NULL plan");
+    if (!u_dev || !ms || reps < 1) return fail(SFAC_EINVAL, "NULL state or output, or reps < 1");
+    const size_t es = p->in.dt == SFAC_FP64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(u_dev) % es) return fail(SFAC_EINVAL, "state pointer not aligned to %zu bytes", es);
+    const int d = p->in.dims;
+    std::vector<hipEvent_t> ev(2 * (size_t)d * reps, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev) {
+        e = hipEventCreate(&x);
+        if (e != hipSuccess) break;
+    }
+    void* keep = p->graph_u;
+    p->set_u(u_dev);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        for (int a = 0; a < d && e == hipSuccess; ++a) {
+            const size_t i = 2 * ((size_t)r * d + a);
+            e = hipEventRecord(ev[i], p->stream);
+            if (e != hipSuccess) break;
+            e = p->in.dt == SFAC_FP64 ? launch_pass(p->d64[a], p->in.ax[a].lds, p->stream)
+                                      : launch_pass(p->d32[a], p->in.ax[a].lds, p->stream);
+            if (e != hipSuccess) break;
+            e = hipEventRecord(ev[i + 1], p->stream);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess) {
+        for (int a = 0; a < d; ++a) {
+            double acc = 0;
+            for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                const size_t i = 2 * ((size_t)r * d + a);
+                float t = 0;
+                e = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+                acc += t;
+            }
+            ms[a] = (float)(acc / reps);
+        }
+    }
+    for (auto& x : ev)
+        if (x) hipEventDestroy(x);
+    // the captured graphs keep their own copies of the launch arguments
+    if (keep) p->set_u(keep);
+    return e == hipSuccess ? SFAC_OK : hip_fail(e, "timed pass launches");
+}
+
+sfac_status sfac_plan_destroy(sfac_plan p) {
+    g_error.clear();
+    if (!p) return SFAC_OK;
+    hipStreamSynchronize(p->stream);
+    p->drop_graphs();
+    if (p->capture) hipStreamDestroy(p->capture);
+    if (p->dev) hipFree(p->dev);
+    delete p;
+    return SFAC_OK;
+}
+
+size_t sfac_plan_device_bytes(sfac_plan p) { return p ? p->dev_bytes : 0; }
+
+sfac_status sfac_plan_flags(sfac_plan p, uint32_t* flags, double* max_abs) {
+    g_error.clear();
+    if (!p) return fail(SFAC_EINVAL, "NULL plan");
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    unsigned char buf[16];
+    e = hipMemcpy(buf, p->dev + p->off_stat, 16, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy status");
+    unsigned long long bits;
+    unsigned int fl;
+    memcpy(&bits, buf, 8);
+    memcpy(&fl, buf + 8, 4);
+    if (flags) *flags = fl;
+    if (max_abs) memcpy(max_abs, &bits, 8);
+    return SFAC_OK;
+}
+
+sfac_status sfac_plan_reset_flags(sfac_plan p) {
+    g_error.clear();
+    if (!p) return fail(SFAC_EINVAL, "NULL plan");
+    hipError_t e = hipMemsetAsync(p->dev + p->off_stat, 0, 16, p->stream);
+    return e == hipSuccess ? SFAC_OK : hip_fail(e, "hipMemsetAsync");
+}
+
+sfac_status sfac_plan_method(sfac_plan p, int32_t axis, int32_t* method, int32_t* length) {
+    g_error.clear();
+    if (!p) return fail(SFAC_EINVAL, "NULL plan");
+    if (axis < 1 || axis > p->in.dims) return fail(SFAC_EINVAL, "axis %d outside 1..%d", axis, p->in.dims);
+    if (method) *method = p->in.ax[axis - 1].host.method;
+    if (length) *length = p->in.ax[axis - 1].host.length;
+    return SFAC_OK;
+}
+
+sfac_status sfac_axis_tables(int32_t n, double alpha, double eps, double tau, double h, int32_t method,
+                             int32_t* length, double* scale_c, double* scale_s, int32_t* radices,
+                             int32_t* nstages) {
+    g_error.clear();
+    int32_t ns[1] = {n};
+    double al[1] = {alpha}, hs[1] = {h};
+    sfac_status st = validate_instance(1, ns, al, eps, tau, hs, "");
+    if (st != SFAC_OK) return st;
+    int m = method;
+    if (m == SFAC_METHOD_AUTO) m = sfac::auto_method(n, SFAC_FP64);
+    if (m != SFAC_METHOD_DIAG && m != SFAC_METHOD_EMBED) return fail(SFAC_EUNSUPPORTED, "no method for N = %d", n);
+    sfac::AxisTables t;
+    std::string err = sfac::build_axis_tables(sfac::AxisParams{n, alpha, eps, tau, h}, m, &t);
+    if (!err.empty()) return fail(SFAC_EUNSUPPORTED, "%s", err.c_str());
+    if (length) *length = t.length;
+    if (scale_c) std::copy(t.scale_c.begin(), t.scale_c.end(), scale_c);
+    if (scale_s) std::copy(t.scale_s.begin(), t.scale_s.end(), scale_s);
+    if (radices) std::copy(t.radices.begin(), t.radices.end(), radices);
+    if (nstages) *nstages = (int32_t)t.radices.size();
+    return SFAC_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== batches
+struct sfac_batch_s {
+    std::vector<Instance> inst;
+    sfac_dtype dt = SFAC_FP64;
+    hipStream_t stream = nullptr;
+    unsigned char* dev = nullptr;           // tables of every instance + status words
+    size_t dev_bytes = 0;
+    std::vector<size_t> table_off;          // per instance offset of its tables
+    size_t off_stat = 0;                    // per instance 16 bytes
+    size_t lds_max = 0;
+    // launch arena (descriptors and block offsets), rewritten by each batch_step call
+    unsigned char* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::vector<unsigned char> arena_host;
+};
+
+namespace {
+
+template <typename T>
+sfac_status batch_run(sfac_batch b, void* const* u_dev, const int64_t* nsteps) {
+    const int count = (int)b->inst.size();
+    // phases: maximal step ranges with a fixed set of active instances
+    std::vector<int64_t> bounds;
+    for (int i = 0; i < count; ++i)
+        if (nsteps[i] > 0) bounds.push_back(nsteps[i]);
+    std::sort(bounds.begin(), bounds.end());
+    bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
+    if (bounds.empty()) return SFAC_OK;
+    const size_t desc_sz = sizeof(sfac::PassDesc<T>);
+    struct Launch {
+        size_t off_desc, off_start;
+        int ndesc, blocks;
+        int64_t reps;
+        int phase;
+    };
+    std::vector<Launch> plan;
+    std::vector<unsigned char>& host = b->arena_host;
+    host.clear();
+    auto push = [&](const void* p, size_t n) {
+        size_t off = align_up(host.size(), 256);
+        host.resize(off + n);
+        memcpy(host.data() + off, p, n);
+        return off;
+    };
+    int64_t done = 0;
+    int phase = 0;
+    for (int64_t bound : bounds) {
+        const int64_t reps = bound - done;
+        for (int pass = 0; pass < 3; ++pass) {
+            std::vector<sfac::PassDesc<T>> ds;
+            std::vector<int> starts(1, 0);
+            for (int i = 0; i < count; ++i) {
+                const Instance& in = b->inst[i];
+                if (nsteps[i] < bound || pass >= in.dims) continue;
+                unsigned long long* sm = reinterpret_cast<unsigned long long*>(b->dev + b->off_stat + 16 * i);
+                unsigned int* sf = reinterpret_cast<unsigned int*>(b->dev + b->off_stat + 16 * i + 8);
+                sfac::PassDesc<T> d = make_desc<T>(in, pass, b->dev + b->table_off[i], static_cast<T*>(u_dev[i]), sm, sf);
+                ds.push_back(d);
+                starts.push_back(starts.back() + sfac::pass_blocks(d));
+            }
+            if (ds.empty()) continue;
+            Launch l;
+            l.off_desc = push(ds.data(), ds.size() * desc_sz);
+            l.off_start = push(starts.data(), starts.size() * sizeof(int));
+            l.ndesc = (int)ds.size();
+            l.blocks = starts.back();
+            l.reps = reps;
+            l.phase = phase;
+            plan.push_back(l);
+        }
+        done = bound;
+        ++phase;
+    }
+    // the arena may still be read by the previous call's launches
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (host.size() > b->arena_bytes) {
+        if (b->arena) hipFree(b->arena);
+        b->arena = nullptr;
+        b->arena_bytes = 0;
+        e = hipMalloc(&b->arena, host.size());
+        if (e != hipSuccess) return fail(SFAC_ENOMEM, "hipMalloc(%zu) for the launch arena: %s", host.size(),
+                                         hipGetErrorString(e));
+        b->arena_bytes = host.size();
+    }
+    e = hipMemcpy(b->arena, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy launch arena");
+    // launches: phase after phase; inside a phase, step after step, pass after pass
+    size_t li = 0;
+    while (li < plan.size()) {
+        size_t lj = li;
+        while (lj < plan.size() && plan[lj].phase == plan[li].phase) ++lj;
+        for (int64_t r = 0; r < plan[li].reps; ++r) {
+            for (size_t k = li; k < lj; ++k) {
+                const Launch& l = plan[k];
+                e = sfac::launch_axis_pass_multi<T>(reinterpret_cast<const sfac::PassDesc<T>*>(b->arena + l.off_desc),
+                                                    reinterpret_cast<const int*>(b->arena + l.off_start), l.ndesc,
+                                                    l.blocks, b->lds_max, b->stream);
+                if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
+            }
+        }
+        li = lj;
+    }
+    return SFAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instance_desc* desc, sfac_dtype dt,
+                              void* hip_stream) {
+    g_error.clear();
+    if (!out) return fail(SFAC_EINVAL, "NULL output handle");
+    *out = nullptr;
+    if (count < 1 || !desc) return fail(SFAC_EINVAL, "count = %d with %s descriptors", count, desc ? "" : "NULL");
+    if (dt != SFAC_FP64 && dt != SFAC_FP32) return fail(SFAC_EINVAL, "unknown dtype %d", (int)dt);
+    std::unique_ptr<sfac_batch_s> b(new (std::nothrow) sfac_batch_s());
+    if (!b) return fail(SFAC_ENOMEM, "host allocation failed");
+    b->dt = dt;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->inst.resize(count);
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        char who[64];
+        snprintf(who, sizeof who, "instance %d: ", i);
+        const sfac_instance_desc& d = desc[i];
+        sfac_status st = build_instance(&b->inst[i], d.dims, d.n, d.alpha, d.eps, d.tau, d.h, dt, nullptr, who);
+        if (st != SFAC_OK) return st;
+        b->table_off.push_back(off);
+        off = align_up(off + b->inst[i].table_bytes, 256);
+        b->lds_max = std::max(b->lds_max, b->inst[i].lds_max);
+    }
+    b->off_stat = off;
+    b->dev_bytes = off + align_up(16 * (size_t)count, 256);
+    std::vector<unsigned char> host(b->dev_bytes, 0);
+    for (int i = 0; i < count; ++i) {
+        for (int a = 0; a < b->inst[i].dims; ++a) {
+            if (dt == SFAC_FP64)
+                axis_table_fill<double>(b->inst[i].ax[a].host, b->inst[i].ax[a], host.data() + b->table_off[i]);
+            else
+                axis_table_fill<float>(b->inst[i].ax[a].host, b->inst[i].ax[a], host.data() + b->table_off[i]);
+        }
+    }
+    hipError_t e = hipMalloc(&b->dev, b->dev_bytes);
+    if (e != hipSuccess) {
+        b->dev = nullptr;
+        return fail(SFAC_ENOMEM, "hipMalloc(%zu): %s", b->dev_bytes, hipGetErrorString(e));
+    }
+    e = hipMemcpy(b->dev, host.data(), b->dev_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(b->dev);
+        return hip_fail(e, "hipMemcpy tables");
+    }
+    if (b->lds_max > 64 * 1024) {
+        e = dt == SFAC_FP64 ? sfac::allow_lds<double>(b->lds_max) : sfac::allow_lds<float>(b->lds_max);
+        if (e != hipSuccess) {
+            hipFree(b->dev);
+            return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
+        }
+    }
+    *out = b.release();
+    return SFAC_OK;
+}
+
+sfac_status sfac_batch_step(sfac_batch b, void* const* u_dev, const int64_t* nsteps) {
+    g_error.clear();
+    if (!b) return fail(SFAC_EINVAL, "NULL batch");
+    if (!u_dev || !nsteps) return fail(SFAC_EINVAL, "NULL state or step array");
+    const size_t es = b->dt == SFAC_FP64 ? 8 : 4;
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        if (nsteps[i] < 0) return fail(SFAC_EINVAL, "instance %zu: nsteps = %lld", i, (long long)nsteps[i]);
+        if (nsteps[i] > 0 && !u_dev[i]) return fail(SFAC_EINVAL, "instance %zu: NULL state pointer", i);
+        if (reinterpret_cast<uintptr_t>(u_dev[i]) % es) return fail(SFAC_EINVAL, "instance %zu: misaligned state", i);
+    }
+    return b->dt == SFAC_FP64 ? batch_run<double>(b, u_dev, nsteps) : batch_run<float>(b, u_dev, nsteps);
+}
+
+sfac_status sfac_batch_destroy(sfac_batch b) {
+    g_error.clear();
+    if (!b) return SFAC_OK;
+    hipStreamSynchronize(b->stream);
+    if (b->arena) hipFree(b->arena);
+    if (b->dev) hipFree(b->dev);
+    delete b;
+    return SFAC_OK;
+}
+
+size_t sfac_batch_device_bytes(sfac_batch b) { return b ? b->dev_bytes + b->arena_bytes : 0; }
+
+}  // extern "C"

@@ -1,0 +1,263 @@
+// Host-side construction of the per-axis tables (FP64 results from long double arithmetic).
+//
+// For one axis with N interior nodes, order alpha, mesh width h, parameter eps and step tau:
+//   * g_k and omega_k by the recursions of eqs. (g_coe), (omega_coe);
+//   * the first column b_k of the symmetric Toeplitz B_alpha = kappa (D + D^T) of eq. (B),
+//     kappa = -eps^2 / (2 h^alpha cos(alpha pi / 2)): entry (i, j) of D is omega_{i-j+1}, so
+//     b_0 = 2 kappa omega_1, b_1 = kappa (omega_0 + omega_2), b_k = kappa omega_{k+1} (k >= 2);
+//   * the first columns of the circulant C and skew-circulant S of eqs. (C), (S):
+//     c_0 = s_0 = b_0 / 2, c_k = (b_k + b_{N-k}) / 2, s_k = (b_k - b_{N-k}) / 2;
+//   * the spectra of Remark 1 with the forward transform e^{-2 pi i j k / N}:
+//     lambda_j = sum_k c_k e^{-2 pi i j k / N},  mu_j = sum_k s_k psi_k e^{-2 pi i j k / N},
+//     psi_k = e^{-i pi k / N}; both are real because c and s are symmetric.
+// The diagonal method keeps e^{tau/2 lambda_j}/N and e^{tau mu_j}/N (the 1/N of the inverse
+// transform folded in). The embedded method turns both exponentials back into their first
+// columns (each is a symmetric Toeplitz matrix) and keeps the length-M spectra of those
+// columns placed as circular convolution kernels, divided by M.
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "sfac_internal.hpp"
+
+namespace sfac {
+
+namespace {
+
+using ld = long double;
+const ld kPi = 3.141592653589793238462643383279502884L;
+
+// cos(pi r / n) for r < 2n, exact integer angle reduction by the caller
+std::vector<ld> half_turn_cosines(int n) {
+    std::vector<ld> t(2 * (size_t)n);
+    for (int r = 0; r < 2 * n; ++r) t[r] = cosl(kPi * (ld)r / (ld)n);
+    return t;
+}
+
+int ilog2(int v) {
+    int e = 0;
+    while ((1 << e) < v) ++e;
+    return e;
+}
+
+}  // namespace
+
+int embed_length(int n) {
+    int m = 2;
+    while (m < 2 * n - 1) m <<= 1;
+    return m;
+}
+
+bool factor_radices(int n, std::vector<int>* radices) {
+    radices->clear();
+    if (n < 1) return false;
+    int e = 0;
+    while ((n & 1) == 0) {
+        n >>= 1;
+        ++e;
+    }
+    std::vector<int> merged;
+    int threes = 0;
+    for (int p = 3; n > 1; p += 2) {
+        if (p > kMaxPrimeRadix) return false;
+        while (n % p == 0) {
+            n /= p;
+            if (p == 3)
+                ++threes;
+            else
+                merged.push_back(p);
+        }
+    }
+    // pairs of 3s become one radix-9 pass (no more arithmetic than two radix-3 passes)
+    for (; threes >= 2; threes -= 2) merged.push_back(9);
+    if (threes) merged.push_back(3);
+    // powers of two: as few passes as possible, bits spread evenly, each radix <= 16
+    if (e > 0) {
+        int stages = (e + 3) / 4;
+        for (int s = 0; s < stages; ++s) {
+            int bits = e / stages + (s < e % stages ? 1 : 0);
+            merged.push_back(1 << bits);
+        }
+    }
+    // largest radices first
+    for (size_t i = 0; i < merged.size(); ++i)
+        for (size_t j = i + 1; j < merged.size(); ++j)
+            if (merged[j] > merged[i]) std::swap(merged[i], merged[j]);
+    *radices = merged;
+    return (int)radices->size() <= kMaxStages;
+}
+
+namespace {
+
+// Rough cost per interior point of one exponential factor: flops plus a charge per
+// pass through local memory, used only to choose between the two exact methods.
+double factor_cost(const std::vector<int>& radices, double length_ratio) {
+    double flops = 0, passes = 0;
+    for (size_t s = 0; s < radices.size(); ++s) {
+        int r = radices[s];
+        bool pow2 = (r & (r - 1)) == 0;
+        flops += pow2 ? 5.0 * ilog2(r) : 4.0 * r;
+        if (s) flops += 6.0;
+        passes += 1.0;
+    }
+    return length_ratio * (2.0 * flops + 16.0 * passes);
+}
+
+}  // namespace
+
+int auto_method(int n, sfac_dtype) {
+    if (n <= 2) return SFAC_METHOD_DIAG;
+    std::vector<int> rd;
+    bool diag_ok = n <= kMaxDiagLength && factor_radices(n, &rd);
+    int m = embed_length(n);
+    std::vector<int> re;
+    bool embed_ok = m <= kMaxEmbedLength && factor_radices(m, &re);
+    if (!embed_ok) return diag_ok ? SFAC_METHOD_DIAG : 0;
+    if (!diag_ok) return SFAC_METHOD_EMBED;
+    double cd = factor_cost(rd, 1.0);
+    double ce = factor_cost(re, (double)m / (double)n);
+    return cd <= ce ? SFAC_METHOD_DIAG : SFAC_METHOD_EMBED;
+}
+
+std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out) {
+    const int N = p.n;
+    char msg[256];
+    if (N < 1) return "N must be >= 1";
+    if (!(p.alpha > 1.0 && p.alpha <= 2.0)) {
+        snprintf(msg, sizeof msg, "alpha = %g is outside (1, 2]", p.alpha);
+        return msg;
+    }
+    if (!(p.eps >= 0.0) || !std::isfinite(p.eps)) return "eps must be finite and >= 0";
+    if (!(p.tau > 0.0) || !std::isfinite(p.tau)) return "tau must be finite and > 0";
+    if (!(p.h > 0.0) || !std::isfinite(p.h)) return "h must be finite and > 0";
+
+    AxisTables& t = *out;
+    t = AxisTables();
+    t.n = N;
+    t.method = method;
+    if (method == SFAC_METHOD_DIAG) {
+        if (N > kMaxDiagLength) {
+            snprintf(msg, sizeof msg, "N = %d exceeds the diagonal method's limit %d", N, kMaxDiagLength);
+            return msg;
+        }
+        if (!factor_radices(N, &t.radices)) {
+            snprintf(msg, sizeof msg, "N = %d has a prime factor above %d (use the embedded method)",
+                     N, kMaxPrimeRadix);
+            return msg;
+        }
+        t.length = N;
+    } else if (method == SFAC_METHOD_EMBED) {
+        int m = embed_length(N);
+        if (m > kMaxEmbedLength) {
+            snprintf(msg, sizeof msg, "N = %d exceeds the embedded method's limit %d", N, kMaxEmbedLength / 2);
+            return msg;
+        }
+        factor_radices(m, &t.radices);
+        t.length = m;
+    } else {
+        return "unknown method";
+    }
+
+    // eqs. (g_coe), (omega_coe): omega_0 .. omega_N
+    std::vector<ld> g(N + 2), w(N + 2);
+    const ld a = p.alpha;
+    g[0] = 1.0L;
+    for (int k = 0; k + 1 < N + 2; ++k) g[k + 1] = (1.0L - (a + 1.0L) / (ld)(k + 1)) * g[k];
+    w[0] = 0.5L * a * g[0];
+    for (int k = 0; k + 1 < N + 2; ++k) w[k + 1] = 0.5L * a * g[k + 1] + 0.5L * (2.0L - a) * g[k];
+
+    // eq. (B): kappa and the first column of B
+    const ld kappa = -((ld)p.eps * (ld)p.eps) / (2.0L * powl((ld)p.h, a) * cosl(a * kPi / 2.0L));
+    std::vector<ld> b(N);
+    b[0] = 2.0L * kappa * w[1];
+    if (N >= 2) b[1] = kappa * (w[0] + w[2]);
+    for (int k = 2; k < N; ++k) b[k] = kappa * w[k + 1];
+
+    // eqs. (C), (S)
+    std::vector<ld> c(N), s(N);
+    c[0] = s[0] = 0.5L * b[0];
+    for (int k = 1; k < N; ++k) {
+        c[k] = 0.5L * (b[k] + b[N - k]);
+        s[k] = 0.5L * (b[k] - b[N - k]);
+    }
+
+    // Remark 1: spectra (real parts; the imaginary parts vanish by symmetry)
+    const std::vector<ld> cosn = half_turn_cosines(N);  // cos(pi r / N)
+    std::vector<ld> lam(N), mu(N);
+    for (int j = 0; j < N; ++j) {
+        ld sl = 0, sm = 0;
+        for (int k = 0; k < N; ++k) {
+            sl += c[k] * cosn[(size_t)((2LL * j * k) % (2LL * N))];
+            sm += s[k] * cosn[(size_t)(((long long)k * (2LL * j + 1)) % (2LL * N))];
+        }
+        lam[j] = sl;
+        mu[j] = sm;
+    }
+    const ld tau = p.tau;
+    std::vector<ld> ec(N), es(N);
+    for (int j = 0; j < N; ++j) {
+        ec[j] = expl(0.5L * tau * lam[j]);
+        es[j] = expl(tau * mu[j]);
+    }
+
+    const int L = t.length;
+    t.tw_re.resize(L);
+    t.tw_im.resize(L);
+    for (int m = 0; m < L; ++m) {
+        ld ang = 2.0L * kPi * (ld)m / (ld)L;
+        t.tw_re[m] = (double)cosl(ang);
+        t.tw_im[m] = (double)-sinl(ang);
+    }
+
+    if (method == SFAC_METHOD_DIAG) {
+        t.scale_c.resize(N);
+        t.scale_s.resize(N);
+        t.psi_re.resize(N);
+        t.psi_im.resize(N);
+        for (int j = 0; j < N; ++j) {
+            t.scale_c[j] = (double)(ec[j] / (ld)N);
+            t.scale_s[j] = (double)(es[j] / (ld)N);
+        }
+        for (int k = 0; k < N; ++k) {
+            ld ang = kPi * (ld)k / (ld)N;
+            t.psi_re[k] = (double)cosl(ang);
+            t.psi_im[k] = (double)-sinl(ang);
+        }
+    } else {
+        // first columns of e^{tau/2 C} (circulant, gamma) and e^{tau S} (skew-circulant, sigma):
+        // gamma_k = (1/N) sum_j e^{tau/2 lambda_j} cos(2 pi j k / N),
+        // sigma_k = (1/N) sum_j e^{tau mu_j} cos(pi k (2j + 1) / N); both matrices are symmetric
+        // Toeplitz, so entry (p, q) is gamma_{|p-q|} resp. sigma_{|p-q|}.
+        std::vector<ld> gam(N), sig(N);
+        for (int k = 0; k < N; ++k) {
+            ld sg = 0, ss = 0;
+            for (int j = 0; j < N; ++j) {
+                sg += ec[j] * cosn[(size_t)((2LL * j * k) % (2LL * N))];
+                ss += es[j] * cosn[(size_t)(((long long)k * (2LL * j + 1)) % (2LL * N))];
+            }
+            gam[k] = sg / (ld)N;
+            sig[k] = ss / (ld)N;
+        }
+        // length-M circular kernels g[d mod M] = col[|d|], |d| < N; their spectra are real:
+        // G[m] = col[0] + 2 sum_{d=1}^{N-1} col[d] cos(2 pi m d / M); the 1/M of the inverse
+        // transform is folded in.
+        std::vector<ld> cosm(L);
+        for (int r = 0; r < L; ++r) cosm[r] = cosl(2.0L * kPi * (ld)r / (ld)L);
+        t.scale_c.resize(L);
+        t.scale_s.resize(L);
+        for (int m = 0; m < L; ++m) {
+            ld gc = gam[0], gs = sig[0];
+            for (int d = 1; d < N; ++d) {
+                ld cs = cosm[(size_t)(((long long)m * d) % L)];
+                gc += 2.0L * gam[d] * cs;
+                gs += 2.0L * sig[d] * cs;
+            }
+            t.scale_c[m] = (double)(gc / (ld)L);
+            t.scale_s[m] = (double)(gs / (ld)L);
+        }
+    }
+    return std::string();
+}
+
+}  // namespace sfac

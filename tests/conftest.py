@@ -28,3 +28,12 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def sfac_lib():
+    """The built library; built in-tree first if it is missing."""
+    from paper_2209_08437_amd import sfac, build_lib
+    if not os.path.exists(sfac.LIB_PATH):
+        build_lib.build()
+    return sfac.lib()

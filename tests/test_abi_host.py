@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI (no GPU needed): exported symbols, argument validation, and
+the FP64 tables the library builds on the host against the oracle's dense matrices."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import sfac_oracle as O
+from paper_2209_08437_amd import sfac
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sfac.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfac_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(sfac_lib):
+    names = _declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(sfac_lib, n), n
+    assert set(names) == set(sfac.EXPORTS)
+
+
+def _create(dims, ns, alphas, eps, tau, hs, dt=sfac.FP64, opt=None):
+    L = sfac.lib()
+    h = ctypes.c_void_p()
+    n_arr = (ctypes.c_int32 * max(1, len(ns)))(*ns)
+    a_arr = (ctypes.c_double * max(1, len(alphas)))(*alphas)
+    h_arr = (ctypes.c_double * max(1, len(hs)))(*hs)
+    st = L.sfac_plan_create(ctypes.byref(h), dims, n_arr, a_arr, eps, tau, h_arr, dt, None,
+                            ctypes.byref(opt) if opt is not None else None)
+    return st, h, L.sfac_last_error().decode()
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(dims=4, ns=[8] * 4, alphas=[1.5] * 4, eps=0.1, tau=0.01, hs=[0.1] * 4), "dims"),
+    (dict(dims=0, ns=[8], alphas=[1.5], eps=0.1, tau=0.01, hs=[0.1]), "dims"),
+    (dict(dims=2, ns=[8, 0], alphas=[1.5, 1.5], eps=0.1, tau=0.01, hs=[0.1, 0.1]), "N_2"),
+    (dict(dims=2, ns=[8, 8], alphas=[1.0, 1.5], eps=0.1, tau=0.01, hs=[0.1, 0.1]), "alpha_1"),
+    (dict(dims=2, ns=[8, 8], alphas=[1.5, 2.01], eps=0.1, tau=0.01, hs=[0.1, 0.1]), "alpha_2"),
+    (dict(dims=2, ns=[8, 8], alphas=[1.5, 1.5], eps=-0.1, tau=0.01, hs=[0.1, 0.1]), "eps"),
+    (dict(dims=2, ns=[8, 8], alphas=[1.5, 1.5], eps=0.1, tau=0.0, hs=[0.1, 0.1]), "tau"),
+    (dict(dims=2, ns=[8, 8], alphas=[1.5, 1.5], eps=0.1, tau=float("nan"), hs=[0.1, 0.1]), "tau"),
+    (dict(dims=2, ns=[8, 8], alphas=[1.5, 1.5], eps=0.1, tau=0.01, hs=[0.1, -1.0]), "h_2"),
+])
+def test_invalid_arguments_are_rejected(sfac_lib, case, expect):
+    st, h, msg = _create(**case)
+    assert st == sfac.EINVAL and not h.value
+    assert expect in msg
+
+
+def test_unsupported_sizes(sfac_lib):
+    st, h, msg = _create(2, [5000, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1])
+    assert st == sfac.EUNSUPPORTED and not h.value, msg
+    opt = sfac.Options()
+    opt.method[0] = sfac.METHOD_DIAG
+    st, h, msg = _create(2, [127, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)   # 127 is prime
+    assert st == sfac.EUNSUPPORTED and "prime factor" in msg
+    opt = sfac.Options()
+    opt.graph_chunk = 5000
+    st, h, msg = _create(2, [8, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EINVAL and "graph_chunk" in msg
+
+
+def test_null_handles(sfac_lib):
+    L = sfac_lib
+    assert L.sfac_plan_destroy(None) == sfac.OK
+    assert L.sfac_batch_destroy(None) == sfac.OK
+    assert L.sfac_plan_device_bytes(None) == 0
+    assert L.sfac_step(None, None, 1) == sfac.EINVAL
+    assert "NULL plan" in L.sfac_last_error().decode()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 31, 63, 64, 100, 127, 255, 1023])
+def test_radix_plans(sfac_lib, n):
+    for method in ("diag", "embed"):
+        try:
+            length, _, _, rad = sfac.axis_tables(n, 1.5, 0.1, 0.01, 2.0 / (n + 1), method)
+        except sfac.SfacError as e:
+            assert method == "diag" and e.status == sfac.EUNSUPPORTED
+            continue
+        assert int(np.prod(rad)) == length if rad else length == 1
+        assert all(r in (2, 3, 4, 5, 7, 8, 9, 11, 13, 16, 17, 19, 23, 29, 31) for r in rad)
+        if method == "embed":
+            assert length >= 2 * n - 1 and length & (length - 1) == 0
+
+
+@pytest.mark.parametrize("n,alpha", [(1, 1.5), (2, 1.3), (7, 1.9), (31, 1.5), (63, 1.2), (255, 1.7)])
+def test_host_tables_match_oracle(sfac_lib, n, alpha):
+    """The library's diagonal tables are e^{tau/2 lambda}/N and e^{tau mu}/N; the embedded
+    tables are spectra of the first columns of e^{tau/2 C} and e^{tau S}. Both are compared
+    with the oracle's dense matrices."""
+    eps, tau, h = 0.13, 0.02, 2.0 / (n + 1)
+    ops = O.AxisOperators(n, alpha, eps, h, tau)
+    try:
+        L, sc, ss, _ = sfac.axis_tables(n, alpha, eps, tau, h, "diag")
+    except sfac.SfacError:
+        L = None
+    if L is not None:
+        lam = O.circulant_spectrum(ops.C)
+        mu = O.skew_spectrum(ops.S)
+        # the library's forward transform carries e^{-i pi k (2j+1)/N}, the paper's e^{+i pi k (2j-1)/N}:
+        # the same eigenvalues, indexed one apart
+        assert np.allclose(sc * n, np.exp(0.5 * tau * lam), rtol=1e-13, atol=0)
+        assert np.allclose(ss * n, np.exp(tau * np.roll(mu, -1)), rtol=1e-13, atol=0)
+    M, gc, gs, _ = sfac.axis_tables(n, alpha, eps, tau, h, "embed")
+    kc = np.fft.ifft(gc).real * M              # circular kernels, index 0..M-1
+    ks = np.fft.ifft(gs).real * M
+    assert np.allclose(kc[:n], ops.EC[:, 0], rtol=0, atol=1e-14)
+    assert np.allclose(ks[:n], ops.ES[:, 0], rtol=0, atol=1e-14)
+    assert np.allclose(kc[M - n + 1:][::-1], ops.EC[1:, 0], rtol=0, atol=1e-14)   # symmetric kernel
+    assert np.allclose(kc[n:M - n + 1], 0, atol=1e-14)

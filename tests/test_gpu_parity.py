@@ -1,0 +1,242 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, element by element on
+seeded inputs, plus the invariants that hold at any size.
+
+Tolerances (relative max-norm, max|gpu - oracle| / max|oracle|):
+  FP64: 1e-12.
+  FP32: 2e-5 for runs of up to a few hundred steps. The FP32 path rounds the state to 24 bits
+        after every pass; each pass is contractive (Lemma 1, 2: ||e^{tC}||, ||e^{tS}|| <= 1) and
+        the nonlinear step has Lipschitz constant e^{tau/2}, so per-step rounding of a few
+        units of 6e-8 accumulates at most linearly in the step count with growth e^{T}.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sfac_oracle as O
+from paper_2209_08437_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-4
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_solve(u0, ns, alphas, eps, hs, tau, steps, dtype="f64", method=None, use_graph=True, chunk=32):
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    u = torch.tensor(np.asarray(u0), dtype=tdt, device="cuda").contiguous()
+    with sfac.Plan(ns, alphas, eps, tau, hs, dtype, method=method, use_graph=use_graph,
+                   graph_chunk=chunk) as p:
+        p.step(u, steps)
+        flags = p.flags()
+    torch.cuda.synchronize()
+    return u.double().cpu().numpy(), flags
+
+
+def rel_err(a, ref):
+    return float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def _methods_for(ns):
+    from paper_2209_08437_amd import sfac
+    out = [None, "embed"]
+    ok = True
+    for n in ns:
+        try:
+            sfac.axis_tables(n, 1.5, 0.1, 0.01, 0.1, "diag")
+        except sfac.SfacError:
+            ok = False
+    if ok:
+        out.append("diag")
+    return out
+
+
+# ------------------------------------------------------------------ plain 2D, N = 63
+@pytest.mark.parametrize("method", [None, "diag", "embed"])
+def test_plain_2d_63_fp64(sfac_lib, method):
+    inst = W.plain_2d_63()
+    _say(f"case plain_2d_63 fp64 method={method}")
+    ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
+    got, (flags, vmax) = gpu_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau,
+                                   inst.steps, "f64", method)
+    e = rel_err(got, ref)
+    _say(f"  rel err {e:.3e}  max|u| {vmax:.6f}")
+    assert e <= FP64_TOL
+    # the sticky maximum covers every step since the reset, so it bounds the final state
+    assert flags == 0 and np.abs(ref).max() * (1 - 1e-12) <= vmax <= 1.0
+
+
+@pytest.mark.parametrize("method", [None, "embed"])
+def test_plain_2d_63_fp32(sfac_lib, method):
+    inst = W.plain_2d_63()
+    _say(f"case plain_2d_63 fp32 method={method}")
+    ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
+    got, (flags, vmax) = gpu_solve(inst.u0.astype(np.float32), inst.ns, inst.alphas, inst.eps,
+                                   inst.hs, inst.tau, inst.steps, "f32", method)
+    e = rel_err(got, ref)
+    _say(f"  rel err {e:.3e}")
+    assert e <= FP32_TOL and flags == 0
+
+
+# --------------------------------------------------------------- ragged / edge shapes
+SHAPES = [(1,), (2,), (5,), (64,), (127,), (1, 1), (2, 3), (3, 2), (7, 5), (17, 31), (64, 33),
+          (100, 9), (127, 64), (3, 4, 5), (7, 6, 9), (16, 17, 11), (1, 5, 2)]
+
+
+@pytest.mark.parametrize("ns", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_shapes_fp64(sfac_lib, ns):
+    rng = np.random.default_rng(sum(ns) * 7 + len(ns))
+    alphas = tuple(float(a) for a in rng.uniform(1.05, 2.0, len(ns)))
+    eps, tau = 0.3, 0.02
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.95, 0.95, seed=sum(ns))
+    ref = O.two_level_solve(u0, ns, alphas, eps, hs, tau, 3)
+    for method in _methods_for(ns):
+        _say(f"case shape {ns} method={method}")
+        got, (flags, _) = gpu_solve(u0, ns, alphas, eps, hs, tau, 3, "f64", method)
+        e = rel_err(got, ref)
+        assert e <= FP64_TOL, (method, e)
+        assert flags == 0
+
+
+def test_special_parameters(sfac_lib):
+    """alpha = 2 (three-point Laplacian) and eps = 0 (pure Bernoulli flow, closed form)."""
+    ns = (20, 13)
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field((13, 20), -1.0, 1.0, seed=3)
+    _say("case alpha=2")
+    ref = O.two_level_solve(u0, ns, (2.0, 2.0), 0.2, hs, 0.01, 5)
+    got, _ = gpu_solve(u0, ns, (2.0, 2.0), 0.2, hs, 0.01, 5)
+    assert rel_err(got, ref) <= FP64_TOL
+    _say("case eps=0")
+    got, _ = gpu_solve(u0, ns, (1.5, 1.5), 0.0, hs, 0.03, 25)
+    T = 25 * 0.03
+    closed = u0 / np.sqrt(u0 ** 2 + (1 - u0 ** 2) * np.exp(-2 * T))
+    assert np.abs(got - closed).max() <= 1e-13
+
+
+# ----------------------------------------------------- full-size workloads (few steps)
+@pytest.mark.parametrize("method", [None, "diag"])
+def test_large_2d_1023_full_size(sfac_lib, method):
+    inst = W.large_2d_1023()
+    steps = 2
+    _say(f"case large_2d_1023 fp64 {steps} steps method={method}")
+    ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, steps)
+    got, (flags, _) = gpu_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, steps,
+                                "f64", method)
+    e = rel_err(got, ref)
+    _say(f"  rel err {e:.3e}")
+    assert e <= FP64_TOL and flags == 0
+    got32, _ = gpu_solve(inst.u0.astype(np.float32), inst.ns, inst.alphas, inst.eps, inst.hs,
+                         inst.tau, steps, "f32", method)
+    e32 = rel_err(got32, ref)
+    _say(f"  fp32 rel err {e32:.3e}")
+    assert e32 <= FP32_TOL
+
+
+def test_large_3d_255_full_size_one_step(sfac_lib):
+    inst = W.large_3d_255()
+    _say("case large_3d_255 fp64 1 step")
+    ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, 1)
+    got, (flags, _) = gpu_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, 1)
+    e = rel_err(got, ref)
+    _say(f"  rel err {e:.3e}")
+    assert e <= FP64_TOL and flags == 0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_subsample_3d_63_all_steps(sfac_lib, dtype):
+    big = W.large_3d_255()
+    inst = W.subsample_3d_63(big)
+    _say(f"case subsample_3d_63 {dtype} {inst.steps} steps")
+    ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
+    u0 = inst.u0 if dtype == "f64" else inst.u0.astype(np.float32)
+    got, (flags, vmax) = gpu_solve(u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps, dtype)
+    e = rel_err(got, ref)
+    _say(f"  rel err {e:.3e} max|u| {vmax:.6f}")
+    assert e <= (FP64_TOL if dtype == "f64" else FP32_TOL)
+    assert flags == 0 and vmax <= 1.0
+
+
+# --------------------------------------------------------------------- invariants
+def test_odd_symmetry_and_resumability_bitwise(sfac_lib):
+    ns = (63, 40)
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field((40, 63), -0.9, 0.9, seed=12)
+    args = (ns, (1.3, 1.8), 0.1, hs, 0.01)
+    _say("case invariants")
+    a, _ = gpu_solve(u0, *args, 40)
+    b, _ = gpu_solve(-u0, *args, 40)
+    assert np.array_equal(b, -a)
+    c, _ = gpu_solve(u0, *args, 40, use_graph=False)
+    assert np.array_equal(c, a)
+    d, _ = gpu_solve(u0, *args, 40, chunk=7)
+    assert np.array_equal(d, a)
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    u = torch.tensor(u0, device="cuda")
+    with sfac.Plan(ns, (1.3, 1.8), 0.1, 0.01, hs) as p:
+        p.step(u, 13)
+        p.step(u, 27)
+    torch.cuda.synchronize()
+    assert np.array_equal(u.cpu().numpy(), a)
+
+
+def test_flags_report_nonfinite_and_above_one(sfac_lib):
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    ns = (16, 16)
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field((16, 16), -0.9, 0.9, seed=1)
+    _say("case flags")
+    with sfac.Plan(ns, (1.5, 1.5), 0.1, 0.01, hs) as p:
+        u = torch.tensor(u0, device="cuda")
+        p.step(u, 3)
+        f, m = p.flags()
+        assert f == 0 and 0 < m <= 1
+        u[3, 4] = float("nan")
+        p.step(u, 1)
+        f, _ = p.flags()
+        assert f & sfac.FLAG_NONFINITE
+        p.reset_flags()
+        u = torch.tensor(u0 * 1.5, device="cuda")       # |u0| > 1 leaves the DMP's premise
+        p.step(u, 1)
+        f, m = p.flags()
+        assert f & sfac.FLAG_ABOVE_ONE and m > 1
+
+
+# -------------------------------------------------------------------------- batch
+def test_batch_matches_single_bitwise_and_oracle(sfac_lib):
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    insts = W.batched_2d(count=6, steps=5, seed=21, sizes=(31, 63, 100, 127))
+    extra = W.Instance((9, 10, 11), (1.2, 1.5, 1.8), 0.2, 0.01, W.mesh_widths((9, 10, 11)), 4)
+    extra.u0 = W.uniform_field((11, 10, 9), -0.9, 0.9, seed=2)
+    insts.append(extra)
+    steps = [i.steps for i in insts]
+    steps[1] = 0
+    steps[2] = 2
+    _say("case batch fp64")
+    states = [torch.tensor(i.u0, device="cuda") for i in insts]
+    b = sfac.Batch(insts, "f64")
+    b.step(states, steps)
+    torch.cuda.synchronize()
+    for i, inst in enumerate(insts):
+        alone, _ = gpu_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, steps[i])
+        got = states[i].cpu().numpy()
+        assert np.array_equal(got, alone), i
+        ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, steps[i])
+        assert rel_err(got, ref) <= FP64_TOL, i
+    b.close()
