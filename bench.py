@@ -80,6 +80,88 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps):
     return result
 
 
+def batched_run(args):
+    """All instances of the batched workload stepped together (sfac_batch_step), against the
+    same instances stepped one after another with plain FP64 plans."""
+    import numpy as np
+    import torch
+    from paper_2209_08437_amd import sfac, workloads as W
+    insts = W.batched_2d(count=args.batch_count, steps=args.steps or 500)
+    steps = insts[0].steps
+    pts = sum(i.points for i in insts)
+    res = {}
+    for dt in ("f32", "f64"):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        states = [torch.tensor(i.u0, dtype=tdt, device="cuda") for i in insts]
+        b = sfac.Batch(insts, dt)
+        b.step(states, min(args.warmup, steps))
+        torch.cuda.synchronize()
+        states = [torch.tensor(i.u0, dtype=tdt, device="cuda") for i in insts]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(states, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        vmax = max(b.flags(k)[1] for k in range(len(insts)))
+        res[dt] = {"value": pts * steps / wall, "wall_s": wall, "max_abs": vmax}
+        log(f"[bench] batched {len(insts)} instances {dt}: {steps} steps in {wall * 1e3:.1f} ms")
+        b.close()
+    # plain FP64 path: one plan per instance, stepped one after another
+    plans = [sfac.Plan(i.ns, i.alphas, i.eps, i.tau, i.hs, "f64") for i in insts]
+    states = [torch.tensor(i.u0, dtype=torch.float64, device="cuda") for i in insts]
+    for p, u in zip(plans, states):
+        p.step(u, min(args.warmup, steps))
+    torch.cuda.synchronize()
+    states = [torch.tensor(i.u0, dtype=torch.float64, device="cuda") for i in insts]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, u in zip(plans, states):
+        p.step(u, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res["f64_sequential"] = {"value": pts * steps / wall, "wall_s": wall}
+    for p in plans:
+        p.close()
+    sizes = sorted(set(i.ns[0] for i in insts))
+    return {
+        "metric": METRIC, "value": round(res["f32"]["value"], 1), "unit": "grid-point-steps/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(res["f32"]["wall_s"] * 1e3 / steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched one-launch-per-pass solve: {len(insts)} independent 2D instances, n from "
+                               f"{sizes}, alpha_l ~ U(1.1,1.9), eps ~ U(0.02,0.2), tau ~ U(1e-3,1e-2), {steps} steps",
+                   "points": pts},
+        "batched_f64": round(res["f64"]["value"], 1),
+        "plain_f64_sequential": round(res["f64_sequential"]["value"], 1),
+        "speedup_f32_batched_vs_plain_f64": round(res["f32"]["value"] / res["f64_sequential"]["value"], 3),
+        "max_abs": max(res["f32"]["max_abs"], res["f64"]["max_abs"]),
+    }
+
+
+def served_run(args):
+    """A bounded sample of the served stream through the continuous-batching server."""
+    import numpy as np
+    from paper_2209_08437_amd import serve, workloads as W
+    reqs = W.served_stream(count=args.serve_count)
+    ex = serve.GpuExecutor()
+    srv = serve.Server(ex, budget_bytes=int(args.serve_budget_gb * 2 ** 30), tick_steps=args.tick_steps)
+    tickets, summ = srv.run(reqs)
+    n3 = sum(1 for r in reqs if r.inst.dims == 3)
+    log(f"[bench] served {summ['completed']}/{len(reqs)} requests in {summ['makespan_s']:.2f} s, "
+        f"p50 {summ['p50_latency_s']:.3f} s p99 {summ['p99_latency_s']:.3f} s")
+    return {
+        "metric": METRIC, "value": round(summ["throughput_gps"], 1), "unit": "grid-point-steps/s", "n_gpus": 1,
+        "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"served solve stream: first {len(reqs)} requests of the seeded Poisson stream "
+                               f"(mean 200 req/s; {n3} 3D n in [31,255], {len(reqs) - n3} 2D n in [63,1023]; "
+                               "steps in [50,2000]; FP64:FP32 1:1)",
+                   "budget_bytes": srv.budget, "tick_steps": srv.tick_steps},
+        "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
+        "offered_gps": summ["offered_gps"], "served_fraction_of_offered": summ["throughput_gps"] / summ["offered_gps"],
+        "summary": {k: v for k, v in summ.items() if k not in ("p50_latency_s", "p99_latency_s")},
+    }
+
+
 def cpu_baseline(inst, seconds):
     """The CPU oracle as it stands, on a bounded sample of the same workload: table set-up
     (dense per-axis exponentials) timed apart, then as many whole steps as fit the budget."""
@@ -121,6 +203,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=20)
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--serve-count", type=int, default=48)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--tick-steps", type=int, default=50)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a buffer of the workload's state size 20 times (a plain copy "
+                         "kernel of known traffic, to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -132,8 +221,24 @@ def main():
         build_lib.build()
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.workload == "batched_2d":
+        print(json.dumps(batched_run(args)), flush=True)
+        return
+    if args.workload == "served":
+        print(json.dumps(served_run(args)), flush=True)
+        return
     inst, desc = workload(args.workload)
     steps = args.steps if args.steps is not None else inst.steps
+    if args.copy_probe:
+        tdt = torch.float64 if args.dtype == "f64" else torch.float32
+        a = torch.tensor(inst.u0, dtype=tdt, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read_per_copy": a.numel() * a.element_size(),
+                          "copy_probe_bytes_written_per_copy": b.numel() * b.element_size(), "copies": 20}))
+        return
     esize = 8 if args.dtype == "f64" else 4
     pts = inst.points
     main_r = gpu_rate(inst, args.dtype, steps, args.warmup, args.pass_reps)

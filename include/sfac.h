@@ -157,9 +157,38 @@ sfac_status sfac_axis_tables(int32_t n, double alpha, double eps, double tau, do
  * The string stays valid until the next library call on the same thread. */
 const char* sfac_last_error(void);
 
+/* ---------------------------------------------------------------- grouped stepping
+ * Several independent plans stepped together: every axis pass of every plan that needs it is
+ * one launch per kernel variant (transform length and arithmetic) and pass, instead of one
+ * launch per plan. Used for batched solves and by the solve server's continuous batching. */
+typedef struct sfac_group_s* sfac_group;
+
+/* sfac_group_create - a launch workspace ordered on hip_stream (NULL = legacy default stream).
+ * Plans stepped through a group should be created on the same stream, so that
+ * sfac_plan_flags (which synchronizes the plan's stream) sees the group's work. */
+sfac_status sfac_group_create(sfac_group* out, void* hip_stream);
+
+/*
+ * sfac_group_step - advance plans[i]'s state u_dev[i] by nsteps[i] >= 0 steps, i < count. A plan
+ * may appear once. Plans of both arithmetics may be mixed. Each state ends bitwise equal to
+ * stepping its plan alone with sfac_step: the same kernels run on it in the same order (no
+ * step is fused across plans or steps). Waits for the group's previous call to finish (its
+ * launch descriptors are rewritten), then queues the work asynchronously on the group's stream.
+ * Errors: SFAC_EINVAL (NULL arguments, a repeated plan, negative steps, misaligned state),
+ * SFAC_ENOMEM, SFAC_EDEVICE.
+ */
+sfac_status sfac_group_step(sfac_group g, int32_t count, const sfac_plan* plans, void* const* u_dev,
+                            const int64_t* nsteps);
+
+/* sfac_group_destroy - waits for the group's work and frees it; NULL is accepted. */
+sfac_status sfac_group_destroy(sfac_group g);
+
+/* sfac_group_device_bytes - device memory of the group's launch workspace. */
+size_t sfac_group_device_bytes(sfac_group g);
+
 /* ---------------------------------------------------------------- batched form
- * Many independent instances (each its own dims, N, alpha, eps, tau, h) stepped together:
- * every axis pass of every instance in the batch is one launch over all instances' lines. */
+ * A fixed set of independent instances (each its own dims, N, alpha, eps, tau, h) with one
+ * plan each and a group to step them together. */
 typedef struct {
     int32_t dims;       /* 1, 2 or 3 */
     int32_t n[3];       /* N_l, axis 1 first; unused entries ignored */
@@ -181,11 +210,16 @@ sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instanc
  * sfac_batch_step - advance instance i by nsteps[i] steps (>= 0) in place; u_dev[i] is its
  * state as for sfac_step. Instances with fewer steps drop out of the launches once done.
  * An instance's result is bitwise the same as stepping it alone with sfac_step.
- * Asynchronous on the batch's stream. Errors: SFAC_EINVAL, SFAC_EDEVICE.
+ * Asynchronous on the batch's stream (waits for the batch's previous call first).
+ * Errors: SFAC_EINVAL, SFAC_ENOMEM, SFAC_EDEVICE.
  */
 sfac_status sfac_batch_step(sfac_batch b, void* const* u_dev, const int64_t* nsteps);
 
-/* sfac_batch_destroy - release the batch; NULL is accepted. */
+/* sfac_batch_plan - the plan of instance i (for sfac_plan_flags etc.), NULL if out of range.
+ * It belongs to the batch: do not destroy it. */
+sfac_plan sfac_batch_plan(sfac_batch b, int32_t i);
+
+/* sfac_batch_destroy - release the batch and its plans; NULL is accepted. */
 sfac_status sfac_batch_destroy(sfac_batch b);
 
 /* sfac_batch_device_bytes - device memory the batch holds, excluding the states. */

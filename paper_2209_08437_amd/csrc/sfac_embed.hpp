@@ -1,0 +1,201 @@
+// Register-resident axis pass for the embedded method (power-of-two transform length M).
+//
+// Each complex line (two real lines packed as real and imaginary parts) is held by T = M/E
+// threads, E = min(16, M) elements per thread. A length-M transform is an in-place
+// decimation-in-frequency Cooley-Tukey pass sequence with radices R_0..R_{NST-1} (<= 16); the
+// inverse runs the conjugate-transposed passes in reverse order (decimation in time), so the
+// forward output (digit-reversed positions) is consumed where it lies and the inverse output
+// comes back in natural order in exactly the registers the next forward transform reads: the
+// only data movement between passes is one LDS exchange between consecutive radix passes.
+// Per factor: forward transform, multiply by the kernel spectrum (stored on the host in the
+// same digit-reversed position order), inverse transform, keep the first N entries.
+// The pass twiddles of every thread are the same for all six transforms of a pass, so they
+// are loaded once into registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "sfac_fft.hpp"
+
+namespace sfac {
+
+constexpr int embed_stages(int log2m) { return log2m <= 4 ? 1 : (log2m + 3) / 4; }
+constexpr int embed_bits(int log2m, int s) {
+    return log2m / embed_stages(log2m) + (s < log2m % embed_stages(log2m) ? 1 : 0);
+}
+
+template <int LOG2M>
+struct EmbedGeom {
+    static constexpr int M = 1 << LOG2M;
+    static constexpr int LOG2E = LOG2M < 4 ? LOG2M : 4;
+    static constexpr int E = 1 << LOG2E;
+    static constexpr int LOG2T = LOG2M - LOG2E;
+    static constexpr int T = 1 << LOG2T;
+    static constexpr int NST = embed_stages(LOG2M);
+    static constexpr int bits(int s) { return embed_bits(LOG2M, s); }
+    static constexpr int R(int s) { return 1 << bits(s); }
+    // log2 of the stride S_s between the elements of one radix-R_s butterfly
+    static constexpr int log2S(int s) {
+        int acc = LOG2M;
+        for (int q = 0; q <= s; ++q) acc -= bits(q);
+        return acc;
+    }
+    // log2 of M / B_s, B_s = S_s R_s the span of a stage-s block (= product of earlier radices)
+    static constexpr int log2Pre(int s) {
+        int acc = 0;
+        for (int q = 0; q < s; ++q) acc += bits(q);
+        return acc;
+    }
+};
+
+// Position (in the in-place layout) of element k of butterfly slot i of thread t at stage s.
+template <int LOG2M, int S>
+__device__ __forceinline__ int embed_pos(int t, int i, int k) {
+    using G = EmbedGeom<LOG2M>;
+    constexpr int ls = G::log2S(S);
+    constexpr int lb = ls + G::bits(S);
+    const int b = t + (i << G::LOG2T);
+    const int blk = b >> ls;
+    const int o = b & ((1 << ls) - 1);
+    return (blk << lb) + o + (k << ls);
+}
+
+// Bank-conflict-avoiding permutation of positions inside one line: XOR the low bits of the
+// position with bits of its higher digits. The bit choice was measured on gfx950 with the
+// conflict counter over this kernel's exchange patterns (16-byte elements: bits 3 and 8 into the
+// low 4 bits; 8-byte elements: bits 3 and 7 into the low 5 bits). The XOR stays inside an
+// aligned group of at most M positions, so the permutation maps [0, M) onto itself.
+template <typename T, int LOG2M>
+__device__ __forceinline__ int embed_swz(int p) {
+    constexpr bool wide = sizeof(cplx<T>) == 16;
+    constexpr int A = 3, B = wide ? 8 : 7, W = wide ? 4 : 5;
+    constexpr int bitsw = W < LOG2M ? W : LOG2M;
+    constexpr int mask = (1 << bitsw) - 1;
+    return p ^ (((p >> A) ^ (p >> B)) & mask);
+}
+
+// Twiddle of element k of slot i at stage s: W_M^{o k M / B_s}.
+template <int LOG2M, int S>
+__device__ __forceinline__ int embed_tw_index(int t, int i, int k) {
+    using G = EmbedGeom<LOG2M>;
+    constexpr int ls = G::log2S(S);
+    const int b = t + (i << G::LOG2T);
+    const int o = b & ((1 << ls) - 1);
+    return (o * k) << G::log2Pre(S);
+}
+
+template <typename T, int LOG2M>
+struct EmbedLine {
+    using G = EmbedGeom<LOG2M>;
+    static constexpr int NTW = G::NST > 1 ? G::NST - 1 : 1;
+    cplx<T> a[G::E];
+    cplx<T> tw[NTW][G::E];
+
+    __device__ __forceinline__ void load_twiddles(const cplx<T>* __restrict__ table, int t) {
+        load_tw_stages(table, t, std::make_integer_sequence<int, G::NST - 1>{});
+    }
+    template <int... S>
+    __device__ __forceinline__ void load_tw_stages(const cplx<T>* __restrict__ table, int t,
+                                                   std::integer_sequence<int, S...>) {
+        (load_tw_stage<S>(table, t), ...);
+    }
+    template <int S>
+    __device__ __forceinline__ void load_tw_stage(const cplx<T>* __restrict__ table, int t) {
+        constexpr int R = G::R(S);
+#pragma unroll
+        for (int i = 0; i < G::E / R; ++i) {
+#pragma unroll
+            for (int k = 1; k < R; ++k) tw[S][i * R + k] = table[embed_tw_index<LOG2M, S>(t, i, k)];
+        }
+    }
+
+    // forward radix pass S: DFT of every butterfly, then the pass twiddles (not after the last)
+    template <int S>
+    __device__ __forceinline__ void fwd_stage() {
+        constexpr int R = G::R(S);
+#pragma unroll
+        for (int i = 0; i < G::E / R; ++i) {
+            dft<R, -1>(&a[i * R]);
+            if constexpr (S < G::NST - 1) {
+#pragma unroll
+                for (int k = 1; k < R; ++k) a[i * R + k] = cmul(a[i * R + k], tw[S][i * R + k]);
+            }
+        }
+    }
+    // inverse radix pass S: conjugate twiddles, then the inverse DFT
+    template <int S>
+    __device__ __forceinline__ void inv_stage() {
+        constexpr int R = G::R(S);
+#pragma unroll
+        for (int i = 0; i < G::E / R; ++i) {
+            if constexpr (S < G::NST - 1) {
+#pragma unroll
+                for (int k = 1; k < R; ++k) a[i * R + k] = cmulc(a[i * R + k], tw[S][i * R + k]);
+            }
+            dft<R, +1>(&a[i * R]);
+        }
+    }
+
+    // move the line's elements from the layout of pass SA to the layout of pass SB through LDS
+    template <int SA, int SB>
+    __device__ __forceinline__ void exchange(cplx<T>* __restrict__ line, int t) {
+        constexpr int RA = G::R(SA), RB = G::R(SB);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < G::E / RA; ++i)
+#pragma unroll
+            for (int k = 0; k < RA; ++k) line[embed_swz<T, LOG2M>(embed_pos<LOG2M, SA>(t, i, k))] = a[i * RA + k];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < G::E / RB; ++i)
+#pragma unroll
+            for (int k = 0; k < RB; ++k) a[i * RB + k] = line[embed_swz<T, LOG2M>(embed_pos<LOG2M, SB>(t, i, k))];
+    }
+
+    template <int S>
+    __device__ __forceinline__ void fwd_from(cplx<T>* line, int t) {
+        if constexpr (S > 0) exchange<S - 1, S>(line, t);
+        fwd_stage<S>();
+        if constexpr (S + 1 < G::NST) fwd_from<S + 1>(line, t);
+    }
+    template <int S>
+    __device__ __forceinline__ void inv_from(cplx<T>* line, int t) {
+        if constexpr (S < G::NST - 1) exchange<S + 1, S>(line, t);
+        inv_stage<S>();
+        if constexpr (S > 0) inv_from<S - 1>(line, t);
+    }
+
+    // multiply by the kernel spectrum, stored in last-pass position order
+    __device__ __forceinline__ void scale(const T* __restrict__ g, int t) {
+        constexpr int S = G::NST - 1;
+        constexpr int R = G::R(S);
+#pragma unroll
+        for (int i = 0; i < G::E / R; ++i)
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const T s = g[embed_pos<LOG2M, S>(t, i, k)];
+                a[i * R + k].x *= s;
+                a[i * R + k].y *= s;
+            }
+    }
+
+    // natural position of register (i, k) at pass 0
+    static __device__ __forceinline__ int nat(int t, int i, int k) { return embed_pos<LOG2M, 0>(t, i, k); }
+
+    // one exponential factor: forward transform, spectrum, inverse transform, truncation
+    __device__ __forceinline__ void factor(const T* __restrict__ g, cplx<T>* line, int t, int n) {
+        fwd_from<0>(line, t);
+        scale(g, t);
+        inv_from<G::NST - 1>(line, t);
+        constexpr int R0 = G::R(0);
+#pragma unroll
+        for (int i = 0; i < G::E / R0; ++i)
+#pragma unroll
+            for (int k = 0; k < R0; ++k)
+                if (nat(t, i, k) >= n) a[i * R0 + k] = {(T)0, (T)0};
+    }
+};
+
+}  // namespace sfac

@@ -12,8 +12,10 @@
 
 namespace sfac {
 
+// Aligned to its size so that LDS and global accesses of one element are single 16-byte
+// (double) or 8-byte (float) operations.
 template <typename T>
-struct cplx {
+struct alignas(2 * sizeof(T)) cplx {
     T x, y;
 };
 

@@ -29,7 +29,14 @@ struct AxisTables {
     std::vector<double> scale_c, scale_s;
     // diag only: psi_k = e^{-i pi k / N}
     std::vector<double> psi_re, psi_im;
+    // embed only: scale_c / scale_s permuted to the digit-reversed positions of the
+    // register-resident transform (position p holds frequency embed_frequency(p))
+    std::vector<double> gpos_c, gpos_s;
 };
+
+// Frequency index held at in-place position p after all decimation-in-frequency passes of the
+// register-resident power-of-two transform of length 2^log2m.
+int embed_frequency(int p, int log2m);
 
 // Per-axis parameters of the method.
 struct AxisParams {

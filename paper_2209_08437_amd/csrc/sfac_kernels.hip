@@ -10,6 +10,7 @@
 
 #include <cstdint>
 
+#include "sfac_embed.hpp"
 #include "sfac_fft.hpp"
 #include "sfac_kernels.hpp"
 
@@ -17,12 +18,14 @@ namespace sfac {
 
 namespace {
 
-// J^Q_{tau/2} v = v / sqrt(v^2 + (1 - v^2) e^{-tau}), with 1 - v^2 formed as (1 - v)(1 + v)
+// J^Q_{tau/2} v = v / sqrt(v^2 + (1 - v^2) e^{-tau}), with 1 - v^2 formed as (1 - v)(1 + v).
+// e^{-tau} is carried as hi + lo in the state's type (lo = 0 for FP64): in FP32 the rounding of
+// e^{-tau} would otherwise bias every half-step the same way.
 template <typename T>
-__device__ __forceinline__ T nonlinear_half_step(T v, T decay) {
+__device__ __forceinline__ T nonlinear_half_step(T v, T decay, T decay_lo) {
     const T one = (T)1;
     const T q = (one - v) * (one + v);
-    return v / sqrt(v * v + q * decay);
+    return v / sqrt(v * v + (q * decay + q * decay_lo));
 }
 
 template <int DIR, typename T>
@@ -64,6 +67,20 @@ __device__ cplx<T>* transform(const PassDesc<T>& d, cplx<T>* cur, cplx<T>* other
     return cur;
 }
 
+// Wave-level reduction of the store statistics, then one atomic per wave.
+__device__ __forceinline__ void publish_stats(double vmax, unsigned int bad, unsigned long long* smax,
+                                              unsigned int* sflags) {
+    for (int off = 32; off > 0; off >>= 1) {
+        vmax = fmax(vmax, __shfl_xor(vmax, off));
+        bad |= __shfl_xor(bad, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (vmax > 1.0) bad |= SFAC_FLAG_ABOVE_ONE;
+        if (bad) atomicOr(sflags, bad);
+        atomicMax(smax, (unsigned long long)__double_as_longlong(vmax));
+    }
+}
+
 template <typename T>
 __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>* buf1) {
     const int N = d.N, L = d.L, lpb = d.lpb;
@@ -90,7 +107,7 @@ __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>*
     const int nreal = (int)(avail < 2 * lpb ? avail : 2 * lpb);
     const int lines = (nreal + 1) >> 1;
     const bool nl_in = d.nl_in != 0;
-    const T decay = d.decay;
+    const T decay = d.decay, decay_lo = d.decay_lo;
 
     // load (with zero padding to the transform length and a zero partner for an odd line)
     const int total = lines * L;
@@ -109,8 +126,8 @@ __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>*
             z.x = p[0];
             if (2 * b + 1 < nreal) z.y = p[lstride];
             if (nl_in) {
-                z.x = nonlinear_half_step(z.x, decay);
-                z.y = nonlinear_half_step(z.y, decay);
+                z.x = nonlinear_half_step(z.x, decay, decay_lo);
+                z.y = nonlinear_half_step(z.y, decay, decay_lo);
             }
         }
         buf0[b * L + k] = z;
@@ -172,8 +189,8 @@ __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>*
         }
         cplx<T> z = cur[b * L + k];
         if (nl_out) {
-            z.x = nonlinear_half_step(z.x, decay);
-            z.y = nonlinear_half_step(z.y, decay);
+            z.x = nonlinear_half_step(z.x, decay, decay_lo);
+            z.y = nonlinear_half_step(z.y, decay, decay_lo);
         }
         T* p = base + (long long)(2 * b) * lstride + (long long)k * kstride;
         p[0] = z.x;
@@ -187,18 +204,99 @@ __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>*
                 vmax = fmax(vmax, fmax(ax, ay));
         }
     }
-    if (nl_out) {
-        // wave reduction, then one atomic per wave
-        for (int off = 32; off > 0; off >>= 1) {
-            vmax = fmax(vmax, __shfl_xor(vmax, off));
-            bad |= __shfl_xor(bad, off);
+    if (nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
+}
+
+// Lines of one tile: a tile is 2*lpb real lines (rows of the contiguous axis, or adjacent
+// columns of a strided one) packed pairwise into lpb complex lines.
+template <typename T>
+struct TileGeom {
+    T* base;             // element 0 of the tile's first real line
+    long long lstride;   // distance between adjacent real lines
+    long long kstride;   // distance between adjacent elements of a line
+    int nreal;           // real lines in this tile (<= 2 lpb)
+    __device__ TileGeom(const PassDesc<T>& d, int tile) {
+        long long first, avail;
+        if (d.inner == 1) {
+            first = (long long)tile * 2 * d.lpb;
+            avail = d.outer - first;
+            base = d.u + first * d.N;
+            lstride = d.N;
+            kstride = 1;
+        } else {
+            const long long o = tile / d.tiles_per_outer;
+            first = (long long)(tile % d.tiles_per_outer) * 2 * d.lpb;
+            avail = d.inner - first;
+            base = d.u + o * (long long)d.N * d.inner + first;
+            lstride = 1;
+            kstride = d.inner;
         }
-        if ((threadIdx.x & 63) == 0) {
-            if (vmax > 1.0) bad |= SFAC_FLAG_ABOVE_ONE;
-            if (bad) atomicOr(d.stat_flags, bad);
-            atomicMax(d.stat_max, (unsigned long long)__double_as_longlong(vmax));
-        }
+        nreal = (int)(avail < 2 * d.lpb ? avail : 2 * d.lpb);
     }
+};
+
+// Embedded method, register-resident transforms of length 2^LOG2M.
+template <typename T, int LOG2M>
+__device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
+    using G = EmbedGeom<LOG2M>;
+    using Line = EmbedLine<T, LOG2M>;
+    const int line = threadIdx.x >> G::LOG2T;
+    const int t = threadIdx.x & (G::T - 1);
+    const TileGeom<T> tg(d, tile);
+    const int N = d.N;
+    const bool act = 2 * line < tg.nreal;
+    const bool two = 2 * line + 1 < tg.nreal;
+    const T decay = d.decay, decay_lo = d.decay_lo;
+    Line L;
+    L.load_twiddles(d.tw, t);
+    const T* src = tg.base + (long long)(2 * line) * tg.lstride;
+    constexpr int R0 = G::R(0);
+#pragma unroll
+    for (int i = 0; i < G::E / R0; ++i)
+#pragma unroll
+        for (int k = 0; k < R0; ++k) {
+            const int n = Line::nat(t, i, k);
+            cplx<T> z = {(T)0, (T)0};
+            if (act && n < N) {
+                const T* p = src + (long long)n * tg.kstride;
+                z.x = p[0];
+                if (two) z.y = p[tg.lstride];
+                if (d.nl_in) {
+                    z.x = nonlinear_half_step(z.x, decay, decay_lo);
+                    z.y = nonlinear_half_step(z.y, decay, decay_lo);
+                }
+            }
+            L.a[i * R0 + k] = z;
+        }
+    cplx<T>* ln = lds + line * G::M;
+    L.factor(d.gpos_c, ln, t, N);
+    L.factor(d.gpos_s, ln, t, N);
+    L.factor(d.gpos_c, ln, t, N);
+    T* dst = tg.base + (long long)(2 * line) * tg.lstride;
+    double vmax = 0.0;
+    unsigned int bad = 0;
+#pragma unroll
+    for (int i = 0; i < G::E / R0; ++i)
+#pragma unroll
+        for (int k = 0; k < R0; ++k) {
+            const int n = Line::nat(t, i, k);
+            if (act && n < N) {
+                cplx<T> z = L.a[i * R0 + k];
+                if (d.nl_out) {
+                    z.x = nonlinear_half_step(z.x, decay, decay_lo);
+                    z.y = nonlinear_half_step(z.y, decay, decay_lo);
+                    const double ax = fabs((double)z.x), ay = two ? fabs((double)z.y) : 0.0;
+                    if (!(ax <= 1.7976931348623157e308) || !(ay <= 1.7976931348623157e308))
+                        bad |= SFAC_FLAG_NONFINITE;
+                    else
+                        vmax = fmax(vmax, fmax(ax, ay));
+                }
+                T* p = dst + (long long)n * tg.kstride;
+                p[0] = z.x;
+                if (two) p[tg.lstride] = z.y;
+            }
+        }
+    if (d.nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
 }
 
 // blockIdx -> tile, grouping neighbouring tiles on one XCD (blocks are dealt round-robin to
@@ -216,6 +314,82 @@ __global__ void __launch_bounds__(kBlockThreads) axis_pass_single(PassDesc<T> d)
     const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
     if (tile >= d.ntiles) return;
     run_tile(d, tile, buf0, buf1);
+}
+
+template <typename T, int LOG2M>
+__global__ void __launch_bounds__(kBlockThreads) embed_pass_single(PassDesc<T> d) {
+    extern __shared__ unsigned char smem_raw[];
+    const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
+    if (tile >= d.ntiles) return;
+    run_embed_tile<T, LOG2M>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+}
+
+// Several instances with the same transform length in one launch (batched form).
+template <typename T, int LOG2M>
+__global__ void __launch_bounds__(kBlockThreads) embed_pass_multi(const PassDesc<T>* __restrict__ descs,
+                                                                  const int* __restrict__ block_start,
+                                                                  int ndesc) {
+    extern __shared__ unsigned char smem_raw[];
+    int lo = 0, hi = ndesc;
+    const int b = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (block_start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const PassDesc<T> d = descs[lo];
+    const int local = b - block_start[lo];
+    const int tile = d.xcd_remap ? xcd_tile(local, d.ntiles) : local;
+    if (tile >= d.ntiles) return;
+    // the block has the group's largest size; threads beyond d.lpb lines hold no line (their
+    // LDS rows lie inside the block's allocation) and only take part in the barriers
+    run_embed_tile<T, LOG2M>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+}
+
+template <typename T, int LOG2M>
+struct EmbedKernels {
+    static const void* single() { return reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M>); }
+    static const void* multi() { return reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M>); }
+};
+
+template <typename T>
+const void* embed_single_fn(int log2m) {
+    switch (log2m) {
+        case 1: return EmbedKernels<T, 1>::single();
+        case 2: return EmbedKernels<T, 2>::single();
+        case 3: return EmbedKernels<T, 3>::single();
+        case 4: return EmbedKernels<T, 4>::single();
+        case 5: return EmbedKernels<T, 5>::single();
+        case 6: return EmbedKernels<T, 6>::single();
+        case 7: return EmbedKernels<T, 7>::single();
+        case 8: return EmbedKernels<T, 8>::single();
+        case 9: return EmbedKernels<T, 9>::single();
+        case 10: return EmbedKernels<T, 10>::single();
+        case 11: return EmbedKernels<T, 11>::single();
+        case 12: return EmbedKernels<T, 12>::single();
+        default: return nullptr;
+    }
+}
+
+template <typename T>
+const void* embed_multi_fn(int log2m) {
+    switch (log2m) {
+        case 1: return EmbedKernels<T, 1>::multi();
+        case 2: return EmbedKernels<T, 2>::multi();
+        case 3: return EmbedKernels<T, 3>::multi();
+        case 4: return EmbedKernels<T, 4>::multi();
+        case 5: return EmbedKernels<T, 5>::multi();
+        case 6: return EmbedKernels<T, 6>::multi();
+        case 7: return EmbedKernels<T, 7>::multi();
+        case 8: return EmbedKernels<T, 8>::multi();
+        case 9: return EmbedKernels<T, 9>::multi();
+        case 10: return EmbedKernels<T, 10>::multi();
+        case 11: return EmbedKernels<T, 11>::multi();
+        case 12: return EmbedKernels<T, 12>::multi();
+        default: return nullptr;
+    }
 }
 
 template <typename T>
@@ -253,14 +427,27 @@ template <typename T>
 hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream) {
     const int blocks = pass_blocks(d);
     if (blocks <= 0) return hipSuccess;
+    if (d.method == 2) {
+        const void* fn = embed_single_fn<T>(d.log2m);
+        if (!fn) return hipErrorInvalidValue;
+        void* args[] = {const_cast<PassDesc<T>*>(&d)};
+        return hipLaunchKernel(fn, dim3(blocks), dim3(d.threads), args, lds_bytes, stream);
+    }
     hipLaunchKernelGGL(axis_pass_single<T>, dim3(blocks), dim3(kBlockThreads), lds_bytes, stream, d);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_axis_pass_multi(const PassDesc<T>* descs_dev, const int* block_start_dev, int ndesc,
-                                  int total_blocks, size_t lds_bytes, hipStream_t stream) {
+hipError_t launch_axis_pass_multi(int method, int log2m, int threads, const PassDesc<T>* descs_dev,
+                                  const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
+                                  hipStream_t stream) {
     if (total_blocks <= 0) return hipSuccess;
+    if (method == 2) {
+        const void* fn = embed_multi_fn<T>(log2m);
+        if (!fn) return hipErrorInvalidValue;
+        void* args[] = {&descs_dev, &block_start_dev, &ndesc};
+        return hipLaunchKernel(fn, dim3(total_blocks), dim3(threads), args, lds_bytes, stream);
+    }
     hipLaunchKernelGGL(axis_pass_multi<T>, dim3(total_blocks), dim3(kBlockThreads), lds_bytes, stream,
                        descs_dev, block_start_dev, ndesc);
     return hipGetLastError();
@@ -271,6 +458,12 @@ hipError_t allow_lds(size_t lds_bytes) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_single<T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
+    for (int lg = 1; lg <= 12; ++lg) {
+        e = hipFuncSetAttribute(embed_single_fn<T>(lg), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute(embed_multi_fn<T>(lg), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_multi<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
@@ -279,10 +472,10 @@ template int pass_blocks<double>(const PassDesc<double>&);
 template int pass_blocks<float>(const PassDesc<float>&);
 template hipError_t launch_axis_pass<double>(const PassDesc<double>&, size_t, hipStream_t);
 template hipError_t launch_axis_pass<float>(const PassDesc<float>&, size_t, hipStream_t);
-template hipError_t launch_axis_pass_multi<double>(const PassDesc<double>*, const int*, int, int, size_t,
-                                                   hipStream_t);
-template hipError_t launch_axis_pass_multi<float>(const PassDesc<float>*, const int*, int, int, size_t,
-                                                  hipStream_t);
+template hipError_t launch_axis_pass_multi<double>(int, int, int, const PassDesc<double>*, const int*, int, int,
+                                                   size_t, hipStream_t);
+template hipError_t launch_axis_pass_multi<float>(int, int, int, const PassDesc<float>*, const int*, int, int,
+                                                  size_t, hipStream_t);
 template hipError_t allow_lds<double>(size_t);
 template hipError_t allow_lds<float>(size_t);
 

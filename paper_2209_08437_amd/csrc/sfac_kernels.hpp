@@ -22,6 +22,8 @@ struct PassDesc {
     const T* scale_c;                // diag: e^{tau/2 lambda}/N; embed: kernel spectrum / M
     const T* scale_s;                // diag: e^{tau mu}/N;       embed: kernel spectrum / M
     const cplx<T>* psi;              // diag: e^{-i pi k / N}, k < N
+    const T* gpos_c;                 // embed: kernel spectra / M in digit-reversed position order
+    const T* gpos_s;
     unsigned long long* stat_max;    // bits of the largest |u| stored (non-negative double)
     unsigned int* stat_flags;        // SFAC_FLAG_* bits
     long long inner, outer;
@@ -35,7 +37,9 @@ struct PassDesc {
     int ntiles;                      // tiles in this pass
     int nl_in, nl_out;               // apply J^Q_{tau/2} on load / on store (+ statistics)
     int xcd_remap;                   // group neighbouring tiles per XCD
-    T decay;                         // e^{-tau}
+    int log2m;                       // embed: log2 of the transform length
+    int threads;                     // launch block size
+    T decay, decay_lo;               // e^{-tau} = decay + decay_lo (decay_lo = 0 in FP64)
 };
 
 template <typename T>
@@ -44,9 +48,12 @@ int pass_blocks(const PassDesc<T>& d);
 template <typename T>
 hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream);
 
+// One launch over several instances' tiles of one pass. method 2 (embedded) launches need
+// every descriptor to share log2m; `threads` is the block size (the largest of the group).
 template <typename T>
-hipError_t launch_axis_pass_multi(const PassDesc<T>* descs_dev, const int* block_start_dev, int ndesc,
-                                  int total_blocks, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_axis_pass_multi(int method, int log2m, int threads, const PassDesc<T>* descs_dev,
+                                  const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
+                                  hipStream_t stream);
 
 // Raise the dynamic-LDS limit of the pass kernels to lds_bytes (needed above 64 KiB).
 template <typename T>

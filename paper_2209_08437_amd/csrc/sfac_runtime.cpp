@@ -11,8 +11,10 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
+#include "sfac_embed.hpp"
 #include "sfac_internal.hpp"
 #include "sfac_kernels.hpp"
 
@@ -42,8 +44,9 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Device copy of one axis' tables in the plan's arithmetic type.
 struct AxisDevice {
     sfac::AxisTables host;
-    size_t off_tw = 0, off_sc = 0, off_ss = 0, off_psi = 0;
+    size_t off_tw = 0, off_sc = 0, off_ss = 0, off_psi = 0, off_gc = 0, off_gs = 0;
     int lpb = 1;
+    int threads = 256;
     size_t lds = 0;
 };
 
@@ -58,6 +61,10 @@ size_t axis_table_bytes(const sfac::AxisTables& t, size_t base, AxisDevice* ad) 
     off = align_up(off + sizeof(T) * t.scale_s.size(), 256);
     ad->off_psi = off;
     off = align_up(off + sizeof(sfac::cplx<T>) * t.psi_re.size(), 256);
+    ad->off_gc = off;
+    off = align_up(off + sizeof(T) * t.gpos_c.size(), 256);
+    ad->off_gs = off;
+    off = align_up(off + sizeof(T) * t.gpos_s.size(), 256);
     return off;
 }
 
@@ -71,6 +78,10 @@ void axis_table_fill(const sfac::AxisTables& t, const AxisDevice& ad, unsigned c
     for (size_t m = 0; m < t.scale_s.size(); ++m) ss[m] = (T)t.scale_s[m];
     auto* ps = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_psi);
     for (size_t m = 0; m < t.psi_re.size(); ++m) ps[m] = {(T)t.psi_re[m], (T)t.psi_im[m]};
+    auto* gc = reinterpret_cast<T*>(host + ad.off_gc);
+    for (size_t m = 0; m < t.gpos_c.size(); ++m) gc[m] = (T)t.gpos_c[m];
+    auto* gs = reinterpret_cast<T*>(host + ad.off_gs);
+    for (size_t m = 0; m < t.gpos_s.size(); ++m) gs[m] = (T)t.gpos_s[m];
 }
 
 // One instance's geometry and tables: the part a plan and a batch entry share.
@@ -139,18 +150,35 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
         }
         off = dt == SFAC_FP64 ? axis_table_bytes<double>(in->ax[a].host, off, &in->ax[a])
                               : axis_table_bytes<float>(in->ax[a].host, off, &in->ax[a]);
-        // lines per block: as many as fit the LDS budget (two buffers), at most the lines there are
         const int L = in->ax[a].host.length;
-        const size_t per_line = 2 * elem * (size_t)L;
         long long inner = 1, outer = 1;
         for (int b = 0; b < a; ++b) inner *= n[b];
         for (int b = a + 1; b < dims; ++b) outer *= n[b];
         const long long avail = (inner == 1 ? outer : inner);
-        int lpb = (int)std::max<size_t>(1, kLdsBudget / per_line);
-        lpb = (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2));
-        lpb = std::min(lpb, 64);
-        in->ax[a].lpb = lpb;
-        in->ax[a].lds = per_line * lpb;
+        const long long lines_total = outer * inner / avail * ((avail + 1) / 2);
+        if (m == SFAC_METHOD_EMBED) {
+            // register-resident kernel: T = M/E threads per line, up to 256 threads per block;
+            // fewer lines per block while that still leaves blocks for every CU
+            int log2m = 0;
+            while ((1 << log2m) < L) ++log2m;
+            const int E = log2m < 4 ? (1 << log2m) : 16;
+            const int T = L / E;
+            int lpb = sfac::kBlockThreads / T;
+            while (lpb > 1 && (lines_total + lpb - 1) / lpb < 1024) lpb >>= 1;
+            lpb = (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2));
+            in->ax[a].lpb = lpb;
+            in->ax[a].threads = lpb * T;
+            in->ax[a].lds = elem * (size_t)L * lpb;
+        } else {
+            // generic kernel: two LDS buffers per line, as many lines as fit the budget
+            const size_t per_line = 2 * elem * (size_t)L;
+            int lpb = (int)std::max<size_t>(1, kLdsBudget / per_line);
+            lpb = (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2));
+            lpb = std::min(lpb, 64);
+            in->ax[a].lpb = lpb;
+            in->ax[a].threads = sfac::kBlockThreads;
+            in->ax[a].lds = per_line * lpb;
+        }
         if (in->ax[a].lds > kLdsMax)
             return fail(SFAC_EUNSUPPORTED, "%saxis %d: transform length %d needs %zu bytes of LDS", who, a + 1, L,
                         in->ax[a].lds);
@@ -171,6 +199,11 @@ sfac::PassDesc<T> make_desc(const Instance& in, int a, unsigned char* dev_tables
     d.scale_c = reinterpret_cast<const T*>(dev_tables + ad.off_sc);
     d.scale_s = reinterpret_cast<const T*>(dev_tables + ad.off_ss);
     d.psi = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_psi);
+    d.gpos_c = reinterpret_cast<const T*>(dev_tables + ad.off_gc);
+    d.gpos_s = reinterpret_cast<const T*>(dev_tables + ad.off_gs);
+    d.threads = ad.threads;
+    d.log2m = 0;
+    while ((1 << d.log2m) < t.length) ++d.log2m;
     d.stat_max = stat_max;
     d.stat_flags = stat_flags;
     long long inner = 1, outer = 1;
@@ -194,7 +227,9 @@ sfac::PassDesc<T> make_desc(const Instance& in, int a, unsigned char* dev_tables
     d.nl_in = a == 0;
     d.nl_out = a == in.dims - 1;
     d.xcd_remap = inner > 1 ? 1 : 0;
-    d.decay = (T)std::exp(-in.tau);
+    const double decay = std::exp(-in.tau);
+    d.decay = (T)decay;
+    d.decay_lo = (T)(decay - (double)d.decay);
     return d;
 }
 
@@ -485,105 +520,159 @@ sfac_status sfac_axis_tables(int32_t n, double alpha, double eps, double tau, do
 
 }  // extern "C"
 
-// ===================================================================== batches
-struct sfac_batch_s {
-    std::vector<Instance> inst;
-    sfac_dtype dt = SFAC_FP64;
+// ===================================================================== groups
+// A group is a reusable launch workspace: sfac_group_step advances any set of plans together,
+// with one launch per (pass, arithmetic, kernel variant) covering every plan that needs it.
+struct sfac_group_s {
     hipStream_t stream = nullptr;
-    unsigned char* dev = nullptr;           // tables of every instance + status words
-    size_t dev_bytes = 0;
-    std::vector<size_t> table_off;          // per instance offset of its tables
-    size_t off_stat = 0;                    // per instance 16 bytes
-    size_t lds_max = 0;
-    // launch arena (descriptors and block offsets), rewritten by each batch_step call
-    unsigned char* arena = nullptr;
+    unsigned char* arena = nullptr;        // descriptors and block offsets of the current call
     size_t arena_bytes = 0;
-    std::vector<unsigned char> arena_host;
+    std::vector<unsigned char> host;
 };
 
 namespace {
 
+struct GroupLaunch {
+    size_t off_desc, off_start;
+    int ndesc, blocks;
+    int64_t reps;
+    int phase;
+    int fp64, method, log2m, threads;
+    size_t lds;
+};
+
+// Appends the launches of the plans of one arithmetic type. Phases are the maximal step ranges
+// with a fixed set of active plans; inside a phase every step issues pass 0, 1, 2 in order, so
+// each plan sees exactly the launch sequence sfac_step would give it.
 template <typename T>
-sfac_status batch_run(sfac_batch b, void* const* u_dev, const int64_t* nsteps) {
-    const int count = (int)b->inst.size();
-    // phases: maximal step ranges with a fixed set of active instances
-    std::vector<int64_t> bounds;
-    for (int i = 0; i < count; ++i)
-        if (nsteps[i] > 0) bounds.push_back(nsteps[i]);
-    std::sort(bounds.begin(), bounds.end());
-    bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
-    if (bounds.empty()) return SFAC_OK;
-    const size_t desc_sz = sizeof(sfac::PassDesc<T>);
-    struct Launch {
-        size_t off_desc, off_start;
-        int ndesc, blocks;
-        int64_t reps;
-        int phase;
-    };
-    std::vector<Launch> plan;
-    std::vector<unsigned char>& host = b->arena_host;
-    host.clear();
+void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
+                const std::vector<int64_t>& bounds, const std::vector<sfac_plan>& plans,
+                const std::vector<void*>& us, const std::vector<int64_t>& steps) {
     auto push = [&](const void* p, size_t n) {
-        size_t off = align_up(host.size(), 256);
-        host.resize(off + n);
-        memcpy(host.data() + off, p, n);
+        size_t off = align_up(host->size(), 256);
+        host->resize(off + n);
+        memcpy(host->data() + off, p, n);
         return off;
     };
     int64_t done = 0;
-    int phase = 0;
-    for (int64_t bound : bounds) {
-        const int64_t reps = bound - done;
+    for (size_t ph = 0; ph < bounds.size(); ++ph) {
+        const int64_t bound = bounds[ph];
         for (int pass = 0; pass < 3; ++pass) {
-            std::vector<sfac::PassDesc<T>> ds;
-            std::vector<int> starts(1, 0);
-            for (int i = 0; i < count; ++i) {
-                const Instance& in = b->inst[i];
-                if (nsteps[i] < bound || pass >= in.dims) continue;
-                unsigned long long* sm = reinterpret_cast<unsigned long long*>(b->dev + b->off_stat + 16 * i);
-                unsigned int* sf = reinterpret_cast<unsigned int*>(b->dev + b->off_stat + 16 * i + 8);
-                sfac::PassDesc<T> d = make_desc<T>(in, pass, b->dev + b->table_off[i], static_cast<T*>(u_dev[i]), sm, sf);
-                ds.push_back(d);
-                starts.push_back(starts.back() + sfac::pass_blocks(d));
+            std::vector<std::pair<int, int>> keys;   // (method, log2m)
+            std::vector<std::vector<sfac::PassDesc<T>>> groups;
+            std::vector<size_t> glds;
+            for (size_t i = 0; i < plans.size(); ++i) {
+                sfac_plan p = plans[i];
+                if (steps[i] < bound || pass >= p->in.dims) continue;
+                sfac::PassDesc<T> d = make_desc<T>(p->in, pass, p->dev, static_cast<T*>(us[i]), p->stat_max(),
+                                                   p->stat_flags());
+                const std::pair<int, int> key(d.method, d.method == SFAC_METHOD_EMBED ? d.log2m : 0);
+                size_t g = std::find(keys.begin(), keys.end(), key) - keys.begin();
+                if (g == keys.size()) {
+                    keys.push_back(key);
+                    groups.emplace_back();
+                    glds.push_back(0);
+                }
+                groups[g].push_back(d);
+                glds[g] = std::max(glds[g], p->in.ax[pass].lds);
             }
-            if (ds.empty()) continue;
-            Launch l;
-            l.off_desc = push(ds.data(), ds.size() * desc_sz);
-            l.off_start = push(starts.data(), starts.size() * sizeof(int));
-            l.ndesc = (int)ds.size();
-            l.blocks = starts.back();
-            l.reps = reps;
-            l.phase = phase;
-            plan.push_back(l);
+            for (size_t g = 0; g < groups.size(); ++g) {
+                std::vector<int> starts(1, 0);
+                int threads = sfac::kBlockThreads;
+                if (keys[g].first == SFAC_METHOD_EMBED) {
+                    threads = 0;
+                    for (const auto& d : groups[g]) threads = std::max(threads, d.threads);
+                    const int E = keys[g].second < 4 ? (1 << keys[g].second) : 16;
+                    glds[g] = (size_t)threads * E * sizeof(sfac::cplx<T>);
+                }
+                for (const auto& d : groups[g]) starts.push_back(starts.back() + sfac::pass_blocks(d));
+                GroupLaunch l;
+                l.off_desc = push(groups[g].data(), groups[g].size() * sizeof(sfac::PassDesc<T>));
+                l.off_start = push(starts.data(), starts.size() * sizeof(int));
+                l.ndesc = (int)groups[g].size();
+                l.blocks = starts.back();
+                l.reps = bound - done;
+                l.phase = (int)ph;
+                l.fp64 = std::is_same<T, double>::value;
+                l.method = keys[g].first;
+                l.log2m = keys[g].second;
+                l.threads = threads;
+                l.lds = glds[g];
+                out->push_back(l);
+            }
         }
         done = bound;
-        ++phase;
+    }
+}
+
+template <typename T>
+hipError_t group_launch(sfac_group g, const GroupLaunch& l) {
+    return sfac::launch_axis_pass_multi<T>(l.method, l.log2m, l.threads,
+                                           reinterpret_cast<const sfac::PassDesc<T>*>(g->arena + l.off_desc),
+                                           reinterpret_cast<const int*>(g->arena + l.off_start), l.ndesc,
+                                           l.blocks, l.lds, g->stream);
+}
+
+sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void* const* u_dev,
+                      const int64_t* nsteps) {
+    std::vector<sfac_plan> p64, p32;
+    std::vector<void*> u64, u32;
+    std::vector<int64_t> s64, s32, bounds;
+    size_t lds_need = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        sfac_plan p = plans[i];
+        if (!p) return fail(SFAC_EINVAL, "plan %d is NULL", i);
+        if (nsteps[i] < 0) return fail(SFAC_EINVAL, "plan %d: nsteps = %lld", i, (long long)nsteps[i]);
+        if (nsteps[i] == 0) continue;
+        const size_t es = p->in.dt == SFAC_FP64 ? 8 : 4;
+        if (!u_dev[i]) return fail(SFAC_EINVAL, "plan %d: NULL state pointer", i);
+        if (reinterpret_cast<uintptr_t>(u_dev[i]) % es) return fail(SFAC_EINVAL, "plan %d: misaligned state", i);
+        for (int32_t j = 0; j < i; ++j)
+            if (plans[j] == p && nsteps[j] > 0) return fail(SFAC_EINVAL, "plan %d appears twice", i);
+        (p->in.dt == SFAC_FP64 ? p64 : p32).push_back(p);
+        (p->in.dt == SFAC_FP64 ? u64 : u32).push_back(u_dev[i]);
+        (p->in.dt == SFAC_FP64 ? s64 : s32).push_back(nsteps[i]);
+        bounds.push_back(nsteps[i]);
+        lds_need = std::max(lds_need, p->in.lds_max);
+    }
+    if (bounds.empty()) return SFAC_OK;
+    std::sort(bounds.begin(), bounds.end());
+    bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
+    std::vector<GroupLaunch> plan;
+    g->host.clear();
+    group_plan<double>(&plan, &g->host, bounds, p64, u64, s64);
+    group_plan<float>(&plan, &g->host, bounds, p32, u32, s32);
+    for (const auto& l : plan) lds_need = std::max(lds_need, l.lds);
+    if (lds_need > 64 * 1024) {
+        hipError_t e = sfac::allow_lds<double>(lds_need);
+        if (e == hipSuccess) e = sfac::allow_lds<float>(lds_need);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
     }
     // the arena may still be read by the previous call's launches
-    hipError_t e = hipStreamSynchronize(b->stream);
+    hipError_t e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if (host.size() > b->arena_bytes) {
-        if (b->arena) hipFree(b->arena);
-        b->arena = nullptr;
-        b->arena_bytes = 0;
-        e = hipMalloc(&b->arena, host.size());
-        if (e != hipSuccess) return fail(SFAC_ENOMEM, "hipMalloc(%zu) for the launch arena: %s", host.size(),
-                                         hipGetErrorString(e));
-        b->arena_bytes = host.size();
+    if (g->host.size() > g->arena_bytes) {
+        if (g->arena) hipFree(g->arena);
+        g->arena = nullptr;
+        g->arena_bytes = 0;
+        e = hipMalloc(&g->arena, g->host.size());
+        if (e != hipSuccess)
+            return fail(SFAC_ENOMEM, "hipMalloc(%zu) for the launch arena: %s", g->host.size(), hipGetErrorString(e));
+        g->arena_bytes = g->host.size();
     }
-    e = hipMemcpy(b->arena, host.data(), host.size(), hipMemcpyHostToDevice);
+    e = hipMemcpy(g->arena, g->host.data(), g->host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy launch arena");
-    // launches: phase after phase; inside a phase, step after step, pass after pass
+    // phase after phase; inside a phase, step after step; inside a step, the launches in order
+    std::stable_sort(plan.begin(), plan.end(),
+                     [](const GroupLaunch& a, const GroupLaunch& b) { return a.phase < b.phase; });
     size_t li = 0;
     while (li < plan.size()) {
         size_t lj = li;
         while (lj < plan.size() && plan[lj].phase == plan[li].phase) ++lj;
         for (int64_t r = 0; r < plan[li].reps; ++r) {
             for (size_t k = li; k < lj; ++k) {
-                const Launch& l = plan[k];
-                e = sfac::launch_axis_pass_multi<T>(reinterpret_cast<const sfac::PassDesc<T>*>(b->arena + l.off_desc),
-                                                    reinterpret_cast<const int*>(b->arena + l.off_start), l.ndesc,
-                                                    l.blocks, b->lds_max, b->stream);
-                if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
+                e = plan[k].fp64 ? group_launch<double>(g, plan[k]) : group_launch<float>(g, plan[k]);
+                if (e != hipSuccess) return hip_fail(e, "grouped kernel launch");
             }
         }
         li = lj;
@@ -593,7 +682,44 @@ sfac_status batch_run(sfac_batch b, void* const* u_dev, const int64_t* nsteps) {
 
 }  // namespace
 
+// ===================================================================== batches
+struct sfac_batch_s {
+    std::vector<sfac_plan> plans;
+    sfac_group group = nullptr;
+};
+
 extern "C" {
+
+sfac_status sfac_group_create(sfac_group* out, void* hip_stream) {
+    g_error.clear();
+    if (!out) return fail(SFAC_EINVAL, "NULL output handle");
+    *out = nullptr;
+    sfac_group g = new (std::nothrow) sfac_group_s();
+    if (!g) return fail(SFAC_ENOMEM, "host allocation failed");
+    g->stream = static_cast<hipStream_t>(hip_stream);
+    *out = g;
+    return SFAC_OK;
+}
+
+sfac_status sfac_group_step(sfac_group g, int32_t count, const sfac_plan* plans, void* const* u_dev,
+                            const int64_t* nsteps) {
+    g_error.clear();
+    if (!g) return fail(SFAC_EINVAL, "NULL group");
+    if (count < 0 || (count > 0 && (!plans || !u_dev || !nsteps)))
+        return fail(SFAC_EINVAL, "count = %d with NULL arrays", count);
+    return group_run(g, count, plans, u_dev, nsteps);
+}
+
+sfac_status sfac_group_destroy(sfac_group g) {
+    g_error.clear();
+    if (!g) return SFAC_OK;
+    hipStreamSynchronize(g->stream);
+    if (g->arena) hipFree(g->arena);
+    delete g;
+    return SFAC_OK;
+}
+
+size_t sfac_group_device_bytes(sfac_group g) { return g ? g->arena_bytes : 0; }
 
 sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instance_desc* desc, sfac_dtype dt,
                               void* hip_stream) {
@@ -604,47 +730,23 @@ sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instanc
     if (dt != SFAC_FP64 && dt != SFAC_FP32) return fail(SFAC_EINVAL, "unknown dtype %d", (int)dt);
     std::unique_ptr<sfac_batch_s> b(new (std::nothrow) sfac_batch_s());
     if (!b) return fail(SFAC_ENOMEM, "host allocation failed");
-    b->dt = dt;
-    b->stream = static_cast<hipStream_t>(hip_stream);
-    b->inst.resize(count);
-    size_t off = 0;
-    for (int i = 0; i < count; ++i) {
-        char who[64];
-        snprintf(who, sizeof who, "instance %d: ", i);
+    sfac_options opt{};
+    opt.use_graph = 0;
+    for (int32_t i = 0; i < count; ++i) {
         const sfac_instance_desc& d = desc[i];
-        sfac_status st = build_instance(&b->inst[i], d.dims, d.n, d.alpha, d.eps, d.tau, d.h, dt, nullptr, who);
-        if (st != SFAC_OK) return st;
-        b->table_off.push_back(off);
-        off = align_up(off + b->inst[i].table_bytes, 256);
-        b->lds_max = std::max(b->lds_max, b->inst[i].lds_max);
-    }
-    b->off_stat = off;
-    b->dev_bytes = off + align_up(16 * (size_t)count, 256);
-    std::vector<unsigned char> host(b->dev_bytes, 0);
-    for (int i = 0; i < count; ++i) {
-        for (int a = 0; a < b->inst[i].dims; ++a) {
-            if (dt == SFAC_FP64)
-                axis_table_fill<double>(b->inst[i].ax[a].host, b->inst[i].ax[a], host.data() + b->table_off[i]);
-            else
-                axis_table_fill<float>(b->inst[i].ax[a].host, b->inst[i].ax[a], host.data() + b->table_off[i]);
+        sfac_plan p = nullptr;
+        sfac_status st = sfac_plan_create(&p, d.dims, d.n, d.alpha, d.eps, d.tau, d.h, dt, hip_stream, &opt);
+        if (st != SFAC_OK) {
+            std::string msg = g_error;
+            for (sfac_plan q : b->plans) sfac_plan_destroy(q);
+            return fail(st, "instance %d: %s", i, msg.c_str());
         }
+        b->plans.push_back(p);
     }
-    hipError_t e = hipMalloc(&b->dev, b->dev_bytes);
-    if (e != hipSuccess) {
-        b->dev = nullptr;
-        return fail(SFAC_ENOMEM, "hipMalloc(%zu): %s", b->dev_bytes, hipGetErrorString(e));
-    }
-    e = hipMemcpy(b->dev, host.data(), b->dev_bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        hipFree(b->dev);
-        return hip_fail(e, "hipMemcpy tables");
-    }
-    if (b->lds_max > 64 * 1024) {
-        e = dt == SFAC_FP64 ? sfac::allow_lds<double>(b->lds_max) : sfac::allow_lds<float>(b->lds_max);
-        if (e != hipSuccess) {
-            hipFree(b->dev);
-            return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
-        }
+    sfac_status st = sfac_group_create(&b->group, hip_stream);
+    if (st != SFAC_OK) {
+        for (sfac_plan q : b->plans) sfac_plan_destroy(q);
+        return st;
     }
     *out = b.release();
     return SFAC_OK;
@@ -654,25 +756,28 @@ sfac_status sfac_batch_step(sfac_batch b, void* const* u_dev, const int64_t* nst
     g_error.clear();
     if (!b) return fail(SFAC_EINVAL, "NULL batch");
     if (!u_dev || !nsteps) return fail(SFAC_EINVAL, "NULL state or step array");
-    const size_t es = b->dt == SFAC_FP64 ? 8 : 4;
-    for (size_t i = 0; i < b->inst.size(); ++i) {
-        if (nsteps[i] < 0) return fail(SFAC_EINVAL, "instance %zu: nsteps = %lld", i, (long long)nsteps[i]);
-        if (nsteps[i] > 0 && !u_dev[i]) return fail(SFAC_EINVAL, "instance %zu: NULL state pointer", i);
-        if (reinterpret_cast<uintptr_t>(u_dev[i]) % es) return fail(SFAC_EINVAL, "instance %zu: misaligned state", i);
-    }
-    return b->dt == SFAC_FP64 ? batch_run<double>(b, u_dev, nsteps) : batch_run<float>(b, u_dev, nsteps);
+    return group_run(b->group, (int32_t)b->plans.size(), b->plans.data(), u_dev, nsteps);
+}
+
+sfac_plan sfac_batch_plan(sfac_batch b, int32_t i) {
+    if (!b || i < 0 || i >= (int32_t)b->plans.size()) return nullptr;
+    return b->plans[i];
 }
 
 sfac_status sfac_batch_destroy(sfac_batch b) {
     g_error.clear();
     if (!b) return SFAC_OK;
-    hipStreamSynchronize(b->stream);
-    if (b->arena) hipFree(b->arena);
-    if (b->dev) hipFree(b->dev);
+    sfac_group_destroy(b->group);
+    for (sfac_plan p : b->plans) sfac_plan_destroy(p);
     delete b;
     return SFAC_OK;
 }
 
-size_t sfac_batch_device_bytes(sfac_batch b) { return b ? b->dev_bytes + b->arena_bytes : 0; }
+size_t sfac_batch_device_bytes(sfac_batch b) {
+    if (!b) return 0;
+    size_t s = sfac_group_device_bytes(b->group);
+    for (sfac_plan p : b->plans) s += sfac_plan_device_bytes(p);
+    return s;
+}
 
 }  // extern "C"

@@ -19,6 +19,7 @@
 #include <string>
 #include <vector>
 
+#include "sfac_embed.hpp"
 #include "sfac_internal.hpp"
 
 namespace sfac {
@@ -35,13 +36,20 @@ std::vector<ld> half_turn_cosines(int n) {
     return t;
 }
 
-int ilog2(int v) {
-    int e = 0;
-    while ((1 << e) < v) ++e;
-    return e;
-}
-
 }  // namespace
+
+int embed_frequency(int p, int log2m) {
+    const int nst = embed_stages(log2m);
+    int k = 0, mult = 1, rem = log2m;
+    for (int s = 0; s < nst; ++s) {
+        const int bits = embed_bits(log2m, s);
+        rem -= bits;
+        k += (p >> rem) * mult;   // digit of pass s: the block index at that pass
+        p &= (1 << rem) - 1;
+        mult <<= bits;
+    }
+    return k;
+}
 
 int embed_length(int n) {
     int m = 2;
@@ -88,36 +96,16 @@ bool factor_radices(int n, std::vector<int>* radices) {
     return (int)radices->size() <= kMaxStages;
 }
 
-namespace {
-
-// Rough cost per interior point of one exponential factor: flops plus a charge per
-// pass through local memory, used only to choose between the two exact methods.
-double factor_cost(const std::vector<int>& radices, double length_ratio) {
-    double flops = 0, passes = 0;
-    for (size_t s = 0; s < radices.size(); ++s) {
-        int r = radices[s];
-        bool pow2 = (r & (r - 1)) == 0;
-        flops += pow2 ? 5.0 * ilog2(r) : 4.0 * r;
-        if (s) flops += 6.0;
-        passes += 1.0;
-    }
-    return length_ratio * (2.0 * flops + 16.0 * passes);
-}
-
-}  // namespace
-
 int auto_method(int n, sfac_dtype) {
-    if (n <= 2) return SFAC_METHOD_DIAG;
-    std::vector<int> rd;
-    bool diag_ok = n <= kMaxDiagLength && factor_radices(n, &rd);
+    // The embedded method runs in the register-resident kernel (every transform pass in
+    // registers, one LDS exchange between passes); the diagonal method runs in the generic
+    // kernel (every pass through LDS), which measured 3-5x slower per pass on gfx950 even where
+    // its flop count is lower. So: embedded wherever its length fits, diagonal beyond.
     int m = embed_length(n);
-    std::vector<int> re;
-    bool embed_ok = m <= kMaxEmbedLength && factor_radices(m, &re);
-    if (!embed_ok) return diag_ok ? SFAC_METHOD_DIAG : 0;
-    if (!diag_ok) return SFAC_METHOD_EMBED;
-    double cd = factor_cost(rd, 1.0);
-    double ce = factor_cost(re, (double)m / (double)n);
-    return cd <= ce ? SFAC_METHOD_DIAG : SFAC_METHOD_EMBED;
+    if (m <= kMaxEmbedLength) return SFAC_METHOD_EMBED;
+    std::vector<int> rd;
+    if (n <= kMaxDiagLength && factor_radices(n, &rd)) return SFAC_METHOD_DIAG;
+    return 0;
 }
 
 std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out) {
@@ -255,6 +243,15 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out) 
             }
             t.scale_c[m] = (double)(gc / (ld)L);
             t.scale_s[m] = (double)(gs / (ld)L);
+        }
+        int log2m = 0;
+        while ((1 << log2m) < L) ++log2m;
+        t.gpos_c.resize(L);
+        t.gpos_s.resize(L);
+        for (int p = 0; p < L; ++p) {
+            const int k = embed_frequency(p, log2m);
+            t.gpos_c[p] = t.scale_c[k];
+            t.gpos_s[p] = t.scale_s[k];
         }
     }
     return std::string();

@@ -20,7 +20,8 @@ EXPORTS = [
     "sfac_plan_create", "sfac_step", "sfac_plan_destroy", "sfac_plan_device_bytes",
     "sfac_plan_flags", "sfac_plan_reset_flags", "sfac_plan_method", "sfac_last_error",
     "sfac_batch_create", "sfac_batch_step", "sfac_batch_destroy", "sfac_batch_device_bytes",
-    "sfac_axis_tables", "sfac_plan_time_passes",
+    "sfac_axis_tables", "sfac_plan_time_passes", "sfac_group_create", "sfac_group_step",
+    "sfac_group_destroy", "sfac_group_device_bytes", "sfac_batch_plan",
 ]
 
 
@@ -71,7 +72,14 @@ def lib():
     L.sfac_axis_tables.argtypes = [i32, dbl, dbl, dbl, dbl, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl),
                                    ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.sfac_plan_time_passes.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_float)]
-    for name in ["sfac_plan_time_passes", "sfac_axis_tables", "sfac_plan_create", "sfac_step", "sfac_plan_destroy", "sfac_plan_flags",
+    L.sfac_group_create.argtypes = [ctypes.POINTER(vp), vp]
+    L.sfac_group_step.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]
+    L.sfac_group_destroy.argtypes = [vp]
+    L.sfac_group_device_bytes.argtypes = [vp]
+    L.sfac_group_device_bytes.restype = ctypes.c_size_t
+    L.sfac_batch_plan.argtypes = [vp, i32]
+    L.sfac_batch_plan.restype = vp
+    for name in ["sfac_group_create", "sfac_group_step", "sfac_group_destroy", "sfac_plan_time_passes", "sfac_axis_tables", "sfac_plan_create", "sfac_step", "sfac_plan_destroy", "sfac_plan_flags",
                  "sfac_plan_reset_flags", "sfac_plan_method", "sfac_batch_create",
                  "sfac_batch_step", "sfac_batch_destroy"]:
         getattr(L, name).restype = ctypes.c_int
@@ -227,6 +235,46 @@ class Plan:
         self.close()
 
 
+class Group:
+    """sfac_group_create / sfac_group_step / sfac_group_destroy: step several plans together.
+    Plans should be created on the same stream as the group."""
+
+    def __init__(self, stream=None):
+        self._h = ctypes.c_void_p()
+        self._stream = _stream_handle(stream)
+        _check(lib().sfac_group_create(ctypes.byref(self._h), self._stream))
+
+    def step(self, plans, states, nsteps):
+        """Advance states[i] with plans[i] by nsteps[i] steps (an int applies to all)."""
+        n = len(plans)
+        if len(states) != n:
+            raise ValueError("one state per plan")
+        if isinstance(nsteps, int):
+            nsteps = [nsteps] * n
+        for p, u in zip(plans, states):
+            _check_state(u, p.shape, p.dt)
+        hs = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+        ptrs = (ctypes.c_void_p * n)(*[u.data_ptr() for u in states])
+        steps = (ctypes.c_int64 * n)(*[int(x) for x in nsteps])
+        _check(lib().sfac_group_step(self._h, n, hs, ptrs, steps))
+        return states
+
+    @property
+    def device_bytes(self):
+        return lib().sfac_group_device_bytes(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sfac_group_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """sfac_batch_create / sfac_batch_step / sfac_batch_destroy.
 
@@ -264,6 +312,16 @@ class Batch:
         steps = (ctypes.c_int64 * self.count)(*[int(s) for s in nsteps])
         _check(lib().sfac_batch_step(self._h, ptrs, steps))
         return states
+
+    def flags(self, i):
+        """(flags, max_abs) of instance i; synchronizes the batch's stream."""
+        h = lib().sfac_batch_plan(self._h, int(i))
+        if not h:
+            raise IndexError(i)
+        f = ctypes.c_uint32()
+        m = ctypes.c_double()
+        _check(lib().sfac_plan_flags(ctypes.c_void_p(h), ctypes.byref(f), ctypes.byref(m)))
+        return f.value, m.value
 
     @property
     def device_bytes(self):

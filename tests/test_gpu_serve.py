@@ -1,0 +1,57 @@
+"""The solve server on the GPU: a short mixed stream (2D and 3D, FP64 and FP32, uneven sizes
+and step counts) under a memory budget that forces queueing; every served result must be
+bitwise equal to the same solve run alone with its own plan, and FP64 results must match the
+oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sfac_oracle as O
+from paper_2209_08437_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _stream(count=10, seed=11):
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for rid in range(count):
+        t += float(rng.exponential(0.01))
+        d = 3 if rid % 3 == 0 else 2
+        n = int(rng.integers(8, 34)) if d == 3 else int(rng.integers(31, 131))
+        ns = (n,) * d
+        inst = W.Instance(ns, tuple(float(a) for a in rng.uniform(1.1, 1.9, d)), float(rng.uniform(0.02, 0.2)),
+                          float(rng.uniform(1e-3, 1e-2)), W.mesh_widths(ns), int(rng.integers(5, 41)))
+        inst.u0 = W.uniform_field(inst.shape, -0.9, 0.9, seed=200 + rid)
+        out.append(W.Request(rid, t, inst, "f64" if rid % 2 else "f32"))
+    return out
+
+
+def test_served_results_equal_lone_solves(sfac_lib):
+    import torch
+    from paper_2209_08437_amd import serve, sfac
+    reqs = _stream()
+    ex = serve.GpuExecutor()
+    sizes = [ex.bytes_needed(r.inst, r.dtype) for r in reqs]
+    budget = max(sizes) + sorted(sizes)[len(sizes) // 2]     # forces some requests to wait
+    print(f"case served stream of {len(reqs)} requests, budget {budget} B", flush=True)
+    srv = serve.Server(ex, budget_bytes=budget, tick_steps=8)
+    tickets, summ = srv.run(reqs)
+    print({k: summ[k] for k in ("completed", "ticks", "peak_active", "p50_latency_s", "p99_latency_s")}, flush=True)
+    assert summ["completed"] == len(reqs) and summ["rejected"] == 0
+    assert summ["peak_bytes"] <= budget
+    for r, tk in zip(sorted(reqs, key=lambda r: r.rid), tickets):
+        i = r.inst
+        tdt = torch.float64 if r.dtype == "f64" else torch.float32
+        u = torch.tensor(i.u0, dtype=tdt, device="cuda")
+        with sfac.Plan(i.ns, i.alphas, i.eps, i.tau, i.hs, r.dtype) as p:
+            p.step(u, i.steps)
+        torch.cuda.synchronize()
+        alone = u.double().cpu().numpy()
+        assert np.array_equal(tk.result, alone), r.rid
+        assert tk.flags == 0 and tk.max_abs <= 1.0
+        if r.dtype == "f64" and r.rid < 6:
+            ref = O.two_level_solve(i.u0, i.ns, i.alphas, i.eps, i.hs, i.tau, i.steps)
+            assert np.abs(tk.result - ref).max() <= 1e-12 * np.abs(ref).max()

@@ -1,0 +1,113 @@
+"""Scheduling logic of the solve server, on the CPU: a stand-in executor steps states with the
+oracle and advances a simulated clock by a modelled device time, so admission, continuous
+batching, rejection and latency accounting are checked without a GPU."""
+import numpy as np
+import pytest
+
+from oracle import sfac_oracle as O
+from paper_2209_08437_amd import serve, workloads as W
+
+
+class SimClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 0.0)
+
+
+class OracleExecutor:
+    """Steps with the CPU oracle; each grouped step costs `per_point_step` simulated seconds per
+    grid-point-step plus a fixed tick overhead."""
+
+    def __init__(self, clock, per_point_step=1e-7, overhead=1e-3):
+        self.clock = clock
+        self.rate = per_point_step
+        self.overhead = overhead
+        self.log = []
+
+    def bytes_needed(self, inst, dtype):
+        return int(np.prod(inst.ns)) * (8 if dtype == "f64" else 4)
+
+    def admit(self, inst, dtype):
+        ops = O.axis_operators(inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau)
+        return {"inst": inst, "ops": ops, "u": np.array(inst.u0, dtype=np.float64)}
+
+    def step(self, handles, nsteps):
+        self.log.append([(id(h), k) for h, k in zip(handles, nsteps)])
+        work = 0
+        for h, k in zip(handles, nsteps):
+            h["u"] = O.two_level_solve(h["u"], None, None, None, None, h["inst"].tau, k, ops=h["ops"])
+            work += int(np.prod(h["inst"].ns)) * k
+        self.clock.t += self.overhead + work * self.rate
+
+    def retire(self, handle):
+        return handle["u"], 0, float(np.abs(handle["u"]).max())
+
+
+def _requests(count=10, seed=3):
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for rid in range(count):
+        t += float(rng.exponential(0.002))
+        d = 2 if rid % 3 else 3
+        n = int(rng.integers(4, 12)) if d == 3 else int(rng.integers(6, 30))
+        ns = (n,) * d
+        inst = W.Instance(ns, tuple(float(a) for a in rng.uniform(1.1, 1.9, d)), float(rng.uniform(0.02, 0.2)),
+                          float(rng.uniform(1e-3, 1e-2)), W.mesh_widths(ns), int(rng.integers(3, 40)))
+        inst.u0 = W.uniform_field(inst.shape, -0.9, 0.9, seed=100 + rid)
+        out.append(W.Request(rid, t, inst, "f64" if rid % 2 else "f32"))
+    return out
+
+
+def test_all_complete_with_results_equal_to_lone_solves():
+    clock = SimClock()
+    ex = OracleExecutor(clock)
+    reqs = _requests()
+    srv = serve.Server(ex, budget_bytes=10 ** 9, tick_steps=7, clock=clock, sleep=clock.sleep)
+    tickets, summ = srv.run(reqs)
+    assert summ["completed"] == len(reqs) and summ["rejected"] == 0
+    for r, tk in zip(sorted(reqs, key=lambda r: r.rid), tickets):
+        i = r.inst
+        alone = O.two_level_solve(i.u0, i.ns, i.alphas, i.eps, i.hs, i.tau, i.steps)
+        assert np.array_equal(tk.result, alone)          # ticks split the steps; bitwise the same
+        assert tk.latency >= 0 and tk.admitted >= tk.arrival
+    assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
+
+
+def test_budget_limits_admission_and_oversize_is_rejected():
+    clock = SimClock()
+    ex = OracleExecutor(clock)
+    reqs = _requests(12, seed=5)
+    sizes = [ex.bytes_needed(r.inst, r.dtype) for r in reqs]
+    budget = max(sizes) - 1                      # the largest requests do not fit, the rest do
+    too_big = {r.rid for r, s in zip(reqs, sizes) if s > budget}
+    assert too_big and len(too_big) < len(reqs)
+    srv = serve.Server(ex, budget_bytes=budget, tick_steps=5, clock=clock, sleep=clock.sleep)
+    tickets, summ = srv.run(reqs)
+    assert summ["peak_bytes"] <= budget
+    for tk in tickets:
+        assert tk.rejected == (tk.rid in too_big)
+        assert (tk.finished is None) == (tk.rid in too_big)
+    assert summ["completed"] == len(reqs) - len(too_big)
+
+
+def test_fifo_admission_and_continuous_joining():
+    clock = SimClock()
+    ex = OracleExecutor(clock, per_point_step=1e-5)
+    reqs = _requests(8, seed=7)
+    srv = serve.Server(ex, budget_bytes=10 ** 9, tick_steps=3, max_active=3, clock=clock, sleep=clock.sleep)
+    tickets, summ = srv.run(reqs)
+    order = sorted(tickets, key=lambda t: t.arrival)
+    adm = [t.admitted for t in order]
+    assert adm == sorted(adm)                       # first come, first served
+    assert summ["peak_active"] == 3
+    # somebody was admitted while earlier requests were still running (joined mid-flight)
+    joined = any(b.admitted < a.finished and b.admitted > a.admitted for a in order for b in order)
+    assert joined
+    # every grouped step advanced each active request by at most the tick size
+    assert all(k <= 3 for tick in ex.log for _, k in tick)
