@@ -40,14 +40,19 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def gpu_rate(inst, dtype, steps, warmup, pass_reps):
+def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True):
     import numpy as np
     import torch
-    from paper_2209_08437_amd import sfac
+    from paper_2209_08437_amd import autotune, sfac
     tdt = torch.float64 if dtype == "f64" else torch.float32
     u0 = torch.tensor(inst.u0, dtype=tdt, device="cuda")
     u = u0.clone()
-    plan = sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype)
+    sched = {}
+    if tune:
+        best = autotune.tune(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, use_cache=False)
+        sched = {k: best[k] for k in ("method", "elems_log2", "lines_per_block")}
+        log(f"[bench] {dtype}: tuned schedule {sched} (pass us {[round(x * 1e3, 1) for x in best['ms']]})")
+    plan = sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, **sched)
     methods = [plan.method(a + 1) for a in range(inst.dims)]
     log(f"[bench] {dtype}: methods per axis {methods}; warmup {warmup} steps")
     plan.step(u, warmup)
@@ -74,7 +79,7 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps):
     torch.cuda.synchronize()
     result = {
         "wall_s": wall, "gpu_ms": gpu_ms, "flags": flags, "max_abs": vmax,
-        "pass_ms": pass_ms, "methods": methods, "state": u.double().cpu().numpy(),
+        "pass_ms": pass_ms, "methods": methods, "state": u.double().cpu().numpy(), "schedule": sched,
     }
     plan.close()
     return result
@@ -203,6 +208,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=20)
+    ap.add_argument("--no-tune", action="store_true", help="default schedules instead of autotuned ones")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--serve-count", type=int, default=48)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
@@ -241,7 +247,7 @@ def main():
         return
     esize = 8 if args.dtype == "f64" else 4
     pts = inst.points
-    main_r = gpu_rate(inst, args.dtype, steps, args.warmup, args.pass_reps)
+    main_r = gpu_rate(inst, args.dtype, steps, args.warmup, args.pass_reps, tune=not args.no_tune)
     value = pts * steps / main_r["wall_s"]
     # roofline of the dominant kernel: the axis pass with the largest mean duration
     pass_ms = main_r["pass_ms"]
@@ -258,12 +264,12 @@ def main():
         "ms_per_step": round(main_r["wall_s"] * 1e3 / steps, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": desc, "grid": list(inst.ns), "points": pts,
-                   "methods": [m for m, _ in main_r["methods"]],
+                   "methods": [m for m, _ in main_r["methods"]], "schedule": main_r["schedule"],
                    "effective_GBps": round(value * 2 * inst.dims * esize / 1e9, 2)},
         "roofline": roof,
     }
     if not args.no_fp32 and args.dtype == "f64":
-        r32 = gpu_rate(inst, "f32", steps, args.warmup, args.pass_reps)
+        r32 = gpu_rate(inst, "f32", steps, args.warmup, args.pass_reps, tune=not args.no_tune)
         import numpy as np
         ref = main_r["state"]
         out["fp32"] = {"value": round(pts * steps / r32["wall_s"], 1), "unit": "grid-point-steps/s",

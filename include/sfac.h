@@ -62,11 +62,14 @@ typedef enum { SFAC_METHOD_AUTO = 0, SFAC_METHOD_DIAG = 1, SFAC_METHOD_EMBED = 2
 typedef struct sfac_plan_s* sfac_plan;
 typedef struct sfac_batch_s* sfac_batch;
 
-/* Optional plan settings; pass NULL for the defaults. */
+/* Optional plan settings; pass NULL for the defaults. Zero-initialised fields mean "default". */
 typedef struct {
-    int32_t method[3];    /* sfac_method per axis (axis 1 first); default SFAC_METHOD_AUTO */
-    int32_t use_graph;    /* 1 (default): replay steps from captured HIP graphs; 0: plain launches */
-    int32_t graph_chunk;  /* steps captured per graph replay (default 32, 1..1024) */
+    int32_t method[3];          /* sfac_method per axis (axis 1 first); default SFAC_METHOD_AUTO */
+    int32_t use_graph;          /* 1 (default): replay steps from captured HIP graphs; 0: plain launches */
+    int32_t graph_chunk;        /* steps captured per graph replay (default 32, 1..1024) */
+    int32_t elems_log2[3];      /* embedded method: log2 of the elements each thread holds, 3 or 4
+                                   (0 = automatic); fewer elements means more threads per line */
+    int32_t lines_per_block[3]; /* pairs of real lines per thread block (0 = automatic) */
 } sfac_options;
 
 /* Per-plan sticky status, read with sfac_plan_flags. */

@@ -1,0 +1,113 @@
+"""Autotuner for the axis-pass schedules.
+
+For one problem shape it times candidate schedules of every axis pass on the device and keeps
+the fastest: the method (embedded or diagonal, where both apply), the number of elements each
+thread holds in the embedded kernel (8 or 16: more threads per line and one more radix pass, or
+fewer threads and one pass less) and the number of line pairs per thread block. Timing uses
+sfac_plan_time_passes (HIP events around each pass on the plan's stream), so only the device
+work is measured. Results are cached in a JSON file keyed by (axis length, lines in the pass,
+stride class, dtype), so a shape is tuned once per machine; `SFAC_TUNE_CACHE` names the file
+(default ~/.cache/sfac_autotune.json).
+
+All candidates compute the same operator and pass the same parity tests; they differ in speed
+and in rounding order only.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+
+
+def cache_path():
+    return os.environ.get("SFAC_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "sfac_autotune.json"))
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(path, data):
+    d = os.path.dirname(path)
+    if d:
+        os.makedirs(d, exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def axis_key(ns, axis, dtype):
+    """Cache key of one axis pass: its length, the number of lines, and whether they are
+    contiguous (axis 1) or strided."""
+    n = ns[axis]
+    lines = int(np.prod(ns)) // n
+    return f"{dtype}:n{n}:lines{lines}:{'contig' if axis == 0 else 'strided'}"
+
+
+def candidates(n):
+    """Schedules worth timing for an axis of n interior nodes: (method, elems_log2, lines_per_block)."""
+    from . import sfac
+    out = []
+    for le, lpb in itertools.product((3, 4), (0, 1, 2, 4)):
+        out.append(("embed", le, lpb))
+    try:
+        sfac.axis_tables(n, 1.5, 0.1, 0.01, 0.1, "diag")
+        out.append(("diag", 0, 0))
+    except sfac.SfacError:
+        pass
+    return out
+
+
+def tune(ns, alphas, eps, tau, hs, dtype="f64", reps=10, use_cache=True, verbose=False):
+    """Best schedule per axis for this shape: returns dict(method=[...], elems_log2=[...],
+    lines_per_block=[...], ms=[...]) ready to pass to sfac.Plan as keyword arguments (after
+    dropping 'ms')."""
+    import torch
+    from . import sfac
+    path = cache_path()
+    cache = _load_cache(path) if use_cache else {}
+    dims = len(ns)
+    best = {"method": [None] * dims, "elems_log2": [0] * dims, "lines_per_block": [0] * dims, "ms": [None] * dims}
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    rng = np.random.default_rng(0)
+    u0 = torch.tensor(rng.uniform(-0.9, 0.9, size=tuple(reversed(ns))), dtype=tdt, device="cuda")
+    for a in range(dims):
+        key = axis_key(ns, a, dtype)
+        if key in cache:
+            m, le, lpb, ms = cache[key]
+        else:
+            results = []
+            for m, le, lpb in candidates(ns[a]):
+                meth = [None] * dims
+                meth[a] = m
+                les = [0] * dims
+                les[a] = le
+                lp = [0] * dims
+                lp[a] = lpb
+                try:
+                    p = sfac.Plan(ns, alphas, eps, tau, hs, dtype, method=meth, elems_log2=les, lines_per_block=lp,
+                                  use_graph=False)
+                except sfac.SfacError:
+                    continue
+                u = u0.clone()
+                p.time_passes(u, 2)
+                t = p.time_passes(u, reps)[a]
+                p.close()
+                results.append((t, m, le, lpb))
+                if verbose:
+                    print(f"  axis {a + 1} {m} elems 2^{le} lines/block {lpb or 'auto'}: {t * 1e3:.1f} us", flush=True)
+            t, m, le, lpb = min(results)
+            ms = t
+            cache[key] = [m, le, lpb, ms]
+        best["method"][a] = m
+        best["elems_log2"][a] = le
+        best["lines_per_block"][a] = lpb
+        best["ms"][a] = ms
+    if use_cache:
+        _save_cache(path, cache)
+    return best

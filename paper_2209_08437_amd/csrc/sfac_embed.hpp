@@ -1,7 +1,8 @@
 // Register-resident axis pass for the embedded method (power-of-two transform length M).
 //
 // Each complex line (two real lines packed as real and imaginary parts) is held by T = M/E
-// threads, E = min(16, M) elements per thread. A length-M transform is an in-place
+// threads, E = min(2^LE, M) elements per thread (LE = 3 or 4: more threads per line and one more
+// radix pass, or fewer threads and more registers; the plan picks per length and problem size). A length-M transform is an in-place
 // decimation-in-frequency Cooley-Tukey pass sequence with radices R_0..R_{NST-1} (<= 16); the
 // inverse runs the conjugate-transposed passes in reverse order (decimation in time), so the
 // forward output (digit-reversed positions) is consumed where it lies and the inverse output
@@ -21,20 +22,25 @@
 
 namespace sfac {
 
-constexpr int embed_stages(int log2m) { return log2m <= 4 ? 1 : (log2m + 3) / 4; }
-constexpr int embed_bits(int log2m, int s) {
-    return log2m / embed_stages(log2m) + (s < log2m % embed_stages(log2m) ? 1 : 0);
+// Radix passes of a length-2^log2m transform with at most 2^log2e elements per thread: as few
+// passes as possible, bits spread evenly, larger radices first.
+constexpr int embed_log2e(int log2m, int log2e_max) { return log2m < log2e_max ? log2m : log2e_max; }
+constexpr int embed_stages(int log2m, int log2e_max) {
+    return log2m <= log2e_max ? 1 : (log2m + log2e_max - 1) / log2e_max;
+}
+constexpr int embed_bits(int log2m, int log2e_max, int s) {
+    return log2m / embed_stages(log2m, log2e_max) + (s < log2m % embed_stages(log2m, log2e_max) ? 1 : 0);
 }
 
-template <int LOG2M>
+template <int LOG2M, int LOG2E_MAX = 4>
 struct EmbedGeom {
     static constexpr int M = 1 << LOG2M;
-    static constexpr int LOG2E = LOG2M < 4 ? LOG2M : 4;
+    static constexpr int LOG2E = embed_log2e(LOG2M, LOG2E_MAX);
     static constexpr int E = 1 << LOG2E;
     static constexpr int LOG2T = LOG2M - LOG2E;
     static constexpr int T = 1 << LOG2T;
-    static constexpr int NST = embed_stages(LOG2M);
-    static constexpr int bits(int s) { return embed_bits(LOG2M, s); }
+    static constexpr int NST = embed_stages(LOG2M, LOG2E_MAX);
+    static constexpr int bits(int s) { return embed_bits(LOG2M, LOG2E_MAX, s); }
     static constexpr int R(int s) { return 1 << bits(s); }
     // log2 of the stride S_s between the elements of one radix-R_s butterfly
     static constexpr int log2S(int s) {
@@ -51,9 +57,9 @@ struct EmbedGeom {
 };
 
 // Position (in the in-place layout) of element k of butterfly slot i of thread t at stage s.
-template <int LOG2M, int S>
+template <int LOG2M, int LE, int S>
 __device__ __forceinline__ int embed_pos(int t, int i, int k) {
-    using G = EmbedGeom<LOG2M>;
+    using G = EmbedGeom<LOG2M, LE>;
     constexpr int ls = G::log2S(S);
     constexpr int lb = ls + G::bits(S);
     const int b = t + (i << G::LOG2T);
@@ -77,18 +83,18 @@ __device__ __forceinline__ int embed_swz(int p) {
 }
 
 // Twiddle of element k of slot i at stage s: W_M^{o k M / B_s}.
-template <int LOG2M, int S>
+template <int LOG2M, int LE, int S>
 __device__ __forceinline__ int embed_tw_index(int t, int i, int k) {
-    using G = EmbedGeom<LOG2M>;
+    using G = EmbedGeom<LOG2M, LE>;
     constexpr int ls = G::log2S(S);
     const int b = t + (i << G::LOG2T);
     const int o = b & ((1 << ls) - 1);
     return (o * k) << G::log2Pre(S);
 }
 
-template <typename T, int LOG2M>
+template <typename T, int LOG2M, int LE>
 struct EmbedLine {
-    using G = EmbedGeom<LOG2M>;
+    using G = EmbedGeom<LOG2M, LE>;
     static constexpr int NTW = G::NST > 1 ? G::NST - 1 : 1;
     cplx<T> a[G::E];
     cplx<T> tw[NTW][G::E];
@@ -107,17 +113,21 @@ struct EmbedLine {
 #pragma unroll
         for (int i = 0; i < G::E / R; ++i) {
 #pragma unroll
-            for (int k = 1; k < R; ++k) tw[S][i * R + k] = table[embed_tw_index<LOG2M, S>(t, i, k)];
+            for (int k = 1; k < R; ++k) tw[S][i * R + k] = table[embed_tw_index<LOG2M, LE, S>(t, i, k)];
         }
     }
 
-    // forward radix pass S: DFT of every butterfly, then the pass twiddles (not after the last)
+    // forward radix pass S: DFT of every butterfly, then the pass twiddles (not after the last).
+    // At pass 0 the inputs k >= R/2 sit at natural positions >= M/2 >= N: always zero.
     template <int S>
     __device__ __forceinline__ void fwd_stage() {
         constexpr int R = G::R(S);
 #pragma unroll
         for (int i = 0; i < G::E / R; ++i) {
-            dft<R, -1>(&a[i * R]);
+            if constexpr (S == 0 && R >= 2)
+                dft_half_input<R, -1>(&a[i * R]);
+            else
+                dft<R, -1>(&a[i * R]);
             if constexpr (S < G::NST - 1) {
 #pragma unroll
                 for (int k = 1; k < R; ++k) a[i * R + k] = cmul(a[i * R + k], tw[S][i * R + k]);
@@ -134,7 +144,11 @@ struct EmbedLine {
 #pragma unroll
                 for (int k = 1; k < R; ++k) a[i * R + k] = cmulc(a[i * R + k], tw[S][i * R + k]);
             }
-            dft<R, +1>(&a[i * R]);
+            // at pass 0 the outputs k >= R/2 land at positions >= M/2 >= N and are discarded
+            if constexpr (S == 0 && R >= 2)
+                dft_half_output<R, +1>(&a[i * R]);
+            else
+                dft<R, +1>(&a[i * R]);
         }
     }
 
@@ -146,12 +160,12 @@ struct EmbedLine {
 #pragma unroll
         for (int i = 0; i < G::E / RA; ++i)
 #pragma unroll
-            for (int k = 0; k < RA; ++k) line[embed_swz<T, LOG2M>(embed_pos<LOG2M, SA>(t, i, k))] = a[i * RA + k];
+            for (int k = 0; k < RA; ++k) line[embed_swz<T, LOG2M>(embed_pos<LOG2M, LE, SA>(t, i, k))] = a[i * RA + k];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < G::E / RB; ++i)
 #pragma unroll
-            for (int k = 0; k < RB; ++k) a[i * RB + k] = line[embed_swz<T, LOG2M>(embed_pos<LOG2M, SB>(t, i, k))];
+            for (int k = 0; k < RB; ++k) a[i * RB + k] = line[embed_swz<T, LOG2M>(embed_pos<LOG2M, LE, SB>(t, i, k))];
     }
 
     template <int S>
@@ -168,33 +182,44 @@ struct EmbedLine {
     }
 
     // multiply by the kernel spectrum, stored in last-pass position order
-    __device__ __forceinline__ void scale(const T* __restrict__ g, int t) {
+    // spectrum values at this thread's last-pass positions; loaded before the forward transform
+    // so that the load latency is hidden behind it
+    __device__ __forceinline__ void load_scale(const T* __restrict__ g, T* gv, int t) {
         constexpr int S = G::NST - 1;
         constexpr int R = G::R(S);
 #pragma unroll
         for (int i = 0; i < G::E / R; ++i)
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const T s = g[embed_pos<LOG2M, S>(t, i, k)];
-                a[i * R + k].x *= s;
-                a[i * R + k].y *= s;
-            }
+            for (int k = 0; k < R; ++k) gv[i * R + k] = g[embed_pos<LOG2M, LE, S>(t, i, k)];
+    }
+    __device__ __forceinline__ void scale(const T* gv) {
+#pragma unroll
+        for (int e = 0; e < G::E; ++e) {
+            a[e].x *= gv[e];
+            a[e].y *= gv[e];
+        }
     }
 
     // natural position of register (i, k) at pass 0
-    static __device__ __forceinline__ int nat(int t, int i, int k) { return embed_pos<LOG2M, 0>(t, i, k); }
+    static __device__ __forceinline__ int nat(int t, int i, int k) { return embed_pos<LOG2M, LE, 0>(t, i, k); }
 
     // one exponential factor: forward transform, spectrum, inverse transform, truncation
     __device__ __forceinline__ void factor(const T* __restrict__ g, cplx<T>* line, int t, int n) {
+        T gv[G::E];
+        load_scale(g, gv, t);
         fwd_from<0>(line, t);
-        scale(g, t);
+        scale(gv);
         inv_from<G::NST - 1>(line, t);
         constexpr int R0 = G::R(0);
 #pragma unroll
         for (int i = 0; i < G::E / R0; ++i)
 #pragma unroll
-            for (int k = 0; k < R0; ++k)
-                if (nat(t, i, k) >= n) a[i * R0 + k] = {(T)0, (T)0};
+            for (int k = 0; k < R0; ++k) {
+                if (k >= R0 / 2 && R0 >= 2)
+                    a[i * R0 + k] = {(T)0, (T)0};           // position >= M/2 >= N
+                else if (nat(t, i, k) >= n)
+                    a[i * R0 + k] = {(T)0, (T)0};
+            }
     }
 };
 

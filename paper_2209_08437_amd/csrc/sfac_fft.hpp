@@ -142,6 +142,55 @@ struct DftPow2 {
     }
 };
 
+// Radix-R DFT whose inputs R/2 .. R-1 are zero: even outputs are the half-length DFT of the
+// nonzero inputs, odd outputs the half-length DFT of those inputs times e^{DIR 2 pi i n / R}.
+template <int R, int DIR, typename T, int... K>
+__device__ __forceinline__ void half_in_twiddle(cplx<T>* o, const cplx<T>* a, std::integer_sequence<int, K...>) {
+    ((o[K] = twiddle<K, R, DIR>(a[K])), ...);
+}
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft_half_input(cplx<T>* a) {
+    if constexpr (R == 1) {
+        return;
+    } else {
+        cplx<T> e[R / 2], o[R / 2];
+#pragma unroll
+        for (int n = 0; n < R / 2; ++n) e[n] = a[n];
+        half_in_twiddle<R, DIR>(o, a, std::make_integer_sequence<int, R / 2>{});
+        DftPow2<R / 2, DIR, T>::run(e);
+        DftPow2<R / 2, DIR, T>::run(o);
+#pragma unroll
+        for (int m = 0; m < R / 2; ++m) {
+            a[2 * m] = e[m];
+            a[2 * m + 1] = o[m];
+        }
+    }
+}
+
+// Radix-R DFT of which only outputs 0 .. R/2-1 are needed (the others are left undefined):
+// y_n = DFT_{R/2}(even inputs)_n + e^{DIR 2 pi i n / R} DFT_{R/2}(odd inputs)_n.
+template <int R, int DIR, typename T, int... K>
+__device__ __forceinline__ void half_out_combine(cplx<T>* a, const cplx<T>* e, const cplx<T>* o,
+                                                 std::integer_sequence<int, K...>) {
+    ((a[K] = e[K] + twiddle<K, R, DIR>(o[K])), ...);
+}
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft_half_output(cplx<T>* a) {
+    if constexpr (R == 1) {
+        return;
+    } else {
+        cplx<T> e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = a[2 * i];
+            o[i] = a[2 * i + 1];
+        }
+        DftPow2<R / 2, DIR, T>::run(e);
+        DftPow2<R / 2, DIR, T>::run(o);
+        half_out_combine<R, DIR>(a, e, o, std::make_integer_sequence<int, R / 2>{});
+    }
+}
+
 // ------------------------------------------------------------------------ odd DFTs
 // y_j = a_0 + sum_k p_k cos(2 pi j k / R) + DIR i sum_k m_k sin(2 pi j k / R), k = 1..H,
 // with p_k = a_k + a_{R-k}, m_k = a_k - a_{R-k}; y_{R-j} flips the sign of the sine part.

@@ -35,8 +35,9 @@ struct AxisTables {
 };
 
 // Frequency index held at in-place position p after all decimation-in-frequency passes of the
-// register-resident power-of-two transform of length 2^log2m.
-int embed_frequency(int p, int log2m);
+// register-resident power-of-two transform of length 2^log2m with at most 2^log2e elements per
+// thread.
+int embed_frequency(int p, int log2m, int log2e);
 
 // Per-axis parameters of the method.
 struct AxisParams {
@@ -45,8 +46,9 @@ struct AxisParams {
 };
 
 // Builds the tables for one axis. Returns an empty string on success, else an error message.
-// `method` is SFAC_METHOD_DIAG or SFAC_METHOD_EMBED (AUTO is resolved by the caller).
-std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out);
+// `method` is SFAC_METHOD_DIAG or SFAC_METHOD_EMBED (AUTO is resolved by the caller); for the
+// embedded method `log2e` (3 or 4) selects the radix-pass schedule the position tables follow.
+std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e = 4);
 
 // Factorisation of n into the supported radices (largest first); empty if n has a prime
 // factor above kMaxPrimeRadix. n == 1 yields an empty list and returns true.

@@ -21,11 +21,26 @@ namespace {
 // J^Q_{tau/2} v = v / sqrt(v^2 + (1 - v^2) e^{-tau}), with 1 - v^2 formed as (1 - v)(1 + v).
 // e^{-tau} is carried as hi + lo in the state's type (lo = 0 for FP64): in FP32 the rounding of
 // e^{-tau} would otherwise bias every half-step the same way.
+// 1/sqrt(x) for x > 0. FP64: the hardware estimate refined by two Newton steps
+// y <- y (3/2 - x y^2 / 2), each of which roughly doubles the number of correct bits. FP32:
+// a correctly rounded square root and division.
+__device__ __forceinline__ double recip_sqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-h * y, y, 0.5);
+        y = fma(y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ float recip_sqrt(float x) { return 1.0f / __builtin_sqrtf(x); }
+
 template <typename T>
 __device__ __forceinline__ T nonlinear_half_step(T v, T decay, T decay_lo) {
     const T one = (T)1;
     const T q = (one - v) * (one + v);
-    return v / sqrt(v * v + (q * decay + q * decay_lo));
+    return v * recip_sqrt(v * v + (q * decay + q * decay_lo));
 }
 
 template <int DIR, typename T>
@@ -77,7 +92,11 @@ __device__ __forceinline__ void publish_stats(double vmax, unsigned int bad, uns
     if ((threadIdx.x & 63) == 0) {
         if (vmax > 1.0) bad |= SFAC_FLAG_ABOVE_ONE;
         if (bad) atomicOr(sflags, bad);
-        atomicMax(smax, (unsigned long long)__double_as_longlong(vmax));
+        // atomics on one address from every wave serialise; the running maximum rarely grows
+        // after the first step, so compare with the (possibly stale, never larger) stored value
+        // first and only then update
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(vmax);
+        if (bits > __atomic_load_n(smax, __ATOMIC_RELAXED)) atomicMax(smax, bits);
     }
 }
 
@@ -236,10 +255,10 @@ struct TileGeom {
 };
 
 // Embedded method, register-resident transforms of length 2^LOG2M.
-template <typename T, int LOG2M>
+template <typename T, int LOG2M, int LE>
 __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
-    using G = EmbedGeom<LOG2M>;
-    using Line = EmbedLine<T, LOG2M>;
+    using G = EmbedGeom<LOG2M, LE>;
+    using Line = EmbedLine<T, LOG2M, LE>;
     const int line = threadIdx.x >> G::LOG2T;
     const int t = threadIdx.x & (G::T - 1);
     const TileGeom<T> tg(d, tile);
@@ -257,7 +276,7 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
         for (int k = 0; k < R0; ++k) {
             const int n = Line::nat(t, i, k);
             cplx<T> z = {(T)0, (T)0};
-            if (act && n < N) {
+            if ((R0 < 2 || k < R0 / 2) && act && n < N) {
                 const T* p = src + (long long)n * tg.kstride;
                 z.x = p[0];
                 if (two) z.y = p[tg.lstride];
@@ -280,7 +299,7 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
 #pragma unroll
         for (int k = 0; k < R0; ++k) {
             const int n = Line::nat(t, i, k);
-            if (act && n < N) {
+            if ((R0 < 2 || k < R0 / 2) && act && n < N) {
                 cplx<T> z = L.a[i * R0 + k];
                 if (d.nl_out) {
                     z.x = nonlinear_half_step(z.x, decay, decay_lo);
@@ -316,16 +335,16 @@ __global__ void __launch_bounds__(kBlockThreads) axis_pass_single(PassDesc<T> d)
     run_tile(d, tile, buf0, buf1);
 }
 
-template <typename T, int LOG2M>
+template <typename T, int LOG2M, int LE>
 __global__ void __launch_bounds__(kBlockThreads) embed_pass_single(PassDesc<T> d) {
     extern __shared__ unsigned char smem_raw[];
     const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
     if (tile >= d.ntiles) return;
-    run_embed_tile<T, LOG2M>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_embed_tile<T, LOG2M, LE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
 // Several instances with the same transform length in one launch (batched form).
-template <typename T, int LOG2M>
+template <typename T, int LOG2M, int LE>
 __global__ void __launch_bounds__(kBlockThreads) embed_pass_multi(const PassDesc<T>* __restrict__ descs,
                                                                   const int* __restrict__ block_start,
                                                                   int ndesc) {
@@ -345,49 +364,34 @@ __global__ void __launch_bounds__(kBlockThreads) embed_pass_multi(const PassDesc
     if (tile >= d.ntiles) return;
     // the block has the group's largest size; threads beyond d.lpb lines hold no line (their
     // LDS rows lie inside the block's allocation) and only take part in the barriers
-    run_embed_tile<T, LOG2M>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_embed_tile<T, LOG2M, LE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
+// kernel of one (transform length, elements per thread); LE = 3 or 4
 template <typename T, int LOG2M>
-struct EmbedKernels {
-    static const void* single() { return reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M>); }
-    static const void* multi() { return reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M>); }
-};
-
-template <typename T>
-const void* embed_single_fn(int log2m) {
-    switch (log2m) {
-        case 1: return EmbedKernels<T, 1>::single();
-        case 2: return EmbedKernels<T, 2>::single();
-        case 3: return EmbedKernels<T, 3>::single();
-        case 4: return EmbedKernels<T, 4>::single();
-        case 5: return EmbedKernels<T, 5>::single();
-        case 6: return EmbedKernels<T, 6>::single();
-        case 7: return EmbedKernels<T, 7>::single();
-        case 8: return EmbedKernels<T, 8>::single();
-        case 9: return EmbedKernels<T, 9>::single();
-        case 10: return EmbedKernels<T, 10>::single();
-        case 11: return EmbedKernels<T, 11>::single();
-        case 12: return EmbedKernels<T, 12>::single();
-        default: return nullptr;
-    }
+const void* embed_fn_le(int le, bool multi) {
+    if (le == 3)
+        return multi ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, 3>)
+                     : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, 3>);
+    return multi ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, 4>)
+                 : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, 4>);
 }
 
 template <typename T>
-const void* embed_multi_fn(int log2m) {
+const void* embed_fn(int log2m, int le, bool multi) {
     switch (log2m) {
-        case 1: return EmbedKernels<T, 1>::multi();
-        case 2: return EmbedKernels<T, 2>::multi();
-        case 3: return EmbedKernels<T, 3>::multi();
-        case 4: return EmbedKernels<T, 4>::multi();
-        case 5: return EmbedKernels<T, 5>::multi();
-        case 6: return EmbedKernels<T, 6>::multi();
-        case 7: return EmbedKernels<T, 7>::multi();
-        case 8: return EmbedKernels<T, 8>::multi();
-        case 9: return EmbedKernels<T, 9>::multi();
-        case 10: return EmbedKernels<T, 10>::multi();
-        case 11: return EmbedKernels<T, 11>::multi();
-        case 12: return EmbedKernels<T, 12>::multi();
+        case 1: return embed_fn_le<T, 1>(le, multi);
+        case 2: return embed_fn_le<T, 2>(le, multi);
+        case 3: return embed_fn_le<T, 3>(le, multi);
+        case 4: return embed_fn_le<T, 4>(le, multi);
+        case 5: return embed_fn_le<T, 5>(le, multi);
+        case 6: return embed_fn_le<T, 6>(le, multi);
+        case 7: return embed_fn_le<T, 7>(le, multi);
+        case 8: return embed_fn_le<T, 8>(le, multi);
+        case 9: return embed_fn_le<T, 9>(le, multi);
+        case 10: return embed_fn_le<T, 10>(le, multi);
+        case 11: return embed_fn_le<T, 11>(le, multi);
+        case 12: return embed_fn_le<T, 12>(le, multi);
         default: return nullptr;
     }
 }
@@ -428,7 +432,7 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
     const int blocks = pass_blocks(d);
     if (blocks <= 0) return hipSuccess;
     if (d.method == 2) {
-        const void* fn = embed_single_fn<T>(d.log2m);
+        const void* fn = embed_fn<T>(d.log2m, d.log2e, false);
         if (!fn) return hipErrorInvalidValue;
         void* args[] = {const_cast<PassDesc<T>*>(&d)};
         return hipLaunchKernel(fn, dim3(blocks), dim3(d.threads), args, lds_bytes, stream);
@@ -438,12 +442,12 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
 }
 
 template <typename T>
-hipError_t launch_axis_pass_multi(int method, int log2m, int threads, const PassDesc<T>* descs_dev,
+hipError_t launch_axis_pass_multi(int method, int log2m, int log2e, int threads, const PassDesc<T>* descs_dev,
                                   const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
                                   hipStream_t stream) {
     if (total_blocks <= 0) return hipSuccess;
     if (method == 2) {
-        const void* fn = embed_multi_fn<T>(log2m);
+        const void* fn = embed_fn<T>(log2m, log2e, true);
         if (!fn) return hipErrorInvalidValue;
         void* args[] = {&descs_dev, &block_start_dev, &ndesc};
         return hipLaunchKernel(fn, dim3(total_blocks), dim3(threads), args, lds_bytes, stream);
@@ -458,12 +462,13 @@ hipError_t allow_lds(size_t lds_bytes) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_single<T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    for (int lg = 1; lg <= 12; ++lg) {
-        e = hipFuncSetAttribute(embed_single_fn<T>(lg), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute(embed_multi_fn<T>(lg), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) return e;
-    }
+    for (int lg = 1; lg <= 12; ++lg)
+        for (int le = 3; le <= 4; ++le)
+            for (int multi = 0; multi < 2; ++multi) {
+                e = hipFuncSetAttribute(embed_fn<T>(lg, le, multi), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds_bytes);
+                if (e != hipSuccess) return e;
+            }
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_multi<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
@@ -472,9 +477,9 @@ template int pass_blocks<double>(const PassDesc<double>&);
 template int pass_blocks<float>(const PassDesc<float>&);
 template hipError_t launch_axis_pass<double>(const PassDesc<double>&, size_t, hipStream_t);
 template hipError_t launch_axis_pass<float>(const PassDesc<float>&, size_t, hipStream_t);
-template hipError_t launch_axis_pass_multi<double>(int, int, int, const PassDesc<double>*, const int*, int, int,
-                                                   size_t, hipStream_t);
-template hipError_t launch_axis_pass_multi<float>(int, int, int, const PassDesc<float>*, const int*, int, int,
+template hipError_t launch_axis_pass_multi<double>(int, int, int, int, const PassDesc<double>*, const int*, int,
+                                                   int, size_t, hipStream_t);
+template hipError_t launch_axis_pass_multi<float>(int, int, int, int, const PassDesc<float>*, const int*, int, int,
                                                   size_t, hipStream_t);
 template hipError_t allow_lds<double>(size_t);
 template hipError_t allow_lds<float>(size_t);

@@ -38,6 +38,7 @@ struct PassDesc {
     int nl_in, nl_out;               // apply J^Q_{tau/2} on load / on store (+ statistics)
     int xcd_remap;                   // group neighbouring tiles per XCD
     int log2m;                       // embed: log2 of the transform length
+    int log2e;                       // embed: log2 of the largest elements-per-thread count (3 or 4)
     int threads;                     // launch block size
     T decay, decay_lo;               // e^{-tau} = decay + decay_lo (decay_lo = 0 in FP64)
 };
@@ -49,9 +50,9 @@ template <typename T>
 hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream);
 
 // One launch over several instances' tiles of one pass. method 2 (embedded) launches need
-// every descriptor to share log2m; `threads` is the block size (the largest of the group).
+// every descriptor to share log2m and log2e; `threads` is the block size (the group's largest).
 template <typename T>
-hipError_t launch_axis_pass_multi(int method, int log2m, int threads, const PassDesc<T>* descs_dev,
+hipError_t launch_axis_pass_multi(int method, int log2m, int log2e, int threads, const PassDesc<T>* descs_dev,
                                   const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
                                   hipStream_t stream);
 

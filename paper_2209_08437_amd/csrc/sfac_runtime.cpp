@@ -47,6 +47,7 @@ struct AxisDevice {
     size_t off_tw = 0, off_sc = 0, off_ss = 0, off_psi = 0, off_gc = 0, off_gs = 0;
     int lpb = 1;
     int threads = 256;
+    int log2e = 4;
     size_t lds = 0;
 };
 
@@ -124,8 +125,9 @@ sfac_status validate_instance(int dims, const int32_t* n, const double* alpha, d
 
 // Tables for every axis of one instance (host side); methods[a] may be AUTO.
 sfac_status build_instance(Instance* in, int dims, const int32_t* n, const double* alpha, double eps,
-                           double tau, const double* h, sfac_dtype dt, const int32_t* methods,
+                           double tau, const double* h, sfac_dtype dt, const sfac_options* opt,
                            const char* who) {
+    const int32_t* methods = opt ? opt->method : nullptr;
     sfac_status st = validate_instance(dims, n, alpha, eps, tau, h, who);
     if (st != SFAC_OK) return st;
     in->dims = dims;
@@ -142,8 +144,24 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
         if (m == SFAC_METHOD_AUTO) m = sfac::auto_method(n[a], dt);
         if (m != SFAC_METHOD_DIAG && m != SFAC_METHOD_EMBED)
             return fail(SFAC_EUNSUPPORTED, "%saxis %d: no method supports N = %d", who, a + 1, n[a]);
+        // embedded method: elements per thread. Fewer (8) doubles the threads of a line: worth it
+        // when the pass would otherwise have too few waves to hide latency (under two per SIMD
+        // of a 256-CU device); more (16) needs one radix pass less.
+        int log2e = opt && opt->elems_log2[a] ? opt->elems_log2[a] : 0;
+        if (log2e != 0 && log2e != 3 && log2e != 4)
+            return fail(SFAC_EINVAL, "%saxis %d: elems_log2 = %d, expected 3 or 4", who, a + 1, log2e);
+        {
+            long long inner0 = 1, outer0 = 1;
+            for (int b = 0; b < a; ++b) inner0 *= n[b];
+            for (int b = a + 1; b < dims; ++b) outer0 *= n[b];
+            const long long avail0 = inner0 == 1 ? outer0 : inner0;
+            const long long lines0 = outer0 * inner0 / avail0 * ((avail0 + 1) / 2);
+            int mlen = sfac::embed_length(n[a]);
+            if (log2e == 0) log2e = lines0 * (mlen / 16) / 64 < 2048 ? 3 : 4;
+        }
+        in->ax[a].log2e = log2e;
         sfac::AxisParams p{n[a], alpha[a], eps, tau, h[a]};
-        std::string err = sfac::build_axis_tables(p, m, &in->ax[a].host);
+        std::string err = sfac::build_axis_tables(p, m, &in->ax[a].host, log2e);
         if (!err.empty()) {
             const bool range = err.find("exceeds") != std::string::npos || err.find("prime factor") != std::string::npos;
             return fail(range ? SFAC_EUNSUPPORTED : SFAC_EINVAL, "%saxis %d: %s", who, a + 1, err.c_str());
@@ -161,11 +179,12 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
             // fewer lines per block while that still leaves blocks for every CU
             int log2m = 0;
             while ((1 << log2m) < L) ++log2m;
-            const int E = log2m < 4 ? (1 << log2m) : 16;
+            const int E = 1 << sfac::embed_log2e(log2m, in->ax[a].log2e);
             const int T = L / E;
             int lpb = sfac::kBlockThreads / T;
             while (lpb > 1 && (lines_total + lpb - 1) / lpb < 1024) lpb >>= 1;
-            lpb = (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2));
+            if (opt && opt->lines_per_block[a] > 0) lpb = std::min(opt->lines_per_block[a], sfac::kBlockThreads / T);
+            lpb = std::max(1, (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2)));
             in->ax[a].lpb = lpb;
             in->ax[a].threads = lpb * T;
             in->ax[a].lds = elem * (size_t)L * lpb;
@@ -173,6 +192,7 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
             // generic kernel: two LDS buffers per line, as many lines as fit the budget
             const size_t per_line = 2 * elem * (size_t)L;
             int lpb = (int)std::max<size_t>(1, kLdsBudget / per_line);
+            if (opt && opt->lines_per_block[a] > 0) lpb = opt->lines_per_block[a];
             lpb = (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2));
             lpb = std::min(lpb, 64);
             in->ax[a].lpb = lpb;
@@ -202,6 +222,7 @@ sfac::PassDesc<T> make_desc(const Instance& in, int a, unsigned char* dev_tables
     d.gpos_c = reinterpret_cast<const T*>(dev_tables + ad.off_gc);
     d.gpos_s = reinterpret_cast<const T*>(dev_tables + ad.off_gs);
     d.threads = ad.threads;
+    d.log2e = ad.log2e;
     d.log2m = 0;
     while ((1 << d.log2m) < t.length) ++d.log2m;
     d.stat_max = stat_max;
@@ -314,14 +335,17 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
     if (opt) {
         if (opt->graph_chunk < 0 || opt->graph_chunk > 1024)
             return fail(SFAC_EINVAL, "graph_chunk = %d, expected 1..1024 (0 = default)", opt->graph_chunk);
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
             if (opt->method[a] < SFAC_METHOD_AUTO || opt->method[a] > SFAC_METHOD_EMBED)
                 return fail(SFAC_EINVAL, "unknown method %d for axis %d", opt->method[a], a + 1);
+            if (opt->lines_per_block[a] < 0 || opt->lines_per_block[a] > 256)
+                return fail(SFAC_EINVAL, "lines_per_block = %d for axis %d, expected 0..256",
+                            opt->lines_per_block[a], a + 1);
+        }
     }
     std::unique_ptr<sfac_plan_s> p(new (std::nothrow) sfac_plan_s());
     if (!p) return fail(SFAC_ENOMEM, "host allocation failed");
-    sfac_status st = build_instance(&p->in, dims, n_axis, alpha_axis, eps, tau, h_axis, dt,
-                                    opt ? opt->method : nullptr, "");
+    sfac_status st = build_instance(&p->in, dims, n_axis, alpha_axis, eps, tau, h_axis, dt, opt, "");
     if (st != SFAC_OK) return st;
     p->stream = static_cast<hipStream_t>(hip_stream);
     if (opt) {
@@ -537,7 +561,7 @@ struct GroupLaunch {
     int ndesc, blocks;
     int64_t reps;
     int phase;
-    int fp64, method, log2m, threads;
+    int fp64, method, log2m, log2e, threads;
     size_t lds;
 };
 
@@ -558,7 +582,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
     for (size_t ph = 0; ph < bounds.size(); ++ph) {
         const int64_t bound = bounds[ph];
         for (int pass = 0; pass < 3; ++pass) {
-            std::vector<std::pair<int, int>> keys;   // (method, log2m)
+            std::vector<std::pair<int, int>> keys;   // (method, log2m * 8 + log2e)
             std::vector<std::vector<sfac::PassDesc<T>>> groups;
             std::vector<size_t> glds;
             for (size_t i = 0; i < plans.size(); ++i) {
@@ -566,7 +590,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                 if (steps[i] < bound || pass >= p->in.dims) continue;
                 sfac::PassDesc<T> d = make_desc<T>(p->in, pass, p->dev, static_cast<T*>(us[i]), p->stat_max(),
                                                    p->stat_flags());
-                const std::pair<int, int> key(d.method, d.method == SFAC_METHOD_EMBED ? d.log2m : 0);
+                const std::pair<int, int> key(d.method, d.method == SFAC_METHOD_EMBED ? d.log2m * 8 + d.log2e : 0);
                 size_t g = std::find(keys.begin(), keys.end(), key) - keys.begin();
                 if (g == keys.size()) {
                     keys.push_back(key);
@@ -582,7 +606,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                 if (keys[g].first == SFAC_METHOD_EMBED) {
                     threads = 0;
                     for (const auto& d : groups[g]) threads = std::max(threads, d.threads);
-                    const int E = keys[g].second < 4 ? (1 << keys[g].second) : 16;
+                    const int E = 1 << sfac::embed_log2e(keys[g].second / 8, keys[g].second % 8);
                     glds[g] = (size_t)threads * E * sizeof(sfac::cplx<T>);
                 }
                 for (const auto& d : groups[g]) starts.push_back(starts.back() + sfac::pass_blocks(d));
@@ -595,7 +619,8 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                 l.phase = (int)ph;
                 l.fp64 = std::is_same<T, double>::value;
                 l.method = keys[g].first;
-                l.log2m = keys[g].second;
+                l.log2m = keys[g].second / 8;
+                l.log2e = keys[g].second % 8;
                 l.threads = threads;
                 l.lds = glds[g];
                 out->push_back(l);
@@ -607,7 +632,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
 
 template <typename T>
 hipError_t group_launch(sfac_group g, const GroupLaunch& l) {
-    return sfac::launch_axis_pass_multi<T>(l.method, l.log2m, l.threads,
+    return sfac::launch_axis_pass_multi<T>(l.method, l.log2m, l.log2e, l.threads,
                                            reinterpret_cast<const sfac::PassDesc<T>*>(g->arena + l.off_desc),
                                            reinterpret_cast<const int*>(g->arena + l.off_start), l.ndesc,
                                            l.blocks, l.lds, g->stream);

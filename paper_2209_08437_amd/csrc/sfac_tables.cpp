@@ -38,11 +38,11 @@ std::vector<ld> half_turn_cosines(int n) {
 
 }  // namespace
 
-int embed_frequency(int p, int log2m) {
-    const int nst = embed_stages(log2m);
+int embed_frequency(int p, int log2m, int log2e) {
+    const int nst = embed_stages(log2m, log2e);
     int k = 0, mult = 1, rem = log2m;
     for (int s = 0; s < nst; ++s) {
-        const int bits = embed_bits(log2m, s);
+        const int bits = embed_bits(log2m, log2e, s);
         rem -= bits;
         k += (p >> rem) * mult;   // digit of pass s: the block index at that pass
         p &= (1 << rem) - 1;
@@ -108,7 +108,7 @@ int auto_method(int n, sfac_dtype) {
     return 0;
 }
 
-std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out) {
+std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e) {
     const int N = p.n;
     char msg[256];
     if (N < 1) return "N must be >= 1";
@@ -249,7 +249,7 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out) 
         t.gpos_c.resize(L);
         t.gpos_s.resize(L);
         for (int p = 0; p < L; ++p) {
-            const int k = embed_frequency(p, log2m);
+            const int k = embed_frequency(p, log2m, log2e);
             t.gpos_c[p] = t.scale_c[k];
             t.gpos_s[p] = t.scale_s[k];
         }

@@ -33,7 +33,8 @@ class SfacError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32 * 3), ("use_graph", ctypes.c_int32),
-                ("graph_chunk", ctypes.c_int32)]
+                ("graph_chunk", ctypes.c_int32), ("elems_log2", ctypes.c_int32 * 3),
+                ("lines_per_block", ctypes.c_int32 * 3)]
 
 
 class InstanceDesc(ctypes.Structure):
@@ -155,10 +156,12 @@ class Plan:
     """sfac_plan_create / sfac_step / sfac_plan_destroy for one instance.
 
     ns, alphas, hs: per-axis sequences, axis 1 first. dtype: "f64" or "f32".
-    method: None (automatic), "diag" or "embed" (one for all axes) or a per-axis sequence."""
+    method: None (automatic), "diag" or "embed" (one for all axes) or a per-axis sequence.
+    elems_log2, lines_per_block: kernel schedule per axis (None or 0 = automatic; see
+    sfac_options in include/sfac.h and autotune.py)."""
 
     def __init__(self, ns, alphas, eps, tau, hs, dtype="f64", stream=None, method=None,
-                 use_graph=True, graph_chunk=32):
+                 use_graph=True, graph_chunk=32, elems_log2=None, lines_per_block=None):
         L = lib()
         self.dims = len(ns)
         if not (len(alphas) == len(hs) == self.dims):
@@ -172,6 +175,12 @@ class Plan:
             opt.method[a] = codes[meth[a]] if a < self.dims else METHOD_AUTO
         opt.use_graph = 1 if use_graph else 0
         opt.graph_chunk = int(graph_chunk)
+        for a in range(min(3, self.dims)):
+            if elems_log2 is not None:
+                opt.elems_log2[a] = int(elems_log2[a] if isinstance(elems_log2, (list, tuple)) else elems_log2)
+            if lines_per_block is not None:
+                opt.lines_per_block[a] = int(lines_per_block[a] if isinstance(lines_per_block, (list, tuple))
+                                             else lines_per_block)
         n_arr = (ctypes.c_int32 * self.dims)(*self.ns)
         a_arr = (ctypes.c_double * self.dims)(*[float(a) for a in alphas])
         h_arr = (ctypes.c_double * self.dims)(*[float(h) for h in hs])

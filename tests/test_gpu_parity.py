@@ -117,6 +117,46 @@ def test_shapes_fp64(sfac_lib, ns):
         assert flags == 0
 
 
+@pytest.mark.parametrize("le", [3, 4])
+@pytest.mark.parametrize("lpb", [0, 1, 3])
+@pytest.mark.parametrize("ns", [(100, 37), (1023, 9), (9, 16, 33)], ids=lambda s: "x".join(map(str, s)))
+def test_embed_schedules_fp64(sfac_lib, ns, le, lpb):
+    """Every schedule the autotuner may pick (elements per thread, line pairs per block)."""
+    rng = np.random.default_rng(len(ns) * 100 + ns[0])
+    alphas = tuple(float(a) for a in rng.uniform(1.05, 1.95, len(ns)))
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=ns[0] + 3)
+    ref = O.two_level_solve(u0, ns, alphas, 0.2, hs, 0.01, 3)
+    _say(f"case schedule {ns} elems 2^{le} lines/block {lpb}")
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    u = torch.tensor(u0, device="cuda")
+    with sfac.Plan(ns, alphas, 0.2, 0.01, hs, "f64", method="embed", elems_log2=le, lines_per_block=lpb) as p:
+        p.step(u, 3)
+    torch.cuda.synchronize()
+    assert rel_err(u.cpu().numpy(), ref) <= FP64_TOL
+
+
+def test_autotuned_schedule_matches_oracle(sfac_lib, tmp_path, monkeypatch):
+    monkeypatch.setenv("SFAC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_2209_08437_amd import autotune, sfac
+    torch = _torch()
+    ns = (127, 64)
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field((64, 127), -0.9, 0.9, seed=4)
+    _say("case autotune 127x64")
+    best = autotune.tune(ns, (1.4, 1.6), 0.1, 0.01, hs, "f64", reps=3)
+    sched = {k: best[k] for k in ("method", "elems_log2", "lines_per_block")}
+    u = torch.tensor(u0, device="cuda")
+    with sfac.Plan(ns, (1.4, 1.6), 0.1, 0.01, hs, "f64", **sched) as p:
+        p.step(u, 4)
+    torch.cuda.synchronize()
+    ref = O.two_level_solve(u0, ns, (1.4, 1.6), 0.1, hs, 0.01, 4)
+    assert rel_err(u.cpu().numpy(), ref) <= FP64_TOL
+    again = autotune.tune(ns, (1.4, 1.6), 0.1, 0.01, hs, "f64", reps=3)   # from the cache
+    assert again["method"] == best["method"] and again["elems_log2"] == best["elems_log2"]
+
+
 def test_special_parameters(sfac_lib):
     """alpha = 2 (three-point Laplacian) and eps = 0 (pure Bernoulli flow, closed form)."""
     ns = (20, 13)
