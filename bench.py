@@ -50,7 +50,7 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True):
     sched = {}
     if tune:
         best = autotune.tune(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, use_cache=False)
-        sched = {k: best[k] for k in ("method", "elems_log2", "lines_per_block")}
+        sched = {k: best[k] for k in ("method", "elems_log2", "lines_per_block", "kernel")}
         log(f"[bench] {dtype}: tuned schedule {sched} (pass us {[round(x * 1e3, 1) for x in best['ms']]})")
     plan = sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, **sched)
     methods = [plan.method(a + 1) for a in range(inst.dims)]

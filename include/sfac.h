@@ -70,6 +70,11 @@ typedef struct {
     int32_t elems_log2[3];      /* embedded method: log2 of the elements each thread holds, 3 or 4
                                    (0 = automatic); fewer elements means more threads per line */
     int32_t lines_per_block[3]; /* pairs of real lines per thread block (0 = automatic) */
+    int32_t kernel[3];          /* diagonal method: 0 automatic, 1 the generic kernel (every N whose
+                                   prime factors are <= 31), 2 the register-resident two-step kernel
+                                   (N = A B for the pairs it is built for; SFAC_EUNSUPPORTED else).
+                                   Nonzero selects the diagonal method under SFAC_METHOD_AUTO and is
+                                   SFAC_EINVAL with SFAC_METHOD_EMBED */
 } sfac_options;
 
 /* Per-plan sticky status, read with sfac_plan_flags. */

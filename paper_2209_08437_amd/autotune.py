@@ -49,15 +49,23 @@ def axis_key(ns, axis, dtype):
     return f"{dtype}:n{n}:lines{lines}:{'contig' if axis == 0 else 'strided'}"
 
 
+# N = A B pairs of the register-resident diagonal kernel (the library's list)
+DIAG2_PAIRS = ((3, 5), (5, 7), (7, 9), (9, 11), (11, 13), (13, 15), (15, 17), (5, 9), (7, 11))
+
+
 def candidates(n):
-    """Schedules worth timing for an axis of n interior nodes: (method, elems_log2, lines_per_block)."""
+    """Schedules worth timing for an axis of n interior nodes:
+    (method, elems_log2, lines_per_block, kernel)."""
     from . import sfac
     out = []
     for le, lpb in itertools.product((3, 4), (0, 1, 2, 4)):
-        out.append(("embed", le, lpb))
+        out.append(("embed", le, lpb, 0))
+    if any(a * b == n for a, b in DIAG2_PAIRS):
+        for lpb in (0, 1, 2, 4):
+            out.append(("diag", 0, lpb, 2))
     try:
         sfac.axis_tables(n, 1.5, 0.1, 0.01, 0.1, "diag")
-        out.append(("diag", 0, 0))
+        out.append(("diag", 0, 0, 1))
     except sfac.SfacError:
         pass
     return out
@@ -65,48 +73,52 @@ def candidates(n):
 
 def tune(ns, alphas, eps, tau, hs, dtype="f64", reps=10, use_cache=True, verbose=False):
     """Best schedule per axis for this shape: returns dict(method=[...], elems_log2=[...],
-    lines_per_block=[...], ms=[...]) ready to pass to sfac.Plan as keyword arguments (after
-    dropping 'ms')."""
+    lines_per_block=[...], kernel=[...], ms=[...]) ready to pass to sfac.Plan as keyword arguments
+    (after dropping 'ms')."""
     import torch
     from . import sfac
     path = cache_path()
     cache = _load_cache(path) if use_cache else {}
     dims = len(ns)
-    best = {"method": [None] * dims, "elems_log2": [0] * dims, "lines_per_block": [0] * dims, "ms": [None] * dims}
+    best = {"method": [None] * dims, "elems_log2": [0] * dims, "lines_per_block": [0] * dims,
+            "kernel": [0] * dims, "ms": [None] * dims}
     tdt = torch.float64 if dtype == "f64" else torch.float32
     rng = np.random.default_rng(0)
     u0 = torch.tensor(rng.uniform(-0.9, 0.9, size=tuple(reversed(ns))), dtype=tdt, device="cuda")
     for a in range(dims):
         key = axis_key(ns, a, dtype)
-        if key in cache:
-            m, le, lpb, ms = cache[key]
+        if key in cache and len(cache[key]) == 5:
+            m, le, lpb, kern, ms = cache[key]
         else:
             results = []
-            for m, le, lpb in candidates(ns[a]):
+            for m, le, lpb, kern in candidates(ns[a]):
                 meth = [None] * dims
                 meth[a] = m
                 les = [0] * dims
                 les[a] = le
                 lp = [0] * dims
                 lp[a] = lpb
+                kk = [0] * dims
+                kk[a] = kern
                 try:
                     p = sfac.Plan(ns, alphas, eps, tau, hs, dtype, method=meth, elems_log2=les, lines_per_block=lp,
-                                  use_graph=False)
+                                  kernel=kk, use_graph=False)
                 except sfac.SfacError:
                     continue
                 u = u0.clone()
                 p.time_passes(u, 2)
                 t = p.time_passes(u, reps)[a]
                 p.close()
-                results.append((t, m, le, lpb))
+                results.append((t, m, le, lpb, kern))
                 if verbose:
-                    print(f"  axis {a + 1} {m} elems 2^{le} lines/block {lpb or 'auto'}: {t * 1e3:.1f} us", flush=True)
-            t, m, le, lpb = min(results)
-            ms = t
-            cache[key] = [m, le, lpb, ms]
+                    print(f"  axis {a + 1} {m} kernel {kern} elems 2^{le} lines/block {lpb or 'auto'}: "
+                          f"{t * 1e3:.1f} us", flush=True)
+            ms, m, le, lpb, kern = min(results)
+            cache[key] = [m, le, lpb, kern, ms]
         best["method"][a] = m
         best["elems_log2"][a] = le
         best["lines_per_block"][a] = lpb
+        best["kernel"][a] = kern
         best["ms"][a] = ms
     if use_cache:
         _save_cache(path, cache)

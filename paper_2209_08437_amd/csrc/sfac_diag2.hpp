@@ -1,0 +1,121 @@
+// Register-resident axis pass for the diagonal method (Remark 1) when N = A * B with small A, B.
+//
+// A length-N transform is done in two steps: B DFTs of length A over x[b + B a] (one per
+// thread b), the twiddles e^{-2 pi i b k1 / N}, one LDS exchange, then A DFTs of length B (one per
+// thread k1) that leave X[k1 + A k2] in thread k1. The inverse runs the conjugate steps in
+// reverse order and returns x[b + B a] to thread b, exactly where the next forward transform
+// reads it. Per factor: [psi multiply] forward transform, multiply by the eigenvalue factor,
+// inverse transform, [conj(psi) multiply]: two LDS exchanges per factor, no padding.
+// A line is held by P = max(A, B) threads; threads beyond A (or B) idle in the other step.
+// Tables are stored per thread in the order the thread walks them (see the host builder).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sfac_fft.hpp"
+
+namespace sfac {
+
+template <int A, int B>
+struct Diag2Geom {
+    static constexpr int N = A * B;
+    static constexpr int P = A > B ? A : B;   // threads per line
+    static constexpr int E = P;               // registers per thread (max of the two step sizes)
+};
+
+template <typename T, int A, int B>
+struct Diag2Line {
+    using G = Diag2Geom<A, B>;
+    cplx<T> a[G::E];
+    cplx<T> tw[A];   // e^{-2 pi i b k1 / N}, k1 < A, for this thread's b
+
+    // twpos[b * A + k1] = e^{-2 pi i b k1 / N}
+    __device__ __forceinline__ void load_twiddles(const cplx<T>* __restrict__ twpos, int t) {
+        if (t < B) {
+#pragma unroll
+            for (int k = 0; k < A; ++k) tw[k] = twpos[t * A + k];
+        }
+    }
+
+    // x <- psi . x (or conj(psi) . x) at this thread's natural positions b + B a;
+    // psipos[b * A + a] = psi_{b + B a}
+    template <bool CONJ>
+    __device__ __forceinline__ void psi_mul(const cplx<T>* __restrict__ psipos, int t) {
+        if (t < B) {
+#pragma unroll
+            for (int k = 0; k < A; ++k) {
+                const cplx<T> w = psipos[t * A + k];
+                a[k] = CONJ ? cmulc(a[k], w) : cmul(a[k], w);
+            }
+        }
+    }
+
+    // forward: DFT_A in thread b, twiddle, exchange, DFT_B in thread k1
+    __device__ __forceinline__ void forward(cplx<T>* __restrict__ line, int t) {
+        if (t < B) {
+            dft<A, -1>(a);
+#pragma unroll
+            for (int k = 1; k < A; ++k) a[k] = cmul(a[k], tw[k]);
+        }
+        __syncthreads();
+        if (t < B) {
+#pragma unroll
+            for (int k = 0; k < A; ++k) line[k * B + t] = a[k];
+        }
+        __syncthreads();
+        if (t < A) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) a[b] = line[t * B + b];
+            dft<B, -1>(a);
+        }
+    }
+
+    // inverse: conjugate DFT_B in thread k1, exchange, conjugate twiddle and DFT_A in thread b
+    __device__ __forceinline__ void inverse(cplx<T>* __restrict__ line, int t) {
+        if (t < A) dft<B, +1>(a);
+        __syncthreads();
+        if (t < A) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) line[t * B + b] = a[b];
+        }
+        __syncthreads();
+        if (t < B) {
+#pragma unroll
+            for (int k = 0; k < A; ++k) a[k] = line[k * B + t];
+#pragma unroll
+            for (int k = 1; k < A; ++k) a[k] = cmulc(a[k], tw[k]);
+            dft<A, +1>(a);
+        }
+    }
+
+    // eigenvalue factor at X[k1 + A k2], stored as gpos[k1 * B + k2]
+    __device__ __forceinline__ void load_scale(const T* __restrict__ gpos, T* gv, int t) {
+        if (t < A) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) gv[b] = gpos[t * B + b];
+        }
+    }
+    __device__ __forceinline__ void scale(const T* gv, int t) {
+        if (t < A) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                a[b].x *= gv[b];
+                a[b].y *= gv[b];
+            }
+        }
+    }
+
+    template <bool SKEW>
+    __device__ __forceinline__ void factor(const T* __restrict__ gpos, const cplx<T>* __restrict__ psipos,
+                                           cplx<T>* line, int t) {
+        T gv[B];
+        load_scale(gpos, gv, t);
+        if constexpr (SKEW) psi_mul<false>(psipos, t);
+        forward(line, t);
+        scale(gv, t);
+        inverse(line, t);
+        if constexpr (SKEW) psi_mul<true>(psipos, t);
+    }
+};
+
+}  // namespace sfac

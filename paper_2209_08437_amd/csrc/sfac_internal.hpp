@@ -30,9 +30,17 @@ struct AxisTables {
     // diag only: psi_k = e^{-i pi k / N}
     std::vector<double> psi_re, psi_im;
     // embed only: scale_c / scale_s permuted to the digit-reversed positions of the
-    // register-resident transform (position p holds frequency embed_frequency(p))
+    // register-resident transform (position p holds frequency embed_frequency(p));
+    // two-step diagonal kernel (N = A B): gpos[k1 B + k2] = scale[k1 + A k2]
     std::vector<double> gpos_c, gpos_s;
+    // two-step diagonal kernel only: A, B and the per-thread tables
+    // tw2[b A + k1] = e^{-2 pi i b k1 / N}, psi2[b A + a] = psi_{b + B a}
+    int d2a = 0, d2b = 0;
+    std::vector<double> tw2_re, tw2_im, psi2_re, psi2_im;
 };
+
+// Factor pairs N = A * B handled by the register-resident diagonal kernel (false if none).
+bool diag2_pair(int n, int* a, int* b);
 
 // Frequency index held at in-place position p after all decimation-in-frequency passes of the
 // register-resident power-of-two transform of length 2^log2m with at most 2^log2e elements per
@@ -48,7 +56,8 @@ struct AxisParams {
 // Builds the tables for one axis. Returns an empty string on success, else an error message.
 // `method` is SFAC_METHOD_DIAG or SFAC_METHOD_EMBED (AUTO is resolved by the caller); for the
 // embedded method `log2e` (3 or 4) selects the radix-pass schedule the position tables follow.
-std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e = 4);
+std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e = 4,
+                              bool diag2 = true);
 
 // Factorisation of n into the supported radices (largest first); empty if n has a prime
 // factor above kMaxPrimeRadix. n == 1 yields an empty list and returns true.

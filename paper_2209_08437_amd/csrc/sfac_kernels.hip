@@ -10,6 +10,7 @@
 
 #include <cstdint>
 
+#include "sfac_diag2.hpp"
 #include "sfac_embed.hpp"
 #include "sfac_fft.hpp"
 #include "sfac_kernels.hpp"
@@ -318,6 +319,66 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     if (d.nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
 }
 
+// Diagonal method, register-resident two-step transforms of length N = A B.
+template <typename T, int A, int B>
+__device__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
+    using G = Diag2Geom<A, B>;
+    using Line = Diag2Line<T, A, B>;
+    const int line = threadIdx.x / G::P;
+    const int t = threadIdx.x - line * G::P;
+    const TileGeom<T> tg(d, tile);
+    const bool act = 2 * line < tg.nreal;
+    const bool two = 2 * line + 1 < tg.nreal;
+    const T decay = d.decay, decay_lo = d.decay_lo;
+    Line L;
+    L.load_twiddles(d.tw2, t);
+    const T* src = tg.base + (long long)(2 * line) * tg.lstride;
+    if (t < B) {
+#pragma unroll
+        for (int k = 0; k < A; ++k) {
+            const int n = t + B * k;
+            cplx<T> z = {(T)0, (T)0};
+            if (act) {
+                const T* p = src + (long long)n * tg.kstride;
+                z.x = p[0];
+                if (two) z.y = p[tg.lstride];
+                if (d.nl_in) {
+                    z.x = nonlinear_half_step(z.x, decay, decay_lo);
+                    z.y = nonlinear_half_step(z.y, decay, decay_lo);
+                }
+            }
+            L.a[k] = z;
+        }
+    }
+    cplx<T>* ln = lds + line * G::N;
+    L.template factor<false>(d.gpos_c, d.psi2, ln, t);
+    L.template factor<true>(d.gpos_s, d.psi2, ln, t);
+    L.template factor<false>(d.gpos_c, d.psi2, ln, t);
+    T* dst = tg.base + (long long)(2 * line) * tg.lstride;
+    double vmax = 0.0;
+    unsigned int bad = 0;
+    if (t < B && act) {
+#pragma unroll
+        for (int k = 0; k < A; ++k) {
+            const int n = t + B * k;
+            cplx<T> z = L.a[k];
+            if (d.nl_out) {
+                z.x = nonlinear_half_step(z.x, decay, decay_lo);
+                z.y = nonlinear_half_step(z.y, decay, decay_lo);
+                const double ax = fabs((double)z.x), ay = two ? fabs((double)z.y) : 0.0;
+                if (!(ax <= 1.7976931348623157e308) || !(ay <= 1.7976931348623157e308))
+                    bad |= SFAC_FLAG_NONFINITE;
+                else
+                    vmax = fmax(vmax, fmax(ax, ay));
+            }
+            T* p = dst + (long long)n * tg.kstride;
+            p[0] = z.x;
+            if (two) p[tg.lstride] = z.y;
+        }
+    }
+    if (d.nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
+}
+
 // blockIdx -> tile, grouping neighbouring tiles on one XCD (blocks are dealt round-robin to
 // the 8 XCDs, so block b runs on XCD b % 8): tiles that share cache lines then share an L2.
 __device__ __forceinline__ int xcd_tile(int block, int ntiles) {
@@ -365,6 +426,58 @@ __global__ void __launch_bounds__(kBlockThreads) embed_pass_multi(const PassDesc
     // the block has the group's largest size; threads beyond d.lpb lines hold no line (their
     // LDS rows lie inside the block's allocation) and only take part in the barriers
     run_embed_tile<T, LOG2M, LE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+}
+
+template <typename T, int A, int B>
+__global__ void __launch_bounds__(kBlockThreads) diag2_pass_single(PassDesc<T> d) {
+    extern __shared__ unsigned char smem_raw[];
+    const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
+    if (tile >= d.ntiles) return;
+    run_diag2_tile<T, A, B>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+}
+
+template <typename T, int A, int B>
+__global__ void __launch_bounds__(kBlockThreads) diag2_pass_multi(const PassDesc<T>* __restrict__ descs,
+                                                                  const int* __restrict__ block_start,
+                                                                  int ndesc) {
+    extern __shared__ unsigned char smem_raw[];
+    int lo = 0, hi = ndesc;
+    const int b = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (block_start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const PassDesc<T> d = descs[lo];
+    const int local = b - block_start[lo];
+    const int tile = d.xcd_remap ? xcd_tile(local, d.ntiles) : local;
+    if (tile >= d.ntiles) return;
+    run_diag2_tile<T, A, B>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+}
+
+template <typename T, int A, int B>
+const void* diag2_fn_ab(bool multi) {
+    return multi ? reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B>)
+                 : reinterpret_cast<const void*>(&diag2_pass_single<T, A, B>);
+}
+
+// the (A, B) pairs the host may plan (see diag2_pair)
+template <typename T>
+const void* diag2_fn(int a, int b, bool multi) {
+    switch (a * 64 + b) {
+        case 3 * 64 + 5: return diag2_fn_ab<T, 3, 5>(multi);
+        case 5 * 64 + 7: return diag2_fn_ab<T, 5, 7>(multi);
+        case 7 * 64 + 9: return diag2_fn_ab<T, 7, 9>(multi);
+        case 9 * 64 + 11: return diag2_fn_ab<T, 9, 11>(multi);
+        case 11 * 64 + 13: return diag2_fn_ab<T, 11, 13>(multi);
+        case 13 * 64 + 15: return diag2_fn_ab<T, 13, 15>(multi);
+        case 15 * 64 + 17: return diag2_fn_ab<T, 15, 17>(multi);
+        case 5 * 64 + 9: return diag2_fn_ab<T, 5, 9>(multi);
+        case 7 * 64 + 11: return diag2_fn_ab<T, 7, 11>(multi);
+        default: return nullptr;
+    }
 }
 
 // kernel of one (transform length, elements per thread); LE = 3 or 4
@@ -431,8 +544,8 @@ template <typename T>
 hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream) {
     const int blocks = pass_blocks(d);
     if (blocks <= 0) return hipSuccess;
-    if (d.method == 2) {
-        const void* fn = embed_fn<T>(d.log2m, d.log2e, false);
+    if (d.method == 2 || (d.method == 1 && d.d2a > 0)) {
+        const void* fn = d.method == 2 ? embed_fn<T>(d.log2m, d.log2e, false) : diag2_fn<T>(d.d2a, d.d2b, false);
         if (!fn) return hipErrorInvalidValue;
         void* args[] = {const_cast<PassDesc<T>*>(&d)};
         return hipLaunchKernel(fn, dim3(blocks), dim3(d.threads), args, lds_bytes, stream);
@@ -442,12 +555,13 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
 }
 
 template <typename T>
-hipError_t launch_axis_pass_multi(int method, int log2m, int log2e, int threads, const PassDesc<T>* descs_dev,
+hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const PassDesc<T>* descs_dev,
                                   const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
                                   hipStream_t stream) {
     if (total_blocks <= 0) return hipSuccess;
-    if (method == 2) {
-        const void* fn = embed_fn<T>(log2m, log2e, true);
+    if (kind == 1 || kind == 2) {
+        const void* fn = kind == 1 ? embed_fn<T>(variant / 8, variant % 8, true)
+                                   : diag2_fn<T>(variant / 64, variant % 64, true);
         if (!fn) return hipErrorInvalidValue;
         void* args[] = {&descs_dev, &block_start_dev, &ndesc};
         return hipLaunchKernel(fn, dim3(total_blocks), dim3(threads), args, lds_bytes, stream);
@@ -469,6 +583,14 @@ hipError_t allow_lds(size_t lds_bytes) {
                                         (int)lds_bytes);
                 if (e != hipSuccess) return e;
             }
+    for (int a = 3; a <= 17; ++a)
+        for (int b = a; b <= 17; ++b)
+            for (int multi = 0; multi < 2; ++multi) {
+                const void* fn = diag2_fn<T>(a, b, multi);
+                if (!fn) continue;
+                e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+                if (e != hipSuccess) return e;
+            }
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_multi<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
@@ -477,9 +599,9 @@ template int pass_blocks<double>(const PassDesc<double>&);
 template int pass_blocks<float>(const PassDesc<float>&);
 template hipError_t launch_axis_pass<double>(const PassDesc<double>&, size_t, hipStream_t);
 template hipError_t launch_axis_pass<float>(const PassDesc<float>&, size_t, hipStream_t);
-template hipError_t launch_axis_pass_multi<double>(int, int, int, int, const PassDesc<double>*, const int*, int,
-                                                   int, size_t, hipStream_t);
-template hipError_t launch_axis_pass_multi<float>(int, int, int, int, const PassDesc<float>*, const int*, int, int,
+template hipError_t launch_axis_pass_multi<double>(int, int, int, const PassDesc<double>*, const int*, int, int,
+                                                   size_t, hipStream_t);
+template hipError_t launch_axis_pass_multi<float>(int, int, int, const PassDesc<float>*, const int*, int, int,
                                                   size_t, hipStream_t);
 template hipError_t allow_lds<double>(size_t);
 template hipError_t allow_lds<float>(size_t);

@@ -24,6 +24,8 @@ struct PassDesc {
     const cplx<T>* psi;              // diag: e^{-i pi k / N}, k < N
     const T* gpos_c;                 // embed: kernel spectra / M in digit-reversed position order
     const T* gpos_s;
+    const cplx<T>* tw2;              // two-step diagonal kernel: per-thread twiddles and psi
+    const cplx<T>* psi2;
     unsigned long long* stat_max;    // bits of the largest |u| stored (non-negative double)
     unsigned int* stat_flags;        // SFAC_FLAG_* bits
     long long inner, outer;
@@ -39,6 +41,7 @@ struct PassDesc {
     int xcd_remap;                   // group neighbouring tiles per XCD
     int log2m;                       // embed: log2 of the transform length
     int log2e;                       // embed: log2 of the largest elements-per-thread count (3 or 4)
+    int d2a, d2b;                    // diag: N = d2a * d2b for the two-step kernel, 0 for the generic one
     int threads;                     // launch block size
     T decay, decay_lo;               // e^{-tau} = decay + decay_lo (decay_lo = 0 in FP64)
 };
@@ -49,10 +52,11 @@ int pass_blocks(const PassDesc<T>& d);
 template <typename T>
 hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream);
 
-// One launch over several instances' tiles of one pass. method 2 (embedded) launches need
-// every descriptor to share log2m and log2e; `threads` is the block size (the group's largest).
+// One launch over several instances' tiles of one pass; every descriptor of the launch uses the
+// same kernel variant; `threads` is the block size (the group's largest).
+// kind: 0 generic, 1 embedded (variant = log2m * 8 + log2e), 2 two-step diagonal (variant = a * 64 + b)
 template <typename T>
-hipError_t launch_axis_pass_multi(int method, int log2m, int log2e, int threads, const PassDesc<T>* descs_dev,
+hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const PassDesc<T>* descs_dev,
                                   const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
                                   hipStream_t stream);
 

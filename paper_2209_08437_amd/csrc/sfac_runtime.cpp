@@ -44,7 +44,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Device copy of one axis' tables in the plan's arithmetic type.
 struct AxisDevice {
     sfac::AxisTables host;
-    size_t off_tw = 0, off_sc = 0, off_ss = 0, off_psi = 0, off_gc = 0, off_gs = 0;
+    size_t off_tw = 0, off_sc = 0, off_ss = 0, off_psi = 0, off_gc = 0, off_gs = 0, off_tw2 = 0, off_psi2 = 0;
     int lpb = 1;
     int threads = 256;
     int log2e = 4;
@@ -66,6 +66,10 @@ size_t axis_table_bytes(const sfac::AxisTables& t, size_t base, AxisDevice* ad) 
     off = align_up(off + sizeof(T) * t.gpos_c.size(), 256);
     ad->off_gs = off;
     off = align_up(off + sizeof(T) * t.gpos_s.size(), 256);
+    ad->off_tw2 = off;
+    off = align_up(off + sizeof(sfac::cplx<T>) * t.tw2_re.size(), 256);
+    ad->off_psi2 = off;
+    off = align_up(off + sizeof(sfac::cplx<T>) * t.psi2_re.size(), 256);
     return off;
 }
 
@@ -83,6 +87,10 @@ void axis_table_fill(const sfac::AxisTables& t, const AxisDevice& ad, unsigned c
     for (size_t m = 0; m < t.gpos_c.size(); ++m) gc[m] = (T)t.gpos_c[m];
     auto* gs = reinterpret_cast<T*>(host + ad.off_gs);
     for (size_t m = 0; m < t.gpos_s.size(); ++m) gs[m] = (T)t.gpos_s[m];
+    auto* tw2 = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_tw2);
+    for (size_t m = 0; m < t.tw2_re.size(); ++m) tw2[m] = {(T)t.tw2_re[m], (T)t.tw2_im[m]};
+    auto* psi2 = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_psi2);
+    for (size_t m = 0; m < t.psi2_re.size(); ++m) psi2[m] = {(T)t.psi2_re[m], (T)t.psi2_im[m]};
 }
 
 // One instance's geometry and tables: the part a plan and a batch entry share.
@@ -140,8 +148,13 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
         in->n[a] = n[a];
         in->alpha[a] = alpha[a];
         in->h[a] = h[a];
+        const int kern = opt ? opt->kernel[a] : 0;
+        if (kern < 0 || kern > 2) return fail(SFAC_EINVAL, "%saxis %d: kernel = %d, expected 0, 1 or 2", who, a + 1, kern);
         int m = methods ? methods[a] : SFAC_METHOD_AUTO;
-        if (m == SFAC_METHOD_AUTO) m = sfac::auto_method(n[a], dt);
+        if (kern != 0 && m == SFAC_METHOD_EMBED)
+            return fail(SFAC_EINVAL, "%saxis %d: a diagonal-method kernel was chosen for the embedded method", who,
+                        a + 1);
+        if (m == SFAC_METHOD_AUTO) m = kern != 0 ? SFAC_METHOD_DIAG : sfac::auto_method(n[a], dt);
         if (m != SFAC_METHOD_DIAG && m != SFAC_METHOD_EMBED)
             return fail(SFAC_EUNSUPPORTED, "%saxis %d: no method supports N = %d", who, a + 1, n[a]);
         // embedded method: elements per thread. Fewer (8) doubles the threads of a line: worth it
@@ -161,7 +174,11 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
         }
         in->ax[a].log2e = log2e;
         sfac::AxisParams p{n[a], alpha[a], eps, tau, h[a]};
-        std::string err = sfac::build_axis_tables(p, m, &in->ax[a].host, log2e);
+        std::string err = sfac::build_axis_tables(p, m, &in->ax[a].host, log2e, kern != 1);
+        if (!err.empty() && kern == 2 && m == SFAC_METHOD_DIAG) err = "";
+        if (kern == 2 && m == SFAC_METHOD_DIAG && in->ax[a].host.d2a == 0)
+            return fail(SFAC_EUNSUPPORTED, "%saxis %d: N = %d is not a product the register-resident diagonal "
+                        "kernel handles", who, a + 1, n[a]);
         if (!err.empty()) {
             const bool range = err.find("exceeds") != std::string::npos || err.find("prime factor") != std::string::npos;
             return fail(range ? SFAC_EUNSUPPORTED : SFAC_EINVAL, "%saxis %d: %s", who, a + 1, err.c_str());
@@ -187,6 +204,16 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
             lpb = std::max(1, (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2)));
             in->ax[a].lpb = lpb;
             in->ax[a].threads = lpb * T;
+            in->ax[a].lds = elem * (size_t)L * lpb;
+        } else if (in->ax[a].host.d2a > 0) {
+            // two-step diagonal kernel: P = max(A, B) threads per line
+            const int P = std::max(in->ax[a].host.d2a, in->ax[a].host.d2b);
+            int lpb = sfac::kBlockThreads / P;
+            while (lpb > 1 && (lines_total + lpb - 1) / lpb < 1024) lpb >>= 1;
+            if (opt && opt->lines_per_block[a] > 0) lpb = std::min(opt->lines_per_block[a], sfac::kBlockThreads / P);
+            lpb = std::max(1, (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2)));
+            in->ax[a].lpb = lpb;
+            in->ax[a].threads = lpb * P;
             in->ax[a].lds = elem * (size_t)L * lpb;
         } else {
             // generic kernel: two LDS buffers per line, as many lines as fit the budget
@@ -223,6 +250,10 @@ sfac::PassDesc<T> make_desc(const Instance& in, int a, unsigned char* dev_tables
     d.gpos_s = reinterpret_cast<const T*>(dev_tables + ad.off_gs);
     d.threads = ad.threads;
     d.log2e = ad.log2e;
+    d.d2a = t.d2a;
+    d.d2b = t.d2b;
+    d.tw2 = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_tw2);
+    d.psi2 = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_psi2);
     d.log2m = 0;
     while ((1 << d.log2m) < t.length) ++d.log2m;
     d.stat_max = stat_max;
@@ -561,7 +592,7 @@ struct GroupLaunch {
     int ndesc, blocks;
     int64_t reps;
     int phase;
-    int fp64, method, log2m, log2e, threads;
+    int fp64, kind, variant, threads;
     size_t lds;
 };
 
@@ -582,7 +613,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
     for (size_t ph = 0; ph < bounds.size(); ++ph) {
         const int64_t bound = bounds[ph];
         for (int pass = 0; pass < 3; ++pass) {
-            std::vector<std::pair<int, int>> keys;   // (method, log2m * 8 + log2e)
+            std::vector<std::pair<int, int>> keys;   // (kernel kind, variant): see launch_axis_pass_multi
             std::vector<std::vector<sfac::PassDesc<T>>> groups;
             std::vector<size_t> glds;
             for (size_t i = 0; i < plans.size(); ++i) {
@@ -590,7 +621,8 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                 if (steps[i] < bound || pass >= p->in.dims) continue;
                 sfac::PassDesc<T> d = make_desc<T>(p->in, pass, p->dev, static_cast<T*>(us[i]), p->stat_max(),
                                                    p->stat_flags());
-                const std::pair<int, int> key(d.method, d.method == SFAC_METHOD_EMBED ? d.log2m * 8 + d.log2e : 0);
+                const int kind = d.method == SFAC_METHOD_EMBED ? 1 : (d.d2a > 0 ? 2 : 0);
+                const std::pair<int, int> key(kind, kind == 1 ? d.log2m * 8 + d.log2e : (kind == 2 ? d.d2a * 64 + d.d2b : 0));
                 size_t g = std::find(keys.begin(), keys.end(), key) - keys.begin();
                 if (g == keys.size()) {
                     keys.push_back(key);
@@ -603,11 +635,17 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
             for (size_t g = 0; g < groups.size(); ++g) {
                 std::vector<int> starts(1, 0);
                 int threads = sfac::kBlockThreads;
-                if (keys[g].first == SFAC_METHOD_EMBED) {
+                if (keys[g].first == 1) {
                     threads = 0;
                     for (const auto& d : groups[g]) threads = std::max(threads, d.threads);
                     const int E = 1 << sfac::embed_log2e(keys[g].second / 8, keys[g].second % 8);
                     glds[g] = (size_t)threads * E * sizeof(sfac::cplx<T>);
+                } else if (keys[g].first == 2) {
+                    // a full block of P-thread lines; lines beyond a descriptor's lpb idle
+                    threads = 0;
+                    for (const auto& d : groups[g]) threads = std::max(threads, d.threads);
+                    const int A = keys[g].second / 64, B = keys[g].second % 64, P = std::max(A, B);
+                    glds[g] = (size_t)(threads / P) * A * B * sizeof(sfac::cplx<T>);
                 }
                 for (const auto& d : groups[g]) starts.push_back(starts.back() + sfac::pass_blocks(d));
                 GroupLaunch l;
@@ -618,9 +656,8 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                 l.reps = bound - done;
                 l.phase = (int)ph;
                 l.fp64 = std::is_same<T, double>::value;
-                l.method = keys[g].first;
-                l.log2m = keys[g].second / 8;
-                l.log2e = keys[g].second % 8;
+                l.kind = keys[g].first;
+                l.variant = keys[g].second;
                 l.threads = threads;
                 l.lds = glds[g];
                 out->push_back(l);
@@ -632,7 +669,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
 
 template <typename T>
 hipError_t group_launch(sfac_group g, const GroupLaunch& l) {
-    return sfac::launch_axis_pass_multi<T>(l.method, l.log2m, l.log2e, l.threads,
+    return sfac::launch_axis_pass_multi<T>(l.kind, l.variant, l.threads,
                                            reinterpret_cast<const sfac::PassDesc<T>*>(g->arena + l.off_desc),
                                            reinterpret_cast<const int*>(g->arena + l.off_start), l.ndesc,
                                            l.blocks, l.lds, g->stream);

@@ -51,6 +51,18 @@ int embed_frequency(int p, int log2m, int log2e) {
     return k;
 }
 
+bool diag2_pair(int n, int* a, int* b) {
+    // the instantiated (A, B) pairs of the register-resident diagonal kernel
+    static const int pairs[][2] = {{3, 5}, {5, 7}, {7, 9}, {9, 11}, {11, 13}, {13, 15}, {15, 17}, {5, 9}, {7, 11}};
+    for (const auto& pr : pairs)
+        if (pr[0] * pr[1] == n) {
+            *a = pr[0];
+            *b = pr[1];
+            return true;
+        }
+    return false;
+}
+
 int embed_length(int n) {
     int m = 2;
     while (m < 2 * n - 1) m <<= 1;
@@ -97,10 +109,13 @@ bool factor_radices(int n, std::vector<int>* radices) {
 }
 
 int auto_method(int n, sfac_dtype) {
-    // The embedded method runs in the register-resident kernel (every transform pass in
-    // registers, one LDS exchange between passes); the diagonal method runs in the generic
-    // kernel (every pass through LDS), which measured 3-5x slower per pass on gfx950 even where
-    // its flop count is lower. So: embedded wherever its length fits, diagonal beyond.
+    // The diagonal method in its register-resident two-step kernel (N = A B for the built pairs)
+    // needs no padding and one LDS exchange per transform; the embedded method runs every N in
+    // its register-resident kernel; the generic diagonal kernel (every pass through LDS) measured
+    // 3-5x slower per pass. So: two-step diagonal where it exists, else embedded while its length
+    // fits, else generic diagonal.
+    int a = 0, b = 0;
+    if (diag2_pair(n, &a, &b)) return SFAC_METHOD_DIAG;
     int m = embed_length(n);
     if (m <= kMaxEmbedLength) return SFAC_METHOD_EMBED;
     std::vector<int> rd;
@@ -108,7 +123,7 @@ int auto_method(int n, sfac_dtype) {
     return 0;
 }
 
-std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e) {
+std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e, bool diag2) {
     const int N = p.n;
     char msg[256];
     if (N < 1) return "N must be >= 1";
@@ -211,6 +226,30 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, 
             ld ang = kPi * (ld)k / (ld)N;
             t.psi_re[k] = (double)cosl(ang);
             t.psi_im[k] = (double)-sinl(ang);
+        }
+        int A = 0, B = 0;
+        if (diag2 && diag2_pair(N, &A, &B)) {
+            t.d2a = A;
+            t.d2b = B;
+            t.tw2_re.resize(N);
+            t.tw2_im.resize(N);
+            t.psi2_re.resize(N);
+            t.psi2_im.resize(N);
+            t.gpos_c.resize(N);
+            t.gpos_s.resize(N);
+            for (int b = 0; b < B; ++b)
+                for (int k = 0; k < A; ++k) {
+                    ld ang = 2.0L * kPi * (ld)((long long)b * k % N) / (ld)N;
+                    t.tw2_re[b * A + k] = (double)cosl(ang);
+                    t.tw2_im[b * A + k] = (double)-sinl(ang);
+                    t.psi2_re[b * A + k] = t.psi_re[b + B * k];
+                    t.psi2_im[b * A + k] = t.psi_im[b + B * k];
+                }
+            for (int k1 = 0; k1 < A; ++k1)
+                for (int k2 = 0; k2 < B; ++k2) {
+                    t.gpos_c[k1 * B + k2] = t.scale_c[k1 + A * k2];
+                    t.gpos_s[k1 * B + k2] = t.scale_s[k1 + A * k2];
+                }
         }
     } else {
         // first columns of e^{tau/2 C} (circulant, gamma) and e^{tau S} (skew-circulant, sigma):

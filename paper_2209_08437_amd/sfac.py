@@ -34,7 +34,7 @@ class SfacError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32 * 3), ("use_graph", ctypes.c_int32),
                 ("graph_chunk", ctypes.c_int32), ("elems_log2", ctypes.c_int32 * 3),
-                ("lines_per_block", ctypes.c_int32 * 3)]
+                ("lines_per_block", ctypes.c_int32 * 3), ("kernel", ctypes.c_int32 * 3)]
 
 
 class InstanceDesc(ctypes.Structure):
@@ -161,7 +161,7 @@ class Plan:
     sfac_options in include/sfac.h and autotune.py)."""
 
     def __init__(self, ns, alphas, eps, tau, hs, dtype="f64", stream=None, method=None,
-                 use_graph=True, graph_chunk=32, elems_log2=None, lines_per_block=None):
+                 use_graph=True, graph_chunk=32, elems_log2=None, lines_per_block=None, kernel=None):
         L = lib()
         self.dims = len(ns)
         if not (len(alphas) == len(hs) == self.dims):
@@ -178,6 +178,8 @@ class Plan:
         for a in range(min(3, self.dims)):
             if elems_log2 is not None:
                 opt.elems_log2[a] = int(elems_log2[a] if isinstance(elems_log2, (list, tuple)) else elems_log2)
+            if kernel is not None:
+                opt.kernel[a] = int(kernel[a] if isinstance(kernel, (list, tuple)) else kernel)
             if lines_per_block is not None:
                 opt.lines_per_block[a] = int(lines_per_block[a] if isinstance(lines_per_block, (list, tuple))
                                              else lines_per_block)

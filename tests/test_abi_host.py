@@ -63,6 +63,19 @@ def test_unsupported_sizes(sfac_lib):
     st, h, msg = _create(2, [127, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)   # 127 is prime
     assert st == sfac.EUNSUPPORTED and "prime factor" in msg
     opt = sfac.Options()
+    opt.kernel[0] = 2                                                                # 64 is no A B pair
+    st, h, msg = _create(2, [64, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EUNSUPPORTED and "register-resident" in msg
+    opt = sfac.Options()
+    opt.kernel[1] = 3
+    st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EINVAL and "kernel" in msg
+    opt = sfac.Options()
+    opt.method[0] = sfac.METHOD_EMBED
+    opt.kernel[0] = 1
+    st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EINVAL and "embedded" in msg
+    opt = sfac.Options()
     opt.graph_chunk = 5000
     st, h, msg = _create(2, [8, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
     assert st == sfac.EINVAL and "graph_chunk" in msg

@@ -137,6 +137,35 @@ def test_embed_schedules_fp64(sfac_lib, ns, le, lpb):
     assert rel_err(u.cpu().numpy(), ref) <= FP64_TOL
 
 
+@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("lpb", [0, 1, 5])
+@pytest.mark.parametrize("ns", [(63, 30), (255, 11), (15, 35, 63), (99, 143)], ids=lambda s: "x".join(map(str, s)))
+def test_diag_kernels_fp64(sfac_lib, ns, kernel, lpb):
+    """The diagonal method (length-N transforms, psi twiddles) in the generic kernel (1) and in
+    the register-resident two-step kernel (2, N = A B); axes it cannot take use the embedded one."""
+    from paper_2209_08437_amd import autotune, sfac
+    torch = _torch()
+    rng = np.random.default_rng(sum(ns) + kernel)
+    alphas = tuple(float(a) for a in rng.uniform(1.05, 1.95, len(ns)))
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=sum(ns))
+    ref = O.two_level_solve(u0, ns, alphas, 0.15, hs, 0.01, 3)
+    ok2 = [any(a * b == n for a, b in autotune.DIAG2_PAIRS) for n in ns]
+    meth = ["diag" if (ok2[i] or kernel == 1) else "embed" for i in range(len(ns))]
+    kern = [kernel if meth[i] == "diag" else 0 for i in range(len(ns))]
+    _say(f"case diag {ns} kernel {kern} lines/block {lpb}")
+    u = torch.tensor(u0, device="cuda")
+    try:
+        p = sfac.Plan(ns, alphas, 0.15, 0.01, hs, "f64", method=meth, kernel=kern, lines_per_block=lpb)
+    except sfac.SfacError as e:
+        assert kernel == 1 and e.status == sfac.EUNSUPPORTED    # a prime factor above 31
+        return
+    with p:
+        p.step(u, 3)
+    torch.cuda.synchronize()
+    assert rel_err(u.cpu().numpy(), ref) <= FP64_TOL
+
+
 def test_autotuned_schedule_matches_oracle(sfac_lib, tmp_path, monkeypatch):
     monkeypatch.setenv("SFAC_TUNE_CACHE", str(tmp_path / "tune.json"))
     from paper_2209_08437_amd import autotune, sfac
@@ -146,7 +175,7 @@ def test_autotuned_schedule_matches_oracle(sfac_lib, tmp_path, monkeypatch):
     u0 = W.uniform_field((64, 127), -0.9, 0.9, seed=4)
     _say("case autotune 127x64")
     best = autotune.tune(ns, (1.4, 1.6), 0.1, 0.01, hs, "f64", reps=3)
-    sched = {k: best[k] for k in ("method", "elems_log2", "lines_per_block")}
+    sched = {k: best[k] for k in ("method", "elems_log2", "lines_per_block", "kernel")}
     u = torch.tensor(u0, device="cuda")
     with sfac.Plan(ns, (1.4, 1.6), 0.1, 0.01, hs, "f64", **sched) as p:
         p.step(u, 4)
