@@ -7,9 +7,24 @@ FP64) and the default K = 1000 timed steps is its full run. The state is residen
 the timed region starts; the timed region is one sfac_step call of K steps (HIP graph replays)
 bracketed by device synchronizations.
 
+Each axis pass runs the schedule (method, kernel, elements per thread, lines per block) that
+the autotuner picked on an MI355X for this shape, read from the table that ships with the
+package (`--tune-cache none` tunes afresh on the device at hand).
+
 Besides the headline value the JSON line carries: the FP32 rate of the same workload, the
-roofline of the axis-pass kernel (algorithmic bytes per launch over its mean duration, timed
-with HIP events on the plan's stream), and the CPU oracle timed on a bounded sample.
+roofline of the dominant axis-pass kernel, and the CPU oracle timed on a bounded sample.
+
+Roofline. Each axis pass reads and writes the state once (2 x points x element bytes) and does
+the conventional FFT count of flops on every point: 6 transforms of 5 L log2 L flops per complex
+line of 2 real lines, i.e. 15 log2 N flops per point, plus 9 for the three spectrum scalings and
+the two psi twiddles, plus the nonlinear half-steps (about 20 flops per point per step, split
+over the d passes). At these intensities (about 14 flop/byte in FP64, 28 in FP32) the pass is
+bound by vector arithmetic, not by HBM (the MI355X ridge is 78.6 TFLOP/s / 8 TB/s = 9.8
+flop/byte), so the roofline reported is the arithmetic one: algorithmic flops per launch over
+the kernel's mean launch duration (HIP events on the plan's stream), against the vector peak of
+the dtype. The HBM figure of the same launch is reported beside it, and `traffic` is the HBM
+bytes per launch measured with hardware counters (rocprofv3 FETCH_SIZE and WRITE_SIZE,
+calibrated on a plain copy kernel) when the committed record matches the current kernel sources.
 """
 import argparse
 import json
@@ -23,6 +38,8 @@ if ROOT not in sys.path:
 
 METRIC = "grid-point-steps/s (N^d·steps/s) FP64 vs FP32 + HBM GB/s; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}     # MI355X published vector peaks
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def log(msg):
@@ -40,7 +57,13 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True):
+def pass_flops(inst, axis):
+    """Algorithmic flops of one pass along `axis` (0-based) over the whole grid."""
+    import math
+    return inst.points * (15.0 * math.log2(inst.ns[axis]) + 9.0 + 20.0 / inst.dims)
+
+
+def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None):
     import numpy as np
     import torch
     from paper_2209_08437_amd import autotune, sfac
@@ -49,7 +72,13 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True):
     u = u0.clone()
     sched = {}
     if tune:
-        best = autotune.tune(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, use_cache=False)
+        if tune_cache == "none":
+            best = autotune.tune(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, use_cache=False)
+        elif tune_cache:
+            best = autotune.tune(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, path=tune_cache)
+        else:
+            best = autotune.tune(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype,
+                                 path=autotune.PACKAGED, save=False)
         sched = {k: best[k] for k in ("method", "elems_log2", "lines_per_block", "kernel")}
         log(f"[bench] {dtype}: tuned schedule {sched} (pass us {[round(x * 1e3, 1) for x in best['ms']]})")
     plan = sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, **sched)
@@ -73,13 +102,17 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True):
     flags, vmax = plan.flags()
     log(f"[bench] {dtype}: {steps} steps in {wall * 1e3:.2f} ms wall ({gpu_ms:.2f} ms events), "
         f"max|u| {vmax:.6f}, flags {flags}")
-    # per-pass kernel durations (HIP events on the plan's stream around each launch)
+    # per-pass kernel durations: HIP events on the plan's stream around each launch give the
+    # passes' shares; an event pair per launch adds a few microseconds to each, so the timed
+    # region's step time (graph replays, events only at its ends) is split by those shares
     uu = u0.clone()
-    pass_ms = plan.time_passes(uu, pass_reps)
+    pass_ev = plan.time_passes(uu, pass_reps)
     torch.cuda.synchronize()
+    step_ms = gpu_ms / steps
+    pass_ms = [step_ms * t / sum(pass_ev) for t in pass_ev]
     result = {
         "wall_s": wall, "gpu_ms": gpu_ms, "flags": flags, "max_abs": vmax,
-        "pass_ms": pass_ms, "methods": methods, "state": u.double().cpu().numpy(), "schedule": sched,
+        "pass_ms": pass_ms, "pass_ms_events": pass_ev, "methods": methods, "state": u.double().cpu().numpy(), "schedule": sched,
     }
     plan.close()
     return result
@@ -209,13 +242,17 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="default schedules instead of autotuned ones")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: tune only shapes missing from it and add them (default: "
+                         "the schedules measured on an MI355X that ship with the package, read only; "
+                         "'none': tune every axis afresh)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--serve-count", type=int, default=48)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--tick-steps", type=int, default=50)
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only copy a buffer of the workload's state size 20 times (a plain copy "
-                         "kernel of known traffic, to calibrate hardware byte counters)")
+                    help="only copy a 512 MiB buffer 20 times (a plain copy kernel of known traffic, "
+                         "larger than every cache level, to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -236,28 +273,40 @@ def main():
     inst, desc = workload(args.workload)
     steps = args.steps if args.steps is not None else inst.steps
     if args.copy_probe:
-        tdt = torch.float64 if args.dtype == "f64" else torch.float32
-        a = torch.tensor(inst.u0, dtype=tdt, device="cuda")
+        a = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         for _ in range(20):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read_per_copy": a.numel() * a.element_size(),
-                          "copy_probe_bytes_written_per_copy": b.numel() * b.element_size(), "copies": 20}))
+        print(json.dumps({"copy_probe_bytes_per_copy": a.numel() * a.element_size(), "copies": 20}))
         return
     esize = 8 if args.dtype == "f64" else 4
     pts = inst.points
-    main_r = gpu_rate(inst, args.dtype, steps, args.warmup, args.pass_reps, tune=not args.no_tune)
+    main_r = gpu_rate(inst, args.dtype, steps, args.warmup, args.pass_reps, tune=not args.no_tune,
+                      tune_cache=args.tune_cache)
     value = pts * steps / main_r["wall_s"]
     # roofline of the dominant kernel: the axis pass with the largest mean duration
     pass_ms = main_r["pass_ms"]
     a_dom = max(range(len(pass_ms)), key=lambda a: pass_ms[a])
+    flops_per_launch = pass_flops(inst, a_dom)
+    tflops = flops_per_launch / (pass_ms[a_dom] * 1e-3) / 1e12
+    peak = VALU_PEAK_TFLOPS[args.dtype]
     bytes_per_launch = 2 * pts * esize           # one read and one write of the state
-    achieved = bytes_per_launch / (pass_ms[a_dom] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"axis_pass_single<{'double' if esize == 8 else 'float'}> axis {a_dom + 1}",
-            "pass_ms": [round(x, 5) for x in pass_ms], "bytes_per_launch": bytes_per_launch}
+    gbps = bytes_per_launch / (pass_ms[a_dom] * 1e-3) / 1e9
+    from paper_2209_08437_amd import profiling
+    rec = profiling.load_traffic(TRAFFIC_RECORD, args.workload, args.dtype, main_r["schedule"] or None)
+    traffic = rec["per_axis"][a_dom]["bytes"] if rec else None
+    meth, length = main_r["methods"][a_dom]
+    roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(tflops / peak, 4), "traffic": traffic,
+            "kernel": f"{meth} axis pass ({'double' if esize == 8 else 'float'}, transform length {length}), "
+                      f"axis {a_dom + 1}",
+            "flops_per_launch": round(flops_per_launch), "pass_ms": [round(x, 5) for x in pass_ms],
+            "pass_ms_events": [round(x, 5) for x in main_r["pass_ms_events"]],
+            "hbm": {"achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbps / HBM_PEAK_GBS, 4), "bytes_per_launch": bytes_per_launch},
+            "traffic_record": (f"profiles/traffic.json ({rec['profile']})" if rec else
+                               "none for the current kernel sources")}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "grid-point-steps/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup,
@@ -269,14 +318,15 @@ def main():
         "roofline": roof,
     }
     if not args.no_fp32 and args.dtype == "f64":
-        r32 = gpu_rate(inst, "f32", steps, args.warmup, args.pass_reps, tune=not args.no_tune)
+        r32 = gpu_rate(inst, "f32", steps, args.warmup, args.pass_reps, tune=not args.no_tune,
+                       tune_cache=args.tune_cache)
         import numpy as np
         ref = main_r["state"]
         out["fp32"] = {"value": round(pts * steps / r32["wall_s"], 1), "unit": "grid-point-steps/s",
                        "ms_per_step": round(r32["wall_s"] * 1e3 / steps, 5),
                        "rel_err_vs_fp64_gpu": float(np.abs(r32["state"] - ref).max() / np.abs(ref).max()),
                        "max_abs": r32["max_abs"], "flags": r32["flags"],
-                       "pass_ms": [round(x, 5) for x in r32["pass_ms"]]}
+                       "pass_ms": [round(x, 5) for x in r32["pass_ms"]], "schedule": r32["schedule"]}
     out["max_abs"] = main_r["max_abs"]
     out["flags"] = main_r["flags"]
     if not args.no_cpu:

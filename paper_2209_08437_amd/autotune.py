@@ -19,6 +19,10 @@ import os
 import numpy as np
 
 
+# schedules measured on an MI355X for the benchmark shapes (written by this tuner, read only)
+PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
+
+
 def cache_path():
     return os.environ.get("SFAC_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "sfac_autotune.json"))
 
@@ -71,13 +75,14 @@ def candidates(n):
     return out
 
 
-def tune(ns, alphas, eps, tau, hs, dtype="f64", reps=10, use_cache=True, verbose=False):
+def tune(ns, alphas, eps, tau, hs, dtype="f64", reps=10, use_cache=True, verbose=False, path=None, save=True):
     """Best schedule per axis for this shape: returns dict(method=[...], elems_log2=[...],
     lines_per_block=[...], kernel=[...], ms=[...]) ready to pass to sfac.Plan as keyword arguments
-    (after dropping 'ms')."""
+    (after dropping 'ms'). `path` names the cache file (default: cache_path()); with save=False
+    shapes missing from it are tuned but the file is left as it is."""
     import torch
     from . import sfac
-    path = cache_path()
+    path = path or cache_path()
     cache = _load_cache(path) if use_cache else {}
     dims = len(ns)
     best = {"method": [None] * dims, "elems_log2": [0] * dims, "lines_per_block": [0] * dims,
@@ -120,6 +125,6 @@ def tune(ns, alphas, eps, tau, hs, dtype="f64", reps=10, use_cache=True, verbose
         best["lines_per_block"][a] = lpb
         best["kernel"][a] = kern
         best["ms"][a] = ms
-    if use_cache:
+    if use_cache and save:
         _save_cache(path, cache)
     return best

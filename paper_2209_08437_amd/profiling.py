@@ -1,0 +1,245 @@
+"""Helpers for the committed rocprofv3 summaries (text under profiles/).
+
+* `source_hash()` fingerprints the kernel sources, so that a counter-derived HBM traffic figure
+  is used only while the kernels it was measured on are unchanged.
+* `stats_markdown()` turns a `--kernel-trace --stats` CSV into a short markdown table.
+* `traffic_from_pmc()` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of a workload and
+  the same two counters read on a plain copy kernel of known size into calibrated HBM bytes
+  per launch of each axis-pass kernel.
+
+The axis of a pass-kernel dispatch is recovered from the dispatch order: every step launches
+the passes of axes 1..d in order, and the profiled command launches nothing else with the
+pass kernels' names.
+"""
+import csv
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+PASS_KERNEL_TAGS = ("_pass_single", "_pass_multi")
+
+
+KERNEL_SOURCES = ("sfac_kernels.hip", "sfac_kernels.hpp", "sfac_fft.hpp", "sfac_embed.hpp", "sfac_diag2.hpp")
+
+
+def source_hash():
+    """SHA-256 over the names and bytes of the device-code sources, first 16 hex digits."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def short_name(name):
+    """Kernel name without the namespaces and the argument list."""
+    s = name.replace("(anonymous namespace)::", "").split("(")[0]
+    for p in ("void ", "sfac::"):
+        s = s.replace(p, "")
+    return s.strip()
+
+
+def trace_axis_means(trace_csv, dims):
+    """Mean duration (us) per (kernel, axis) of the pass-kernel dispatches in a kernel trace, one
+    list per element type; the axis is the dispatch's place in the d-periodic launch order."""
+    rows = sorted(_rows(trace_csv), key=lambda r: int(r["Start_Timestamp"]))
+    seq = {}
+    for r in rows:
+        k = r["Kernel_Name"]
+        if not any(t in k for t in PASS_KERNEL_TAGS):
+            continue
+        et = "double" if "<double" in k else "float"
+        seq.setdefault(et, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), short_name(k)))
+    out = {}
+    for et, v in seq.items():
+        res = []
+        for a in range(dims):
+            xs = [v[i][0] for i in range(a, len(v), dims)]
+            res.append({"axis": a + 1, "kernel": v[a][1], "dispatches": len(xs),
+                        "mean_us": sum(xs) / len(xs) / 1e3, "min_us": min(xs) / 1e3, "max_us": max(xs) / 1e3})
+        out[et] = res
+    return out
+
+
+def stats_markdown(stats_csv, top=8):
+    rows = _rows(stats_csv)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | total ms | average us | min us | max us | share % |",
+           "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def _pass_counters(pmc_csv, counter, dims):
+    """Mean counter value (KiB) per axis over the pass-kernel dispatches of one --pmc run."""
+    rows = [r for r in _rows(pmc_csv) if r["Counter_Name"] == counter]
+    per_dispatch = {}
+    names = {}
+    for r in rows:
+        if not any(t in r["Kernel_Name"] for t in PASS_KERNEL_TAGS):
+            continue
+        d = int(r["Dispatch_Id"])
+        per_dispatch[d] = per_dispatch.get(d, 0.0) + float(r["Counter_Value"])
+        names[d] = short_name(r["Kernel_Name"])
+    order = sorted(per_dispatch)
+    sums = [0.0] * dims
+    counts = [0] * dims
+    kern = [None] * dims
+    for i, d in enumerate(order):
+        a = i % dims
+        sums[a] += per_dispatch[d]
+        counts[a] += 1
+        kern[a] = names[d]
+    return [s / c if c else None for s, c in zip(sums, counts)], counts, kern
+
+
+def _copy_counter(pmc_csv, counter):
+    """Mean counter value (KiB) over the copy kernel's dispatches of a --copy-probe run."""
+    vals = {}
+    for r in _rows(pmc_csv):
+        if r["Counter_Name"] != counter or any(t in r["Kernel_Name"] for t in PASS_KERNEL_TAGS):
+            continue
+        d = int(r["Dispatch_Id"])
+        vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
+    # the probe's copies are its largest dispatches; take those
+    big = sorted(vals.values())[-20:]
+    return sum(big) / len(big)
+
+
+def traffic_from_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, dims):
+    """Calibrated HBM bytes per pass launch: counter KiB x 1024 x (copy bytes / copy counter bytes)."""
+    f, nf, kf = _pass_counters(fetch_csv, "FETCH_SIZE", dims)
+    w, nw, _ = _pass_counters(write_csv, "WRITE_SIZE", dims)
+    cf = _copy_counter(copy_fetch_csv, "FETCH_SIZE") * 1024.0
+    cw = _copy_counter(copy_write_csv, "WRITE_SIZE") * 1024.0
+    scale_f = copy_bytes / cf
+    scale_w = copy_bytes / cw
+    per_axis = []
+    for a in range(dims):
+        fb = f[a] * 1024.0 * scale_f
+        wb = w[a] * 1024.0 * scale_w
+        per_axis.append({"axis": a + 1, "kernel": kf[a], "dispatches": nf[a],
+                         "fetch_kib_raw": round(f[a], 1), "write_kib_raw": round(w[a], 1),
+                         "fetch_bytes": round(fb), "write_bytes": round(wb), "bytes": round(fb + wb)})
+    return {"copy_bytes": copy_bytes, "copy_fetch_kib_raw": round(cf / 1024.0, 1),
+            "copy_write_kib_raw": round(cw / 1024.0, 1), "fetch_scale": scale_f, "write_scale": scale_w,
+            "per_axis": per_axis}
+
+
+def load_traffic(path, workload, dtype, schedule=None):
+    """The committed traffic record of (workload, dtype), or None if absent, if the kernel
+    sources changed since it was measured, or if it was measured with another schedule."""
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = data.get(f"{workload}:{dtype}")
+    if not rec or rec.get("source_hash") != source_hash():
+        return None
+    if schedule is not None and rec.get("schedule") != schedule:
+        return None
+    return rec
+
+
+# the commands that make the profiles of one workload W (run from /tmp; R is the repository root,
+# O the output directory; DT is f64 and f32 in turn)
+COMMANDS = """\
+python3 $R/bench.py --workload $W --no-cpu --tune-cache $O/tune.json        # tunes once, fills the cache
+rocprofv3 --kernel-trace --stats --output-format csv -d $O/trace_$W -o run -- python3 $R/bench.py --workload $W --no-cpu --tune-cache $O/tune.json
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --steps 20 --warmup 2 --pass-reps 2 --tune-cache $O/tune.json
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --steps 20 --warmup 2 --pass-reps 2 --tune-cache $O/tune.json
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/copy_FETCH_SIZE -o run -- python3 $R/bench.py --copy-probe
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/copy_WRITE_SIZE -o run -- python3 $R/bench.py --copy-probe"""
+
+
+def _schedules(err_log):
+    """Tuned schedule per dtype from the '[bench] <dtype>: tuned schedule {...}' lines of bench.py."""
+    import ast
+    out = {}
+    try:
+        for line in open(err_log):
+            if "tuned schedule" in line:
+                dt = line.split("]")[1].split(":")[0].strip()
+                out[dt] = ast.literal_eval(line[line.index("{"):line.index("}") + 1])
+    except OSError:
+        pass
+    return out
+
+
+def _main():
+    """Write the markdown summary of one workload's profiles and update the traffic record."""
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dir", required=True, help="directory holding the rocprofv3 outputs")
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--dims", type=int, required=True)
+    ap.add_argument("--out", required=True, help="markdown summary to write")
+    ap.add_argument("--traffic", required=True, help="JSON traffic record to update")
+    a = ap.parse_args()
+    d, w = a.dir, a.workload
+    bench = json.load(open(os.path.join(d, f"bench_{w}.json")))
+    lines = [f"# Axis-pass kernels, workload {w}", ""]
+    lines += ["Commands (run from /tmp on one MI355X; `$R` is the repository root, `$O` the output "
+              "directory, `$DT` f64 and f32 in turn):", "", "```"]
+    lines += [COMMANDS.replace("$W", w), "```", ""]
+    lines += ["## Kernel trace (`--kernel-trace --stats`)", "",
+              stats_markdown(os.path.join(d, f"trace_{w}", "run_kernel_stats.csv")), ""]
+    means = trace_axis_means(os.path.join(d, f"trace_{w}", "run_kernel_trace.csv"), a.dims)
+    lines += ["Per axis (dispatch order; graph replays of warm-up and timed steps plus the per-pass timing):", "",
+              "| element | axis | kernel | dispatches | mean us | min us | max us |", "|---|---|---|---|---|---|---|"]
+    for et, res in means.items():
+        for r in res:
+            lines.append(f"| {et} | {r['axis']} | `{r['kernel']}` | {r['dispatches']} | {r['mean_us']:.2f} | "
+                         f"{r['min_us']:.2f} | {r['max_us']:.2f} |")
+    lines += ["", f"bench.py in the same session (no profiler): FP64 {bench['ms_per_step'] * 1e3:.2f} us/step, "
+              f"pass us {[round(x * 1e3, 2) for x in bench['roofline']['pass_ms']]}; FP32 "
+              f"{bench['fp32']['ms_per_step'] * 1e3:.2f} us/step, pass us "
+              f"{[round(x * 1e3, 2) for x in bench['fp32']['pass_ms']]}.", ""]
+    scheds = _schedules(os.path.join(d, f"bench_{w}.err"))
+    rec_all = {}
+    try:
+        rec_all = json.load(open(a.traffic))
+    except (OSError, ValueError):
+        pass
+    lines += ["## HBM traffic (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`)", "",
+              "Counters in KiB per dispatch, calibrated on a plain copy of 512 MiB (bench.py --copy-probe): "
+              "bytes = KiB x 1024 x (copy bytes / copy counter bytes).", "",
+              "| dtype | axis | kernel | FETCH KiB | WRITE KiB | calibrated bytes | algorithmic bytes | ratio |",
+              "|---|---|---|---|---|---|---|---|"]
+    for dt, es in (("f64", 8), ("f32", 4)):
+        t = traffic_from_pmc(os.path.join(d, f"FETCH_SIZE_{w}_{dt}", "run_counter_collection.csv"),
+                             os.path.join(d, f"WRITE_SIZE_{w}_{dt}", "run_counter_collection.csv"),
+                             os.path.join(d, "copy_FETCH_SIZE", "run_counter_collection.csv"),
+                             os.path.join(d, "copy_WRITE_SIZE", "run_counter_collection.csv"), 512 << 20, a.dims)
+        pts = 1
+        for n in bench["config"]["grid"]:
+            pts *= n
+        alg = 2 * pts * es
+        for r in t["per_axis"]:
+            lines.append(f"| {dt} | {r['axis']} | `{r['kernel']}` | {r['fetch_kib_raw']} | {r['write_kib_raw']} | "
+                         f"{r['bytes']} | {alg} | {r['bytes'] / alg:.3f} |")
+        rec_all[f"{w}:{dt}"] = {"source_hash": source_hash(), "profile": os.path.basename(a.out),
+                                "algorithmic_bytes": alg, "schedule": scheds.get(dt), **t}
+    lines += ["", f"Copy calibration: FETCH_SIZE read {t['copy_fetch_kib_raw']} KiB and WRITE_SIZE "
+              f"{t['copy_write_kib_raw']} KiB per 512 MiB copy (scales {t['fetch_scale']:.4f}, "
+              f"{t['write_scale']:.4f}).", f"Device-code source hash: `{source_hash()}`.", ""]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines))
+    with open(a.traffic, "w") as f:
+        json.dump(rec_all, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    _main()
