@@ -67,8 +67,9 @@ typedef struct {
     int32_t method[3];          /* sfac_method per axis (axis 1 first); default SFAC_METHOD_AUTO */
     int32_t use_graph;          /* 1 (default): replay steps from captured HIP graphs; 0: plain launches */
     int32_t graph_chunk;        /* steps captured per graph replay (default 32, 1..1024) */
-    int32_t elems_log2[3];      /* embedded method: log2 of the elements each thread holds, 3 or 4
-                                   (0 = automatic); fewer elements means more threads per line */
+    int32_t elems_log2[3];      /* embedded method: log2 of the elements each thread holds, 2, 3 or 4
+                                   (0 = automatic; 2 only for transform lengths 64..2048); fewer
+                                   elements means more threads per line */
     int32_t lines_per_block[3]; /* pairs of real lines per thread block (0 = automatic) */
     int32_t kernel[3];          /* diagonal method: 0 automatic, 1 the generic kernel (every N whose
                                    prime factors are <= 31), 2 the register-resident two-step kernel

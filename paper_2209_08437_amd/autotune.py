@@ -1,9 +1,10 @@
 """Autotuner for the axis-pass schedules.
 
 For one problem shape it times candidate schedules of every axis pass on the device and keeps
-the fastest: the method (embedded or diagonal, where both apply), the number of elements each
-thread holds in the embedded kernel (8 or 16: more threads per line and one more radix pass, or
-fewer threads and one pass less) and the number of line pairs per thread block. Timing uses
+the fastest: the method (embedded or diagonal, where both apply), the diagonal kernel (generic
+or register-resident two-step), the number of elements each thread holds in the embedded kernel
+(4, 8 or 16: more threads per line and more radix passes, or fewer threads and fewer passes) and
+the number of line pairs per thread block. Timing uses
 sfac_plan_time_passes (HIP events around each pass on the plan's stream), so only the device
 work is measured. Results are cached in a JSON file keyed by (axis length, lines in the pass,
 stride class, dtype), so a shape is tuned once per machine; `SFAC_TUNE_CACHE` names the file
@@ -64,6 +65,12 @@ def candidates(n):
     out = []
     for le, lpb in itertools.product((3, 4), (0, 1, 2, 4)):
         out.append(("embed", le, lpb, 0))
+    m = 2
+    while m < 2 * n - 1:
+        m *= 2
+    if 64 <= m <= 2048:
+        for lpb in (0, 1, 2):
+            out.append(("embed", 2, lpb, 0))
     if any(a * b == n for a, b in DIAG2_PAIRS):
         for lpb in (0, 1, 2, 4):
             out.append(("diag", 0, lpb, 2))

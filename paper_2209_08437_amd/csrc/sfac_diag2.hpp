@@ -66,6 +66,7 @@ struct Diag2Line {
         if (t < A) {
 #pragma unroll
             for (int b = 0; b < B; ++b) a[b] = line[t * B + b];
+            __builtin_amdgcn_sched_barrier(0);   // all reads in flight before the arithmetic
             dft<B, -1>(a);
         }
     }
@@ -82,6 +83,7 @@ struct Diag2Line {
         if (t < B) {
 #pragma unroll
             for (int k = 0; k < A; ++k) a[k] = line[k * B + t];
+            __builtin_amdgcn_sched_barrier(0);   // all reads in flight before the arithmetic
 #pragma unroll
             for (int k = 1; k < A; ++k) a[k] = cmulc(a[k], tw[k]);
             dft<A, +1>(a);

@@ -1,8 +1,8 @@
 // Register-resident axis pass for the embedded method (power-of-two transform length M).
 //
 // Each complex line (two real lines packed as real and imaginary parts) is held by T = M/E
-// threads, E = min(2^LE, M) elements per thread (LE = 3 or 4: more threads per line and one more
-// radix pass, or fewer threads and more registers; the plan picks per length and problem size). A length-M transform is an in-place
+// threads, E = min(2^LE, M) elements per thread (LE = 2, 3 or 4: more threads per line and more
+// radix passes, or fewer threads and more registers; the plan picks per length and problem size). A length-M transform is an in-place
 // decimation-in-frequency Cooley-Tukey pass sequence with radices R_0..R_{NST-1} (<= 16); the
 // inverse runs the conjugate-transposed passes in reverse order (decimation in time), so the
 // forward output (digit-reversed positions) is consumed where it lies and the inverse output
@@ -54,7 +54,36 @@ struct EmbedGeom {
         for (int q = 0; q < s; ++q) acc += bits(q);
         return acc;
     }
+    // log2 of the butterflies each thread holds at pass s
+    static constexpr int log2I(int s) { return LOG2E - bits(s); }
+    // log2 of the wavefronts (64 threads) one line spans; 0 when a line fits in one wavefront
+    static constexpr int LOG2W = LOG2T > 6 ? LOG2T - 6 : 0;
+    // first pass whose butterflies leave the top LOG2W position bits alone (those bits are
+    // butterfly bits of earlier passes only)
+    static constexpr int SLOC = [] {
+        int s = 1;
+        while (s < NST && log2Pre(s) < LOG2W) ++s;
+        return s;
+    }();
+    // the exchange between passes a and b stays inside one wavefront
+    static constexpr bool local(int a, int b) { return LOG2W == 0 || (a >= SLOC && b >= SLOC); }
+    // threads of one line (the block holds whole lines)
+    static constexpr int max_block = T > 256 ? T : 256;
 };
+
+// Butterfly index of slot i of thread t at pass S. Before pass SLOC it is t + i T. From pass
+// SLOC on the wavefront bits of t move to the top, above the slot bits, so that the top position
+// bits name the wavefront; they are butterfly bits of passes before SLOC only, so the exchanges
+// between passes >= SLOC stay inside one wavefront and need no workgroup barrier.
+template <int LOG2M, int LE, int S>
+__device__ __forceinline__ int embed_butterfly(int t, int i) {
+    using G = EmbedGeom<LOG2M, LE>;
+    if constexpr (S < G::SLOC || G::LOG2W == 0) {
+        return t + (i << G::LOG2T);
+    } else {
+        return (t & 63) | (i << 6) | ((t >> 6) << (6 + G::log2I(S)));
+    }
+}
 
 // Position (in the in-place layout) of element k of butterfly slot i of thread t at stage s.
 template <int LOG2M, int LE, int S>
@@ -62,10 +91,18 @@ __device__ __forceinline__ int embed_pos(int t, int i, int k) {
     using G = EmbedGeom<LOG2M, LE>;
     constexpr int ls = G::log2S(S);
     constexpr int lb = ls + G::bits(S);
-    const int b = t + (i << G::LOG2T);
+    const int b = embed_butterfly<LOG2M, LE, S>(t, i);
     const int blk = b >> ls;
     const int o = b & ((1 << ls) - 1);
     return (blk << lb) + o + (k << ls);
+}
+
+// Orders the LDS accesses of one wavefront: its lanes execute in lockstep and its LDS operations
+// complete in issue order, so only the compiler must be kept from moving them across.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Bank-conflict-avoiding permutation of positions inside one line: XOR the low bits of the
@@ -87,7 +124,7 @@ template <int LOG2M, int LE, int S>
 __device__ __forceinline__ int embed_tw_index(int t, int i, int k) {
     using G = EmbedGeom<LOG2M, LE>;
     constexpr int ls = G::log2S(S);
-    const int b = t + (i << G::LOG2T);
+    const int b = embed_butterfly<LOG2M, LE, S>(t, i);
     const int o = b & ((1 << ls) - 1);
     return (o * k) << G::log2Pre(S);
 }
@@ -152,20 +189,34 @@ struct EmbedLine {
         }
     }
 
-    // move the line's elements from the layout of pass SA to the layout of pass SB through LDS
+    // move the line's elements from the layout of pass SA to the layout of pass SB through LDS.
+    // Between passes >= SLOC (or when a line fits in one wavefront) every wavefront writes and
+    // then reads only positions whose top bits name it, so a wavefront-level ordering suffices;
+    // the other exchanges cross wavefronts and take a workgroup barrier before the writes (no
+    // wavefront may still be reading the positions) and between writes and reads.
     template <int SA, int SB>
     __device__ __forceinline__ void exchange(cplx<T>* __restrict__ line, int t) {
         constexpr int RA = G::R(SA), RB = G::R(SB);
-        __syncthreads();
+        constexpr bool local = G::local(SA, SB);
+        if constexpr (local)
+            wave_sync();
+        else
+            __syncthreads();
 #pragma unroll
         for (int i = 0; i < G::E / RA; ++i)
 #pragma unroll
             for (int k = 0; k < RA; ++k) line[embed_swz<T, LOG2M>(embed_pos<LOG2M, LE, SA>(t, i, k))] = a[i * RA + k];
-        __syncthreads();
+        if constexpr (local)
+            wave_sync();
+        else
+            __syncthreads();
 #pragma unroll
         for (int i = 0; i < G::E / RB; ++i)
 #pragma unroll
             for (int k = 0; k < RB; ++k) a[i * RB + k] = line[embed_swz<T, LOG2M>(embed_pos<LOG2M, LE, SB>(t, i, k))];
+        // issue all reads of the exchange back to back: one LDS latency per exchange instead of
+        // one per element (the scheduler otherwise interleaves them with the arithmetic)
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     template <int S>

@@ -396,8 +396,18 @@ __global__ void __launch_bounds__(kBlockThreads) axis_pass_single(PassDesc<T> d)
     run_tile(d, tile, buf0, buf1);
 }
 
+// block size bound of an embedded-method kernel: 256 threads, or one line of 512 threads with
+// four elements each (then two blocks per CU, so that the compiler keeps to 128 registers and a
+// SIMD holds four wavefronts)
+constexpr int embed_max_block(int log2m, int le) {
+    return (1 << (log2m - embed_log2e(log2m, le))) > kBlockThreads ? (1 << (log2m - embed_log2e(log2m, le)))
+                                                                     : kBlockThreads;
+}
+#define SFAC_EMBED_BOUNDS(LOG2M, LE) \
+    __launch_bounds__(embed_max_block(LOG2M, LE), embed_max_block(LOG2M, LE) > kBlockThreads ? 2 : 1)
+
 template <typename T, int LOG2M, int LE>
-__global__ void __launch_bounds__(kBlockThreads) embed_pass_single(PassDesc<T> d) {
+__global__ void SFAC_EMBED_BOUNDS(LOG2M, LE) embed_pass_single(PassDesc<T> d) {
     extern __shared__ unsigned char smem_raw[];
     const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
     if (tile >= d.ntiles) return;
@@ -406,7 +416,7 @@ __global__ void __launch_bounds__(kBlockThreads) embed_pass_single(PassDesc<T> d
 
 // Several instances with the same transform length in one launch (batched form).
 template <typename T, int LOG2M, int LE>
-__global__ void __launch_bounds__(kBlockThreads) embed_pass_multi(const PassDesc<T>* __restrict__ descs,
+__global__ void SFAC_EMBED_BOUNDS(LOG2M, LE) embed_pass_multi(const PassDesc<T>* __restrict__ descs,
                                                                   const int* __restrict__ block_start,
                                                                   int ndesc) {
     extern __shared__ unsigned char smem_raw[];
@@ -483,6 +493,12 @@ const void* diag2_fn(int a, int b, bool multi) {
 // kernel of one (transform length, elements per thread); LE = 3 or 4
 template <typename T, int LOG2M>
 const void* embed_fn_le(int le, bool multi) {
+    if (le == 2) {
+        if constexpr (LOG2M >= 6 && LOG2M <= 11)
+            return multi ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, 2>)
+                         : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, 2>);
+        return nullptr;
+    }
     if (le == 3)
         return multi ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, 3>)
                      : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, 3>);
@@ -577,10 +593,11 @@ hipError_t allow_lds(size_t lds_bytes) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     for (int lg = 1; lg <= 12; ++lg)
-        for (int le = 3; le <= 4; ++le)
+        for (int le = 2; le <= 4; ++le)
             for (int multi = 0; multi < 2; ++multi) {
-                e = hipFuncSetAttribute(embed_fn<T>(lg, le, multi), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds_bytes);
+                const void* fn = embed_fn<T>(lg, le, multi);
+                if (!fn) continue;
+                e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
                 if (e != hipSuccess) return e;
             }
     for (int a = 3; a <= 17; ++a)

@@ -161,8 +161,8 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
         // when the pass would otherwise have too few waves to hide latency (under two per SIMD
         // of a 256-CU device); more (16) needs one radix pass less.
         int log2e = opt && opt->elems_log2[a] ? opt->elems_log2[a] : 0;
-        if (log2e != 0 && log2e != 3 && log2e != 4)
-            return fail(SFAC_EINVAL, "%saxis %d: elems_log2 = %d, expected 3 or 4", who, a + 1, log2e);
+        if (log2e != 0 && log2e != 2 && log2e != 3 && log2e != 4)
+            return fail(SFAC_EINVAL, "%saxis %d: elems_log2 = %d, expected 2, 3 or 4", who, a + 1, log2e);
         {
             long long inner0 = 1, outer0 = 1;
             for (int b = 0; b < a; ++b) inner0 *= n[b];
@@ -196,11 +196,15 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
             // fewer lines per block while that still leaves blocks for every CU
             int log2m = 0;
             while ((1 << log2m) < L) ++log2m;
+            if (in->ax[a].log2e == 2 && (log2m < 6 || log2m > 11))
+                return fail(SFAC_EUNSUPPORTED, "%saxis %d: elems_log2 = 2 needs a transform length of 64 to 2048, "
+                            "not %d", who, a + 1, L);
             const int E = 1 << sfac::embed_log2e(log2m, in->ax[a].log2e);
             const int T = L / E;
-            int lpb = sfac::kBlockThreads / T;
+            const int max_block = std::max(T, sfac::kBlockThreads);   // one line of 512 threads at E = 4
+            int lpb = max_block / T;
             while (lpb > 1 && (lines_total + lpb - 1) / lpb < 1024) lpb >>= 1;
-            if (opt && opt->lines_per_block[a] > 0) lpb = std::min(opt->lines_per_block[a], sfac::kBlockThreads / T);
+            if (opt && opt->lines_per_block[a] > 0) lpb = std::min(opt->lines_per_block[a], max_block / T);
             lpb = std::max(1, (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2)));
             in->ax[a].lpb = lpb;
             in->ax[a].threads = lpb * T;

@@ -67,6 +67,14 @@ def test_unsupported_sizes(sfac_lib):
     st, h, msg = _create(2, [64, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
     assert st == sfac.EUNSUPPORTED and "register-resident" in msg
     opt = sfac.Options()
+    opt.elems_log2[0] = 2                                                            # M = 32 < 64
+    st, h, msg = _create(2, [9, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EUNSUPPORTED and "elems_log2 = 2" in msg
+    opt = sfac.Options()
+    opt.elems_log2[0] = 5
+    st, h, msg = _create(2, [9, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EINVAL and "elems_log2" in msg
+    opt = sfac.Options()
     opt.kernel[1] = 3
     st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
     assert st == sfac.EINVAL and "kernel" in msg

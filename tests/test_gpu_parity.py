@@ -117,11 +117,21 @@ def test_shapes_fp64(sfac_lib, ns):
         assert flags == 0
 
 
-@pytest.mark.parametrize("le", [3, 4])
+def _embed_length(n):
+    m = 2
+    while m < 2 * n - 1:
+        m *= 2
+    return m
+
+
+@pytest.mark.parametrize("le", [2, 3, 4])
 @pytest.mark.parametrize("lpb", [0, 1, 3])
-@pytest.mark.parametrize("ns", [(100, 37), (1023, 9), (9, 16, 33)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("ns", [(100, 37), (1023, 9), (9, 16, 33), (700, 5)], ids=lambda s: "x".join(map(str, s)))
 def test_embed_schedules_fp64(sfac_lib, ns, le, lpb):
-    """Every schedule the autotuner may pick (elements per thread, line pairs per block)."""
+    """Every schedule the autotuner may pick (elements per thread, line pairs per block); four
+    elements per thread exist for transform lengths 64..2048 only (other axes keep the default)."""
+    if le == 2:
+        le = [2 if 64 <= _embed_length(n) <= 2048 else 0 for n in ns]
     rng = np.random.default_rng(len(ns) * 100 + ns[0])
     alphas = tuple(float(a) for a in rng.uniform(1.05, 1.95, len(ns)))
     hs = W.mesh_widths(ns)
