@@ -72,7 +72,7 @@ def candidates(n):
         for lpb in (0, 1, 2):
             out.append(("embed", 2, lpb, 0))
     if any(a * b == n for a, b in DIAG2_PAIRS):
-        for lpb in (0, 1, 2, 4):
+        for lpb in (0, 2, 5, 7, 10):
             out.append(("diag", 0, lpb, 2))
     try:
         sfac.axis_tables(n, 1.5, 0.1, 0.01, 0.1, "diag")

@@ -1,9 +1,12 @@
-// Register-resident axis pass for the diagonal method (Remark 1) when N = A * B with small A, B.
+// Register-resident axis pass for the diagonal method (Remark 1) when N = A * B with small
+// coprime A, B.
 //
-// A length-N transform is done in two steps: B DFTs of length A over x[b + B a] (one per
-// thread b), the twiddles e^{-2 pi i b k1 / N}, one LDS exchange, then A DFTs of length B (one per
-// thread k1) that leave X[k1 + A k2] in thread k1. The inverse runs the conjugate steps in
-// reverse order and returns x[b + B a] to thread b, exactly where the next forward transform
+// A length-N transform is done in two steps with the prime-factor (Good-Thomas) index maps, so
+// no twiddles sit between them. Thread b (b < B) holds x[(B a + A b) mod N] for a < A and does
+// one DFT of length A; after one LDS exchange thread k1 (k1 < A) holds the A-point results of
+// all b and does one DFT of length B, which leaves X[(B (B^-1 mod A) k1 + A (A^-1 mod B) k2) mod N]
+// in its registers k2. The inverse runs the conjugate steps in reverse order and returns every
+// element to the thread and register that loaded it, exactly where the next forward transform
 // reads it. Per factor: [psi multiply] forward transform, multiply by the eigenvalue factor,
 // inverse transform, [conj(psi) multiply]: two LDS exchanges per factor, no padding.
 // A line is held by P = max(A, B) threads; threads beyond A (or B) idle in the other step.
@@ -21,24 +24,20 @@ struct Diag2Geom {
     static constexpr int N = A * B;
     static constexpr int P = A > B ? A : B;   // threads per line
     static constexpr int E = P;               // registers per thread (max of the two step sizes)
+    // natural position of register k of thread t (t < B, k < A)
+    static __device__ __forceinline__ int pos(int t, int k) {
+        const int n = B * k + A * t;
+        return n < N ? n : n - N;
+    }
 };
 
 template <typename T, int A, int B>
 struct Diag2Line {
     using G = Diag2Geom<A, B>;
     cplx<T> a[G::E];
-    cplx<T> tw[A];   // e^{-2 pi i b k1 / N}, k1 < A, for this thread's b
 
-    // twpos[b * A + k1] = e^{-2 pi i b k1 / N}
-    __device__ __forceinline__ void load_twiddles(const cplx<T>* __restrict__ twpos, int t) {
-        if (t < B) {
-#pragma unroll
-            for (int k = 0; k < A; ++k) tw[k] = twpos[t * A + k];
-        }
-    }
-
-    // x <- psi . x (or conj(psi) . x) at this thread's natural positions b + B a;
-    // psipos[b * A + a] = psi_{b + B a}
+    // x <- psi . x (or conj(psi) . x) at this thread's natural positions;
+    // psipos[t A + k] = psi at position pos(t, k)
     template <bool CONJ>
     __device__ __forceinline__ void psi_mul(const cplx<T>* __restrict__ psipos, int t) {
         if (t < B) {
@@ -50,13 +49,9 @@ struct Diag2Line {
         }
     }
 
-    // forward: DFT_A in thread b, twiddle, exchange, DFT_B in thread k1
+    // forward: DFT_A in thread b, exchange, DFT_B in thread k1
     __device__ __forceinline__ void forward(cplx<T>* __restrict__ line, int t) {
-        if (t < B) {
-            dft<A, -1>(a);
-#pragma unroll
-            for (int k = 1; k < A; ++k) a[k] = cmul(a[k], tw[k]);
-        }
+        if (t < B) dft<A, -1>(a);
         __syncthreads();
         if (t < B) {
 #pragma unroll
@@ -71,7 +66,7 @@ struct Diag2Line {
         }
     }
 
-    // inverse: conjugate DFT_B in thread k1, exchange, conjugate twiddle and DFT_A in thread b
+    // inverse: conjugate DFT_B in thread k1, exchange, conjugate DFT_A in thread b
     __device__ __forceinline__ void inverse(cplx<T>* __restrict__ line, int t) {
         if (t < A) dft<B, +1>(a);
         __syncthreads();
@@ -84,13 +79,11 @@ struct Diag2Line {
 #pragma unroll
             for (int k = 0; k < A; ++k) a[k] = line[k * B + t];
             __builtin_amdgcn_sched_barrier(0);   // all reads in flight before the arithmetic
-#pragma unroll
-            for (int k = 1; k < A; ++k) a[k] = cmulc(a[k], tw[k]);
             dft<A, +1>(a);
         }
     }
 
-    // eigenvalue factor at X[k1 + A k2], stored as gpos[k1 * B + k2]
+    // eigenvalue factor of the frequency register k2 of thread k1 holds, stored as gpos[k1 B + k2]
     __device__ __forceinline__ void load_scale(const T* __restrict__ gpos, T* gv, int t) {
         if (t < A) {
 #pragma unroll

@@ -1,6 +1,7 @@
 // Device-side building blocks: complex arithmetic, compile-time trigonometric constants,
-// small DFT kernels (radices 2..16 by power-of-two recursion, odd radices up to 31 by the
-// symmetric direct form) and a Stockham stage over lines held in local data share (LDS).
+// small DFT kernels (radices 2..16 by power-of-two recursion, odd composite lengths with coprime
+// factors by the prime-factor algorithm, other odd lengths up to 31 by the symmetric direct
+// form) and a Stockham stage over lines held in local data share (LDS).
 //
 // Transform convention: forward (DIR = -1) is y_j = sum_k x_k e^{-2 pi i j k / L}; inverse
 // (DIR = +1) uses e^{+2 pi i j k / L} without the 1/L, which the caller folds into its tables.
@@ -219,28 +220,78 @@ __device__ __forceinline__ void odd_out(cplx<T>* y, cplx<T> a0, const cplx<T>* p
     }
 }
 
+// In place: every input is folded into p, m (and a0) before the first output is written.
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft_odd(cplx<T>* a) {
     constexpr int H = (R - 1) / 2;
     cplx<T> p[H], m[H];
-    cplx<T> y0 = a[0];
+    const cplx<T> a0 = a[0];
+    cplx<T> y0 = a0;
 #pragma unroll
     for (int k = 1; k <= H; ++k) {
         p[k - 1] = a[k] + a[R - k];
         m[k - 1] = a[k] - a[R - k];
         y0 = y0 + p[k - 1];
     }
-    cplx<T> y[R];
-    y[0] = y0;
-    odd_out<R, DIR, 1>(y, a[0], p, m);
+    odd_out<R, DIR, 1>(a, a0, p, m);
+    a[0] = y0;
+}
+
+// Odd R = R1 R2 with coprime R1, R2 > 1: R1 is the full power of R's smallest prime factor
+// (0 when R has no such split: a prime or a prime power).
+constexpr int pfa_split(int r) {
+    if (r % 2 == 0) return 0;
+    for (int p = 3; p * p <= r; p += 2)
+        if (r % p == 0) {
+            int q = 1;
+            while (r % p == 0) {
+                r /= p;
+                q *= p;
+            }
+            return r > 1 ? q : 0;
+        }
+    return 0;
+}
+constexpr int mod_inverse(int a, int m) {
+    for (int x = 1; x < m; ++x)
+        if ((a * x) % m == 1) return x;
+    return 1;
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cplx<T>* a);
+
+// Prime-factor (Good-Thomas) DFT of length R1 R2, gcd(R1, R2) = 1: input index
+// n = (R2 n1 + R1 n2) mod R, output index k = (R2 (R2^-1 mod R1) k1 + R1 (R1^-1 mod R2) k2) mod R
+// turn the length-R DFT into R2 DFTs of length R1 and R1 of length R2 with no twiddles.
+template <int R1, int R2, int DIR, typename T>
+__device__ __forceinline__ void dft_pfa(cplx<T>* a) {
+    constexpr int R = R1 * R2;
+    constexpr int i2 = mod_inverse(R2 % R1, R1), i1 = mod_inverse(R1 % R2, R2);
+    cplx<T> u[R2][R1];
 #pragma unroll
-    for (int r = 0; r < R; ++r) a[r] = y[r];
+    for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) u[n2][n1] = a[(R2 * n1 + R1 * n2) % R];
+        dft<R1, DIR>(u[n2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        cplx<T> v[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) v[n2] = u[n2][k1];
+        dft<R2, DIR>(v);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) a[(R2 * i2 * k1 + R1 * i1 * k2) % R] = v[k2];
+    }
 }
 
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cplx<T>* a) {
     if constexpr ((R & (R - 1)) == 0)
         DftPow2<R, DIR, T>::run(a);
+    else if constexpr (pfa_split(R) > 0)
+        dft_pfa<pfa_split(R), R / pfa_split(R), DIR>(a);
     else
         dft_odd<R, DIR>(a);
 }

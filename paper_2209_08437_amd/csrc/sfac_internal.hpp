@@ -31,12 +31,12 @@ struct AxisTables {
     std::vector<double> psi_re, psi_im;
     // embed only: scale_c / scale_s permuted to the digit-reversed positions of the
     // register-resident transform (position p holds frequency embed_frequency(p));
-    // two-step diagonal kernel (N = A B): gpos[k1 B + k2] = scale[k1 + A k2]
+    // two-step diagonal kernel (N = A B, prime-factor maps):
+    // gpos[k1 B + k2] = scale[(B (B^-1 mod A) k1 + A (A^-1 mod B) k2) mod N]
     std::vector<double> gpos_c, gpos_s;
-    // two-step diagonal kernel only: A, B and the per-thread tables
-    // tw2[b A + k1] = e^{-2 pi i b k1 / N}, psi2[b A + a] = psi_{b + B a}
+    // two-step diagonal kernel only: A, B and psi2[b A + a] = psi_{(B a + A b) mod N}
     int d2a = 0, d2b = 0;
-    std::vector<double> tw2_re, tw2_im, psi2_re, psi2_im;
+    std::vector<double> psi2_re, psi2_im;
 };
 
 // Factor pairs N = A * B handled by the register-resident diagonal kernel (false if none).

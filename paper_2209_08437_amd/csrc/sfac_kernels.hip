@@ -319,29 +319,70 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     if (d.nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
 }
 
-// Diagonal method, register-resident two-step transforms of length N = A B.
+// Cooperative copy between the tile's lines in memory and the complex LDS lines (complex line l
+// holds real lines 2l and 2l+1 as real and imaginary parts). With lpb lines of N = A B
+// positions and lpb P threads (P = max(A, B)), thread tau moves positions n0 + P j, j < A, of
+// line tau mod lpb for strided axes (adjacent threads take adjacent lines, whose elements are
+// adjacent in memory) and of line tau / P for the contiguous axis (adjacent threads take
+// adjacent positions), n0 the remaining index. Threads beyond lpb P (a grouped launch's larger
+// block) take no part. Lines beyond the tile load as zero and are not stored.
+template <typename T, int A, int B, bool LOAD>
+__device__ __forceinline__ void stage_tile(const TileGeom<T>& tg, int lpb, cplx<T>* lds) {
+    constexpr int P = A > B ? A : B, N = A * B, J = N / P;
+    const int tau = threadIdx.x;
+    if (tau >= lpb * P) return;
+    const bool contiguous = tg.kstride == 1;
+    const int l = contiguous ? tau / P : tau % lpb;
+    const int n0 = contiguous ? tau - l * P : tau / lpb;
+    const bool x_in = 2 * l < tg.nreal, y_in = 2 * l + 1 < tg.nreal;
+    const T* gx = tg.base + 2 * l * tg.lstride + n0 * tg.kstride;
+    const long long step = (long long)P * tg.kstride;
+    cplx<T>* sl = lds + l * N + n0;
+    if constexpr (LOAD) {
+        cplx<T> v[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            v[j].x = x_in ? gx[j * step] : (T)0;
+            v[j].y = y_in ? gx[j * step + tg.lstride] : (T)0;
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) sl[j * P] = v[j];
+    } else {
+        cplx<T> v[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) v[j] = sl[j * P];
+        T* gw = const_cast<T*>(gx);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (x_in) gw[j * step] = v[j].x;
+            if (y_in) gw[j * step + tg.lstride] = v[j].y;
+        }
+    }
+}
+
+// Diagonal method, register-resident two-step transforms of length N = A B. The tile goes
+// through LDS on the way in and out (the prime-factor layout scatters a thread's positions).
 template <typename T, int A, int B>
 __device__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     using G = Diag2Geom<A, B>;
     using Line = Diag2Line<T, A, B>;
+    constexpr int N = G::N;
     const int line = threadIdx.x / G::P;
     const int t = threadIdx.x - line * G::P;
     const TileGeom<T> tg(d, tile);
     const bool act = 2 * line < tg.nreal;
     const bool two = 2 * line + 1 < tg.nreal;
     const T decay = d.decay, decay_lo = d.decay_lo;
+    stage_tile<T, A, B, true>(tg, d.lpb, lds);
+    __syncthreads();
     Line L;
-    L.load_twiddles(d.tw2, t);
-    const T* src = tg.base + (long long)(2 * line) * tg.lstride;
+    cplx<T>* ln = lds + line * N;
     if (t < B) {
 #pragma unroll
         for (int k = 0; k < A; ++k) {
-            const int n = t + B * k;
             cplx<T> z = {(T)0, (T)0};
             if (act) {
-                const T* p = src + (long long)n * tg.kstride;
-                z.x = p[0];
-                if (two) z.y = p[tg.lstride];
+                z = ln[G::pos(t, k)];
                 if (d.nl_in) {
                     z.x = nonlinear_half_step(z.x, decay, decay_lo);
                     z.y = nonlinear_half_step(z.y, decay, decay_lo);
@@ -350,17 +391,15 @@ __device__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
             L.a[k] = z;
         }
     }
-    cplx<T>* ln = lds + line * G::N;
     L.template factor<false>(d.gpos_c, d.psi2, ln, t);
     L.template factor<true>(d.gpos_s, d.psi2, ln, t);
     L.template factor<false>(d.gpos_c, d.psi2, ln, t);
-    T* dst = tg.base + (long long)(2 * line) * tg.lstride;
     double vmax = 0.0;
     unsigned int bad = 0;
+    __syncthreads();   // the last exchange's reads are done before the staging writes
     if (t < B && act) {
 #pragma unroll
         for (int k = 0; k < A; ++k) {
-            const int n = t + B * k;
             cplx<T> z = L.a[k];
             if (d.nl_out) {
                 z.x = nonlinear_half_step(z.x, decay, decay_lo);
@@ -371,11 +410,11 @@ __device__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
                 else
                     vmax = fmax(vmax, fmax(ax, ay));
             }
-            T* p = dst + (long long)n * tg.kstride;
-            p[0] = z.x;
-            if (two) p[tg.lstride] = z.y;
+            ln[G::pos(t, k)] = z;
         }
     }
+    __syncthreads();
+    stage_tile<T, A, B, false>(tg, d.lpb, lds);
     if (d.nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
 }
 
@@ -439,7 +478,7 @@ __global__ void SFAC_EMBED_BOUNDS(LOG2M, LE) embed_pass_multi(const PassDesc<T>*
 }
 
 template <typename T, int A, int B>
-__global__ void __launch_bounds__(kBlockThreads) diag2_pass_single(PassDesc<T> d) {
+__global__ void __launch_bounds__(kBlockThreads, 3) diag2_pass_single(PassDesc<T> d) {
     extern __shared__ unsigned char smem_raw[];
     const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
     if (tile >= d.ntiles) return;
@@ -447,7 +486,7 @@ __global__ void __launch_bounds__(kBlockThreads) diag2_pass_single(PassDesc<T> d
 }
 
 template <typename T, int A, int B>
-__global__ void __launch_bounds__(kBlockThreads) diag2_pass_multi(const PassDesc<T>* __restrict__ descs,
+__global__ void __launch_bounds__(kBlockThreads, 3) diag2_pass_multi(const PassDesc<T>* __restrict__ descs,
                                                                   const int* __restrict__ block_start,
                                                                   int ndesc) {
     extern __shared__ unsigned char smem_raw[];

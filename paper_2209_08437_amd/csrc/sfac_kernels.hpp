@@ -24,8 +24,7 @@ struct PassDesc {
     const cplx<T>* psi;              // diag: e^{-i pi k / N}, k < N
     const T* gpos_c;                 // embed: kernel spectra / M in digit-reversed position order
     const T* gpos_s;
-    const cplx<T>* tw2;              // two-step diagonal kernel: per-thread twiddles and psi
-    const cplx<T>* psi2;
+    const cplx<T>* psi2;             // two-step diagonal kernel: per-thread psi
     unsigned long long* stat_max;    // bits of the largest |u| stored (non-negative double)
     unsigned int* stat_flags;        // SFAC_FLAG_* bits
     long long inner, outer;

@@ -44,7 +44,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Device copy of one axis' tables in the plan's arithmetic type.
 struct AxisDevice {
     sfac::AxisTables host;
-    size_t off_tw = 0, off_sc = 0, off_ss = 0, off_psi = 0, off_gc = 0, off_gs = 0, off_tw2 = 0, off_psi2 = 0;
+    size_t off_tw = 0, off_sc = 0, off_ss = 0, off_psi = 0, off_gc = 0, off_gs = 0, off_psi2 = 0;
     int lpb = 1;
     int threads = 256;
     int log2e = 4;
@@ -66,8 +66,6 @@ size_t axis_table_bytes(const sfac::AxisTables& t, size_t base, AxisDevice* ad) 
     off = align_up(off + sizeof(T) * t.gpos_c.size(), 256);
     ad->off_gs = off;
     off = align_up(off + sizeof(T) * t.gpos_s.size(), 256);
-    ad->off_tw2 = off;
-    off = align_up(off + sizeof(sfac::cplx<T>) * t.tw2_re.size(), 256);
     ad->off_psi2 = off;
     off = align_up(off + sizeof(sfac::cplx<T>) * t.psi2_re.size(), 256);
     return off;
@@ -87,8 +85,6 @@ void axis_table_fill(const sfac::AxisTables& t, const AxisDevice& ad, unsigned c
     for (size_t m = 0; m < t.gpos_c.size(); ++m) gc[m] = (T)t.gpos_c[m];
     auto* gs = reinterpret_cast<T*>(host + ad.off_gs);
     for (size_t m = 0; m < t.gpos_s.size(); ++m) gs[m] = (T)t.gpos_s[m];
-    auto* tw2 = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_tw2);
-    for (size_t m = 0; m < t.tw2_re.size(); ++m) tw2[m] = {(T)t.tw2_re[m], (T)t.tw2_im[m]};
     auto* psi2 = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_psi2);
     for (size_t m = 0; m < t.psi2_re.size(); ++m) psi2[m] = {(T)t.psi2_re[m], (T)t.psi2_im[m]};
 }
@@ -256,7 +252,6 @@ sfac::PassDesc<T> make_desc(const Instance& in, int a, unsigned char* dev_tables
     d.log2e = ad.log2e;
     d.d2a = t.d2a;
     d.d2b = t.d2b;
-    d.tw2 = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_tw2);
     d.psi2 = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_psi2);
     d.log2m = 0;
     while ((1 << d.log2m) < t.length) ++d.log2m;

@@ -229,26 +229,29 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, 
         }
         int A = 0, B = 0;
         if (diag2 && diag2_pair(N, &A, &B)) {
+            // prime-factor index maps of the two-step kernel: thread b, register a holds position
+            // (B a + A b) mod N; thread k1, register k2 holds frequency
+            // (B (B^-1 mod A) k1 + A (A^-1 mod B) k2) mod N
             t.d2a = A;
             t.d2b = B;
-            t.tw2_re.resize(N);
-            t.tw2_im.resize(N);
+            int binv = 1, ainv = 1;
+            while ((B * binv) % A != 1 % A) ++binv;
+            while ((A * ainv) % B != 1 % B) ++ainv;
             t.psi2_re.resize(N);
             t.psi2_im.resize(N);
             t.gpos_c.resize(N);
             t.gpos_s.resize(N);
             for (int b = 0; b < B; ++b)
-                for (int k = 0; k < A; ++k) {
-                    ld ang = 2.0L * kPi * (ld)((long long)b * k % N) / (ld)N;
-                    t.tw2_re[b * A + k] = (double)cosl(ang);
-                    t.tw2_im[b * A + k] = (double)-sinl(ang);
-                    t.psi2_re[b * A + k] = t.psi_re[b + B * k];
-                    t.psi2_im[b * A + k] = t.psi_im[b + B * k];
+                for (int a = 0; a < A; ++a) {
+                    const int n = (B * a + A * b) % N;
+                    t.psi2_re[b * A + a] = t.psi_re[n];
+                    t.psi2_im[b * A + a] = t.psi_im[n];
                 }
             for (int k1 = 0; k1 < A; ++k1)
                 for (int k2 = 0; k2 < B; ++k2) {
-                    t.gpos_c[k1 * B + k2] = t.scale_c[k1 + A * k2];
-                    t.gpos_s[k1 * B + k2] = t.scale_s[k1 + A * k2];
+                    const int k = (int)(((long long)B * binv * k1 + (long long)A * ainv * k2) % N);
+                    t.gpos_c[k1 * B + k2] = t.scale_c[k];
+                    t.gpos_s[k1 * B + k2] = t.scale_s[k];
                 }
         }
     } else {
