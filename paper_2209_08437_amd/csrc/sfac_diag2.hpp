@@ -111,6 +111,14 @@ struct Diag2Line {
         inverse(line, t);
         if constexpr (SKEW) psi_mul<true>(psipos, t);
     }
+
+    // the three factors e^{tau/2 C} e^{tau S} e^{tau/2 C}, the skew one wrapped in psi and conj(psi)
+    __device__ __forceinline__ void factors(const T* __restrict__ gpos_c, const T* __restrict__ gpos_s,
+                                            const cplx<T>* __restrict__ psipos, cplx<T>* line, int t) {
+        factor<false>(gpos_c, psipos, line, t);
+        factor<true>(gpos_s, psipos, line, t);
+        factor<false>(gpos_c, psipos, line, t);
+    }
 };
 
 }  // namespace sfac

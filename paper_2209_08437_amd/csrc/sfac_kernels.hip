@@ -363,7 +363,7 @@ __device__ __forceinline__ void stage_tile(const TileGeom<T>& tg, int lpb, cplx<
 // Diagonal method, register-resident two-step transforms of length N = A B. The tile goes
 // through LDS on the way in and out (the prime-factor layout scatters a thread's positions).
 template <typename T, int A, int B>
-__device__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
+__device__ __forceinline__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     using G = Diag2Geom<A, B>;
     using Line = Diag2Line<T, A, B>;
     constexpr int N = G::N;
@@ -391,9 +391,7 @@ __device__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
             L.a[k] = z;
         }
     }
-    L.template factor<false>(d.gpos_c, d.psi2, ln, t);
-    L.template factor<true>(d.gpos_s, d.psi2, ln, t);
-    L.template factor<false>(d.gpos_c, d.psi2, ln, t);
+    L.factors(d.gpos_c, d.gpos_s, d.psi2, ln, t);
     double vmax = 0.0;
     unsigned int bad = 0;
     __syncthreads();   // the last exchange's reads are done before the staging writes

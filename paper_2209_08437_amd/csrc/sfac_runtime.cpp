@@ -206,9 +206,10 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
             in->ax[a].threads = lpb * T;
             in->ax[a].lds = elem * (size_t)L * lpb;
         } else if (in->ax[a].host.d2a > 0) {
-            // two-step diagonal kernel: P = max(A, B) threads per line
+            // two-step diagonal kernel: P = max(A, B) threads per line; by default at most 40 KB
+            // of LDS lines per block, so that four blocks fit a CU
             const int P = std::max(in->ax[a].host.d2a, in->ax[a].host.d2b);
-            int lpb = sfac::kBlockThreads / P;
+            int lpb = std::min<int>(sfac::kBlockThreads / P, std::max<size_t>(1, 40960 / (elem * (size_t)L)));
             while (lpb > 1 && (lines_total + lpb - 1) / lpb < 1024) lpb >>= 1;
             if (opt && opt->lines_per_block[a] > 0) lpb = std::min(opt->lines_per_block[a], sfac::kBlockThreads / P);
             lpb = std::max(1, (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2)));

@@ -52,7 +52,7 @@ int embed_frequency(int p, int log2m, int log2e) {
 }
 
 bool diag2_pair(int n, int* a, int* b) {
-    // the instantiated (A, B) pairs of the register-resident diagonal kernel
+    // the instantiated (A, B) pairs of the register-resident diagonal kernel (coprime)
     static const int pairs[][2] = {{3, 5}, {5, 7}, {7, 9}, {9, 11}, {11, 13}, {13, 15}, {15, 17}, {5, 9}, {7, 11}};
     for (const auto& pr : pairs)
         if (pr[0] * pr[1] == n) {

@@ -149,7 +149,8 @@ def test_embed_schedules_fp64(sfac_lib, ns, le, lpb):
 
 @pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("lpb", [0, 1, 5])
-@pytest.mark.parametrize("ns", [(63, 30), (255, 11), (15, 35, 63), (99, 143)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("ns", [(63, 30), (255, 11), (15, 35, 63), (99, 143), (1023, 6)],
+                         ids=lambda s: "x".join(map(str, s)))   # 1023 = 3 11 31: generic kernel only
 def test_diag_kernels_fp64(sfac_lib, ns, kernel, lpb):
     """The diagonal method (length-N transforms, psi twiddles) in the generic kernel (1) and in
     the register-resident two-step kernel (2, N = A B); axes it cannot take use the embedded one."""
