@@ -123,15 +123,21 @@ def batched_run(args):
     same instances stepped one after another with plain FP64 plans."""
     import numpy as np
     import torch
-    from paper_2209_08437_amd import sfac, workloads as W
+    from paper_2209_08437_amd import autotune, sfac, workloads as W
     insts = W.batched_2d(count=args.batch_count, steps=args.steps or 500)
     steps = insts[0].steps
     pts = sum(i.points for i in insts)
     res = {}
+    finals = {}
     for dt in ("f32", "f64"):
         tdt = torch.float64 if dt == "f64" else torch.float32
+        sched = None
+        if not args.no_tune:
+            path = None if args.tune_cache in (None, "none") else args.tune_cache
+            sched = autotune.schedules(insts, dt, path=path)
+            log(f"[bench] batched {dt}: schedules for {len(set(tuple(i.ns) for i in insts))} shapes")
         states = [torch.tensor(i.u0, dtype=tdt, device="cuda") for i in insts]
-        b = sfac.Batch(insts, dt)
+        b = sfac.Batch(insts, dt, schedules=sched)
         b.step(states, min(args.warmup, steps))
         torch.cuda.synchronize()
         states = [torch.tensor(i.u0, dtype=tdt, device="cuda") for i in insts]
@@ -141,7 +147,11 @@ def batched_run(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         vmax = max(b.flags(k)[1] for k in range(len(insts)))
-        res[dt] = {"value": pts * steps / wall, "wall_s": wall, "max_abs": vmax}
+        flags = 0
+        for k in range(len(insts)):
+            flags |= b.flags(k)[0]
+        res[dt] = {"value": pts * steps / wall, "wall_s": wall, "max_abs": vmax, "flags": flags}
+        finals[dt] = [u.double().cpu().numpy() for u in states]
         log(f"[bench] batched {len(insts)} instances {dt}: {steps} steps in {wall * 1e3:.1f} ms")
         b.close()
     # plain FP64 path: one plan per instance, stepped one after another
@@ -172,6 +182,11 @@ def batched_run(args):
         "plain_f64_sequential": round(res["f64_sequential"]["value"], 1),
         "speedup_f32_batched_vs_plain_f64": round(res["f32"]["value"] / res["f64_sequential"]["value"], 3),
         "max_abs": max(res["f32"]["max_abs"], res["f64"]["max_abs"]),
+        "flags": res["f32"]["flags"] | res["f64"]["flags"],
+        "f32_rel_err_vs_f64_gpu_max": float(max(np.abs(a - r).max() / np.abs(r).max()
+                                                for a, r in zip(finals["f32"], finals["f64"]))),
+        "schedules": "autotuned (MI355X table, missing shapes tuned on the device)" if not args.no_tune
+                     else "automatic",
     }
 
 

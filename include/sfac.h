@@ -209,11 +209,13 @@ typedef struct {
 
 /*
  * sfac_batch_create - plan `count` instances (count >= 1) for arithmetic dt on hip_stream.
- * Every instance is validated as by sfac_plan_create; the first invalid one fails the call
- * with its index in the message. Errors as sfac_plan_create.
+ * opts is NULL (automatic schedules) or `count` per-instance options (the kernel schedules an
+ * autotuner picked; use_graph and graph_chunk are ignored). Every instance is validated as by
+ * sfac_plan_create; the first invalid one fails the call with its index in the message.
+ * Errors as sfac_plan_create.
  */
 sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instance_desc* desc,
-                              sfac_dtype dt, void* hip_stream);
+                              sfac_dtype dt, void* hip_stream, const sfac_options* opts);
 
 /*
  * sfac_batch_step - advance instance i by nsteps[i] steps (>= 0) in place; u_dev[i] is its

@@ -135,3 +135,46 @@ def tune(ns, alphas, eps, tau, hs, dtype="f64", reps=10, use_cache=True, verbose
     if use_cache and save:
         _save_cache(path, cache)
     return best
+
+
+SCHEDULE_KEYS = ("method", "elems_log2", "lines_per_block", "kernel")
+
+
+def load_table(path=None):
+    """A schedule cache file as a dict (default: the packaged MI355X table); {} if unreadable."""
+    return _load_cache(path or PACKAGED)
+
+
+def lookup(ns, dtype, path=None, table=None):
+    """The cached schedule of this shape (dict of SCHEDULE_KEYS, per-axis lists) if every axis is
+    in the cache (`table` as returned by load_table, else the file `path`, default the packaged
+    MI355X table), else None. Launches nothing."""
+    cache = table if table is not None else _load_cache(path or PACKAGED)
+    dims = len(ns)
+    out = {k: [None if k == "method" else 0] * dims for k in SCHEDULE_KEYS}
+    for a in range(dims):
+        rec = cache.get(axis_key(ns, a, dtype))
+        if not rec or len(rec) != 5:
+            return None
+        out["method"][a], out["elems_log2"][a], out["lines_per_block"][a], out["kernel"][a] = rec[:4]
+    return out
+
+
+def schedules(instances, dtype="f64", path=None, tune_missing=True, reps=10):
+    """Schedules for a batch: one per instance, looked up by shape in the cache file `path`
+    (default: the packaged MI355X table); shapes it lacks are tuned on the device once per
+    distinct shape (not written back) if tune_missing, else left automatic (None)."""
+    path = path or PACKAGED
+    done = {}
+    out = []
+    for inst in instances:
+        key = (tuple(inst.ns), dtype)
+        if key not in done:
+            sch = lookup(inst.ns, dtype, path)
+            if sch is None and tune_missing:
+                best = tune(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, reps=reps, path=path,
+                            save=False)
+                sch = {k: best[k] for k in SCHEDULE_KEYS}
+            done[key] = sch
+        out.append(done[key])
+    return out

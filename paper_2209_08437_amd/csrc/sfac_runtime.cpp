@@ -784,7 +784,7 @@ sfac_status sfac_group_destroy(sfac_group g) {
 size_t sfac_group_device_bytes(sfac_group g) { return g ? g->arena_bytes : 0; }
 
 sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instance_desc* desc, sfac_dtype dt,
-                              void* hip_stream) {
+                              void* hip_stream, const sfac_options* opts) {
     g_error.clear();
     if (!out) return fail(SFAC_EINVAL, "NULL output handle");
     *out = nullptr;
@@ -792,10 +792,11 @@ sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instanc
     if (dt != SFAC_FP64 && dt != SFAC_FP32) return fail(SFAC_EINVAL, "unknown dtype %d", (int)dt);
     std::unique_ptr<sfac_batch_s> b(new (std::nothrow) sfac_batch_s());
     if (!b) return fail(SFAC_ENOMEM, "host allocation failed");
-    sfac_options opt{};
-    opt.use_graph = 0;
     for (int32_t i = 0; i < count; ++i) {
         const sfac_instance_desc& d = desc[i];
+        sfac_options opt{};
+        if (opts) opt = opts[i];
+        opt.use_graph = 0;   // a batch steps through its group, never through a plan's graphs
         sfac_plan p = nullptr;
         sfac_status st = sfac_plan_create(&p, d.dims, d.n, d.alpha, d.eps, d.tau, d.h, dt, hip_stream, &opt);
         if (st != SFAC_OK) {

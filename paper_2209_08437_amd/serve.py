@@ -45,15 +45,20 @@ class Ticket:
 
 class GpuExecutor:
     """Device side of the server: one plan and one device-resident state per admitted request,
-    one group for the grouped steps, all on one stream."""
+    one group for the grouped steps, all on one stream. Plans take the autotuned schedule of
+    their shape when the schedule table (`schedule_table`: a cache file path; default the
+    packaged MI355X table; False for automatic schedules only) holds it; nothing is tuned
+    while serving."""
 
-    def __init__(self, stream=None):
+    def __init__(self, stream=None, schedule_table=None):
         import torch
-        from . import sfac
+        from . import autotune, sfac
         self.torch = torch
         self.sfac = sfac
+        self.autotune = autotune
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.group = sfac.Group(self.stream)
+        self.table = {} if schedule_table is False else autotune.load_table(schedule_table)
 
     def bytes_needed(self, inst, dtype):
         esize = 8 if dtype == "f64" else 4
@@ -68,9 +73,10 @@ class GpuExecutor:
     def admit(self, inst, dtype):
         torch = self.torch
         tdt = torch.float64 if dtype == "f64" else torch.float32
+        sched = self.autotune.lookup(inst.ns, dtype, table=self.table) if self.table else None
         with torch.cuda.stream(self.stream):
             plan = self.sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype,
-                                  stream=self.stream, use_graph=False)
+                                  stream=self.stream, use_graph=False, **(sched or {}))
             u = torch.as_tensor(np.asarray(inst.u0), dtype=tdt).to("cuda", non_blocking=False)
         return (plan, u)
 

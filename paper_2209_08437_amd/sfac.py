@@ -65,7 +65,8 @@ def lib():
     L.sfac_plan_reset_flags.argtypes = [vp]
     L.sfac_plan_method.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.sfac_last_error.restype = ctypes.c_char_p
-    L.sfac_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(InstanceDesc), ctypes.c_int, vp]
+    L.sfac_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(InstanceDesc), ctypes.c_int, vp,
+                                    ctypes.POINTER(Options)]
     L.sfac_batch_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64)]
     L.sfac_batch_destroy.argtypes = [vp]
     L.sfac_batch_device_bytes.argtypes = [vp]
@@ -152,6 +153,24 @@ def axis_tables(n, alpha, eps, tau, h, method=None):
     return length.value, sc, ss, list(rad[: nst.value])
 
 
+def fill_options(opt, dims, method=None, elems_log2=None, lines_per_block=None, kernel=None):
+    """Write a kernel schedule into an Options struct: each argument is None (automatic), one
+    value for every axis or a per-axis sequence (method: None, "auto", "diag" or "embed")."""
+    def per_axis(v, a):
+        return v[a] if isinstance(v, (list, tuple)) else v
+    codes = {None: METHOD_AUTO, "auto": METHOD_AUTO, "diag": METHOD_DIAG, "embed": METHOD_EMBED}
+    for a in range(3):
+        opt.method[a] = codes[per_axis(method, a)] if a < dims else METHOD_AUTO
+    for a in range(min(3, dims)):
+        if elems_log2 is not None:
+            opt.elems_log2[a] = int(per_axis(elems_log2, a) or 0)
+        if lines_per_block is not None:
+            opt.lines_per_block[a] = int(per_axis(lines_per_block, a) or 0)
+        if kernel is not None:
+            opt.kernel[a] = int(per_axis(kernel, a) or 0)
+    return opt
+
+
 class Plan:
     """sfac_plan_create / sfac_step / sfac_plan_destroy for one instance.
 
@@ -169,20 +188,10 @@ class Plan:
         self.ns = tuple(int(n) for n in ns)
         self.dt = _dtype_code(dtype)
         opt = Options()
-        meth = method if isinstance(method, (list, tuple)) else [method] * self.dims
-        codes = {None: METHOD_AUTO, "auto": METHOD_AUTO, "diag": METHOD_DIAG, "embed": METHOD_EMBED}
-        for a in range(3):
-            opt.method[a] = codes[meth[a]] if a < self.dims else METHOD_AUTO
+        fill_options(opt, self.dims, method=method, elems_log2=elems_log2, lines_per_block=lines_per_block,
+                     kernel=kernel)
         opt.use_graph = 1 if use_graph else 0
         opt.graph_chunk = int(graph_chunk)
-        for a in range(min(3, self.dims)):
-            if elems_log2 is not None:
-                opt.elems_log2[a] = int(elems_log2[a] if isinstance(elems_log2, (list, tuple)) else elems_log2)
-            if kernel is not None:
-                opt.kernel[a] = int(kernel[a] if isinstance(kernel, (list, tuple)) else kernel)
-            if lines_per_block is not None:
-                opt.lines_per_block[a] = int(lines_per_block[a] if isinstance(lines_per_block, (list, tuple))
-                                             else lines_per_block)
         n_arr = (ctypes.c_int32 * self.dims)(*self.ns)
         a_arr = (ctypes.c_double * self.dims)(*[float(a) for a in alphas])
         h_arr = (ctypes.c_double * self.dims)(*[float(h) for h in hs])
@@ -289,12 +298,22 @@ class Group:
 class Batch:
     """sfac_batch_create / sfac_batch_step / sfac_batch_destroy.
 
-    instances: sequence of objects with ns, alphas, eps, tau, hs (e.g. workloads.Instance)."""
+    instances: sequence of objects with ns, alphas, eps, tau, hs (e.g. workloads.Instance).
+    schedules: None (automatic) or one entry per instance, each None or a dict with any of the
+    keys method, elems_log2, lines_per_block, kernel (as for Plan; autotune.schedules returns
+    them)."""
 
-    def __init__(self, instances, dtype="f64", stream=None):
+    def __init__(self, instances, dtype="f64", stream=None, schedules=None):
         L = lib()
         self.count = len(instances)
         self.dt = _dtype_code(dtype)
+        opts = None
+        if schedules is not None:
+            if len(schedules) != self.count:
+                raise ValueError("one schedule (or None) per instance")
+            opts = (Options * self.count)()
+            for i, (inst, sch) in enumerate(zip(instances, schedules)):
+                fill_options(opts[i], len(inst.ns), **(sch or {}))
         arr = (InstanceDesc * self.count)()
         self.shapes = []
         for i, inst in enumerate(instances):
@@ -309,7 +328,7 @@ class Batch:
             self.shapes.append(tuple(reversed([int(n) for n in inst.ns])))
         self._h = ctypes.c_void_p()
         self._stream = _stream_handle(stream)
-        _check(L.sfac_batch_create(ctypes.byref(self._h), self.count, arr, self.dt, self._stream))
+        _check(L.sfac_batch_create(ctypes.byref(self._h), self.count, arr, self.dt, self._stream, opts))
 
     def step(self, states, nsteps):
         """Advance states[i] by nsteps[i] steps (an int applies to all)."""

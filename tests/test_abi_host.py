@@ -137,3 +137,25 @@ def test_host_tables_match_oracle(sfac_lib, n, alpha):
     assert np.allclose(ks[:n], ops.ES[:, 0], rtol=0, atol=1e-14)
     assert np.allclose(kc[M - n + 1:][::-1], ops.EC[1:, 0], rtol=0, atol=1e-14)   # symmetric kernel
     assert np.allclose(kc[n:M - n + 1], 0, atol=1e-14)
+
+
+def test_batch_options_are_validated(sfac_lib):
+    """Per-instance schedules reach validation: a bad one fails the batch with its index."""
+    import ctypes
+    L = sfac.lib()
+    arr = (sfac.InstanceDesc * 2)()
+    for d in arr:
+        d.dims = 2
+        for a in range(2):
+            d.n[a] = 63
+            d.alpha[a] = 1.5
+            d.h[a] = 2.0 / 64
+        d.eps = 0.1
+        d.tau = 0.01
+    opts = (sfac.Options * 2)()
+    opts[0].elems_log2[1] = 7
+    h = ctypes.c_void_p()
+    st = L.sfac_batch_create(ctypes.byref(h), 2, arr, sfac.FP64, None, opts)
+    assert st == sfac.EINVAL and not h.value
+    msg = L.sfac_last_error().decode()
+    assert "instance 0" in msg and "elems_log2" in msg

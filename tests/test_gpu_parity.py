@@ -38,13 +38,15 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def gpu_solve(u0, ns, alphas, eps, hs, tau, steps, dtype="f64", method=None, use_graph=True, chunk=32):
+def gpu_solve(u0, ns, alphas, eps, hs, tau, steps, dtype="f64", method=None, use_graph=True, chunk=32, sched=None):
     torch = _torch()
     from paper_2209_08437_amd import sfac
     tdt = torch.float64 if dtype == "f64" else torch.float32
     u = torch.tensor(np.asarray(u0), dtype=tdt, device="cuda").contiguous()
-    with sfac.Plan(ns, alphas, eps, tau, hs, dtype, method=method, use_graph=use_graph,
-                   graph_chunk=chunk) as p:
+    kw = dict(sched or {})
+    if method is not None:
+        kw["method"] = method
+    with sfac.Plan(ns, alphas, eps, tau, hs, dtype, use_graph=use_graph, graph_chunk=chunk, **kw) as p:
         p.step(u, steps)
         flags = p.flags()
     torch.cuda.synchronize()
@@ -232,14 +234,24 @@ def test_large_2d_1023_full_size(sfac_lib, method):
     assert e32 <= FP32_TOL
 
 
-def test_large_3d_255_full_size_one_step(sfac_lib):
+def _bench_schedule(inst, dtype):
+    """The schedule bench.py runs this workload with (the packaged autotuner table)."""
+    from paper_2209_08437_amd import autotune
+    return autotune.lookup(inst.ns, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("sched", ["bench", "auto"])
+def test_large_3d_255_full_size_one_step(sfac_lib, dtype, sched):
+    """Full 255^3 grid, one step, in bench.py's launch configuration and in the automatic one."""
     inst = W.large_3d_255()
-    _say("case large_3d_255 fp64 1 step")
+    s = _bench_schedule(inst, dtype) if sched == "bench" else None
+    _say(f"case large_3d_255 {dtype} 1 step schedule {s}")
     ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, 1)
-    got, (flags, _) = gpu_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, 1)
+    got, (flags, _) = gpu_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, 1, dtype, sched=s)
     e = rel_err(got, ref)
     _say(f"  rel err {e:.3e}")
-    assert e <= FP64_TOL and flags == 0
+    assert e <= (FP64_TOL if dtype == "f64" else FP32_TOL) and flags == 0
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -328,12 +340,42 @@ def test_batch_matches_single_bitwise_and_oracle(sfac_lib):
     b.close()
 
 
+def test_batch_with_schedules_matches_lone_plans(sfac_lib):
+    """Per-instance schedules (as the autotuner hands them to a batch): each state ends bitwise
+    equal to a lone plan with the same schedule, and within tolerance of the oracle."""
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    insts = W.batched_2d(count=5, steps=4, seed=22, sizes=(63, 100, 255))
+    scheds = [None, {"elems_log2": 4, "lines_per_block": 1}, {"elems_log2": [2, 3]},
+              {"method": "diag", "kernel": 1}, {"lines_per_block": 2}]
+    for dt in ("f64", "f32"):
+        _say(f"case batch schedules {dt}")
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        states = [torch.tensor(i.u0, dtype=tdt, device="cuda") for i in insts]
+        try:
+            b = sfac.Batch(insts, dt, schedules=scheds)
+        except sfac.SfacError as e:
+            pytest.fail(f"batch with schedules rejected: {e}")
+        b.step(states, [i.steps for i in insts])
+        torch.cuda.synchronize()
+        for i, (inst, sch) in enumerate(zip(insts, scheds)):
+            u = torch.tensor(inst.u0, dtype=tdt, device="cuda")
+            with sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dt, **(sch or {})) as p:
+                p.step(u, inst.steps)
+            torch.cuda.synchronize()
+            assert torch.equal(u, states[i]), (dt, i)
+            ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
+            assert rel_err(states[i].double().cpu().numpy(), ref) <= (FP64_TOL if dt == "f64" else FP32_TOL), (dt, i)
+        b.close()
+
+
 def test_large_2d_1023_all_steps_fp64(sfac_lib):
     """The benchmark workload at full size and full length (1000 steps), in the launch
-    configuration bench.py times (automatic method, graph replays), against the oracle."""
+    configuration bench.py times (packaged autotuned schedule, graph replays), against the oracle."""
     inst = W.large_2d_1023()
-    _say(f"case large_2d_1023 fp64 all {inst.steps} steps (oracle on the host, about a minute)")
-    got, (flags, vmax) = gpu_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
+    s = _bench_schedule(inst, "f64")
+    _say(f"case large_2d_1023 fp64 all {inst.steps} steps schedule {s} (oracle on the host, about a minute)")
+    got, (flags, vmax) = gpu_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps, sched=s)
     ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
     e = rel_err(got, ref)
     _say(f"  rel err {e:.3e} max|u| {vmax:.6f}")
