@@ -84,26 +84,26 @@ struct Diag2Line {
     }
 
     // eigenvalue factor of the frequency register k2 of thread k1 holds, stored as gpos[k1 B + k2]
-    __device__ __forceinline__ void load_scale(const T* __restrict__ gpos, T* gv, int t) {
+    __device__ __forceinline__ void load_scale(const Spec<T>* __restrict__ gpos, Spec<T>* gv, int t) {
         if (t < A) {
 #pragma unroll
             for (int b = 0; b < B; ++b) gv[b] = gpos[t * B + b];
         }
     }
-    __device__ __forceinline__ void scale(const T* gv, int t) {
+    __device__ __forceinline__ void scale(const Spec<T>* gv, int t) {
         if (t < A) {
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                a[b].x *= gv[b];
-                a[b].y *= gv[b];
+                a[b].x = spec_mul(a[b].x, gv[b]);
+                a[b].y = spec_mul(a[b].y, gv[b]);
             }
         }
     }
 
     template <bool SKEW>
-    __device__ __forceinline__ void factor(const T* __restrict__ gpos, const cplx<T>* __restrict__ psipos,
+    __device__ __forceinline__ void factor(const Spec<T>* __restrict__ gpos, const cplx<T>* __restrict__ psipos,
                                            cplx<T>* line, int t) {
-        T gv[B];
+        Spec<T> gv[B];
         load_scale(gpos, gv, t);
         if constexpr (SKEW) psi_mul<false>(psipos, t);
         forward(line, t);
@@ -113,7 +113,7 @@ struct Diag2Line {
     }
 
     // the three factors e^{tau/2 C} e^{tau S} e^{tau/2 C}, the skew one wrapped in psi and conj(psi)
-    __device__ __forceinline__ void factors(const T* __restrict__ gpos_c, const T* __restrict__ gpos_s,
+    __device__ __forceinline__ void factors(const Spec<T>* __restrict__ gpos_c, const Spec<T>* __restrict__ gpos_s,
                                             const cplx<T>* __restrict__ psipos, cplx<T>* line, int t) {
         factor<false>(gpos_c, psipos, line, t);
         factor<true>(gpos_s, psipos, line, t);

@@ -235,7 +235,7 @@ struct EmbedLine {
     // multiply by the kernel spectrum, stored in last-pass position order
     // spectrum values at this thread's last-pass positions; loaded before the forward transform
     // so that the load latency is hidden behind it
-    __device__ __forceinline__ void load_scale(const T* __restrict__ g, T* gv, int t) {
+    __device__ __forceinline__ void load_scale(const Spec<T>* __restrict__ g, Spec<T>* gv, int t) {
         constexpr int S = G::NST - 1;
         constexpr int R = G::R(S);
 #pragma unroll
@@ -243,11 +243,11 @@ struct EmbedLine {
 #pragma unroll
             for (int k = 0; k < R; ++k) gv[i * R + k] = g[embed_pos<LOG2M, LE, S>(t, i, k)];
     }
-    __device__ __forceinline__ void scale(const T* gv) {
+    __device__ __forceinline__ void scale(const Spec<T>* gv) {
 #pragma unroll
         for (int e = 0; e < G::E; ++e) {
-            a[e].x *= gv[e];
-            a[e].y *= gv[e];
+            a[e].x = spec_mul(a[e].x, gv[e]);
+            a[e].y = spec_mul(a[e].y, gv[e]);
         }
     }
 
@@ -255,8 +255,8 @@ struct EmbedLine {
     static __device__ __forceinline__ int nat(int t, int i, int k) { return embed_pos<LOG2M, LE, 0>(t, i, k); }
 
     // one exponential factor: forward transform, spectrum, inverse transform, truncation
-    __device__ __forceinline__ void factor(const T* __restrict__ g, cplx<T>* line, int t, int n) {
-        T gv[G::E];
+    __device__ __forceinline__ void factor(const Spec<T>* __restrict__ g, cplx<T>* line, int t, int n) {
+        Spec<T> gv[G::E];
         load_scale(g, gv, t);
         fwd_from<0>(line, t);
         scale(gv);

@@ -20,6 +20,34 @@ struct alignas(2 * sizeof(T)) cplx {
     T x, y;
 };
 
+// An eigenvalue-factor (spectrum) table entry. FP64 holds the value. FP32 holds the value
+// rounded to float and the float remainder, and multiplies as a hi + lo pair (one more FMA), so
+// the table adds no rounding of its own: the same rounded factor applied every step would
+// otherwise give an error that grows linearly with the number of steps.
+template <typename T>
+struct Spec {
+    T v;
+};
+template <>
+struct Spec<float> {
+    float hi, lo;
+};
+__host__ __device__ inline Spec<double> make_spec_double(double v) { return {v}; }
+__host__ __device__ inline Spec<float> make_spec_float(double v) {
+    const float hi = (float)v;
+    return {hi, (float)(v - (double)hi)};
+}
+template <typename T>
+__host__ __device__ inline Spec<T> make_spec(double v);
+template <>
+__host__ __device__ inline Spec<double> make_spec<double>(double v) { return make_spec_double(v); }
+template <>
+__host__ __device__ inline Spec<float> make_spec<float>(double v) { return make_spec_float(v); }
+
+// a * g
+__device__ __forceinline__ double spec_mul(double a, Spec<double> g) { return a * g.v; }
+__device__ __forceinline__ float spec_mul(float a, Spec<float> g) { return __builtin_fmaf(a, g.lo, a * g.hi); }
+
 template <typename T>
 __device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) {
     return {a.x + b.x, a.y + b.y};

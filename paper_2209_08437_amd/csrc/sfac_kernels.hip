@@ -158,7 +158,7 @@ __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>*
     cplx<T>* other = buf1;
     const bool diag = d.method == 1;
     for (int f = 0; f < 3; ++f) {
-        const T* scale = f == 1 ? d.scale_s : d.scale_c;
+        const Spec<T>* scale = f == 1 ? d.scale_s : d.scale_c;
         const bool skew = f == 1;
         if (diag && skew) {  // x <- psi . x
             for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
@@ -171,9 +171,9 @@ __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>*
         other = cur == buf0 ? buf1 : buf0;
         for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
             const int k = idx % L;
-            const T sc = scale[k];
-            cur[idx].x *= sc;
-            cur[idx].y *= sc;
+            const Spec<T> sc = scale[k];
+            cur[idx].x = spec_mul(cur[idx].x, sc);
+            cur[idx].y = spec_mul(cur[idx].y, sc);
         }
         __syncthreads();
         cur = transform<+1>(d, cur, other, lines);
@@ -329,6 +329,7 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
 template <typename T, int A, int B, bool LOAD>
 __device__ __forceinline__ void stage_tile(const TileGeom<T>& tg, int lpb, cplx<T>* lds) {
     constexpr int P = A > B ? A : B, N = A * B, J = N / P;
+    constexpr int LS = diag2_line_stride(A, B, sizeof(cplx<T>));
     const int tau = threadIdx.x;
     if (tau >= lpb * P) return;
     const bool contiguous = tg.kstride == 1;
@@ -337,7 +338,7 @@ __device__ __forceinline__ void stage_tile(const TileGeom<T>& tg, int lpb, cplx<
     const bool x_in = 2 * l < tg.nreal, y_in = 2 * l + 1 < tg.nreal;
     const T* gx = tg.base + 2 * l * tg.lstride + n0 * tg.kstride;
     const long long step = (long long)P * tg.kstride;
-    cplx<T>* sl = lds + l * N + n0;
+    cplx<T>* sl = lds + l * LS + n0;
     if constexpr (LOAD) {
         cplx<T> v[J];
 #pragma unroll
@@ -366,7 +367,6 @@ template <typename T, int A, int B>
 __device__ __forceinline__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     using G = Diag2Geom<A, B>;
     using Line = Diag2Line<T, A, B>;
-    constexpr int N = G::N;
     const int line = threadIdx.x / G::P;
     const int t = threadIdx.x - line * G::P;
     const TileGeom<T> tg(d, tile);
@@ -376,7 +376,7 @@ __device__ __forceinline__ void run_diag2_tile(const PassDesc<T>& d, int tile, c
     stage_tile<T, A, B, true>(tg, d.lpb, lds);
     __syncthreads();
     Line L;
-    cplx<T>* ln = lds + line * N;
+    cplx<T>* ln = lds + line * diag2_line_stride(A, B, sizeof(cplx<T>));
     if (t < B) {
 #pragma unroll
         for (int k = 0; k < A; ++k) {

@@ -12,6 +12,26 @@ namespace sfac {
 
 constexpr int kBlockThreads = 256;
 
+// LDS elements per line of the two-step diagonal kernel (N = A B): N plus a pad that spreads
+// the lanes of neighbouring lines over the banks; the pads come from a bank-conflict model of
+// the kernel's access patterns (16-lane groups of 16-byte elements, 32-lane groups of 8-byte
+// ones) at the usual lines per block.
+constexpr int diag2_line_stride(int a, int b, int elem_bytes) {
+    const int n = a * b;
+    if (elem_bytes == 16) {
+        if (a == 3 && b == 5) return n + 10;
+        if (a == 5 && b == 7) return n + 10;
+        if (a == 15 && b == 17) return n + 2;
+    } else {
+        if (a == 3 && b == 5) return n + 4;
+        if (a == 5 && b == 7) return n + 7;
+        if (a == 7 && b == 9) return n + 9;
+        if (a == 9 && b == 11) return n + 4;
+        if (a == 13 && b == 15) return n + 15;
+    }
+    return n;
+}
+
 // Everything one axis pass of one instance needs. Lines along the axis are addressed as
 // u[o * N * inner + k * inner + i]: o < outer indexes the slower axes, i < inner the faster
 // ones, k < N the position on the line. inner == 1 is the contiguous axis (axis 1).
@@ -19,11 +39,11 @@ template <typename T>
 struct PassDesc {
     T* u;                            // state, device
     const cplx<T>* tw;               // e^{-2 pi i m / L}, m < L
-    const T* scale_c;                // diag: e^{tau/2 lambda}/N; embed: kernel spectrum / M
-    const T* scale_s;                // diag: e^{tau mu}/N;       embed: kernel spectrum / M
+    const Spec<T>* scale_c;          // diag: e^{tau/2 lambda}/N; embed: kernel spectrum / M
+    const Spec<T>* scale_s;          // diag: e^{tau mu}/N;       embed: kernel spectrum / M
     const cplx<T>* psi;              // diag: e^{-i pi k / N}, k < N
-    const T* gpos_c;                 // embed: kernel spectra / M in digit-reversed position order
-    const T* gpos_s;
+    const Spec<T>* gpos_c;           // embed: kernel spectra / M in digit-reversed position order;
+    const Spec<T>* gpos_s;           // two-step diagonal kernel: factors in per-thread order
     const cplx<T>* psi2;             // two-step diagonal kernel: per-thread psi
     unsigned long long* stat_max;    // bits of the largest |u| stored (non-negative double)
     unsigned int* stat_flags;        // SFAC_FLAG_* bits

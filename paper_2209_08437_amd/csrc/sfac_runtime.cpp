@@ -57,15 +57,15 @@ size_t axis_table_bytes(const sfac::AxisTables& t, size_t base, AxisDevice* ad) 
     ad->off_tw = off;
     off = align_up(off + sizeof(sfac::cplx<T>) * t.length, 256);
     ad->off_sc = off;
-    off = align_up(off + sizeof(T) * t.scale_c.size(), 256);
+    off = align_up(off + sizeof(sfac::Spec<T>) * t.scale_c.size(), 256);
     ad->off_ss = off;
-    off = align_up(off + sizeof(T) * t.scale_s.size(), 256);
+    off = align_up(off + sizeof(sfac::Spec<T>) * t.scale_s.size(), 256);
     ad->off_psi = off;
     off = align_up(off + sizeof(sfac::cplx<T>) * t.psi_re.size(), 256);
     ad->off_gc = off;
-    off = align_up(off + sizeof(T) * t.gpos_c.size(), 256);
+    off = align_up(off + sizeof(sfac::Spec<T>) * t.gpos_c.size(), 256);
     ad->off_gs = off;
-    off = align_up(off + sizeof(T) * t.gpos_s.size(), 256);
+    off = align_up(off + sizeof(sfac::Spec<T>) * t.gpos_s.size(), 256);
     ad->off_psi2 = off;
     off = align_up(off + sizeof(sfac::cplx<T>) * t.psi2_re.size(), 256);
     return off;
@@ -75,16 +75,16 @@ template <typename T>
 void axis_table_fill(const sfac::AxisTables& t, const AxisDevice& ad, unsigned char* host) {
     auto* tw = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_tw);
     for (int m = 0; m < t.length; ++m) tw[m] = {(T)t.tw_re[m], (T)t.tw_im[m]};
-    auto* sc = reinterpret_cast<T*>(host + ad.off_sc);
-    for (size_t m = 0; m < t.scale_c.size(); ++m) sc[m] = (T)t.scale_c[m];
-    auto* ss = reinterpret_cast<T*>(host + ad.off_ss);
-    for (size_t m = 0; m < t.scale_s.size(); ++m) ss[m] = (T)t.scale_s[m];
+    auto* sc = reinterpret_cast<sfac::Spec<T>*>(host + ad.off_sc);
+    for (size_t m = 0; m < t.scale_c.size(); ++m) sc[m] = sfac::make_spec<T>(t.scale_c[m]);
+    auto* ss = reinterpret_cast<sfac::Spec<T>*>(host + ad.off_ss);
+    for (size_t m = 0; m < t.scale_s.size(); ++m) ss[m] = sfac::make_spec<T>(t.scale_s[m]);
     auto* ps = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_psi);
     for (size_t m = 0; m < t.psi_re.size(); ++m) ps[m] = {(T)t.psi_re[m], (T)t.psi_im[m]};
-    auto* gc = reinterpret_cast<T*>(host + ad.off_gc);
-    for (size_t m = 0; m < t.gpos_c.size(); ++m) gc[m] = (T)t.gpos_c[m];
-    auto* gs = reinterpret_cast<T*>(host + ad.off_gs);
-    for (size_t m = 0; m < t.gpos_s.size(); ++m) gs[m] = (T)t.gpos_s[m];
+    auto* gc = reinterpret_cast<sfac::Spec<T>*>(host + ad.off_gc);
+    for (size_t m = 0; m < t.gpos_c.size(); ++m) gc[m] = sfac::make_spec<T>(t.gpos_c[m]);
+    auto* gs = reinterpret_cast<sfac::Spec<T>*>(host + ad.off_gs);
+    for (size_t m = 0; m < t.gpos_s.size(); ++m) gs[m] = sfac::make_spec<T>(t.gpos_s[m]);
     auto* psi2 = reinterpret_cast<sfac::cplx<T>*>(host + ad.off_psi2);
     for (size_t m = 0; m < t.psi2_re.size(); ++m) psi2[m] = {(T)t.psi2_re[m], (T)t.psi2_im[m]};
 }
@@ -215,7 +215,7 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
             lpb = std::max(1, (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2)));
             in->ax[a].lpb = lpb;
             in->ax[a].threads = lpb * P;
-            in->ax[a].lds = elem * (size_t)L * lpb;
+            in->ax[a].lds = elem * (size_t)sfac::diag2_line_stride(in->ax[a].host.d2a, in->ax[a].host.d2b, (int)elem) * lpb;
         } else {
             // generic kernel: two LDS buffers per line, as many lines as fit the budget
             const size_t per_line = 2 * elem * (size_t)L;
@@ -244,11 +244,11 @@ sfac::PassDesc<T> make_desc(const Instance& in, int a, unsigned char* dev_tables
     sfac::PassDesc<T> d{};
     d.u = u;
     d.tw = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_tw);
-    d.scale_c = reinterpret_cast<const T*>(dev_tables + ad.off_sc);
-    d.scale_s = reinterpret_cast<const T*>(dev_tables + ad.off_ss);
+    d.scale_c = reinterpret_cast<const sfac::Spec<T>*>(dev_tables + ad.off_sc);
+    d.scale_s = reinterpret_cast<const sfac::Spec<T>*>(dev_tables + ad.off_ss);
     d.psi = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_psi);
-    d.gpos_c = reinterpret_cast<const T*>(dev_tables + ad.off_gc);
-    d.gpos_s = reinterpret_cast<const T*>(dev_tables + ad.off_gs);
+    d.gpos_c = reinterpret_cast<const sfac::Spec<T>*>(dev_tables + ad.off_gc);
+    d.gpos_s = reinterpret_cast<const sfac::Spec<T>*>(dev_tables + ad.off_gs);
     d.threads = ad.threads;
     d.log2e = ad.log2e;
     d.d2a = t.d2a;
@@ -645,7 +645,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                     threads = 0;
                     for (const auto& d : groups[g]) threads = std::max(threads, d.threads);
                     const int A = keys[g].second / 64, B = keys[g].second % 64, P = std::max(A, B);
-                    glds[g] = (size_t)(threads / P) * A * B * sizeof(sfac::cplx<T>);
+                    glds[g] = (size_t)(threads / P) * sfac::diag2_line_stride(A, B, sizeof(sfac::cplx<T>)) * sizeof(sfac::cplx<T>);
                 }
                 for (const auto& d : groups[g]) starts.push_back(starts.back() + sfac::pass_blocks(d));
                 GroupLaunch l;
