@@ -44,6 +44,36 @@ __device__ __forceinline__ T nonlinear_half_step(T v, T decay, T decay_lo) {
     return v * recip_sqrt(v * v + (q * decay + q * decay_lo));
 }
 
+// The two real lines of a pair at one position: adjacent in memory on strided axes
+// (lstride == 1), where one 2-element access (element-aligned, as the hardware allows) replaces
+// two; a missing second line (two == false) reads as zero and is never touched.
+template <typename T>
+struct alignas(sizeof(T)) RealPair {
+    T a, b;
+};
+template <typename T>
+__device__ __forceinline__ void load_pair(const T* p, long long lstride, bool two, T& x, T& y) {
+    if (lstride == 1 && two) {
+        RealPair<T> v;
+        __builtin_memcpy(&v, p, sizeof(v));
+        x = v.a;
+        y = v.b;
+    } else {
+        x = p[0];
+        y = two ? p[lstride] : (T)0;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store_pair(T* p, long long lstride, bool two, T x, T y) {
+    if (lstride == 1 && two) {
+        const RealPair<T> v = {x, y};
+        __builtin_memcpy(p, &v, sizeof(v));
+    } else {
+        p[0] = x;
+        if (two) p[lstride] = y;
+    }
+}
+
 template <int DIR, typename T>
 __device__ __forceinline__ void run_stage(int R, const cplx<T>* src, cplx<T>* dst, int L, int Ns,
                                           int lines, const cplx<T>* tw) {
@@ -278,9 +308,7 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
             const int n = Line::nat(t, i, k);
             cplx<T> z = {(T)0, (T)0};
             if ((R0 < 2 || k < R0 / 2) && act && n < N) {
-                const T* p = src + (long long)n * tg.kstride;
-                z.x = p[0];
-                if (two) z.y = p[tg.lstride];
+                load_pair(src + (long long)n * tg.kstride, tg.lstride, two, z.x, z.y);
                 if (d.nl_in) {
                     z.x = nonlinear_half_step(z.x, decay, decay_lo);
                     z.y = nonlinear_half_step(z.y, decay, decay_lo);
@@ -311,9 +339,7 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
                     else
                         vmax = fmax(vmax, fmax(ax, ay));
                 }
-                T* p = dst + (long long)n * tg.kstride;
-                p[0] = z.x;
-                if (two) p[tg.lstride] = z.y;
+                store_pair(dst + (long long)n * tg.kstride, tg.lstride, two, z.x, z.y);
             }
         }
     if (d.nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
@@ -343,8 +369,12 @@ __device__ __forceinline__ void stage_tile(const TileGeom<T>& tg, int lpb, cplx<
         cplx<T> v[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            v[j].x = x_in ? gx[j * step] : (T)0;
-            v[j].y = y_in ? gx[j * step + tg.lstride] : (T)0;
+            if (x_in) {
+                load_pair(gx + j * step, tg.lstride, y_in, v[j].x, v[j].y);
+            } else {
+                v[j].x = (T)0;
+                v[j].y = (T)0;
+            }
         }
 #pragma unroll
         for (int j = 0; j < J; ++j) sl[j * P] = v[j];
@@ -354,10 +384,8 @@ __device__ __forceinline__ void stage_tile(const TileGeom<T>& tg, int lpb, cplx<
         for (int j = 0; j < J; ++j) v[j] = sl[j * P];
         T* gw = const_cast<T*>(gx);
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            if (x_in) gw[j * step] = v[j].x;
-            if (y_in) gw[j * step + tg.lstride] = v[j].y;
-        }
+        for (int j = 0; j < J; ++j)
+            if (x_in) store_pair(gw + j * step, tg.lstride, y_in, v[j].x, v[j].y);
     }
 }
 

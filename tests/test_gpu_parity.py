@@ -126,6 +126,23 @@ def _embed_length(n):
     return m
 
 
+@pytest.mark.parametrize("ns,methods", [((2048, 3), (None, "diag")), ((4096, 2), (None,)), ((3, 2048), ("embed",))],
+                         ids=["2048x3", "4096x2", "3x2048"])
+def test_maximum_lengths_fp64(sfac_lib, ns, methods):
+    """The longest lines each method takes: N = 2048 for the embedded method (M = 4096) and
+    N = 4096 for the diagonal one (the automatic choice for N > 2048)."""
+    from paper_2209_08437_amd import sfac
+    alphas = (1.35, 1.8)
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=sum(ns))
+    ref = O.two_level_solve(u0, ns, alphas, 0.05, hs, 0.002, 2)
+    for m in methods:
+        _say(f"case maximum length {ns} method={m}")
+        got, (flags, _) = gpu_solve(u0, ns, alphas, 0.05, hs, 0.002, 2, "f64", m)
+        assert rel_err(got, ref) <= FP64_TOL, m
+        assert flags == 0
+
+
 @pytest.mark.parametrize("le", [2, 3, 4])
 @pytest.mark.parametrize("lpb", [0, 1, 3])
 @pytest.mark.parametrize("ns", [(100, 37), (1023, 9), (9, 16, 33), (700, 5)], ids=lambda s: "x".join(map(str, s)))
