@@ -73,7 +73,10 @@ typedef struct {
     int32_t lines_per_block[3]; /* pairs of real lines per thread block (0 = automatic) */
     int32_t kernel[3];          /* diagonal method: 0 automatic, 1 the generic kernel (every N whose
                                    prime factors are <= 31), 2 the register-resident two-step kernel
-                                   (N = A B for the pairs it is built for; SFAC_EUNSUPPORTED else).
+                                   (N = A B for the pairs it is built for; SFAC_EUNSUPPORTED else),
+                                   3 the same kernel with lines aligned to wavefronts (floor(64/P)
+                                   lines of P = max(A, B) threads each; exchanges need no
+                                   workgroup barrier; lines_per_block counts lines as before).
                                    Nonzero selects the diagonal method under SFAC_METHOD_AUTO and is
                                    SFAC_EINVAL with SFAC_METHOD_EMBED */
 } sfac_options;

@@ -71,9 +71,13 @@ def candidates(n):
     if 64 <= m <= 2048:
         for lpb in (0, 1, 2):
             out.append(("embed", 2, lpb, 0))
-    if any(a * b == n for a, b in DIAG2_PAIRS):
+    pair = [(a, b) for a, b in DIAG2_PAIRS if a * b == n]
+    if pair:
         for lpb in (0, 2, 5, 7, 10):
             out.append(("diag", 0, lpb, 2))
+        lpw = 64 // max(pair[0])
+        for w in (0, 1, 2, 4):
+            out.append(("diag", 0, w * lpw, 3))
     try:
         sfac.axis_tables(n, 1.5, 0.1, 0.01, 0.1, "diag")
         out.append(("diag", 0, 0, 1))

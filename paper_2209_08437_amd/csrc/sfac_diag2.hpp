@@ -10,6 +10,9 @@
 // reads it. Per factor: [psi multiply] forward transform, multiply by the eigenvalue factor,
 // inverse transform, [conj(psi) multiply]: two LDS exchanges per factor, no padding.
 // A line is held by P = max(A, B) threads; threads beyond A (or B) idle in the other step.
+// Lines either follow each other across the block (the exchanges take workgroup barriers) or,
+// in the wavefront-aligned layout, floor(64 / P) lines fill each wavefront and its remaining
+// lanes idle (the exchanges stay inside one wavefront and need no workgroup barrier).
 // Tables are stored per thread in the order the thread walks them (see the host builder).
 #pragma once
 
@@ -24,6 +27,7 @@ struct Diag2Geom {
     static constexpr int N = A * B;
     static constexpr int P = A > B ? A : B;   // threads per line
     static constexpr int E = P;               // registers per thread (max of the two step sizes)
+    static constexpr int LPW = 64 / P;        // lines per wavefront in the wavefront-aligned layout
     // natural position of register k of thread t (t < B, k < A)
     static __device__ __forceinline__ int pos(int t, int k) {
         const int n = B * k + A * t;
@@ -31,10 +35,17 @@ struct Diag2Geom {
     }
 };
 
-template <typename T, int A, int B>
+template <typename T, int A, int B, bool WA>
 struct Diag2Line {
     using G = Diag2Geom<A, B>;
     cplx<T> a[G::E];
+
+    static __device__ __forceinline__ void sync() {
+        if constexpr (WA)
+            wave_sync();
+        else
+            __syncthreads();
+    }
 
     // x <- psi . x (or conj(psi) . x) at this thread's natural positions;
     // psipos[t A + k] = psi at position pos(t, k)
@@ -52,12 +63,12 @@ struct Diag2Line {
     // forward: DFT_A in thread b, exchange, DFT_B in thread k1
     __device__ __forceinline__ void forward(cplx<T>* __restrict__ line, int t) {
         if (t < B) dft<A, -1>(a);
-        __syncthreads();
+        sync();
         if (t < B) {
 #pragma unroll
             for (int k = 0; k < A; ++k) line[k * B + t] = a[k];
         }
-        __syncthreads();
+        sync();
         if (t < A) {
 #pragma unroll
             for (int b = 0; b < B; ++b) a[b] = line[t * B + b];
@@ -69,12 +80,12 @@ struct Diag2Line {
     // inverse: conjugate DFT_B in thread k1, exchange, conjugate DFT_A in thread b
     __device__ __forceinline__ void inverse(cplx<T>* __restrict__ line, int t) {
         if (t < A) dft<B, +1>(a);
-        __syncthreads();
+        sync();
         if (t < A) {
 #pragma unroll
             for (int b = 0; b < B; ++b) line[t * B + b] = a[b];
         }
-        __syncthreads();
+        sync();
         if (t < B) {
 #pragma unroll
             for (int k = 0; k < A; ++k) a[k] = line[k * B + t];

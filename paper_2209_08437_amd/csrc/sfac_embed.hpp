@@ -97,13 +97,6 @@ __device__ __forceinline__ int embed_pos(int t, int i, int k) {
     return (blk << lb) + o + (k << ls);
 }
 
-// Orders the LDS accesses of one wavefront: its lanes execute in lockstep and its LDS operations
-// complete in issue order, so only the compiler must be kept from moving them across.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Bank-conflict-avoiding permutation of positions inside one line: XOR the low bits of the
 // position with bits of its higher digits. The bit choice was measured on gfx950 with the

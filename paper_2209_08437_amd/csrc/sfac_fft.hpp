@@ -75,6 +75,14 @@ __device__ __forceinline__ cplx<T> mul_i(cplx<T> a) {
         return {-a.y, a.x};
 }
 
+// Orders the LDS accesses of one wavefront: its lanes execute in lockstep and its LDS operations
+// complete in issue order, so only the compiler must be kept from moving them across.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------- compile-time trigonometry
 // cos and sin of 2 pi p / q with exact rational reduction to the first octant, then a Taylor
 // series at |x| <= pi/4 (terms to x^29; truncation far below one unit in the last place).

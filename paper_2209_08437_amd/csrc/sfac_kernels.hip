@@ -391,14 +391,22 @@ __device__ __forceinline__ void stage_tile(const TileGeom<T>& tg, int lpb, cplx<
 
 // Diagonal method, register-resident two-step transforms of length N = A B. The tile goes
 // through LDS on the way in and out (the prime-factor layout scatters a thread's positions).
-template <typename T, int A, int B>
+template <typename T, int A, int B, bool WA>
 __device__ __forceinline__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     using G = Diag2Geom<A, B>;
-    using Line = Diag2Line<T, A, B>;
-    const int line = threadIdx.x / G::P;
-    const int t = threadIdx.x - line * G::P;
+    using Line = Diag2Line<T, A, B, WA>;
+    int line, t;
+    if constexpr (WA) {
+        // lines never straddle wavefronts; lanes beyond LPW P idle (t = P takes no part)
+        const int lane = threadIdx.x & 63, lw = lane / G::P;
+        line = (threadIdx.x >> 6) * G::LPW + (lw < G::LPW ? lw : G::LPW - 1);
+        t = lw < G::LPW ? lane - lw * G::P : G::P;
+    } else {
+        line = threadIdx.x / G::P;
+        t = threadIdx.x - line * G::P;
+    }
     const TileGeom<T> tg(d, tile);
-    const bool act = 2 * line < tg.nreal;
+    const bool act = 2 * line < tg.nreal && t < G::P;
     const bool two = 2 * line + 1 < tg.nreal;
     const T decay = d.decay, decay_lo = d.decay_lo;
     stage_tile<T, A, B, true>(tg, d.lpb, lds);
@@ -503,15 +511,15 @@ __global__ void SFAC_EMBED_BOUNDS(LOG2M, LE) embed_pass_multi(const PassDesc<T>*
     run_embed_tile<T, LOG2M, LE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
-template <typename T, int A, int B>
+template <typename T, int A, int B, bool WA>
 __global__ void __launch_bounds__(kBlockThreads, 3) diag2_pass_single(PassDesc<T> d) {
     extern __shared__ unsigned char smem_raw[];
     const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
     if (tile >= d.ntiles) return;
-    run_diag2_tile<T, A, B>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_diag2_tile<T, A, B, WA>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
-template <typename T, int A, int B>
+template <typename T, int A, int B, bool WA>
 __global__ void __launch_bounds__(kBlockThreads, 3) diag2_pass_multi(const PassDesc<T>* __restrict__ descs,
                                                                   const int* __restrict__ block_start,
                                                                   int ndesc) {
@@ -529,28 +537,31 @@ __global__ void __launch_bounds__(kBlockThreads, 3) diag2_pass_multi(const PassD
     const int local = b - block_start[lo];
     const int tile = d.xcd_remap ? xcd_tile(local, d.ntiles) : local;
     if (tile >= d.ntiles) return;
-    run_diag2_tile<T, A, B>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_diag2_tile<T, A, B, WA>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
 template <typename T, int A, int B>
-const void* diag2_fn_ab(bool multi) {
-    return multi ? reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B>)
-                 : reinterpret_cast<const void*>(&diag2_pass_single<T, A, B>);
+const void* diag2_fn_ab(bool multi, bool wave) {
+    if (wave)
+        return multi ? reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B, true>)
+                     : reinterpret_cast<const void*>(&diag2_pass_single<T, A, B, true>);
+    return multi ? reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B, false>)
+                 : reinterpret_cast<const void*>(&diag2_pass_single<T, A, B, false>);
 }
 
-// the (A, B) pairs the host may plan (see diag2_pair)
+// the (A, B) pairs the host may plan (see diag2_pair); wave: the wavefront-aligned layout
 template <typename T>
-const void* diag2_fn(int a, int b, bool multi) {
+const void* diag2_fn(int a, int b, bool multi, bool wave) {
     switch (a * 64 + b) {
-        case 3 * 64 + 5: return diag2_fn_ab<T, 3, 5>(multi);
-        case 5 * 64 + 7: return diag2_fn_ab<T, 5, 7>(multi);
-        case 7 * 64 + 9: return diag2_fn_ab<T, 7, 9>(multi);
-        case 9 * 64 + 11: return diag2_fn_ab<T, 9, 11>(multi);
-        case 11 * 64 + 13: return diag2_fn_ab<T, 11, 13>(multi);
-        case 13 * 64 + 15: return diag2_fn_ab<T, 13, 15>(multi);
-        case 15 * 64 + 17: return diag2_fn_ab<T, 15, 17>(multi);
-        case 5 * 64 + 9: return diag2_fn_ab<T, 5, 9>(multi);
-        case 7 * 64 + 11: return diag2_fn_ab<T, 7, 11>(multi);
+        case 3 * 64 + 5: return diag2_fn_ab<T, 3, 5>(multi, wave);
+        case 5 * 64 + 7: return diag2_fn_ab<T, 5, 7>(multi, wave);
+        case 7 * 64 + 9: return diag2_fn_ab<T, 7, 9>(multi, wave);
+        case 9 * 64 + 11: return diag2_fn_ab<T, 9, 11>(multi, wave);
+        case 11 * 64 + 13: return diag2_fn_ab<T, 11, 13>(multi, wave);
+        case 13 * 64 + 15: return diag2_fn_ab<T, 13, 15>(multi, wave);
+        case 15 * 64 + 17: return diag2_fn_ab<T, 15, 17>(multi, wave);
+        case 5 * 64 + 9: return diag2_fn_ab<T, 5, 9>(multi, wave);
+        case 7 * 64 + 11: return diag2_fn_ab<T, 7, 11>(multi, wave);
         default: return nullptr;
     }
 }
@@ -626,7 +637,8 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
     const int blocks = pass_blocks(d);
     if (blocks <= 0) return hipSuccess;
     if (d.method == 2 || (d.method == 1 && d.d2a > 0)) {
-        const void* fn = d.method == 2 ? embed_fn<T>(d.log2m, d.log2e, false) : diag2_fn<T>(d.d2a, d.d2b, false);
+        const void* fn = d.method == 2 ? embed_fn<T>(d.log2m, d.log2e, false)
+                                       : diag2_fn<T>(d.d2a, d.d2b, false, d.d2wave != 0);
         if (!fn) return hipErrorInvalidValue;
         void* args[] = {const_cast<PassDesc<T>*>(&d)};
         return hipLaunchKernel(fn, dim3(blocks), dim3(d.threads), args, lds_bytes, stream);
@@ -642,7 +654,7 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
     if (total_blocks <= 0) return hipSuccess;
     if (kind == 1 || kind == 2) {
         const void* fn = kind == 1 ? embed_fn<T>(variant / 8, variant % 8, true)
-                                   : diag2_fn<T>(variant / 64, variant % 64, true);
+                                   : diag2_fn<T>((variant % 4096) / 64, variant % 64, true, variant >= 4096);
         if (!fn) return hipErrorInvalidValue;
         void* args[] = {&descs_dev, &block_start_dev, &ndesc};
         return hipLaunchKernel(fn, dim3(total_blocks), dim3(threads), args, lds_bytes, stream);
@@ -667,12 +679,13 @@ hipError_t allow_lds(size_t lds_bytes) {
             }
     for (int a = 3; a <= 17; ++a)
         for (int b = a; b <= 17; ++b)
-            for (int multi = 0; multi < 2; ++multi) {
-                const void* fn = diag2_fn<T>(a, b, multi);
-                if (!fn) continue;
-                e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-                if (e != hipSuccess) return e;
-            }
+            for (int multi = 0; multi < 2; ++multi)
+                for (int wave = 0; wave < 2; ++wave) {
+                    const void* fn = diag2_fn<T>(a, b, multi, wave);
+                    if (!fn) continue;
+                    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+                    if (e != hipSuccess) return e;
+                }
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_multi<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }

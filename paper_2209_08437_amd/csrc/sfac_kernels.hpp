@@ -58,6 +58,7 @@ struct PassDesc {
     int ntiles;                      // tiles in this pass
     int nl_in, nl_out;               // apply J^Q_{tau/2} on load / on store (+ statistics)
     int xcd_remap;                   // group neighbouring tiles per XCD
+    int d2wave;                      // two-step diagonal kernel: wavefront-aligned line layout
     int log2m;                       // embed: log2 of the transform length
     int log2e;                       // embed: log2 of the largest elements-per-thread count (3 or 4)
     int d2a, d2b;                    // diag: N = d2a * d2b for the two-step kernel, 0 for the generic one
@@ -73,7 +74,8 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
 
 // One launch over several instances' tiles of one pass; every descriptor of the launch uses the
 // same kernel variant; `threads` is the block size (the group's largest).
-// kind: 0 generic, 1 embedded (variant = log2m * 8 + log2e), 2 two-step diagonal (variant = a * 64 + b)
+// kind: 0 generic, 1 embedded (variant = log2m * 8 + log2e), 2 two-step diagonal (variant = a * 64 + b,
+// plus 4096 for the wavefront-aligned line layout)
 template <typename T>
 hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const PassDesc<T>* descs_dev,
                                   const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,

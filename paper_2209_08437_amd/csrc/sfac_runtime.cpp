@@ -48,6 +48,7 @@ struct AxisDevice {
     int lpb = 1;
     int threads = 256;
     int log2e = 4;
+    int d2wave = 0;   // two-step diagonal kernel in the wavefront-aligned layout
     size_t lds = 0;
 };
 
@@ -145,7 +146,8 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
         in->alpha[a] = alpha[a];
         in->h[a] = h[a];
         const int kern = opt ? opt->kernel[a] : 0;
-        if (kern < 0 || kern > 2) return fail(SFAC_EINVAL, "%saxis %d: kernel = %d, expected 0, 1 or 2", who, a + 1, kern);
+        if (kern < 0 || kern > 3)
+            return fail(SFAC_EINVAL, "%saxis %d: kernel = %d, expected 0, 1, 2 or 3", who, a + 1, kern);
         int m = methods ? methods[a] : SFAC_METHOD_AUTO;
         if (kern != 0 && m == SFAC_METHOD_EMBED)
             return fail(SFAC_EINVAL, "%saxis %d: a diagonal-method kernel was chosen for the embedded method", who,
@@ -171,8 +173,8 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
         in->ax[a].log2e = log2e;
         sfac::AxisParams p{n[a], alpha[a], eps, tau, h[a]};
         std::string err = sfac::build_axis_tables(p, m, &in->ax[a].host, log2e, kern != 1);
-        if (!err.empty() && kern == 2 && m == SFAC_METHOD_DIAG) err = "";
-        if (kern == 2 && m == SFAC_METHOD_DIAG && in->ax[a].host.d2a == 0)
+        if (!err.empty() && kern >= 2 && m == SFAC_METHOD_DIAG) err = "";
+        if (kern >= 2 && m == SFAC_METHOD_DIAG && in->ax[a].host.d2a == 0)
             return fail(SFAC_EUNSUPPORTED, "%saxis %d: N = %d is not a product the register-resident diagonal "
                         "kernel handles", who, a + 1, n[a]);
         if (!err.empty()) {
@@ -209,13 +211,25 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
             // two-step diagonal kernel: P = max(A, B) threads per line; by default at most 40 KB
             // of LDS lines per block, so that four blocks fit a CU
             const int P = std::max(in->ax[a].host.d2a, in->ax[a].host.d2b);
-            int lpb = std::min<int>(sfac::kBlockThreads / P, std::max<size_t>(1, 40960 / (elem * (size_t)L)));
-            while (lpb > 1 && (lines_total + lpb - 1) / lpb < 1024) lpb >>= 1;
-            if (opt && opt->lines_per_block[a] > 0) lpb = std::min(opt->lines_per_block[a], sfac::kBlockThreads / P);
+            const size_t ls = sfac::diag2_line_stride(in->ax[a].host.d2a, in->ax[a].host.d2b, (int)elem);
+            const bool wave = kern == 3;
+            const int lpw = 64 / P;   // lines per wavefront in the wavefront-aligned layout
+            const int max_lines = wave ? (sfac::kBlockThreads / 64) * lpw : sfac::kBlockThreads / P;
+            int lpb = std::min<int>(max_lines, std::max<size_t>(1, 40960 / (elem * ls)));
+            if (wave) lpb = std::max(lpw, lpb / lpw * lpw);
+            while (lpb > (wave ? lpw : 1) && (lines_total + lpb - 1) / lpb < 1024) lpb = wave ? lpb - lpw : lpb >> 1;
+            if (opt && opt->lines_per_block[a] > 0) lpb = std::min(opt->lines_per_block[a], max_lines);
             lpb = std::max(1, (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2)));
             in->ax[a].lpb = lpb;
-            in->ax[a].threads = lpb * P;
-            in->ax[a].lds = elem * (size_t)sfac::diag2_line_stride(in->ax[a].host.d2a, in->ax[a].host.d2b, (int)elem) * lpb;
+            in->ax[a].d2wave = wave ? 1 : 0;
+            if (wave) {
+                const int waves = (lpb + lpw - 1) / lpw;
+                in->ax[a].threads = waves * 64;
+                in->ax[a].lds = elem * ls * (size_t)(waves * lpw);   // every line slot of the block
+            } else {
+                in->ax[a].threads = lpb * P;
+                in->ax[a].lds = elem * ls * lpb;
+            }
         } else {
             // generic kernel: two LDS buffers per line, as many lines as fit the budget
             const size_t per_line = 2 * elem * (size_t)L;
@@ -253,6 +267,7 @@ sfac::PassDesc<T> make_desc(const Instance& in, int a, unsigned char* dev_tables
     d.log2e = ad.log2e;
     d.d2a = t.d2a;
     d.d2b = t.d2b;
+    d.d2wave = ad.d2wave;
     d.psi2 = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_psi2);
     d.log2m = 0;
     while ((1 << d.log2m) < t.length) ++d.log2m;
@@ -622,7 +637,9 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                 sfac::PassDesc<T> d = make_desc<T>(p->in, pass, p->dev, static_cast<T*>(us[i]), p->stat_max(),
                                                    p->stat_flags());
                 const int kind = d.method == SFAC_METHOD_EMBED ? 1 : (d.d2a > 0 ? 2 : 0);
-                const std::pair<int, int> key(kind, kind == 1 ? d.log2m * 8 + d.log2e : (kind == 2 ? d.d2a * 64 + d.d2b : 0));
+                const int variant = kind == 1 ? d.log2m * 8 + d.log2e
+                                              : (kind == 2 ? d.d2a * 64 + d.d2b + (d.d2wave ? 4096 : 0) : 0);
+                const std::pair<int, int> key(kind, variant);
                 size_t g = std::find(keys.begin(), keys.end(), key) - keys.begin();
                 if (g == keys.size()) {
                     keys.push_back(key);
@@ -641,11 +658,14 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                     const int E = 1 << sfac::embed_log2e(keys[g].second / 8, keys[g].second % 8);
                     glds[g] = (size_t)threads * E * sizeof(sfac::cplx<T>);
                 } else if (keys[g].first == 2) {
-                    // a full block of P-thread lines; lines beyond a descriptor's lpb idle
+                    // a full block of P-thread lines (or of wavefronts of 64/P lines); lines beyond
+                    // a descriptor's lpb idle
                     threads = 0;
                     for (const auto& d : groups[g]) threads = std::max(threads, d.threads);
-                    const int A = keys[g].second / 64, B = keys[g].second % 64, P = std::max(A, B);
-                    glds[g] = (size_t)(threads / P) * sfac::diag2_line_stride(A, B, sizeof(sfac::cplx<T>)) * sizeof(sfac::cplx<T>);
+                    const int v = keys[g].second % 4096;
+                    const int A = v / 64, B = v % 64, P = std::max(A, B);
+                    const int lines = keys[g].second >= 4096 ? (threads / 64) * (64 / P) : threads / P;
+                    glds[g] = (size_t)lines * sfac::diag2_line_stride(A, B, sizeof(sfac::cplx<T>)) * sizeof(sfac::cplx<T>);
                 }
                 for (const auto& d : groups[g]) starts.push_back(starts.back() + sfac::pass_blocks(d));
                 GroupLaunch l;

@@ -166,13 +166,14 @@ def test_embed_schedules_fp64(sfac_lib, ns, le, lpb):
     assert rel_err(u.cpu().numpy(), ref) <= FP64_TOL
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 @pytest.mark.parametrize("lpb", [0, 1, 5])
 @pytest.mark.parametrize("ns", [(63, 30), (255, 11), (15, 35, 63), (99, 143), (1023, 6)],
                          ids=lambda s: "x".join(map(str, s)))   # 1023 = 3 11 31: generic kernel only
 def test_diag_kernels_fp64(sfac_lib, ns, kernel, lpb):
     """The diagonal method (length-N transforms, psi twiddles) in the generic kernel (1) and in
-    the register-resident two-step kernel (2, N = A B); axes it cannot take use the embedded one."""
+    the register-resident two-step kernel (2, N = A B; 3, its wavefront-aligned layout); axes the
+    two-step kernel cannot take use the embedded one."""
     from paper_2209_08437_amd import autotune, sfac
     torch = _torch()
     rng = np.random.default_rng(sum(ns) + kernel)
