@@ -163,3 +163,23 @@ def test_batch_options_are_validated(sfac_lib):
     assert st == sfac.EINVAL and not h.value
     msg = L.sfac_last_error().decode()
     assert "instance 0" in msg and "elems_log2" in msg
+
+
+def test_plain_c_client_compiles_links_and_runs(sfac_lib, tmp_path):
+    """include/sfac.h is a C header: a C11 program (gcc, no C++) links libsfac.so and makes the
+    host-only calls."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    libdir = os.path.dirname(sfac.LIB_PATH)
+    exe = str(tmp_path / "host_calls")
+    cmd = [gcc, "-std=c11", "-Wall", "-Werror", "-o", exe, os.path.join(root, "tests", "c_abi", "host_calls.c"),
+           "-I", os.path.join(root, "include"), "-L", libdir, "-lsfac", f"-Wl,-rpath,{libdir}", "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr + r.stdout
+    assert "ok" in r.stdout
