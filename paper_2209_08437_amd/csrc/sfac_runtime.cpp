@@ -594,10 +594,43 @@ sfac_status sfac_axis_tables(int32_t n, double alpha, double eps, double tau, do
 // A group is a reusable launch workspace: sfac_group_step advances any set of plans together,
 // with one launch per (pass, arithmetic, kernel variant) covering every plan that needs it.
 struct sfac_group_s {
+    static constexpr int kAux = 4;        // streams the launches of one pass fan out to
     hipStream_t stream = nullptr;
     unsigned char* arena = nullptr;        // descriptors and block offsets of the current call
     size_t arena_bytes = 0;
     std::vector<unsigned char> host;
+    hipStream_t capture = nullptr;         // private streams used only while capturing a step
+    hipStream_t aux[kAux] = {};
+    hipEvent_t fork = nullptr, join[kAux] = {};
+    std::vector<hipGraph_t> graphs;        // the current call's step graphs (one per phase)
+    std::vector<hipGraphExec_t> execs;
+
+    void drop_graphs() {
+        for (auto x : execs) hipGraphExecDestroy(x);
+        for (auto x : graphs) hipGraphDestroy(x);
+        execs.clear();
+        graphs.clear();
+    }
+    hipError_t ensure_streams() {
+        hipError_t e = hipSuccess;
+        if (!capture) e = hipStreamCreateWithFlags(&capture, hipStreamNonBlocking);
+        for (int k = 0; k < kAux && e == hipSuccess; ++k)
+            if (!aux[k]) e = hipStreamCreateWithFlags(&aux[k], hipStreamNonBlocking);
+        if (e == hipSuccess && !fork) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        for (int k = 0; k < kAux && e == hipSuccess; ++k)
+            if (!join[k]) e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
+        return e;
+    }
+    void release() {
+        drop_graphs();
+        if (fork) hipEventDestroy(fork);
+        for (int k = 0; k < kAux; ++k) {
+            if (join[k]) hipEventDestroy(join[k]);
+            if (aux[k]) hipStreamDestroy(aux[k]);
+        }
+        if (capture) hipStreamDestroy(capture);
+        if (arena) hipFree(arena);
+    }
 };
 
 namespace {
@@ -606,7 +639,7 @@ struct GroupLaunch {
     size_t off_desc, off_start;
     int ndesc, blocks;
     int64_t reps;
-    int phase;
+    int phase, pass;
     int fp64, kind, variant, threads;
     size_t lds;
 };
@@ -675,6 +708,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                 l.blocks = starts.back();
                 l.reps = bound - done;
                 l.phase = (int)ph;
+                l.pass = pass;
                 l.fp64 = std::is_same<T, double>::value;
                 l.kind = keys[g].first;
                 l.variant = keys[g].second;
@@ -688,11 +722,46 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
 }
 
 template <typename T>
-hipError_t group_launch(sfac_group g, const GroupLaunch& l) {
+hipError_t group_launch(sfac_group g, const GroupLaunch& l, hipStream_t s) {
     return sfac::launch_axis_pass_multi<T>(l.kind, l.variant, l.threads,
                                            reinterpret_cast<const sfac::PassDesc<T>*>(g->arena + l.off_desc),
                                            reinterpret_cast<const int*>(g->arena + l.off_start), l.ndesc,
-                                           l.blocks, l.lds, g->stream);
+                                           l.blocks, l.lds, s);
+}
+
+// Captures one step of a phase: pass after pass; the launches of one pass (different kernel
+// variants and arithmetic, disjoint plans) fan out over the auxiliary streams and join before
+// the next pass, so every plan still sees its passes in order.
+sfac_status capture_step(sfac_group g, const GroupLaunch* first, const GroupLaunch* last, hipGraph_t* graph) {
+    hipError_t e = hipStreamBeginCapture(g->capture, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (int pass = 0; pass < 3 && le == hipSuccess; ++pass) {
+        std::vector<const GroupLaunch*> ls;
+        for (const GroupLaunch* l = first; l != last; ++l)
+            if (l->pass == pass) ls.push_back(l);
+        if (ls.empty()) continue;
+        if (ls.size() == 1) {
+            le = ls[0]->fp64 ? group_launch<double>(g, *ls[0], g->capture) : group_launch<float>(g, *ls[0], g->capture);
+            continue;
+        }
+        le = hipEventRecord(g->fork, g->capture);
+        const int used = (int)std::min<size_t>(ls.size(), sfac_group_s::kAux);
+        for (int k = 0; k < used && le == hipSuccess; ++k) le = hipStreamWaitEvent(g->aux[k], g->fork, 0);
+        for (size_t k = 0; k < ls.size() && le == hipSuccess; ++k) {
+            hipStream_t s = g->aux[k % sfac_group_s::kAux];
+            le = ls[k]->fp64 ? group_launch<double>(g, *ls[k], s) : group_launch<float>(g, *ls[k], s);
+        }
+        for (int k = 0; k < used && le == hipSuccess; ++k) le = hipEventRecord(g->join[k], g->aux[k]);
+        for (int k = 0; k < used && le == hipSuccess; ++k) le = hipStreamWaitEvent(g->capture, g->join[k], 0);
+    }
+    e = hipStreamEndCapture(g->capture, graph);
+    if (le != hipSuccess) {
+        if (e == hipSuccess && *graph) hipGraphDestroy(*graph);
+        return hip_fail(le, "grouped kernel launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    return SFAC_OK;
 }
 
 sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void* const* u_dev,
@@ -730,9 +799,12 @@ sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void*
         if (e == hipSuccess) e = sfac::allow_lds<float>(lds_need);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
     }
-    // the arena may still be read by the previous call's launches
+    // the arena (and the previous call's graphs) may still be in use by the previous call
     hipError_t e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    g->drop_graphs();
+    e = g->ensure_streams();
+    if (e != hipSuccess) return hip_fail(e, "group streams and events");
     if (g->host.size() > g->arena_bytes) {
         if (g->arena) hipFree(g->arena);
         g->arena = nullptr;
@@ -744,18 +816,24 @@ sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void*
     }
     e = hipMemcpy(g->arena, g->host.data(), g->host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy launch arena");
-    // phase after phase; inside a phase, step after step; inside a step, the launches in order
+    // phase after phase; one captured step per phase, replayed for the phase's steps
     std::stable_sort(plan.begin(), plan.end(),
                      [](const GroupLaunch& a, const GroupLaunch& b) { return a.phase < b.phase; });
     size_t li = 0;
     while (li < plan.size()) {
         size_t lj = li;
         while (lj < plan.size() && plan[lj].phase == plan[li].phase) ++lj;
+        hipGraph_t graph = nullptr;
+        sfac_status st = capture_step(g, plan.data() + li, plan.data() + lj, &graph);
+        if (st != SFAC_OK) return st;
+        g->graphs.push_back(graph);
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        g->execs.push_back(exec);
         for (int64_t r = 0; r < plan[li].reps; ++r) {
-            for (size_t k = li; k < lj; ++k) {
-                e = plan[k].fp64 ? group_launch<double>(g, plan[k]) : group_launch<float>(g, plan[k]);
-                if (e != hipSuccess) return hip_fail(e, "grouped kernel launch");
-            }
+            e = hipGraphLaunch(exec, g->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
         }
         li = lj;
     }
@@ -796,7 +874,7 @@ sfac_status sfac_group_destroy(sfac_group g) {
     g_error.clear();
     if (!g) return SFAC_OK;
     hipStreamSynchronize(g->stream);
-    if (g->arena) hipFree(g->arena);
+    g->release();
     delete g;
     return SFAC_OK;
 }
