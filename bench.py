@@ -81,11 +81,21 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None):
                                  path=autotune.PACKAGED, save=False)
         sched = {k: best[k] for k in ("method", "elems_log2", "lines_per_block", "kernel")}
         log(f"[bench] {dtype}: tuned schedule {sched} (pass us {[round(x * 1e3, 1) for x in best['ms']]})")
+    # plan creation: host tables in long double, one device allocation, upload (first step
+    # captures the step graphs and is timed apart from it)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
     plan = sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, **sched)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - tp) * 1e3
     methods = [plan.method(a + 1) for a in range(inst.dims)]
     log(f"[bench] {dtype}: methods per axis {methods}; warmup {warmup} steps")
+    tp = time.perf_counter()
     plan.step(u, warmup)
     torch.cuda.synchronize()
+    warm_ms = (time.perf_counter() - tp) * 1e3
+    log(f"[bench] {dtype}: plan created in {plan_ms:.2f} ms; {warmup} warm-up steps (graph capture included) "
+        f"{warm_ms:.2f} ms")
     u.copy_(u0)
     plan.reset_flags()
     torch.cuda.synchronize()
@@ -113,6 +123,7 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None):
     result = {
         "wall_s": wall, "gpu_ms": gpu_ms, "flags": flags, "max_abs": vmax,
         "pass_ms": pass_ms, "pass_ms_events": pass_ev, "methods": methods, "state": u.double().cpu().numpy(), "schedule": sched,
+        "plan_create_ms": plan_ms, "warmup_ms": warm_ms,
     }
     plan.close()
     return result
@@ -329,7 +340,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": desc, "grid": list(inst.ns), "points": pts,
                    "methods": [m for m, _ in main_r["methods"]], "schedule": main_r["schedule"],
-                   "effective_GBps": round(value * 2 * inst.dims * esize / 1e9, 2)},
+                   "effective_GBps": round(value * 2 * inst.dims * esize / 1e9, 2),
+                   "plan_create_ms": round(main_r["plan_create_ms"], 3),
+                   "warmup_ms": round(main_r["warmup_ms"], 3)},
         "roofline": roof,
     }
     if not args.no_fp32 and args.dtype == "f64":
@@ -341,7 +354,8 @@ def main():
                        "ms_per_step": round(r32["wall_s"] * 1e3 / steps, 5),
                        "rel_err_vs_fp64_gpu": float(np.abs(r32["state"] - ref).max() / np.abs(ref).max()),
                        "max_abs": r32["max_abs"], "flags": r32["flags"],
-                       "pass_ms": [round(x, 5) for x in r32["pass_ms"]], "schedule": r32["schedule"]}
+                       "pass_ms": [round(x, 5) for x in r32["pass_ms"]], "schedule": r32["schedule"],
+                       "plan_create_ms": round(r32["plan_create_ms"], 3)}
     out["max_abs"] = main_r["max_abs"]
     out["flags"] = main_r["flags"]
     if not args.no_cpu:

@@ -121,6 +121,7 @@ class Server:
         peak_bytes = 0
         t0 = self.clock()
         busy = 0.0
+        admit_s = []         # per admitted request: plan tables, device upload of state and tables
         while nxt < len(reqs) or queue or active:
             now = self.clock() - t0
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
@@ -143,7 +144,10 @@ class Server:
                     tk.finished = tk.admitted
                     tk.result = np.array(r.inst.u0, dtype=np.float64, copy=True)
                     continue
-                active.append([tk, self.ex.admit(r.inst, r.dtype), tk.steps, need])
+                ta = self.clock()
+                handle = self.ex.admit(r.inst, r.dtype)
+                admit_s.append(self.clock() - ta)
+                active.append([tk, handle, tk.steps, need])
                 used += need
             peak_active = max(peak_active, len(active))
             peak_bytes = max(peak_bytes, used)
@@ -171,6 +175,8 @@ class Server:
         makespan = self.clock() - t0
         done = [t for t in tickets.values() if t.finished is not None]
         lat = np.array([t.latency for t in done]) if done else np.zeros(0)
+        wait = np.array([t.admitted - t.arrival for t in done]) if done else np.zeros(0)
+        adm = np.array(admit_s)
         work = sum(t.points * t.steps for t in done)
         span_arrivals = (reqs[-1].arrival - reqs[0].arrival) if len(reqs) > 1 else 0.0
         offered = sum(t.points * t.steps for t in tickets.values())
@@ -184,5 +190,9 @@ class Server:
             "mean_latency_s": float(lat.mean()) if len(lat) else None,
             "offered_gps": offered / span_arrivals if span_arrivals > 0 else math.inf,
             "peak_active": peak_active, "peak_bytes": peak_bytes, "budget_bytes": self.budget,
+            "p50_queue_wait_s": float(np.percentile(wait, 50)) if len(wait) else None,
+            "admit_p50_ms": float(np.percentile(adm, 50)) * 1e3 if len(adm) else None,
+            "admit_max_ms": float(adm.max()) * 1e3 if len(adm) else None,
+            "admit_total_s": float(adm.sum()),
         }
         return [tickets[r.rid] for r in sorted(reqs, key=lambda r: r.rid)], summary

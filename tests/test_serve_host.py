@@ -77,6 +77,9 @@ def test_all_complete_with_results_equal_to_lone_solves():
         assert np.array_equal(tk.result, alone)          # ticks split the steps; bitwise the same
         assert tk.latency >= 0 and tk.admitted >= tk.arrival
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
+    # admission cost (plan tables and upload) is timed per admitted request
+    assert 0 <= summ["admit_p50_ms"] <= summ["admit_max_ms"]
+    assert summ["p50_queue_wait_s"] >= 0
 
 
 def test_budget_limits_admission_and_oversize_is_rejected():
