@@ -186,13 +186,24 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, 
     }
 
     // Remark 1: spectra (real parts; the imaginary parts vanish by symmetry)
+    // Angle indices (2 j k mod 2N and k (2j + 1) mod 2N) advance by a fixed step per term, kept
+    // reduced by one conditional subtraction instead of a division per term.
     const std::vector<ld> cosn = half_turn_cosines(N);  // cos(pi r / N)
+    const int twoN = 2 * N;
+    auto advance = [](int& r, int step, int mod) {
+        r += step;
+        if (r >= mod) r -= mod;
+    };
     std::vector<ld> lam(N), mu(N);
     for (int j = 0; j < N; ++j) {
         ld sl = 0, sm = 0;
+        const int st1 = (int)((2LL * j) % twoN), st2 = (int)((2LL * j + 1) % twoN);
+        int r1 = 0, r2 = 0;  // 2 j k and k (2j + 1), mod 2N, at k
         for (int k = 0; k < N; ++k) {
-            sl += c[k] * cosn[(size_t)((2LL * j * k) % (2LL * N))];
-            sm += s[k] * cosn[(size_t)(((long long)k * (2LL * j + 1)) % (2LL * N))];
+            sl += c[k] * cosn[r1];
+            sm += s[k] * cosn[r2];
+            advance(r1, st1, twoN);
+            advance(r2, st2, twoN);
         }
         lam[j] = sl;
         mu[j] = sm;
@@ -262,9 +273,13 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, 
         std::vector<ld> gam(N), sig(N);
         for (int k = 0; k < N; ++k) {
             ld sg = 0, ss = 0;
+            const int st = (int)((2LL * k) % twoN);
+            int r1 = 0, r2 = k % twoN;  // 2 j k and k (2j + 1), mod 2N, at j
             for (int j = 0; j < N; ++j) {
-                sg += ec[j] * cosn[(size_t)((2LL * j * k) % (2LL * N))];
-                ss += es[j] * cosn[(size_t)(((long long)k * (2LL * j + 1)) % (2LL * N))];
+                sg += ec[j] * cosn[r1];
+                ss += es[j] * cosn[r2];
+                advance(r1, st, twoN);
+                advance(r2, st, twoN);
             }
             gam[k] = sg / (ld)N;
             sig[k] = ss / (ld)N;
@@ -278,10 +293,13 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, 
         t.scale_s.resize(L);
         for (int m = 0; m < L; ++m) {
             ld gc = gam[0], gs = sig[0];
+            const int st = m % L;
+            int r = st;  // m d mod M, at d
             for (int d = 1; d < N; ++d) {
-                ld cs = cosm[(size_t)(((long long)m * d) % L)];
+                const ld cs = cosm[r];
                 gc += 2.0L * gam[d] * cs;
                 gs += 2.0L * sig[d] * cs;
+                advance(r, st, L);
             }
             t.scale_c[m] = (double)(gc / (ld)L);
             t.scale_s[m] = (double)(gs / (ld)L);
