@@ -73,7 +73,8 @@ def candidates(n):
             out.append(("embed", 2, lpb, 0))
     pair = [(a, b) for a, b in DIAG2_PAIRS if a * b == n]
     if pair:
-        for lpb in (0, 2, 5, 7, 10):
+        full = 256 // max(pair[0])          # lines of a whole 256-thread block
+        for lpb in sorted({0, 2, 5, 7, 10, full}):
             out.append(("diag", 0, lpb, 2))
         lpw = 64 // max(pair[0])
         for w in (0, 1, 2, 4):
@@ -182,3 +183,40 @@ def schedules(instances, dtype="f64", path=None, tune_missing=True, reps=10):
             done[key] = sch
         out.append(done[key])
     return out
+
+
+def _main():
+    """Tune every distinct shape of the named workloads for both arithmetic types into a cache
+    file (the packaged MI355X table is written this way, on one MI355X):
+    python -m paper_2209_08437_amd.autotune --out FILE large_2d_1023 large_3d_255 plain_2d_63 batched_2d
+    Shapes already in FILE are kept; --fresh starts from an empty file."""
+    import argparse
+    import time
+    from . import workloads as W
+    ap = argparse.ArgumentParser(description=_main.__doc__)
+    ap.add_argument("workloads", nargs="+")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--fresh", action="store_true")
+    ap.add_argument("--reps", type=int, default=10)
+    a = ap.parse_args()
+    if a.fresh and os.path.exists(a.out):
+        os.remove(a.out)
+    seen = set()
+    for name in a.workloads:
+        made = getattr(W, name)()
+        insts = made if isinstance(made, list) else [made]
+        for dt in ("f64", "f32"):
+            for inst in insts:
+                key = (tuple(inst.ns), dt)
+                if key in seen:
+                    continue
+                seen.add(key)
+                t0 = time.perf_counter()
+                best = tune(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dt, reps=a.reps, path=a.out)
+                print(f"{name} {dt} {tuple(inst.ns)}: {{{', '.join(f'{k}: {best[k]}' for k in SCHEDULE_KEYS)}}} "
+                      f"pass us {[round(x * 1e3, 1) for x in best['ms']]} ({time.perf_counter() - t0:.1f} s)",
+                      flush=True)
+
+
+if __name__ == "__main__":
+    _main()
