@@ -46,7 +46,7 @@ __device__ __forceinline__ T nonlinear_half_step(T v, T decay, T decay_lo) {
 
 // FP32 fast form for the register-resident kernels: hardware reciprocal square root estimate
 // (inputs below the normal range scaled by 2^24, the result by 2^12) and one Newton step, within
-// about one ulp at a fifth of the instructions of a correctly rounded square root and division.
+// about one ulp at a third of the instructions of a correctly rounded square root and division.
 // The exact flow maps [-1, 1] into itself (the discrete maximum principle of the nonlinear
 // step); the estimate's rounding may land one ulp outside, so the result is put back for
 // |v| <= 1 only, and values pushed past 1 by the linear step still show.
