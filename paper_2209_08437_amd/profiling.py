@@ -15,6 +15,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -24,13 +25,28 @@ PASS_KERNEL_TAGS = ("_pass_single", "_pass_multi")
 KERNEL_SOURCES = ("sfac_kernels.hip", "sfac_kernels.hpp", "sfac_fft.hpp", "sfac_embed.hpp", "sfac_diag2.hpp")
 
 
-def source_hash():
-    """SHA-256 over the names and bytes of the device-code sources, first 16 hex digits."""
+_COMMENT_OR_STRING = re.compile(r'"(?:\\.|[^"\\\n])*"|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def code_text(text):
+    """Source text with comments removed (string literals kept), lines stripped, blank lines
+    dropped: what the compiler sees, up to layout."""
+    text = _COMMENT_OR_STRING.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", text)
+    return "\n".join(line.strip() for line in text.splitlines() if line.strip())
+
+
+def source_hash(read=None):
+    """SHA-256 over the names and code text (code_text) of the device-code sources, first 16 hex
+    digits; comment-only edits leave it unchanged. `read(name)` returns a source's text (default:
+    the files under csrc/)."""
+    if read is None:
+        def read(name):
+            with open(os.path.join(CSRC, name), encoding="utf-8") as f:
+                return f.read()
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         h.update(name.encode())
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(f.read())
+        h.update(code_text(read(name)).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,0 +1,109 @@
+"""Host tests of the profile helpers: the device-code fingerprint that keys the committed HBM
+traffic record, the counter calibration and the per-axis attribution of pass dispatches."""
+import csv
+import json
+import os
+
+import pytest
+
+from paper_2209_08437_amd import profiling as P
+
+PASS = "void sfac::(anonymous namespace)::embed_pass_single<double, 11, 3>(sfac::PassDesc<double>)"
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def _sources():
+    out = {}
+    for name in P.KERNEL_SOURCES:
+        with open(os.path.join(P.CSRC, name), encoding="utf-8") as f:
+            out[name] = f.read()
+    return out
+
+
+def test_code_text_drops_comments_and_keeps_strings():
+    text = 'int a = 1; // one\n/* two\n   lines */ const char* s = "x // y /* z */";\n\n   b();  \n'
+    assert P.code_text(text) == 'int a = 1;\nconst char* s = "x // y /* z */";\nb();'
+
+
+def test_source_hash_follows_code_not_comments():
+    src = _sources()
+    base = P.source_hash(lambda n: src[n])
+    assert base == P.source_hash()
+    name = "sfac_kernels.hip"
+    # a comment edited, added and a blank line inserted: same code, same fingerprint
+    edited = src[name].replace("//", "// edited:", 1) + "\n\n// trailing note\n"
+    assert P.source_hash(lambda n: edited if n == name else src[n]) == base
+    # a code edit changes it
+    assert "kBlockThreads" in src["sfac_kernels.hpp"]
+    code = src["sfac_kernels.hpp"].replace("kBlockThreads", "kBlockThreadz", 1)
+    assert P.source_hash(lambda n: code if n == "sfac_kernels.hpp" else src[n]) != base
+
+
+def _write_pmc(path, rows):
+    fields = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(fields, r)))
+
+
+def test_traffic_calibration_and_axis_attribution(tmp_path):
+    # two steps of a 2D run: dispatches alternate axis 1, axis 2; each dispatch's counter is
+    # reported in two parts (as per-XCD rows) that must be summed; a copy kernel in between is
+    # not a pass kernel and must be ignored
+    fetch = [(1, PASS, "FETCH_SIZE", 60.0), (1, PASS, "FETCH_SIZE", 40.0),   # axis 1: 100
+             (2, PASS, "FETCH_SIZE", 150.0), (2, PASS, "FETCH_SIZE", 50.0),  # axis 2: 200
+             (3, COPY, "FETCH_SIZE", 9999.0),
+             (4, PASS, "FETCH_SIZE", 110.0),                                 # axis 1: 110
+             (5, PASS, "FETCH_SIZE", 210.0)]                                 # axis 2: 210
+    write = [(1, PASS, "WRITE_SIZE", 300.0), (2, PASS, "WRITE_SIZE", 400.0),
+             (4, PASS, "WRITE_SIZE", 320.0), (5, PASS, "WRITE_SIZE", 420.0)]
+    copy_bytes = 1 << 20
+    # the copy probe: 20 large copies whose FETCH counter reads half the copied bytes and whose
+    # WRITE counter reads all of them, plus one small unrelated dispatch
+    cf = [(i, COPY, "FETCH_SIZE", copy_bytes / 2 / 1024) for i in range(1, 21)] + [(21, COPY, "FETCH_SIZE", 1.0)]
+    cw = [(i, COPY, "WRITE_SIZE", copy_bytes / 1024) for i in range(1, 21)] + [(21, COPY, "WRITE_SIZE", 1.0)]
+    paths = {}
+    for key, rows in (("f", fetch), ("w", write), ("cf", cf), ("cw", cw)):
+        paths[key] = str(tmp_path / f"{key}.csv")
+        _write_pmc(paths[key], rows)
+    t = P.traffic_from_pmc(paths["f"], paths["w"], paths["cf"], paths["cw"], copy_bytes, 2)
+    assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
+    a1, a2 = t["per_axis"]
+    assert (a1["dispatches"], a2["dispatches"]) == (2, 2)
+    assert a1["fetch_kib_raw"] == 105.0 and a2["fetch_kib_raw"] == 205.0
+    assert a1["write_kib_raw"] == 310.0 and a2["write_kib_raw"] == 410.0
+    assert a1["bytes"] == round(105.0 * 1024 * 2 + 310.0 * 1024)
+    assert a2["bytes"] == round(205.0 * 1024 * 2 + 410.0 * 1024)
+    assert a1["kernel"] == "embed_pass_single<double, 11, 3>"
+
+
+def test_trace_axis_means(tmp_path):
+    path = str(tmp_path / "trace.csv")
+    fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    rows = [(PASS, 1000, 3000), (PASS, 3000, 7000), (COPY, 7000, 9000), (PASS, 9000, 12000), (PASS, 12000, 17000)]
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in reversed(rows):     # unordered on disk: sorted by start time
+            w.writerow(dict(zip(fields, r)))
+    m = P.trace_axis_means(path, 2)["double"]
+    assert [r["dispatches"] for r in m] == [2, 2]
+    assert m[0]["mean_us"] == pytest.approx(2.5) and m[1]["mean_us"] == pytest.approx(4.5)
+    assert m[0]["min_us"] == pytest.approx(2.0) and m[1]["max_us"] == pytest.approx(5.0)
+
+
+def test_traffic_record_used_only_for_current_code_and_schedule(tmp_path):
+    sched = {"method": ["embed", "embed"], "elems_log2": [3, 3], "lines_per_block": [4, 4], "kernel": [0, 0]}
+    rec = {"source_hash": P.source_hash(), "schedule": sched, "per_axis": [{"axis": 1, "bytes": 1}]}
+    path = str(tmp_path / "traffic.json")
+    with open(path, "w") as f:
+        json.dump({"w:f64": rec, "old:f64": dict(rec, source_hash="0" * 16)}, f)
+    assert P.load_traffic(path, "w", "f64", sched)["per_axis"][0]["bytes"] == 1
+    assert P.load_traffic(path, "w", "f64") is not None
+    assert P.load_traffic(path, "w", "f32", sched) is None
+    assert P.load_traffic(path, "old", "f64", sched) is None
+    assert P.load_traffic(path, "w", "f64", dict(sched, lines_per_block=[0, 0])) is None
+    assert P.load_traffic(str(tmp_path / "missing.json"), "w", "f64") is None
+
