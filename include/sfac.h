@@ -71,14 +71,20 @@ typedef struct {
                                    (0 = automatic; 2 only for transform lengths 64..2048); fewer
                                    elements means more threads per line */
     int32_t lines_per_block[3]; /* pairs of real lines per thread block (0 = automatic) */
-    int32_t kernel[3];          /* diagonal method: 0 automatic, 1 the generic kernel (every N whose
+    int32_t kernel[3];          /* 0 automatic. Diagonal method: 1 the generic kernel (every N whose
                                    prime factors are <= 31), 2 the register-resident two-step kernel
                                    (N = A B for the pairs it is built for; SFAC_EUNSUPPORTED else),
                                    3 the same kernel with lines aligned to wavefronts (floor(64/P)
                                    lines of P = max(A, B) threads each; exchanges need no
                                    workgroup barrier; lines_per_block counts lines as before).
-                                   Nonzero selects the diagonal method under SFAC_METHOD_AUTO and is
-                                   SFAC_EINVAL with SFAC_METHOD_EMBED */
+                                   1-3 select the diagonal method under SFAC_METHOD_AUTO and are
+                                   SFAC_EINVAL with SFAC_METHOD_EMBED.
+                                   Embedded method: 4 the tile is loaded and stored through LDS,
+                                   adjacent threads on adjacent memory (on a strided axis, adjacent
+                                   line pairs at one position), with at least two line pairs per
+                                   block by default; for transform lengths >= 64
+                                   (SFAC_EUNSUPPORTED else). 4 selects the embedded method under
+                                   SFAC_METHOD_AUTO and is SFAC_EINVAL with SFAC_METHOD_DIAG */
 } sfac_options;
 
 /* Per-plan sticky status, read with sfac_plan_flags. */

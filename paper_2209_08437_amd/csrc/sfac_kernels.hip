@@ -310,8 +310,48 @@ struct TileGeom {
     }
 };
 
-// Embedded method, register-resident transforms of length 2^LOG2M.
-template <typename T, int LOG2M, int LE>
+// Tile I/O of the embedded method through LDS (option `stage`). Every element of the tile makes
+// one trip between HBM and its pair's LDS line; the walk puts adjacent threads on adjacent
+// memory: along the line on the contiguous axis, across adjacent line pairs at one position on
+// strided axes (a strided pass of one pair per block reads 16-byte runs per position; lpb pairs
+// make runs of lpb x 16 bytes). Positions n < N of line pair l sit at the swizzled position n of
+// LDS line l; a thread walks at most E/2 positions since N <= M/2. Threads beyond lpb lines (a
+// batched launch sized for a larger descriptor) take no part.
+template <typename T, int LOG2M, int LE, bool LOAD>
+__device__ __forceinline__ void embed_stage(const PassDesc<T>& d, const TileGeom<T>& tg, cplx<T>* lds) {
+    using G = EmbedGeom<LOG2M, LE>;
+    const int lpb = d.lpb, tau = threadIdx.x;
+    if (tau >= lpb * G::T) return;
+    const bool contiguous = tg.kstride == 1;
+    const int l = contiguous ? tau >> G::LOG2T : tau % lpb;
+    const int n0 = contiguous ? tau & (G::T - 1) : tau / lpb;
+    const bool x_in = 2 * l < tg.nreal, y_in = 2 * l + 1 < tg.nreal;
+    if (!x_in) return;
+    T* g = tg.base + 2LL * l * tg.lstride;
+    cplx<T>* sl = lds + l * G::M;
+    const int N = d.N;
+#pragma unroll
+    for (int j = 0; j < (G::E > 1 ? G::E / 2 : 1); ++j) {
+        const int n = n0 + j * G::T;
+        if (n < N) {
+            if constexpr (LOAD) {
+                cplx<T> z;
+                load_pair(g + (long long)n * tg.kstride, tg.lstride, y_in, z.x, z.y);
+                if (d.nl_in) {
+                    z.x = nonlinear_half_step_fast(z.x, d.decay, d.decay_lo);
+                    z.y = nonlinear_half_step_fast(z.y, d.decay, d.decay_lo);
+                }
+                sl[embed_swz<T, LOG2M>(n)] = z;
+            } else {
+                const cplx<T> z = sl[embed_swz<T, LOG2M>(n)];
+                store_pair(g + (long long)n * tg.kstride, tg.lstride, y_in, z.x, z.y);
+            }
+        }
+    }
+}
+
+// Embedded method, register-resident transforms of length 2^LOG2M; STAGE: tile I/O through LDS.
+template <typename T, int LOG2M, int LE, bool STAGE>
 __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     using G = EmbedGeom<LOG2M, LE>;
     using Line = EmbedLine<T, LOG2M, LE>;
@@ -324,7 +364,12 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     const T decay = d.decay, decay_lo = d.decay_lo;
     Line L;
     L.load_twiddles(d.tw, t);
-    const T* src = tg.base + (long long)(2 * line) * tg.lstride;
+    cplx<T>* ln = lds + line * G::M;
+    if constexpr (STAGE) {
+        embed_stage<T, LOG2M, LE, true>(d, tg, lds);
+        __syncthreads();
+    }
+    T* const own = tg.base + (long long)(2 * line) * tg.lstride;   // this thread's line pair
     constexpr int R0 = G::R(0);
 #pragma unroll
     for (int i = 0; i < G::E / R0; ++i)
@@ -333,21 +378,24 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
             const int n = Line::nat(t, i, k);
             cplx<T> z = {(T)0, (T)0};
             if ((R0 < 2 || k < R0 / 2) && act && n < N) {
-                load_pair(src + (long long)n * tg.kstride, tg.lstride, two, z.x, z.y);
-                if (d.nl_in) {
-                    z.x = nonlinear_half_step_fast(z.x, decay, decay_lo);
-                    z.y = nonlinear_half_step_fast(z.y, decay, decay_lo);
+                if constexpr (STAGE) {
+                    z = ln[embed_swz<T, LOG2M>(n)];
+                } else {
+                    load_pair(own + (long long)n * tg.kstride, tg.lstride, two, z.x, z.y);
+                    if (d.nl_in) {
+                        z.x = nonlinear_half_step_fast(z.x, decay, decay_lo);
+                        z.y = nonlinear_half_step_fast(z.y, decay, decay_lo);
+                    }
                 }
             }
             L.a[i * R0 + k] = z;
         }
-    cplx<T>* ln = lds + line * G::M;
     L.factor(d.gpos_c, ln, t, N);
     L.factor(d.gpos_s, ln, t, N);
     L.factor(d.gpos_c, ln, t, N);
-    T* dst = tg.base + (long long)(2 * line) * tg.lstride;
     double vmax = 0.0;
     unsigned int bad = 0;
+    if constexpr (STAGE) __syncthreads();   // the last exchange's reads are done before the staging writes
 #pragma unroll
     for (int i = 0; i < G::E / R0; ++i)
 #pragma unroll
@@ -364,19 +412,19 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
                     else
                         vmax = fmax(vmax, fmax(ax, ay));
                 }
-                store_pair(dst + (long long)n * tg.kstride, tg.lstride, two, z.x, z.y);
+                if constexpr (STAGE)
+                    ln[embed_swz<T, LOG2M>(n)] = z;
+                else
+                    store_pair(own + (long long)n * tg.kstride, tg.lstride, two, z.x, z.y);
             }
         }
+    if constexpr (STAGE) {
+        __syncthreads();
+        embed_stage<T, LOG2M, LE, false>(d, tg, lds);
+    }
     if (d.nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
 }
 
-// Cooperative copy between the tile's lines in memory and the complex LDS lines (complex line l
-// holds real lines 2l and 2l+1 as real and imaginary parts). With lpb lines of N = A B
-// positions and lpb P threads (P = max(A, B)), thread tau moves positions n0 + P j, j < A, of
-// line tau mod lpb for strided axes (adjacent threads take adjacent lines, whose elements are
-// adjacent in memory) and of line tau / P for the contiguous axis (adjacent threads take
-// adjacent positions), n0 the remaining index. Threads beyond lpb P (a grouped launch's larger
-// block) take no part. Lines beyond the tile load as zero and are not stored.
 template <typename T, int A, int B, bool LOAD>
 __device__ __forceinline__ void stage_tile(const TileGeom<T>& tg, int lpb, cplx<T>* lds) {
     constexpr int P = A > B ? A : B, N = A * B, J = N / P;
@@ -494,27 +542,29 @@ __global__ void __launch_bounds__(kBlockThreads) axis_pass_single(PassDesc<T> d)
     run_tile(d, tile, buf0, buf1);
 }
 
-// block size bound of an embedded-method kernel: 256 threads, or one line of 512 threads with
-// four elements each (then two blocks per CU, so that the compiler keeps to 128 registers and a
-// SIMD holds four wavefronts)
-constexpr int embed_max_block(int log2m, int le) {
-    return (1 << (log2m - embed_log2e(log2m, le))) > kBlockThreads ? (1 << (log2m - embed_log2e(log2m, le)))
-                                                                     : kBlockThreads;
+// Block size bound of an embedded-method kernel: 256 threads, or one line when a line has more
+// threads (512 at four elements each); staged kernels: at least two lines (embed_stage_block).
+// Above 256 threads the second bound asks for two wavefronts per SIMD (a 1024-thread bound
+// alone keeps the kernel within 128 registers, four wavefronts per SIMD).
+constexpr int embed_max_block(int log2m, int le, bool stage) {
+    const int t = 1 << (log2m - embed_log2e(log2m, le));
+    return stage ? embed_stage_block(t) : (t > kBlockThreads ? t : kBlockThreads);
 }
-#define SFAC_EMBED_BOUNDS(LOG2M, LE) \
-    __launch_bounds__(embed_max_block(LOG2M, LE), embed_max_block(LOG2M, LE) > kBlockThreads ? 2 : 1)
+#define SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE)                   \
+    __launch_bounds__(embed_max_block(LOG2M, LE, STAGE),     \
+                      embed_max_block(LOG2M, LE, STAGE) > kBlockThreads ? 2 : 1)
 
-template <typename T, int LOG2M, int LE>
-__global__ void SFAC_EMBED_BOUNDS(LOG2M, LE) embed_pass_single(PassDesc<T> d) {
+template <typename T, int LOG2M, int LE, bool STAGE>
+__global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_single(PassDesc<T> d) {
     extern __shared__ unsigned char smem_raw[];
     const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
     if (tile >= d.ntiles) return;
-    run_embed_tile<T, LOG2M, LE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_embed_tile<T, LOG2M, LE, STAGE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
 // Several instances with the same transform length in one launch (batched form).
-template <typename T, int LOG2M, int LE>
-__global__ void SFAC_EMBED_BOUNDS(LOG2M, LE) embed_pass_multi(const PassDesc<T>* __restrict__ descs,
+template <typename T, int LOG2M, int LE, bool STAGE>
+__global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_multi(const PassDesc<T>* __restrict__ descs,
                                                                   const int* __restrict__ block_start,
                                                                   int ndesc) {
     extern __shared__ unsigned char smem_raw[];
@@ -533,7 +583,7 @@ __global__ void SFAC_EMBED_BOUNDS(LOG2M, LE) embed_pass_multi(const PassDesc<T>*
     if (tile >= d.ntiles) return;
     // the block has the group's largest size; threads beyond d.lpb lines hold no line (their
     // LDS rows lie inside the block's allocation) and only take part in the barriers
-    run_embed_tile<T, LOG2M, LE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_embed_tile<T, LOG2M, LE, STAGE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
 // Waves per SIMD the register budget is cut for. The FP64 15 x 17 kernel with block barriers
@@ -599,37 +649,44 @@ const void* diag2_fn(int a, int b, bool multi, bool wave) {
     }
 }
 
-// kernel of one (transform length, elements per thread); LE = 3 or 4
-template <typename T, int LOG2M>
+// kernel of one (transform length, elements per thread, staging); LE = 2 (M = 64 to 2048), 3 or 4
+template <typename T, int LOG2M, int LE, bool STAGE>
+const void* embed_fn_k(bool multi) {
+    return multi ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, LE, STAGE>)
+                 : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE>);
+}
+template <typename T, int LOG2M, bool STAGE>
 const void* embed_fn_le(int le, bool multi) {
     if (le == 2) {
-        if constexpr (LOG2M >= 6 && LOG2M <= 11)
-            return multi ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, 2>)
-                         : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, 2>);
+        if constexpr (LOG2M >= 6 && LOG2M <= 11) return embed_fn_k<T, LOG2M, 2, STAGE>(multi);
         return nullptr;
     }
-    if (le == 3)
-        return multi ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, 3>)
-                     : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, 3>);
-    return multi ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, 4>)
-                 : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, 4>);
+    if (le == 3) return embed_fn_k<T, LOG2M, 3, STAGE>(multi);
+    return embed_fn_k<T, LOG2M, 4, STAGE>(multi);
+}
+// staged kernels exist for M >= 64 (lines of at least 32 points)
+template <typename T, int LOG2M>
+const void* embed_fn_lm(int le, bool multi, bool stage) {
+    if (!stage) return embed_fn_le<T, LOG2M, false>(le, multi);
+    if constexpr (LOG2M >= 6) return embed_fn_le<T, LOG2M, true>(le, multi);
+    return nullptr;
 }
 
 template <typename T>
-const void* embed_fn(int log2m, int le, bool multi) {
+const void* embed_fn(int log2m, int le, bool multi, bool stage) {
     switch (log2m) {
-        case 1: return embed_fn_le<T, 1>(le, multi);
-        case 2: return embed_fn_le<T, 2>(le, multi);
-        case 3: return embed_fn_le<T, 3>(le, multi);
-        case 4: return embed_fn_le<T, 4>(le, multi);
-        case 5: return embed_fn_le<T, 5>(le, multi);
-        case 6: return embed_fn_le<T, 6>(le, multi);
-        case 7: return embed_fn_le<T, 7>(le, multi);
-        case 8: return embed_fn_le<T, 8>(le, multi);
-        case 9: return embed_fn_le<T, 9>(le, multi);
-        case 10: return embed_fn_le<T, 10>(le, multi);
-        case 11: return embed_fn_le<T, 11>(le, multi);
-        case 12: return embed_fn_le<T, 12>(le, multi);
+        case 1: return embed_fn_lm<T, 1>(le, multi, stage);
+        case 2: return embed_fn_lm<T, 2>(le, multi, stage);
+        case 3: return embed_fn_lm<T, 3>(le, multi, stage);
+        case 4: return embed_fn_lm<T, 4>(le, multi, stage);
+        case 5: return embed_fn_lm<T, 5>(le, multi, stage);
+        case 6: return embed_fn_lm<T, 6>(le, multi, stage);
+        case 7: return embed_fn_lm<T, 7>(le, multi, stage);
+        case 8: return embed_fn_lm<T, 8>(le, multi, stage);
+        case 9: return embed_fn_lm<T, 9>(le, multi, stage);
+        case 10: return embed_fn_lm<T, 10>(le, multi, stage);
+        case 11: return embed_fn_lm<T, 11>(le, multi, stage);
+        case 12: return embed_fn_lm<T, 12>(le, multi, stage);
         default: return nullptr;
     }
 }
@@ -670,7 +727,7 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
     const int blocks = pass_blocks(d);
     if (blocks <= 0) return hipSuccess;
     if (d.method == 2 || (d.method == 1 && d.d2a > 0)) {
-        const void* fn = d.method == 2 ? embed_fn<T>(d.log2m, d.log2e, false)
+        const void* fn = d.method == 2 ? embed_fn<T>(d.log2m, d.log2e, false, d.stage != 0)
                                        : diag2_fn<T>(d.d2a, d.d2b, false, d.d2wave != 0);
         if (!fn) return hipErrorInvalidValue;
         void* args[] = {const_cast<PassDesc<T>*>(&d)};
@@ -686,7 +743,7 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
                                   hipStream_t stream) {
     if (total_blocks <= 0) return hipSuccess;
     if (kind == 1 || kind == 2) {
-        const void* fn = kind == 1 ? embed_fn<T>(variant / 8, variant % 8, true)
+        const void* fn = kind == 1 ? embed_fn<T>((variant % 128) / 8, variant % 8, true, variant >= 128)
                                    : diag2_fn<T>((variant % 4096) / 64, variant % 64, true, variant >= 4096);
         if (!fn) return hipErrorInvalidValue;
         void* args[] = {&descs_dev, &block_start_dev, &ndesc};
@@ -704,12 +761,13 @@ hipError_t allow_lds(size_t lds_bytes) {
     if (e != hipSuccess) return e;
     for (int lg = 1; lg <= 12; ++lg)
         for (int le = 2; le <= 4; ++le)
-            for (int multi = 0; multi < 2; ++multi) {
-                const void* fn = embed_fn<T>(lg, le, multi);
-                if (!fn) continue;
-                e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-                if (e != hipSuccess) return e;
-            }
+            for (int multi = 0; multi < 2; ++multi)
+                for (int stage = 0; stage < 2; ++stage) {
+                    const void* fn = embed_fn<T>(lg, le, multi, stage);
+                    if (!fn) continue;
+                    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+                    if (e != hipSuccess) return e;
+                }
     for (int a = 3; a <= 17; ++a)
         for (int b = a; b <= 17; ++b)
             for (int multi = 0; multi < 2; ++multi)

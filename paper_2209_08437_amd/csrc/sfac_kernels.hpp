@@ -12,6 +12,13 @@ namespace sfac {
 
 constexpr int kBlockThreads = 256;
 
+// Block size bound of the embedded-method kernels whose tiles are staged through LDS, for lines
+// of t threads: room for at least two line pairs, and at least 256 threads. (A larger bound
+// would cut the register budget of the kernels with 16 elements per thread, which then spill.)
+constexpr int embed_stage_block(int t) {
+    return 2 * t > 1024 ? 1024 : (2 * t < 256 ? 256 : 2 * t);
+}
+
 // LDS elements per line of the two-step diagonal kernel (N = A B): N plus a pad that spreads
 // the lanes of neighbouring lines over the banks; the pads come from a bank-conflict model of
 // the kernel's access patterns (16-lane groups of 16-byte elements, 32-lane groups of 8-byte
@@ -60,7 +67,8 @@ struct PassDesc {
     int xcd_remap;                   // group neighbouring tiles per XCD
     int d2wave;                      // two-step diagonal kernel: wavefront-aligned line layout
     int log2m;                       // embed: log2 of the transform length
-    int log2e;                       // embed: log2 of the largest elements-per-thread count (3 or 4)
+    int log2e;                       // embed: log2 of the largest elements-per-thread count (2, 3 or 4)
+    int stage;                       // embed: tile loaded and stored through LDS (coalesced walks)
     int d2a, d2b;                    // diag: N = d2a * d2b for the two-step kernel, 0 for the generic one
     int threads;                     // launch block size
     T decay, decay_lo;               // e^{-tau} = decay + decay_lo (decay_lo = 0 in FP64)
@@ -74,8 +82,8 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
 
 // One launch over several instances' tiles of one pass; every descriptor of the launch uses the
 // same kernel variant; `threads` is the block size (the group's largest).
-// kind: 0 generic, 1 embedded (variant = log2m * 8 + log2e), 2 two-step diagonal (variant = a * 64 + b,
-// plus 4096 for the wavefront-aligned line layout)
+// kind: 0 generic, 1 embedded (variant = log2m * 8 + log2e, plus 128 for the LDS-staged tile),
+// 2 two-step diagonal (variant = a * 64 + b, plus 4096 for the wavefront-aligned line layout)
 template <typename T>
 hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const PassDesc<T>* descs_dev,
                                   const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,

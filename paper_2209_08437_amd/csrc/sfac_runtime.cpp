@@ -49,6 +49,7 @@ struct AxisDevice {
     int threads = 256;
     int log2e = 4;
     int d2wave = 0;   // two-step diagonal kernel in the wavefront-aligned layout
+    int stage = 0;    // embedded kernel with the tile staged through LDS
     size_t lds = 0;
 };
 
@@ -146,13 +147,17 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
         in->alpha[a] = alpha[a];
         in->h[a] = h[a];
         const int kern = opt ? opt->kernel[a] : 0;
-        if (kern < 0 || kern > 3)
-            return fail(SFAC_EINVAL, "%saxis %d: kernel = %d, expected 0, 1, 2 or 3", who, a + 1, kern);
+        if (kern < 0 || kern > 4)
+            return fail(SFAC_EINVAL, "%saxis %d: kernel = %d, expected 0 to 4", who, a + 1, kern);
         int m = methods ? methods[a] : SFAC_METHOD_AUTO;
-        if (kern != 0 && m == SFAC_METHOD_EMBED)
+        if (kern >= 1 && kern <= 3 && m == SFAC_METHOD_EMBED)
             return fail(SFAC_EINVAL, "%saxis %d: a diagonal-method kernel was chosen for the embedded method", who,
                         a + 1);
-        if (m == SFAC_METHOD_AUTO) m = kern != 0 ? SFAC_METHOD_DIAG : sfac::auto_method(n[a], dt);
+        if (kern == 4 && m == SFAC_METHOD_DIAG)
+            return fail(SFAC_EINVAL, "%saxis %d: the staged embedded kernel was chosen for the diagonal method", who,
+                        a + 1);
+        if (m == SFAC_METHOD_AUTO)
+            m = kern == 4 ? SFAC_METHOD_EMBED : (kern != 0 ? SFAC_METHOD_DIAG : sfac::auto_method(n[a], dt));
         if (m != SFAC_METHOD_DIAG && m != SFAC_METHOD_EMBED)
             return fail(SFAC_EUNSUPPORTED, "%saxis %d: no method supports N = %d", who, a + 1, n[a]);
         // embedded method: elements per thread. Fewer (8) doubles the threads of a line: worth it
@@ -199,11 +204,19 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
                             "not %d", who, a + 1, L);
             const int E = 1 << sfac::embed_log2e(log2m, in->ax[a].log2e);
             const int T = L / E;
-            const int max_block = std::max(T, sfac::kBlockThreads);   // one line of 512 threads at E = 4
+            // staged tiles (kernel option 4): at least two lines per block, so that strided passes
+            // read runs of several line pairs; otherwise 256 threads, or one line of 512 at E = 4
+            const bool stage = kern == 4;
+            if (stage && log2m < 6)
+                return fail(SFAC_EUNSUPPORTED, "%saxis %d: staged tiles need a transform length of at least 64, "
+                            "not %d", who, a + 1, L);
+            const int max_block = stage ? sfac::embed_stage_block(T) : std::max(T, sfac::kBlockThreads);
             int lpb = max_block / T;
-            while (lpb > 1 && (lines_total + lpb - 1) / lpb < 1024) lpb >>= 1;
+            const int keep = stage ? 2 : 1;
+            while (lpb > keep && (lines_total + lpb - 1) / lpb < 1024) lpb >>= 1;
             if (opt && opt->lines_per_block[a] > 0) lpb = std::min(opt->lines_per_block[a], max_block / T);
             lpb = std::max(1, (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2)));
+            in->ax[a].stage = stage ? 1 : 0;
             in->ax[a].lpb = lpb;
             in->ax[a].threads = lpb * T;
             in->ax[a].lds = elem * (size_t)L * lpb;
@@ -268,6 +281,7 @@ sfac::PassDesc<T> make_desc(const Instance& in, int a, unsigned char* dev_tables
     d.d2a = t.d2a;
     d.d2b = t.d2b;
     d.d2wave = ad.d2wave;
+    d.stage = ad.stage;
     d.psi2 = reinterpret_cast<const sfac::cplx<T>*>(dev_tables + ad.off_psi2);
     d.log2m = 0;
     while ((1 << d.log2m) < t.length) ++d.log2m;
@@ -670,7 +684,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                 sfac::PassDesc<T> d = make_desc<T>(p->in, pass, p->dev, static_cast<T*>(us[i]), p->stat_max(),
                                                    p->stat_flags());
                 const int kind = d.method == SFAC_METHOD_EMBED ? 1 : (d.d2a > 0 ? 2 : 0);
-                const int variant = kind == 1 ? d.log2m * 8 + d.log2e
+                const int variant = kind == 1 ? d.log2m * 8 + d.log2e + (d.stage ? 128 : 0)
                                               : (kind == 2 ? d.d2a * 64 + d.d2b + (d.d2wave ? 4096 : 0) : 0);
                 const std::pair<int, int> key(kind, variant);
                 size_t g = std::find(keys.begin(), keys.end(), key) - keys.begin();
@@ -688,7 +702,7 @@ void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
                 if (keys[g].first == 1) {
                     threads = 0;
                     for (const auto& d : groups[g]) threads = std::max(threads, d.threads);
-                    const int E = 1 << sfac::embed_log2e(keys[g].second / 8, keys[g].second % 8);
+                    const int E = 1 << sfac::embed_log2e((keys[g].second % 128) / 8, keys[g].second % 8);
                     glds[g] = (size_t)threads * E * sizeof(sfac::cplx<T>);
                 } else if (keys[g].first == 2) {
                     // a full block of P-thread lines (or of wavefronts of 64/P lines); lines beyond

@@ -75,9 +75,18 @@ def test_unsupported_sizes(sfac_lib):
     st, h, msg = _create(2, [9, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
     assert st == sfac.EINVAL and "elems_log2" in msg
     opt = sfac.Options()
-    opt.kernel[1] = 4
+    opt.kernel[1] = 5
     st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
     assert st == sfac.EINVAL and "kernel" in msg
+    opt = sfac.Options()
+    opt.kernel[1] = 4                                                                # staged tiles, M = 16 < 64
+    st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EUNSUPPORTED and "staged" in msg
+    opt = sfac.Options()
+    opt.method[0] = sfac.METHOD_DIAG
+    opt.kernel[0] = 4
+    st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EINVAL and "staged embedded" in msg
     opt = sfac.Options()
     opt.kernel[1] = 3                                                                # 8 is no A B pair
     st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)

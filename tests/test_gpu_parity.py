@@ -166,6 +166,37 @@ def test_embed_schedules_fp64(sfac_lib, ns, le, lpb):
     assert rel_err(u.cpu().numpy(), ref) <= FP64_TOL
 
 
+_STAGED_REF = {}
+
+
+@pytest.mark.parametrize("dtype,le", [("f64", 2), ("f64", 3), ("f64", 4), ("f32", 3)])
+@pytest.mark.parametrize("lpb", [0, 1, 2, 3])
+@pytest.mark.parametrize("ns", [(100, 37), (1023, 40), (40, 33, 35), (700, 35)], ids=lambda s: "x".join(map(str, s)))
+def test_embed_staged_tiles(sfac_lib, ns, lpb, dtype, le):
+    """Embedded method with the tile loaded and stored through LDS (kernel option 4) on every
+    axis: contiguous and strided walks, partial last tiles (odd line counts, lpb not dividing
+    them), one to three line pairs per block."""
+    if ns not in _STAGED_REF:
+        rng = np.random.default_rng(len(ns) * 31 + ns[0])
+        alphas = tuple(float(a) for a in rng.uniform(1.05, 1.95, len(ns)))
+        hs = W.mesh_widths(ns)
+        u0 = W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=ns[0] + 11)
+        _STAGED_REF[ns] = (alphas, hs, u0, O.two_level_solve(u0, ns, alphas, 0.2, hs, 0.01, 3))
+    alphas, hs, u0, ref = _STAGED_REF[ns]
+    _say(f"case staged {ns} {dtype} elems 2^{le} lines/block {lpb}")
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    u = torch.tensor(u0, dtype=tdt, device="cuda")
+    with sfac.Plan(ns, alphas, 0.2, 0.01, hs, dtype, method="embed", elems_log2=le, lines_per_block=lpb,
+                   kernel=4) as p:
+        p.step(u, 3)
+        flags, _ = p.flags()
+    torch.cuda.synchronize()
+    assert rel_err(u.double().cpu().numpy(), ref) <= (FP64_TOL if dtype == "f64" else FP32_TOL)
+    assert flags == 0
+
+
 @pytest.mark.parametrize("kernel", [1, 2, 3])
 @pytest.mark.parametrize("lpb", [0, 1, 5])
 @pytest.mark.parametrize("ns", [(63, 30), (255, 11), (15, 35, 63), (99, 143), (1023, 6)],
@@ -231,6 +262,25 @@ def test_special_parameters(sfac_lib):
     T = 25 * 0.03
     closed = u0 / np.sqrt(u0 ** 2 + (1 - u0 ** 2) * np.exp(-2 * T))
     assert np.abs(got - closed).max() <= 1e-13
+
+
+@pytest.mark.parametrize("ns,method", [((20, 13), "embed"), ((35, 63), "diag"), ((255, 15), "diag")],
+                         ids=["20x13-embed", "35x63-diag2", "255x15-diag2"])
+def test_eps0_closed_form_fp32(sfac_lib, ns, method):
+    """FP32 against the Bernoulli closed form (eps = 0, Sec. 3): pins the FP32 NL half-step of the
+    register-resident kernels. The linear step is the identity up to the rounding of its
+    transforms; a few ulp per step, amplified by at most e^T near u = 0, bound the error."""
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.99, 0.99, seed=5).astype(np.float32).astype(np.float64)
+    steps, tau = 25, 0.03
+    _say(f"case eps=0 fp32 {ns} {method}")
+    got, (_, vmax) = gpu_solve(u0.astype(np.float32), ns, (1.5, 1.5), 0.0, hs, tau, steps, "f32", method)
+    T = steps * tau
+    closed = u0 / np.sqrt(u0 ** 2 + (1 - u0 ** 2) * np.exp(-2 * T))
+    err = np.abs(got - closed).max()
+    _say(f"  max abs err {err:.3e}")
+    assert err <= 2e-5
+    assert vmax <= 1.0
 
 
 # ----------------------------------------------------- full-size workloads (few steps)
@@ -366,6 +416,11 @@ def test_batch_with_schedules_matches_lone_plans(sfac_lib):
     insts = W.batched_2d(count=5, steps=4, seed=22, sizes=(63, 100, 255))
     scheds = [None, {"elems_log2": 4, "lines_per_block": 1}, {"elems_log2": [2, 3]},
               {"method": "diag", "kernel": 1}, {"lines_per_block": 2}]
+    # staged tiles: one shape, so the first two share a launch sized for the larger block
+    insts += W.batched_2d(count=3, steps=4, seed=23, sizes=(100,))
+    scheds += [{"kernel": 4, "lines_per_block": 1, "elems_log2": 3},
+               {"kernel": 4, "lines_per_block": 2, "elems_log2": 3},
+               {"kernel": 4, "lines_per_block": 4, "elems_log2": 2}]
     for dt in ("f64", "f32"):
         _say(f"case batch schedules {dt}")
         tdt = torch.float64 if dt == "f64" else torch.float32
