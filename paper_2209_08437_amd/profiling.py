@@ -3,6 +3,7 @@
 * `source_hash()` fingerprints the kernel sources, so that a counter-derived HBM traffic figure
   is used only while the kernels it was measured on are unchanged.
 * `stats_markdown()` turns a `--kernel-trace --stats` CSV into a short markdown table.
+* `sq_markdown()` summarises shader-sequencer counter runs (VALU and LDS work, waits, occupancy).
 * `traffic_from_pmc()` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of a workload and
   the same two counters read on a plain copy kernel of known size into calibrated HBM bytes
   per launch of each axis-pass kernel.
@@ -153,6 +154,71 @@ def traffic_from_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_
             "per_axis": per_axis}
 
 
+# Shader-sequencer counters of the pass kernels, two passes of eight (FP64 runs of bench.py)
+SQ_SETS = (("A", "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_WAIT_INST_LDS "
+                 "SQ_WAIT_INST_ANY SQ_INSTS_VALU"),
+           ("B", "SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU "
+                 "SQ_ACTIVE_INST_ANY SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64"))
+SQ_COMMAND = ("timeout -s KILL 90 rocprofv3 --pmc $COUNTERS --output-format csv -d $O/$SET_$W -o run -- "
+              "python3 $R/bench.py --workload $W --dtype f64 --no-cpu --no-fp32 --steps 10 --warmup 2 --pass-reps 2")
+# MI355X: 256 CUs of 4 SIMDs; a SIMD issues one wavefront VALU instruction (FP64, or FP32 unpacked) every
+# 4 cycles at 2.4 GHz
+VALU_WAVE_INSTR_PER_US = 256 * 4 / 4 * 2400.0
+
+
+def sq_axis_means(csv_path, dims):
+    """Mean value per axis of every counter in one --pmc run, over the pass-kernel dispatches
+    (a dispatch's rows are summed), with the kernel name of each axis."""
+    per, names = {}, {}
+    for r in _rows(csv_path):
+        if not any(t in r["Kernel_Name"] for t in PASS_KERNEL_TAGS):
+            continue
+        d = int(r["Dispatch_Id"])
+        c = per.setdefault(d, {})
+        c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        names[d] = short_name(r["Kernel_Name"])
+    order = sorted(per)
+    out = []
+    for a in range(dims):
+        ds = order[a::dims]
+        keys = set().union(*(per[d] for d in ds)) if ds else set()
+        out.append({"kernel": names[ds[0]] if ds else None, "dispatches": len(ds),
+                    **{k: sum(per[d].get(k, 0.0) for d in ds) / len(ds) for k in keys}})
+    return out
+
+
+def sq_markdown(directory, workload, dims):
+    """Markdown summary of the SQ_SETS runs of one workload."""
+    runs = [sq_axis_means(os.path.join(directory, f"{name}_{workload}", "run_counter_collection.csv"), dims)
+            for name, _ in SQ_SETS]
+    axes = [{**runs[0][a], **runs[1][a]} for a in range(dims)]
+    lines = [f"# Shader-sequencer counters, workload {workload} (FP64)", "",
+             "Commands (run from /tmp on one MI355X; `$R` is the repository root, `$O` the output directory):", "",
+             "```"]
+    for name, counters in SQ_SETS:
+        lines.append(SQ_COMMAND.replace("$COUNTERS", counters).replace("$SET", name).replace("$W", workload))
+    lines += ["```", "",
+              "Per axis, means over the pass-kernel dispatches of a run (graph replays and per-pass timing). "
+              "Wave-cycle counters are accumulated per wavefront in the same units, so their ratios are shares "
+              "of a wavefront's lifetime. VALU issue time: the VALU instructions at one wavefront instruction "
+              "per SIMD every 4 cycles on 1024 SIMDs at 2.4 GHz.", "",
+              "| axis | kernel | waves | VALU instr. | VALU issue us | FMA / ADD F64 | VALU share | LDS-wait share | "
+              "any-wait share | LDS instr. | bank conflicts | VMEM rd / wr |",
+              "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for a, c in enumerate(axes):
+        wc = c.get("SQ_WAVE_CYCLES", 0.0) or float("nan")
+        lines.append(
+            f"| {a + 1} | `{c['kernel']}` | {c.get('SQ_WAVES', 0):.0f} | {c.get('SQ_INSTS_VALU', 0):.3g} | "
+            f"{c.get('SQ_INSTS_VALU', 0) / VALU_WAVE_INSTR_PER_US:.1f} | "
+            f"{c.get('SQ_INSTS_VALU_FMA_F64', 0):.3g} / {c.get('SQ_INSTS_VALU_ADD_F64', 0):.3g} | "
+            f"{c.get('SQ_ACTIVE_INST_VALU', 0) / wc:.3f} | {c.get('SQ_WAIT_INST_LDS', 0) / wc:.3f} | "
+            f"{c.get('SQ_WAIT_INST_ANY', 0) / wc:.3f} | {c.get('SQ_INSTS_LDS', 0):.3g} | "
+            f"{c.get('SQ_LDS_BANK_CONFLICT', 0):.3g} | {c.get('SQ_INSTS_VMEM_RD', 0):.3g} / "
+            f"{c.get('SQ_INSTS_VMEM_WR', 0):.3g} |")
+    lines += ["", f"Device-code source hash: `{source_hash()}`.", ""]
+    return "\n".join(lines)
+
+
 def load_traffic(path, workload, dtype, schedule=None):
     """The committed traffic record of (workload, dtype), or None if absent, if the kernel
     sources changed since it was measured, or if it was measured with another schedule."""
@@ -201,10 +267,17 @@ def _main():
     ap.add_argument("--dir", required=True, help="directory holding the rocprofv3 outputs")
     ap.add_argument("--workload", required=True)
     ap.add_argument("--dims", type=int, required=True)
-    ap.add_argument("--out", required=True, help="markdown summary to write")
-    ap.add_argument("--traffic", required=True, help="JSON traffic record to update")
+    ap.add_argument("--out", help="markdown summary to write")
+    ap.add_argument("--traffic", help="JSON traffic record to update")
+    ap.add_argument("--sq", help="write the SQ counter summary (SQ_SETS runs) to this file instead")
     a = ap.parse_args()
     d, w = a.dir, a.workload
+    if a.sq:
+        with open(a.sq, "w") as f:
+            f.write(sq_markdown(d, w, a.dims))
+        return
+    if not (a.out and a.traffic):
+        ap.error("--out and --traffic are required without --sq")
     bench = json.load(open(os.path.join(d, f"bench_{w}.json")))
     lines = [f"# Axis-pass kernels, workload {w}", ""]
     lines += ["Commands (run from /tmp on one MI355X; `$R` is the repository root, `$O` the output "

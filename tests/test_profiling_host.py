@@ -107,3 +107,19 @@ def test_traffic_record_used_only_for_current_code_and_schedule(tmp_path):
     assert P.load_traffic(path, "w", "f64", dict(sched, lines_per_block=[0, 0])) is None
     assert P.load_traffic(str(tmp_path / "missing.json"), "w", "f64") is None
 
+
+
+def test_sq_axis_means(tmp_path):
+    # a 2D run: dispatches alternate axes; per-XCD rows of a dispatch are summed, other kernels skipped
+    rows = [(1, PASS, "SQ_WAVES", 1000.0), (1, PASS, "SQ_WAVES", 1048.0), (1, PASS, "SQ_INSTS_VALU", 10.0),
+            (2, PASS, "SQ_WAVES", 2048.0), (2, PASS, "SQ_INSTS_VALU", 30.0),
+            (3, COPY, "SQ_WAVES", 5.0),
+            (4, PASS, "SQ_WAVES", 2048.0), (4, PASS, "SQ_INSTS_VALU", 20.0),
+            (5, PASS, "SQ_WAVES", 2048.0), (5, PASS, "SQ_INSTS_VALU", 50.0)]
+    path = str(tmp_path / "sq.csv")
+    _write_pmc(path, rows)
+    a1, a2 = P.sq_axis_means(path, 2)
+    assert a1["dispatches"] == a2["dispatches"] == 2
+    assert a1["SQ_WAVES"] == 2048.0 and a2["SQ_WAVES"] == 2048.0
+    assert a1["SQ_INSTS_VALU"] == 15.0 and a2["SQ_INSTS_VALU"] == 40.0
+    assert a1["kernel"] == "embed_pass_single<double, 11, 3>"
