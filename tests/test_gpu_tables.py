@@ -1,0 +1,87 @@
+"""The paper's printed convergence tables, reproduced by the GPU FP64 path.
+
+The CPU oracle is pinned to the same tables in test_oracle_pins.py. These tests run the
+library instead, with the paper's parameters and the two-Gaussian initial value of Example 1,
+and compare with the printed values. A printed value of 5 significant digits is exact to half
+a unit in the last digit; a few units are allowed for the rounding of the authors' own
+arithmetic.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2209_08437_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _rel_ok(got, printed):
+    return abs(got - printed) <= 5e-4 * abs(printed)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _solve(u0, ns, alphas, eps, hs, tau, steps, method=None):
+    import torch
+    from paper_2209_08437_amd import sfac
+    u = torch.tensor(np.ascontiguousarray(u0), dtype=torch.float64, device="cuda")
+    with sfac.Plan(ns, alphas, eps, tau, hs, "f64", method=method) as p:
+        p.step(u, steps)
+        flags, _ = p.flags()
+    torch.cuda.synchronize()
+    assert flags == 0
+    return u.cpu().numpy()
+
+
+def test_table2_two_level_column(sfac_lib):
+    """Sec. 5, Example 1, Table 2 (two-level column): ||u(h, tau) - u(h, tau/2)||_inf on 255 x 255
+    interior nodes, T = 1, for all four alpha pairs and tau = 1/100, 1/200."""
+    g = _golden("table2_example1_temporal.json")
+    n, L, eps, T = g["n"], g["domain_length"], g["eps"], g["T"]
+    h = L / (n + 1)
+    u0 = W.two_gaussians_2d(n, L)
+    cache = {}
+
+    def run(alpha, tau):
+        key = (tuple(alpha), tau)
+        if key not in cache:
+            cache[key] = _solve(u0, (n, n), alpha, eps, (h, h), tau, int(round(T / tau)))
+        return cache[key]
+
+    for row in g["rows"]:
+        a, tau = row["alpha"], row["tau"]
+        e = np.abs(run(a, tau) - run(a, tau / 2)).max()
+        _say(f"case table 2 alpha {a} tau {tau}: {e:.5e} (printed {row['two_level']:.5e})")
+        assert _rel_ok(e, row["two_level"]), (a, tau, e, row["two_level"])
+
+
+def test_table1_spatial_error(sfac_lib):
+    """Sec. 5, Example 1, Table 1: the maximum-norm spatial error E_s after one step (tau = T = 1)
+    against the solution on h_ref = 1/2048 (4095 x 4095 interior nodes, the diagonal method's
+    longest lines), sampled at the coarse nodes."""
+    g = _golden("table1_example1_spatial.json")
+    L, eps, tau = g["domain_length"], g["eps"], g["tau"]
+    m_ref = int(round(L / g["h_ref"]))
+    nr = m_ref - 1
+    col = g["columns"][0]
+    a = col["alpha"]
+    _say(f"case table 1 reference {nr} x {nr}")
+    uref = _solve(W.two_gaussians_2d(nr, L), (nr, nr), a, eps, (g["h_ref"],) * 2, tau, 1)
+    for h, printed in zip(col["h"], col["E_s"]):
+        m = int(round(L / h))
+        r = m_ref // m
+        u = _solve(W.two_gaussians_2d(m - 1, L), (m - 1,) * 2, a, eps, (h, h), tau, 1)
+        err = np.abs(uref[r - 1::r, r - 1::r] - u).max()
+        _say(f"case table 1 h {h}: {err:.5e} (printed {printed:.5e})")
+        assert _rel_ok(err, printed), (h, err, printed)
