@@ -19,7 +19,8 @@ What it computes, in the paper's order and notation (Sec. 2):
   Kronecker sums of eq. (2DA) / (3DA) form, so each exponential is the product of the
   per-axis exponentials (all axes' C factors, then all S factors, then all C factors);
 * eq. (strang) with eq. (linear_operator): the one-level scheme with the exact exponential
-  e^{tau A}, used only to reproduce the paper's "Strang splitting" table columns.
+  e^{tau A}, used only to reproduce the paper's "Strang splitting" table columns;
+* Sec. 5, Example 5: the discrete free energy prod(h) (1/4 |u^2 - 1|^2 - 1/2 u^T A u).
 
 Every linear factor is a dense N x N matrix applied by a dense product along one axis of
 the state; there is no FFT, blocking or fusion. Arrays are C-order with axis 1 (the paper's

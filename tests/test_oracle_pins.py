@@ -342,3 +342,59 @@ def test_table1_spatial_error():
         u = O.two_level_solve(W.two_gaussians_2d(m - 1, L), (m - 1,) * 2, a, eps, (h, h), tau, 1)
         err = np.abs(uref[r - 1::r, r - 1::r] - u).max()
         assert _rel_ok(err, printed), (h, err, printed)
+
+
+# ------------------------------------------- discrete energy of Example 5 (Sec. 5)
+def test_energy_of_zero_state():
+    """u = 0: only g(0) = 1/4 per node remains, E = prod(h) N^d / 4."""
+    for ns in ((7, 5), (4, 3, 6)):
+        hs = W.mesh_widths(ns)
+        ops = O.axis_operators(ns, (1.4, 1.7, 1.9)[: len(ns)], 0.3, hs, 0.01)
+        E = O.discrete_energy(np.zeros(tuple(reversed(ns))), ops, hs)
+        assert E == pytest.approx(np.prod(hs) * np.prod(ns) / 4.0, rel=1e-15)
+
+
+def test_energy_quadratic_term_alpha2_sine_modes():
+    """alpha = 2: B = (eps/h)^2 tridiag(1, -2, 1), whose eigenvectors are the sine modes with
+    eigenvalues -(4 eps^2 / h^2) sin^2(k pi / (2 (N + 1))). For u = sin(k1 pi x1) sin(k2 pi x2) at
+    the nodes, u^T A u = (lambda_k1 + lambda_k2) |u|^2 and |u|^2 = (N1 + 1)(N2 + 1)/4."""
+    ns, eps = (11, 8), 0.2
+    hs = W.mesh_widths(ns)
+    ops = O.axis_operators(ns, (2.0, 2.0), eps, hs, 0.01)
+    for k1, k2 in ((1, 1), (3, 2), (11, 8)):
+        s1 = np.sin(k1 * np.pi * np.arange(1, ns[0] + 1) / (ns[0] + 1))
+        s2 = np.sin(k2 * np.pi * np.arange(1, ns[1] + 1) / (ns[1] + 1))
+        u = s2[:, None] * s1[None, :]
+        lam = [-(4 * eps ** 2 / h ** 2) * np.sin(k * np.pi / (2 * (n + 1))) ** 2
+               for k, n, h in ((k1, ns[0], hs[0]), (k2, ns[1], hs[1]))]
+        quartic = np.prod(hs) * 0.25 * np.sum((u * u - 1.0) ** 2)
+        expect = quartic - 0.5 * np.prod(hs) * (lam[0] + lam[1]) * (ns[0] + 1) * (ns[1] + 1) / 4.0
+        assert O.discrete_energy(u, ops, hs) == pytest.approx(expect, rel=1e-13)
+
+
+@pytest.mark.parametrize("ns", [(5, 4), (3, 4, 2)])
+def test_energy_matches_dense_kronecker(ns):
+    """The quadratic term against A assembled as a dense Kronecker sum (brute force)."""
+    alphas = (1.3, 1.6, 1.8)[: len(ns)]
+    hs = W.mesh_widths(ns)
+    ops = O.axis_operators(ns, alphas, 0.4, hs, 0.01)
+    A = _kron_sum([o.B for o in ops])
+    u = W.uniform_field(tuple(reversed(ns)), -1, 1, seed=9)
+    v = u.reshape(-1)
+    expect = np.prod(hs) * (0.25 * np.sum((v * v - 1.0) ** 2) - 0.5 * v @ (A @ v))
+    assert O.discrete_energy(u, ops, hs) == pytest.approx(expect, rel=1e-13)
+
+
+def test_energy_decays_along_the_two_level_scheme():
+    """Example 5 (Sec. 5, Fig. 4): the discrete energy decays monotonically. The 2D setting at
+    a smaller grid: (0, 1)^2, u0 = 0.8 rand - 0.4, eps = 0.01, tau = 0.01."""
+    n = 63
+    ns, hs = (n, n), (1.0 / (n + 1),) * 2
+    ops = O.axis_operators(ns, (1.5, 1.5), 0.01, hs, 0.01)
+    u = W.uniform_field((n, n), -0.4, 0.4, seed=17)
+    energies = [O.discrete_energy(u, ops, hs)]
+    for _ in range(40):
+        u = O.two_level_step(u, ops, 0.01)
+        energies.append(O.discrete_energy(u, ops, hs))
+    d = np.diff(energies)
+    assert np.all(d < 0), d.max()
