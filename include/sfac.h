@@ -151,6 +151,23 @@ sfac_status sfac_plan_reset_flags(sfac_plan p);
  */
 sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float* ms);
 
+/*
+ * sfac_plan_energy - the discrete free energy of Sec. 5, Example 5 (the discretisation of the
+ * Ginzburg-Landau functional of eq. (energy)) of the state u_dev, in the plan's layout and
+ * arithmetic:
+ *     E(u) = prod_l h_l * ( 1/4 sum_i (u_i^2 - 1)^2  -  1/2 u^T A u ),
+ * with A the Kronecker sum over the axes of the matrices B of eq. (B) (the plan's alpha, eps, h).
+ * u_dev is only read. The quadratic term is summed per axis as x^T B x over the lines, through the
+ * zero-padded length-M transform of each line (M the embedded method's length, whatever method
+ * the plan's passes use); sums are kept in FP64 for FP32 plans too. The first call builds the
+ * kernel tables on the host and allocates them (released by sfac_plan_destroy); later calls
+ * allocate nothing. Runs on the plan's stream and synchronizes it before *energy is written,
+ * so it cannot be captured into a graph.
+ * Errors: SFAC_EINVAL (NULL or misaligned arguments), SFAC_EUNSUPPORTED (an axis with N > 2048),
+ * SFAC_ENOMEM, SFAC_EDEVICE.
+ */
+sfac_status sfac_plan_energy(sfac_plan p, const void* u_dev, double* energy);
+
 /* sfac_plan_method - the method (SFAC_METHOD_DIAG or SFAC_METHOD_EMBED) and transform length
  * the plan uses on axis `axis` (1-based). Errors: SFAC_EINVAL. */
 sfac_status sfac_plan_method(sfac_plan p, int32_t axis, int32_t* method, int32_t* length);

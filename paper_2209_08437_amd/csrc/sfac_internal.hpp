@@ -69,4 +69,16 @@ int auto_method(int n, sfac_dtype dt);
 // Smallest power of two >= 2n - 1 (at least 2).
 int embed_length(int n);
 
+// Tables of the energy kernel (discrete energy of Example 5, Sec. 5) for one axis: the
+// length-M transform twiddles and the spectrum of B's circulant embedding divided by M, stored
+// in the transform's last-pass position order (embed_frequency with the kernel's log2e).
+constexpr int kMaxEnergyLength = 4096;
+struct EnergyTables {
+    int n = 0;
+    int length = 0;
+    std::vector<double> tw_re, tw_im;
+    std::vector<double> gpos;
+};
+std::string build_energy_tables(const AxisParams& p, int log2e, EnergyTables* out);
+
 }  // namespace sfac

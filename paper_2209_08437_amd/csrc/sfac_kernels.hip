@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "sfac_diag2.hpp"
 #include "sfac_embed.hpp"
@@ -715,6 +716,93 @@ __global__ void __launch_bounds__(kBlockThreads) axis_pass_multi(const PassDesc<
     run_tile(d, tile, buf0, buf1);
 }
 
+// Discrete energy (Sec. 5, Example 5), one axis. A thread block holds lpb line pairs packed as
+// x + i y. Their zero-padded length-M transform X gives sum_m G[m] |X[m]|^2 = x^T B x + y^T B y:
+// the cross terms of the packing cancel between m and M - m because G is symmetric. The loads
+// also sum the double-well term when d.nl_in is set (once per element: on one axis only).
+// Sums are kept in FP64 whatever T, reduced over each wavefront and added with one atomic each.
+template <typename T, int LOG2M>
+__global__ void __launch_bounds__(kBlockThreads) energy_pass(PassDesc<T> d) {
+    constexpr int LE = energy_log2e(LOG2M);
+    using G = EmbedGeom<LOG2M, LE>;
+    using Line = EmbedLine<T, LOG2M, LE>;
+    extern __shared__ unsigned char smem_raw[];
+    const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
+    if (tile >= d.ntiles) return;
+    const int line = threadIdx.x >> G::LOG2T;
+    const int t = threadIdx.x & (G::T - 1);
+    const TileGeom<T> tg(d, tile);
+    const int N = d.N;
+    const bool act = 2 * line < tg.nreal;
+    const bool two = 2 * line + 1 < tg.nreal;
+    Line L;
+    L.load_twiddles(d.tw, t);
+    const T* own = tg.base + (long long)(2 * line) * tg.lstride;
+    constexpr int R0 = G::R(0);
+    double well = 0.0;
+#pragma unroll
+    for (int i = 0; i < G::E / R0; ++i)
+#pragma unroll
+        for (int k = 0; k < R0; ++k) {
+            const int n = Line::nat(t, i, k);
+            cplx<T> z = {(T)0, (T)0};
+            if ((R0 < 2 || k < R0 / 2) && act && n < N) {
+                load_pair(own + (long long)n * tg.kstride, tg.lstride, two, z.x, z.y);
+                if (d.nl_in) {
+                    const double qx = (double)z.x * (double)z.x - 1.0;
+                    const double qy = (double)z.y * (double)z.y - 1.0;
+                    well += 0.25 * qx * qx + (two ? 0.25 * qy * qy : 0.0);
+                }
+            }
+            L.a[i * R0 + k] = z;
+        }
+    cplx<T>* ln = reinterpret_cast<cplx<T>*>(smem_raw) + line * G::M;
+    L.template fwd_from<0>(ln, t);
+    constexpr int S = G::NST - 1;
+    constexpr int R = G::R(S);
+    double quad = 0.0;
+#pragma unroll
+    for (int i = 0; i < G::E / R; ++i)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const Spec<T> g = d.gpos_c[embed_pos<LOG2M, LE, S>(t, i, k)];
+            double gv;
+            if constexpr (sizeof(T) == 8)
+                gv = (double)g.v;
+            else
+                gv = (double)g.hi + (double)g.lo;
+            const cplx<T> z = L.a[i * R + k];
+            quad += gv * ((double)z.x * (double)z.x + (double)z.y * (double)z.y);
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        quad += __shfl_xor(quad, off);
+        well += __shfl_xor(well, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&d.energy[0], quad);
+        if (d.nl_in) atomicAdd(&d.energy[1], well);
+    }
+}
+
+template <typename T>
+const void* energy_fn(int log2m) {
+    switch (log2m) {
+        case 1: return reinterpret_cast<const void*>(&energy_pass<T, 1>);
+        case 2: return reinterpret_cast<const void*>(&energy_pass<T, 2>);
+        case 3: return reinterpret_cast<const void*>(&energy_pass<T, 3>);
+        case 4: return reinterpret_cast<const void*>(&energy_pass<T, 4>);
+        case 5: return reinterpret_cast<const void*>(&energy_pass<T, 5>);
+        case 6: return reinterpret_cast<const void*>(&energy_pass<T, 6>);
+        case 7: return reinterpret_cast<const void*>(&energy_pass<T, 7>);
+        case 8: return reinterpret_cast<const void*>(&energy_pass<T, 8>);
+        case 9: return reinterpret_cast<const void*>(&energy_pass<T, 9>);
+        case 10: return reinterpret_cast<const void*>(&energy_pass<T, 10>);
+        case 11: return reinterpret_cast<const void*>(&energy_pass<T, 11>);
+        case 12: return reinterpret_cast<const void*>(&energy_pass<T, 12>);
+        default: return nullptr;
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -755,7 +843,23 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
 }
 
 template <typename T>
+hipError_t launch_energy_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream) {
+    const int blocks = pass_blocks(d);
+    if (blocks <= 0) return hipSuccess;
+    const void* fn = energy_fn<T>(d.log2m);
+    if (!fn) return hipErrorInvalidValue;
+    void* args[] = {const_cast<PassDesc<T>*>(&d)};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(d.threads), args, lds_bytes, stream);
+}
+
+// The limit is a per-kernel attribute of the process: it only ever rises, so that a plan made
+// later with a smaller need cannot take LDS away from the launches of an earlier one.
+template <typename T>
 hipError_t allow_lds(size_t lds_bytes) {
+    static std::mutex lock;
+    static size_t granted = 64 * 1024;
+    std::lock_guard<std::mutex> guard(lock);
+    if (lds_bytes <= granted) return hipSuccess;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_single<T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
@@ -768,6 +872,10 @@ hipError_t allow_lds(size_t lds_bytes) {
                     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
                     if (e != hipSuccess) return e;
                 }
+    for (int lg = 1; lg <= 12; ++lg) {
+        e = hipFuncSetAttribute(energy_fn<T>(lg), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
     for (int a = 3; a <= 17; ++a)
         for (int b = a; b <= 17; ++b)
             for (int multi = 0; multi < 2; ++multi)
@@ -777,8 +885,10 @@ hipError_t allow_lds(size_t lds_bytes) {
                     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
                     if (e != hipSuccess) return e;
                 }
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_multi<T>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_multi<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e == hipSuccess) granted = lds_bytes;
+    return e;
 }
 
 template int pass_blocks<double>(const PassDesc<double>&);
@@ -789,6 +899,8 @@ template hipError_t launch_axis_pass_multi<double>(int, int, int, const PassDesc
                                                    size_t, hipStream_t);
 template hipError_t launch_axis_pass_multi<float>(int, int, int, const PassDesc<float>*, const int*, int, int,
                                                   size_t, hipStream_t);
+template hipError_t launch_energy_pass<double>(const PassDesc<double>&, size_t, hipStream_t);
+template hipError_t launch_energy_pass<float>(const PassDesc<float>&, size_t, hipStream_t);
 template hipError_t allow_lds<double>(size_t);
 template hipError_t allow_lds<float>(size_t);
 

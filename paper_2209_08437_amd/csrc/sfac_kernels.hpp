@@ -54,6 +54,7 @@ struct PassDesc {
     const cplx<T>* psi2;             // two-step diagonal kernel: per-thread psi
     unsigned long long* stat_max;    // bits of the largest |u| stored (non-negative double)
     unsigned int* stat_flags;        // SFAC_FLAG_* bits
+    double* energy;                  // energy pass: [0] += sum of x^T B x over its lines, [1] += (u^2 - 1)^2 / 4
     long long inner, outer;
     int N;                           // points per line
     int L;                           // transform length (N or M)
@@ -88,6 +89,17 @@ template <typename T>
 hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const PassDesc<T>* descs_dev,
                                   const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
                                   hipStream_t stream);
+
+// Elements per thread (log2) of the energy kernel for a transform of length 2^log2m: 8, or 16 at
+// M = 4096, so that a line is at most 256 threads.
+constexpr int energy_log2e(int log2m) { return log2m >= 12 ? 4 : 3; }
+
+// One axis of the discrete energy (Sec. 5, Example 5) of d.u: per line pair the length-M transform
+// of the zero-padded pair, sum_m G[m] |X[m]|^2 with d.gpos_c = G (B's circulant embedding, 1/M folded
+// in, last-pass position order) and d.tw the transform twiddles, added to d.energy[0]; with d.nl_in
+// set, also (u^2 - 1)^2 / 4 over the loaded elements, added to d.energy[1]. d.L = M <= 4096.
+template <typename T>
+hipError_t launch_energy_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream);
 
 // Raise the dynamic-LDS limit of the pass kernels to lds_bytes (needed above 64 KiB).
 template <typename T>

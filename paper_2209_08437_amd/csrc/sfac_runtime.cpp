@@ -322,6 +322,13 @@ hipError_t launch_pass(const sfac::PassDesc<T>& d, size_t lds, hipStream_t s) {
 }  // namespace
 
 // ===================================================================== plans
+// Energy kernel of one axis (built on the first sfac_plan_energy call of a plan).
+struct EnergyAxis {
+    size_t off_tw = 0, off_g = 0;
+    int log2m = 0, lpb = 1, threads = 64;
+    size_t lds = 0;
+};
+
 struct sfac_plan_s {
     Instance in;
     hipStream_t stream = nullptr;      // caller's stream (may be the legacy default stream)
@@ -336,15 +343,18 @@ struct sfac_plan_s {
     void* graph_u = nullptr;           // state pointer the graphs were captured for
     hipGraphExec_t exec_chunk = nullptr, exec_one = nullptr;
     hipGraph_t graph_chunk = nullptr, graph_one = nullptr;
+    unsigned char* energy_dev = nullptr;  // [0, 16): the two energy sums; then per-axis tables
+    size_t energy_bytes = 0;
+    EnergyAxis eax[3];
 
     unsigned long long* stat_max() { return reinterpret_cast<unsigned long long*>(dev + off_stat); }
     unsigned int* stat_flags() { return reinterpret_cast<unsigned int*>(dev + off_stat + 8); }
 
     void drop_graphs() {
-        if (exec_chunk) hipGraphExecDestroy(exec_chunk);
-        if (exec_one) hipGraphExecDestroy(exec_one);
-        if (graph_chunk) hipGraphDestroy(graph_chunk);
-        if (graph_one) hipGraphDestroy(graph_one);
+        if (exec_chunk) (void)hipGraphExecDestroy(exec_chunk);
+        if (exec_one) (void)hipGraphExecDestroy(exec_one);
+        if (graph_chunk) (void)hipGraphDestroy(graph_chunk);
+        if (graph_one) (void)hipGraphDestroy(graph_one);
         exec_chunk = exec_one = nullptr;
         graph_chunk = graph_one = nullptr;
         graph_u = nullptr;
@@ -380,6 +390,100 @@ struct sfac_plan_s {
         return SFAC_OK;
     }
 };
+
+namespace {
+
+template <typename T>
+sfac::PassDesc<T> energy_desc(const Instance& in, int a, const EnergyAxis& ea, unsigned char* dev, T* u) {
+    sfac::PassDesc<T> d{};
+    d.u = u;
+    d.tw = reinterpret_cast<const sfac::cplx<T>*>(dev + ea.off_tw);
+    d.gpos_c = reinterpret_cast<const sfac::Spec<T>*>(dev + ea.off_g);
+    d.energy = reinterpret_cast<double*>(dev);
+    d.log2m = ea.log2m;
+    d.log2e = sfac::energy_log2e(ea.log2m);
+    d.threads = ea.threads;
+    long long inner = 1, outer = 1;
+    for (int b = 0; b < a; ++b) inner *= in.n[b];
+    for (int b = a + 1; b < in.dims; ++b) outer *= in.n[b];
+    d.inner = inner;
+    d.outer = outer;
+    d.N = in.n[a];
+    d.L = 1 << ea.log2m;
+    d.method = SFAC_METHOD_EMBED;
+    d.lpb = ea.lpb;
+    if (inner == 1) {
+        d.tiles_per_outer = 0;
+        d.ntiles = (int)((outer + 2LL * d.lpb - 1) / (2LL * d.lpb));
+    } else {
+        d.tiles_per_outer = (int)((inner + 2LL * d.lpb - 1) / (2LL * d.lpb));
+        d.ntiles = (int)(outer * d.tiles_per_outer);
+    }
+    d.nl_in = a == 0;
+    d.xcd_remap = inner > 1 ? 1 : 0;
+    return d;
+}
+
+// Host tables of every axis' energy kernel, uploaded once into a buffer of the plan.
+template <typename T>
+sfac_status energy_setup(sfac_plan p) {
+    std::vector<unsigned char> host(256, 0);
+    size_t lds_max = 0;
+    for (int a = 0; a < p->in.dims; ++a) {
+        const sfac::AxisParams ap{p->in.n[a], p->in.alpha[a], p->in.eps, p->in.tau, p->in.h[a]};
+        sfac::EnergyTables t;
+        int log2m = 0;
+        while ((1 << log2m) < sfac::embed_length(p->in.n[a])) ++log2m;
+        const std::string err = sfac::build_energy_tables(ap, sfac::energy_log2e(log2m), &t);
+        if (!err.empty()) return fail(SFAC_EUNSUPPORTED, "energy, axis %d: %s", a + 1, err.c_str());
+        EnergyAxis& ea = p->eax[a];
+        ea.log2m = log2m;
+        const int M = t.length;
+        const int tl = M >> sfac::embed_log2e(log2m, sfac::energy_log2e(log2m));   // threads per line
+        long long inner = 1, outer = 1;
+        for (int b = 0; b < a; ++b) inner *= p->in.n[b];
+        for (int b = a + 1; b < p->in.dims; ++b) outer *= p->in.n[b];
+        const long long avail = inner == 1 ? outer : inner;
+        ea.lpb = (int)std::max<long long>(1, std::min<long long>(std::max(1, sfac::kBlockThreads / tl),
+                                                                 (avail + 1) / 2));
+        ea.threads = ea.lpb * tl;
+        ea.lds = sizeof(sfac::cplx<T>) * (size_t)M * ea.lpb;
+        lds_max = std::max(lds_max, ea.lds);
+        ea.off_tw = align_up(host.size(), 256);
+        host.resize(ea.off_tw + sizeof(sfac::cplx<T>) * M);
+        auto* tw = reinterpret_cast<sfac::cplx<T>*>(host.data() + ea.off_tw);
+        for (int m = 0; m < M; ++m) tw[m] = {(T)t.tw_re[m], (T)t.tw_im[m]};
+        ea.off_g = align_up(host.size(), 256);
+        host.resize(ea.off_g + sizeof(sfac::Spec<T>) * M);
+        auto* g = reinterpret_cast<sfac::Spec<T>*>(host.data() + ea.off_g);
+        for (int m = 0; m < M; ++m) g[m] = sfac::make_spec<T>(t.gpos[m]);
+    }
+    unsigned char* dev = nullptr;
+    hipError_t e = hipMalloc(&dev, host.size());
+    if (e != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(SFAC_ENOMEM, "hipMalloc(%zu): %s", host.size(), hipGetErrorString(e))
+                                        : hip_fail(e, "hipMalloc");
+    e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && lds_max > 64 * 1024) e = sfac::allow_lds<T>(lds_max);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(e, "energy tables");
+    }
+    p->energy_dev = dev;
+    p->energy_bytes = host.size();
+    return SFAC_OK;
+}
+
+template <typename T>
+hipError_t energy_launch(sfac_plan p, T* u) {
+    hipError_t e = hipMemsetAsync(p->energy_dev, 0, 2 * sizeof(double), p->stream);
+    for (int a = 0; a < p->in.dims && e == hipSuccess; ++a)
+        e = sfac::launch_energy_pass<T>(energy_desc<T>(p->in, a, p->eax[a], p->energy_dev, u), p->eax[a].lds,
+                                        p->stream);
+    return e;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -429,19 +533,19 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
     }
     e = hipMemcpy(p->dev, host.data(), p->dev_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        hipFree(p->dev);
+        (void)hipFree(p->dev);
         return hip_fail(e, "hipMemcpy tables");
     }
     if (p->in.lds_max > 64 * 1024) {
         e = dt == SFAC_FP64 ? sfac::allow_lds<double>(p->in.lds_max) : sfac::allow_lds<float>(p->in.lds_max);
         if (e != hipSuccess) {
-            hipFree(p->dev);
+            (void)hipFree(p->dev);
             return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
         }
     }
     e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        hipFree(p->dev);
+        (void)hipFree(p->dev);
         return hip_fail(e, "hipStreamCreate");
     }
     for (int a = 0; a < p->in.dims; ++a) {
@@ -528,7 +632,7 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
         }
     }
     for (auto& x : ev)
-        if (x) hipEventDestroy(x);
+        if (x) (void)hipEventDestroy(x);
     // the captured graphs keep their own copies of the launch arguments
     if (keep) p->set_u(keep);
     return e == hipSuccess ? SFAC_OK : hip_fail(e, "timed pass launches");
@@ -537,11 +641,36 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
 sfac_status sfac_plan_destroy(sfac_plan p) {
     g_error.clear();
     if (!p) return SFAC_OK;
-    hipStreamSynchronize(p->stream);
+    (void)hipStreamSynchronize(p->stream);
     p->drop_graphs();
-    if (p->capture) hipStreamDestroy(p->capture);
-    if (p->dev) hipFree(p->dev);
+    if (p->capture) (void)hipStreamDestroy(p->capture);
+    if (p->dev) (void)hipFree(p->dev);
+    if (p->energy_dev) (void)hipFree(p->energy_dev);
     delete p;
+    return SFAC_OK;
+}
+
+
+sfac_status sfac_plan_energy(sfac_plan p, const void* u_dev, double* energy) {
+    g_error.clear();
+    if (!p) return fail(SFAC_EINVAL, "NULL plan");
+    if (!u_dev || !energy) return fail(SFAC_EINVAL, "NULL state or output");
+    const size_t es = p->in.dt == SFAC_FP64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(u_dev) % es) return fail(SFAC_EINVAL, "state pointer not aligned to %zu bytes", es);
+    if (!p->energy_dev) {
+        const sfac_status st = p->in.dt == SFAC_FP64 ? energy_setup<double>(p) : energy_setup<float>(p);
+        if (st != SFAC_OK) return st;
+    }
+    // the kernels only read the state
+    hipError_t e = p->in.dt == SFAC_FP64 ? energy_launch<double>(p, static_cast<double*>(const_cast<void*>(u_dev)))
+                                         : energy_launch<float>(p, static_cast<float*>(const_cast<void*>(u_dev)));
+    double sums[2] = {0.0, 0.0};
+    if (e == hipSuccess) e = hipMemcpyAsync(sums, p->energy_dev, sizeof sums, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "energy");
+    double hprod = 1.0;
+    for (int a = 0; a < p->in.dims; ++a) hprod *= p->in.h[a];
+    *energy = hprod * (sums[1] - 0.5 * sums[0]);
     return SFAC_OK;
 }
 
@@ -620,8 +749,8 @@ struct sfac_group_s {
     std::vector<hipGraphExec_t> execs;
 
     void drop_graphs() {
-        for (auto x : execs) hipGraphExecDestroy(x);
-        for (auto x : graphs) hipGraphDestroy(x);
+        for (auto x : execs) (void)hipGraphExecDestroy(x);
+        for (auto x : graphs) (void)hipGraphDestroy(x);
         execs.clear();
         graphs.clear();
     }
@@ -637,13 +766,13 @@ struct sfac_group_s {
     }
     void release() {
         drop_graphs();
-        if (fork) hipEventDestroy(fork);
+        if (fork) (void)hipEventDestroy(fork);
         for (int k = 0; k < kAux; ++k) {
-            if (join[k]) hipEventDestroy(join[k]);
-            if (aux[k]) hipStreamDestroy(aux[k]);
+            if (join[k]) (void)hipEventDestroy(join[k]);
+            if (aux[k]) (void)hipStreamDestroy(aux[k]);
         }
-        if (capture) hipStreamDestroy(capture);
-        if (arena) hipFree(arena);
+        if (capture) (void)hipStreamDestroy(capture);
+        if (arena) (void)hipFree(arena);
     }
 };
 
@@ -771,7 +900,7 @@ sfac_status capture_step(sfac_group g, const GroupLaunch* first, const GroupLaun
     }
     e = hipStreamEndCapture(g->capture, graph);
     if (le != hipSuccess) {
-        if (e == hipSuccess && *graph) hipGraphDestroy(*graph);
+        if (e == hipSuccess && *graph) (void)hipGraphDestroy(*graph);
         return hip_fail(le, "grouped kernel launch during capture");
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -820,7 +949,7 @@ sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void*
     e = g->ensure_streams();
     if (e != hipSuccess) return hip_fail(e, "group streams and events");
     if (g->host.size() > g->arena_bytes) {
-        if (g->arena) hipFree(g->arena);
+        if (g->arena) (void)hipFree(g->arena);
         g->arena = nullptr;
         g->arena_bytes = 0;
         e = hipMalloc(&g->arena, g->host.size());
@@ -887,7 +1016,7 @@ sfac_status sfac_group_step(sfac_group g, int32_t count, const sfac_plan* plans,
 sfac_status sfac_group_destroy(sfac_group g) {
     g_error.clear();
     if (!g) return SFAC_OK;
-    hipStreamSynchronize(g->stream);
+    (void)hipStreamSynchronize(g->stream);
     g->release();
     delete g;
     return SFAC_OK;

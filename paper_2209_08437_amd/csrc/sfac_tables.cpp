@@ -123,6 +123,68 @@ int auto_method(int n, sfac_dtype) {
     return 0;
 }
 
+// eqs. (g_coe), (omega_coe) for omega_0 .. omega_N, then eq. (B): kappa and the first column
+// b_0 .. b_{N-1} of the symmetric Toeplitz B (entry (i, j) is b_{|i - j|})
+static std::vector<ld> first_column_B(const AxisParams& p) {
+    const int N = p.n;
+    std::vector<ld> g(N + 2), w(N + 2);
+    const ld a = p.alpha;
+    g[0] = 1.0L;
+    for (int k = 0; k + 1 < N + 2; ++k) g[k + 1] = (1.0L - (a + 1.0L) / (ld)(k + 1)) * g[k];
+    w[0] = 0.5L * a * g[0];
+    for (int k = 0; k + 1 < N + 2; ++k) w[k + 1] = 0.5L * a * g[k + 1] + 0.5L * (2.0L - a) * g[k];
+    const ld kappa = -((ld)p.eps * (ld)p.eps) / (2.0L * powl((ld)p.h, a) * cosl(a * kPi / 2.0L));
+    std::vector<ld> b(N);
+    b[0] = 2.0L * kappa * w[1];
+    if (N >= 2) b[1] = kappa * (w[0] + w[2]);
+    for (int k = 2; k < N; ++k) b[k] = kappa * w[k + 1];
+    return b;
+}
+
+std::string build_energy_tables(const AxisParams& p, int log2e, EnergyTables* out) {
+    const int N = p.n;
+    if (N < 1) return "N must be >= 1";
+    const int M = embed_length(N);
+    if (M > kMaxEnergyLength) {
+        char msg[128];
+        snprintf(msg, sizeof msg, "N = %d exceeds the energy kernel's limit %d", N, kMaxEnergyLength / 2);
+        return msg;
+    }
+    const std::vector<ld> b = first_column_B(p);
+    // x^T B x = x'^T K x' for x' = x zero-padded to M and K the length-M circulant with
+    // K[d mod M] = b_{|d|} (|d| < N; M >= 2N - 1 keeps the two ends apart), and by Parseval
+    // x'^T K x' = (1/M) sum_m G[m] |X[m]|^2 with G[m] = b_0 + 2 sum_{d>=1} b_d cos(2 pi m d / M)
+    int log2m = 0;
+    while ((1 << log2m) < M) ++log2m;
+    std::vector<ld> cosm(M);
+    for (int r = 0; r < M; ++r) cosm[r] = cosl(2.0L * kPi * (ld)r / (ld)M);
+    std::vector<double> G(M);
+    for (int m = 0; m < M; ++m) {
+        ld acc = b[0];
+        long long r = m % M;
+        for (int d = 1; d < N; ++d) {
+            acc += 2.0L * b[d] * cosm[(size_t)r];
+            r += m;
+            if (r >= M) r -= M;
+        }
+        G[m] = (double)(acc / (ld)M);
+    }
+    EnergyTables& t = *out;
+    t = EnergyTables();
+    t.n = N;
+    t.length = M;
+    t.tw_re.resize(M);
+    t.tw_im.resize(M);
+    for (int m = 0; m < M; ++m) {
+        const ld ang = 2.0L * kPi * (ld)m / (ld)M;
+        t.tw_re[m] = (double)cosl(ang);
+        t.tw_im[m] = (double)-sinl(ang);
+    }
+    t.gpos.resize(M);
+    for (int q = 0; q < M; ++q) t.gpos[q] = G[embed_frequency(q, log2m, log2e)];
+    return std::string();
+}
+
 std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e, bool diag2) {
     const int N = p.n;
     char msg[256];
@@ -162,20 +224,7 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, 
         return "unknown method";
     }
 
-    // eqs. (g_coe), (omega_coe): omega_0 .. omega_N
-    std::vector<ld> g(N + 2), w(N + 2);
-    const ld a = p.alpha;
-    g[0] = 1.0L;
-    for (int k = 0; k + 1 < N + 2; ++k) g[k + 1] = (1.0L - (a + 1.0L) / (ld)(k + 1)) * g[k];
-    w[0] = 0.5L * a * g[0];
-    for (int k = 0; k + 1 < N + 2; ++k) w[k + 1] = 0.5L * a * g[k + 1] + 0.5L * (2.0L - a) * g[k];
-
-    // eq. (B): kappa and the first column of B
-    const ld kappa = -((ld)p.eps * (ld)p.eps) / (2.0L * powl((ld)p.h, a) * cosl(a * kPi / 2.0L));
-    std::vector<ld> b(N);
-    b[0] = 2.0L * kappa * w[1];
-    if (N >= 2) b[1] = kappa * (w[0] + w[2]);
-    for (int k = 2; k < N; ++k) b[k] = kappa * w[k + 1];
+    const std::vector<ld> b = first_column_B(p);
 
     // eqs. (C), (S)
     std::vector<ld> c(N), s(N);

@@ -21,7 +21,7 @@ EXPORTS = [
     "sfac_plan_flags", "sfac_plan_reset_flags", "sfac_plan_method", "sfac_last_error",
     "sfac_batch_create", "sfac_batch_step", "sfac_batch_destroy", "sfac_batch_device_bytes",
     "sfac_axis_tables", "sfac_plan_time_passes", "sfac_group_create", "sfac_group_step",
-    "sfac_group_destroy", "sfac_group_device_bytes", "sfac_batch_plan",
+    "sfac_group_destroy", "sfac_group_device_bytes", "sfac_batch_plan", "sfac_plan_energy",
 ]
 
 
@@ -74,6 +74,7 @@ def lib():
     L.sfac_axis_tables.argtypes = [i32, dbl, dbl, dbl, dbl, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl),
                                    ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.sfac_plan_time_passes.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_float)]
+    L.sfac_plan_energy.argtypes = [vp, vp, ctypes.POINTER(dbl)]
     L.sfac_group_create.argtypes = [ctypes.POINTER(vp), vp]
     L.sfac_group_step.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]
     L.sfac_group_destroy.argtypes = [vp]
@@ -83,7 +84,7 @@ def lib():
     L.sfac_batch_plan.restype = vp
     for name in ["sfac_group_create", "sfac_group_step", "sfac_group_destroy", "sfac_plan_time_passes", "sfac_axis_tables", "sfac_plan_create", "sfac_step", "sfac_plan_destroy", "sfac_plan_flags",
                  "sfac_plan_reset_flags", "sfac_plan_method", "sfac_batch_create",
-                 "sfac_batch_step", "sfac_batch_destroy"]:
+                 "sfac_batch_step", "sfac_batch_destroy", "sfac_plan_energy"]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -216,6 +217,14 @@ class Plan:
         ms = (ctypes.c_float * self.dims)()
         _check(lib().sfac_plan_time_passes(self._h, ctypes.c_void_p(u.data_ptr()), int(reps), ms))
         return list(ms)
+
+    def energy(self, u):
+        """Discrete free energy of Sec. 5, Example 5 of the state u (only read); synchronizes the
+        plan's stream."""
+        _check_state(u, self.shape, self.dt)
+        e = ctypes.c_double()
+        _check(lib().sfac_plan_energy(self._h, ctypes.c_void_p(u.data_ptr()), ctypes.byref(e)))
+        return e.value
 
     def flags(self):
         """(flags, max_abs) since the last reset; synchronizes the plan's stream."""
