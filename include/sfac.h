@@ -168,6 +168,28 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
  */
 sfac_status sfac_plan_energy(sfac_plan p, const void* u_dev, double* energy);
 
+/*
+ * sfac_plan_trace - record the maximum norm max|u| after every step of sfac_step (the quantity
+ * Sec. 5, Example 4 follows step by step; the discrete maximum principle of Theorem 1 bounds it
+ * by 1). capacity > 0 allocates a record of `capacity` entries, zeroed, and restarts the step
+ * count: step k (k = 0, 1, .. counted from this call) writes entry k while k < capacity, later
+ * steps are counted but not recorded. capacity = 0 stops recording and frees the record. The
+ * value is the same largest |u| the last pass of the step folds into sfac_plan_flags. Only
+ * sfac_step records (not sfac_plan_time_passes, groups or batches). Each recorded step adds one
+ * one-thread kernel to the step graphs, which this call has re-captured on the next sfac_step.
+ * Synchronizes the plan's stream. Errors: SFAC_EINVAL, SFAC_ENOMEM, SFAC_EDEVICE.
+ */
+sfac_status sfac_plan_trace(sfac_plan p, int64_t capacity);
+
+/*
+ * sfac_plan_read_trace - synchronize the plan's stream and copy the first min(steps, record
+ * capacity, `capacity`) entries of the record to out[] (host); *recorded receives the steps
+ * counted since sfac_plan_trace (0 when no record is kept). out may be NULL when capacity is 0.
+ * Errors: SFAC_EINVAL (NULL plan or recorded, capacity < 0, NULL out with capacity > 0),
+ * SFAC_EDEVICE.
+ */
+sfac_status sfac_plan_read_trace(sfac_plan p, double* out, int64_t capacity, int64_t* recorded);
+
 /* sfac_plan_method - the method (SFAC_METHOD_DIAG or SFAC_METHOD_EMBED) and transform length
  * the plan uses on axis `axis` (1-based). Errors: SFAC_EINVAL. */
 sfac_status sfac_plan_method(sfac_plan p, int32_t axis, int32_t* method, int32_t* length);

@@ -140,8 +140,10 @@ __device__ cplx<T>* transform(const PassDesc<T>& d, cplx<T>* cur, cplx<T>* other
 }
 
 // Wave-level reduction of the store statistics, then one atomic per wave.
-__device__ __forceinline__ void publish_stats(double vmax, unsigned int bad, unsigned long long* smax,
-                                              unsigned int* sflags) {
+template <typename T>
+__device__ __forceinline__ void publish_stats(double vmax, unsigned int bad, const PassDesc<T>& d) {
+    unsigned long long* smax = d.stat_max;
+    unsigned int* sflags = d.stat_flags;
     for (int off = 32; off > 0; off >>= 1) {
         vmax = fmax(vmax, __shfl_xor(vmax, off));
         bad |= __shfl_xor(bad, off);
@@ -154,6 +156,11 @@ __device__ __forceinline__ void publish_stats(double vmax, unsigned int bad, uns
         // first and only then update
         const unsigned long long bits = (unsigned long long)__double_as_longlong(vmax);
         if (bits > __atomic_load_n(smax, __ATOMIC_RELAXED)) atomicMax(smax, bits);
+        // the per-step record (the maximum norm after every step, Sec. 5, Example 4)
+        if (d.trace) {
+            const long long k = __atomic_load_n(d.trace_step, __ATOMIC_RELAXED);
+            if (k < d.trace_cap) atomicMax(&d.trace[k], bits);
+        }
     }
 }
 
@@ -280,7 +287,7 @@ __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>*
                 vmax = fmax(vmax, fmax(ax, ay));
         }
     }
-    if (nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
+    if (nl_out) publish_stats(vmax, bad, d);
 }
 
 // Lines of one tile: a tile is 2*lpb real lines (rows of the contiguous axis, or adjacent
@@ -423,7 +430,7 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
         __syncthreads();
         embed_stage<T, LOG2M, LE, false>(d, tg, lds);
     }
-    if (d.nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
+    if (d.nl_out) publish_stats(vmax, bad, d);
 }
 
 template <typename T, int A, int B, bool LOAD>
@@ -523,7 +530,7 @@ __device__ __forceinline__ void run_diag2_tile(const PassDesc<T>& d, int tile, c
     }
     __syncthreads();
     stage_tile<T, A, B, false>(tg, d.lpb, lds);
-    if (d.nl_out) publish_stats(vmax, bad, d.stat_max, d.stat_flags);
+    if (d.nl_out) publish_stats(vmax, bad, d);
 }
 
 // blockIdx -> tile, grouping neighbouring tiles on one XCD (blocks are dealt round-robin to
@@ -839,6 +846,17 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
     }
     hipLaunchKernelGGL(axis_pass_multi<T>, dim3(total_blocks), dim3(kBlockThreads), lds_bytes, stream,
                        descs_dev, block_start_dev, ndesc);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void trace_advance(long long* step) {
+    if (threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long*>(step), 1ull);
+}
+}  // namespace
+
+hipError_t launch_trace_advance(long long* step, hipStream_t stream) {
+    hipLaunchKernelGGL(trace_advance, dim3(1), dim3(64), 0, stream, step);
     return hipGetLastError();
 }
 

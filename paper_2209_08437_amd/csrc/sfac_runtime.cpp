@@ -346,6 +346,18 @@ struct sfac_plan_s {
     unsigned char* energy_dev = nullptr;  // [0, 16): the two energy sums; then per-axis tables
     size_t energy_bytes = 0;
     EnergyAxis eax[3];
+    unsigned char* trace_dev = nullptr;   // per-step record: [0, 8) the step index, then trace_cap entries
+    long long trace_cap = 0;
+
+    long long* trace_step() { return reinterpret_cast<long long*>(trace_dev); }
+    unsigned long long* trace_rec() { return reinterpret_cast<unsigned long long*>(trace_dev + 8); }
+    void set_trace() {
+        for (int a = 0; a < in.dims; ++a) {
+            d64[a].trace = d32[a].trace = trace_dev ? trace_rec() : nullptr;
+            d64[a].trace_step = d32[a].trace_step = trace_dev ? trace_step() : nullptr;
+            d64[a].trace_cap = d32[a].trace_cap = trace_dev ? trace_cap : 0;
+        }
+    }
 
     unsigned long long* stat_max() { return reinterpret_cast<unsigned long long*>(dev + off_stat); }
     unsigned int* stat_flags() { return reinterpret_cast<unsigned int*>(dev + off_stat + 8); }
@@ -365,6 +377,10 @@ struct sfac_plan_s {
             for (int a = 0; a < in.dims; ++a) {
                 hipError_t e = in.dt == SFAC_FP64 ? launch_pass(d64[a], in.ax[a].lds, s)
                                                   : launch_pass(d32[a], in.ax[a].lds, s);
+                if (e != hipSuccess) return e;
+            }
+            if (trace_dev) {
+                hipError_t e = sfac::launch_trace_advance(trace_step(), s);
                 if (e != hipSuccess) return e;
             }
         }
@@ -612,8 +628,13 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
             const size_t i = 2 * ((size_t)r * d + a);
             e = hipEventRecord(ev[i], p->stream);
             if (e != hipSuccess) break;
-            e = p->in.dt == SFAC_FP64 ? launch_pass(p->d64[a], p->in.ax[a].lds, p->stream)
-                                      : launch_pass(p->d32[a], p->in.ax[a].lds, p->stream);
+            // plain launches outside sfac_step: not part of the per-step record
+            sfac::PassDesc<double> d64 = p->d64[a];
+            sfac::PassDesc<float> d32 = p->d32[a];
+            d64.trace = nullptr;
+            d32.trace = nullptr;
+            e = p->in.dt == SFAC_FP64 ? launch_pass(d64, p->in.ax[a].lds, p->stream)
+                                      : launch_pass(d32, p->in.ax[a].lds, p->stream);
             if (e != hipSuccess) break;
             e = hipEventRecord(ev[i + 1], p->stream);
         }
@@ -646,6 +667,7 @@ sfac_status sfac_plan_destroy(sfac_plan p) {
     if (p->capture) (void)hipStreamDestroy(p->capture);
     if (p->dev) (void)hipFree(p->dev);
     if (p->energy_dev) (void)hipFree(p->energy_dev);
+    if (p->trace_dev) (void)hipFree(p->trace_dev);
     delete p;
     return SFAC_OK;
 }
@@ -671,6 +693,58 @@ sfac_status sfac_plan_energy(sfac_plan p, const void* u_dev, double* energy) {
     double hprod = 1.0;
     for (int a = 0; a < p->in.dims; ++a) hprod *= p->in.h[a];
     *energy = hprod * (sums[1] - 0.5 * sums[0]);
+    return SFAC_OK;
+}
+
+sfac_status sfac_plan_trace(sfac_plan p, int64_t capacity) {
+    g_error.clear();
+    if (!p) return fail(SFAC_EINVAL, "NULL plan");
+    if (capacity < 0 || capacity > (int64_t(1) << 40)) return fail(SFAC_EINVAL, "capacity = %lld", (long long)capacity);
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    p->drop_graphs();     // the step graphs gain or lose the step-index kernel
+    if (p->trace_dev) (void)hipFree(p->trace_dev);
+    p->trace_dev = nullptr;
+    p->trace_cap = 0;
+    if (capacity > 0) {
+        const size_t bytes = 8 + 8 * (size_t)capacity;
+        e = hipMalloc(&p->trace_dev, bytes);
+        if (e != hipSuccess) {
+            p->trace_dev = nullptr;
+            p->set_trace();
+            return e == hipErrorOutOfMemory ? fail(SFAC_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e))
+                                            : hip_fail(e, "hipMalloc");
+        }
+        e = hipMemset(p->trace_dev, 0, bytes);
+        if (e != hipSuccess) {
+            (void)hipFree(p->trace_dev);
+            p->trace_dev = nullptr;
+            p->set_trace();
+            return hip_fail(e, "hipMemset");
+        }
+        p->trace_cap = capacity;
+    }
+    p->set_trace();
+    return SFAC_OK;
+}
+
+sfac_status sfac_plan_read_trace(sfac_plan p, double* out, int64_t capacity, int64_t* recorded) {
+    g_error.clear();
+    if (!p) return fail(SFAC_EINVAL, "NULL plan");
+    if (!recorded || capacity < 0 || (capacity > 0 && !out)) return fail(SFAC_EINVAL, "NULL output or capacity < 0");
+    *recorded = 0;
+    if (!p->trace_dev) return SFAC_OK;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    long long steps = 0;
+    if (e == hipSuccess) e = hipMemcpy(&steps, p->trace_step(), sizeof steps, hipMemcpyDeviceToHost);
+    const long long n = std::min<long long>(std::min<long long>(steps, p->trace_cap), capacity);
+    if (e == hipSuccess && n > 0) {
+        std::vector<unsigned long long> bits((size_t)n);
+        e = hipMemcpy(bits.data(), p->trace_rec(), 8 * (size_t)n, hipMemcpyDeviceToHost);
+        for (long long i = 0; e == hipSuccess && i < n; ++i) memcpy(&out[i], &bits[(size_t)i], 8);
+    }
+    if (e != hipSuccess) return hip_fail(e, "trace");
+    *recorded = steps;
     return SFAC_OK;
 }
 

@@ -22,6 +22,7 @@ EXPORTS = [
     "sfac_batch_create", "sfac_batch_step", "sfac_batch_destroy", "sfac_batch_device_bytes",
     "sfac_axis_tables", "sfac_plan_time_passes", "sfac_group_create", "sfac_group_step",
     "sfac_group_destroy", "sfac_group_device_bytes", "sfac_batch_plan", "sfac_plan_energy",
+    "sfac_plan_trace", "sfac_plan_read_trace",
 ]
 
 
@@ -75,6 +76,8 @@ def lib():
                                    ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.sfac_plan_time_passes.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_float)]
     L.sfac_plan_energy.argtypes = [vp, vp, ctypes.POINTER(dbl)]
+    L.sfac_plan_trace.argtypes = [vp, i64]
+    L.sfac_plan_read_trace.argtypes = [vp, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)]
     L.sfac_group_create.argtypes = [ctypes.POINTER(vp), vp]
     L.sfac_group_step.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]
     L.sfac_group_destroy.argtypes = [vp]
@@ -84,7 +87,8 @@ def lib():
     L.sfac_batch_plan.restype = vp
     for name in ["sfac_group_create", "sfac_group_step", "sfac_group_destroy", "sfac_plan_time_passes", "sfac_axis_tables", "sfac_plan_create", "sfac_step", "sfac_plan_destroy", "sfac_plan_flags",
                  "sfac_plan_reset_flags", "sfac_plan_method", "sfac_batch_create",
-                 "sfac_batch_step", "sfac_batch_destroy", "sfac_plan_energy"]:
+                 "sfac_batch_step", "sfac_batch_destroy", "sfac_plan_energy",
+                 "sfac_plan_trace", "sfac_plan_read_trace"]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -225,6 +229,20 @@ class Plan:
         e = ctypes.c_double()
         _check(lib().sfac_plan_energy(self._h, ctypes.c_void_p(u.data_ptr()), ctypes.byref(e)))
         return e.value
+
+    def trace(self, capacity):
+        """Record max|u| after each of the next `capacity` steps (0 stops recording)."""
+        _check(lib().sfac_plan_trace(self._h, int(capacity)))
+        self._trace_cap = int(capacity)
+
+    def read_trace(self):
+        """(values recorded so far as a numpy array, steps counted since trace())."""
+        import numpy as np
+        cap = getattr(self, "_trace_cap", 0)
+        out = (ctypes.c_double * max(cap, 1))()
+        n = ctypes.c_int64()
+        _check(lib().sfac_plan_read_trace(self._h, out, cap, ctypes.byref(n)))
+        return np.array(out[:min(n.value, cap)], dtype=np.float64), n.value
 
     def flags(self):
         """(flags, max_abs) since the last reset; synchronizes the plan's stream."""

@@ -109,6 +109,11 @@ def test_null_handles(sfac_lib):
     assert L.sfac_plan_device_bytes(None) == 0
     assert L.sfac_step(None, None, 1) == sfac.EINVAL
     assert "NULL plan" in L.sfac_last_error().decode()
+    import ctypes
+    e, n = ctypes.c_double(), ctypes.c_int64()
+    assert L.sfac_plan_energy(None, None, ctypes.byref(e)) == sfac.EINVAL
+    assert L.sfac_plan_trace(None, 5) == sfac.EINVAL
+    assert L.sfac_plan_read_trace(None, None, 0, ctypes.byref(n)) == sfac.EINVAL
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 7, 31, 63, 64, 100, 127, 255, 1023])
