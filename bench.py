@@ -120,13 +120,50 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None):
     torch.cuda.synchronize()
     step_ms = gpu_ms / steps
     pass_ms = [step_ms * t / sum(pass_ev) for t in pass_ev]
+    diag = diagnostics(plan, u0, u, min(steps, 200))
     result = {
         "wall_s": wall, "gpu_ms": gpu_ms, "flags": flags, "max_abs": vmax,
         "pass_ms": pass_ms, "pass_ms_events": pass_ev, "methods": methods, "state": u.double().cpu().numpy(), "schedule": sched,
-        "plan_create_ms": plan_ms, "warmup_ms": warm_ms,
+        "plan_create_ms": plan_ms, "warmup_ms": warm_ms, "diagnostics": diag,
     }
     plan.close()
     return result
+
+
+def diagnostics(plan, u0, u, k):
+    """Outside the timed region: the discrete energy (Sec. 5, Example 5) of the initial and final
+    states and the time of one evaluation, and what recording max|u| after every step (Example 4)
+    adds to a step, from k graph-replayed steps with and without the record."""
+    import torch
+    from paper_2209_08437_amd import sfac
+    try:
+        e_start = plan.energy(u0)                 # the first call builds the energy tables
+        t = time.perf_counter()
+        e_end = plan.energy(u)
+        energy_ms = (time.perf_counter() - t) * 1e3
+
+        def timed(trace):
+            plan.trace(k if trace else 0)
+            w = u0.clone()
+            plan.step(w, k)                       # captures the step graphs
+            torch.cuda.synchronize()
+            plan.trace(k if trace else 0)         # restart the record
+            w.copy_(u0)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            plan.step(w, k)
+            ev[1].record()
+            torch.cuda.synchronize()
+            return ev[0].elapsed_time(ev[1]) / k, (plan.read_trace() if trace else None)
+
+        plain_ms, _ = timed(False)
+        trace_ms, (rec, n) = timed(True)
+        plan.trace(0)
+        return {"energy_start": e_start, "energy_end": e_end, "energy_call_ms": round(energy_ms, 3),
+                "trace_steps": n, "trace_max_abs": float(rec.max()) if len(rec) else None,
+                "trace_overhead_us_per_step": round((trace_ms - plain_ms) * 1e3, 2)}
+    except sfac.SfacError as err:
+        return {"unavailable": str(err)}
 
 
 def batched_run(args):
@@ -358,6 +395,7 @@ def main():
                        "plan_create_ms": round(r32["plan_create_ms"], 3)}
     out["max_abs"] = main_r["max_abs"]
     out["flags"] = main_r["flags"]
+    out["diagnostics"] = main_r["diagnostics"]
     if not args.no_cpu:
         log(f"[bench] timing the CPU oracle for about {args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)

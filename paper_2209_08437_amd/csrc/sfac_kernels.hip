@@ -156,11 +156,9 @@ __device__ __forceinline__ void publish_stats(double vmax, unsigned int bad, con
         // first and only then update
         const unsigned long long bits = (unsigned long long)__double_as_longlong(vmax);
         if (bits > __atomic_load_n(smax, __ATOMIC_RELAXED)) atomicMax(smax, bits);
-        // the per-step record (the maximum norm after every step, Sec. 5, Example 4)
-        if (d.trace) {
-            const long long k = __atomic_load_n(d.trace_step, __ATOMIC_RELAXED);
-            if (k < d.trace_cap) atomicMax(&d.trace[k], bits);
-        }
+        // the per-step record (the maximum norm after every step, Sec. 5, Example 4): each
+        // wavefront stores into its own slot, reduced after the step (no shared address)
+        if (d.trace_part) d.trace_part[(size_t)blockIdx.x * d.trace_wpb + (threadIdx.x >> 6)] = bits;
     }
 }
 
@@ -850,13 +848,34 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
 }
 
 namespace {
-__global__ void trace_advance(long long* step) {
-    if (threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long*>(step), 1ull);
+constexpr int kCollectThreads = 1024;
+__global__ void __launch_bounds__(kCollectThreads) trace_collect(unsigned long long* parts, long long nparts,
+                                                                 unsigned long long* rec, long long* step,
+                                                                 long long cap) {
+    __shared__ unsigned long long wave_max[kCollectThreads / 64];
+    unsigned long long m = 0;
+    for (long long i = threadIdx.x; i < nparts; i += kCollectThreads) {
+        m = m > parts[i] ? m : parts[i];
+        parts[i] = 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off);
+        m = m > o ? m : o;
+    }
+    if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kCollectThreads / 64; ++w) m = m > wave_max[w] ? m : wave_max[w];
+        const long long k = *step;
+        if (k < cap) rec[k] = m;
+        atomicAdd(reinterpret_cast<unsigned long long*>(step), 1ull);
+    }
 }
 }  // namespace
 
-hipError_t launch_trace_advance(long long* step, hipStream_t stream) {
-    hipLaunchKernelGGL(trace_advance, dim3(1), dim3(64), 0, stream, step);
+hipError_t launch_trace_collect(unsigned long long* parts, long long nparts, unsigned long long* rec, long long* step,
+                                long long cap, hipStream_t stream) {
+    hipLaunchKernelGGL(trace_collect, dim3(1), dim3(kCollectThreads), 0, stream, parts, nparts, rec, step, cap);
     return hipGetLastError();
 }
 

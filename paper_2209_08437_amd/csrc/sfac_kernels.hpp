@@ -55,9 +55,8 @@ struct PassDesc {
     unsigned long long* stat_max;    // bits of the largest |u| stored (non-negative double)
     unsigned int* stat_flags;        // SFAC_FLAG_* bits
     double* energy;                  // energy pass: [0] += sum of x^T B x over its lines, [1] += (u^2 - 1)^2 / 4
-    unsigned long long* trace;       // last pass: per-step record of the largest |u| stored (bits), or null
-    const long long* trace_step;     // index of the current step in `trace` (advanced after each step)
-    long long trace_cap;             // entries of `trace`; steps at or beyond it are not recorded
+    unsigned long long* trace_part;  // last pass: one slot per wavefront (block b, wave w at b * trace_wpb + w)
+    int trace_wpb;                   // for the largest |u| it stored (bits), or null when no record is kept
     long long inner, outer;
     int N;                           // points per line
     int L;                           // transform length (N or M)
@@ -93,8 +92,10 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
                                   const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
                                   hipStream_t stream);
 
-// Advance the per-step record's step index by one (after the last pass of a step, on its stream).
-hipError_t launch_trace_advance(long long* step, hipStream_t stream);
+// After the last pass of a step: reduce the nparts per-wavefront slots of the step's largest |u|
+// into rec[*step] (if *step < cap), clear the slots and advance *step by one.
+hipError_t launch_trace_collect(unsigned long long* parts, long long nparts, unsigned long long* rec, long long* step,
+                                long long cap, hipStream_t stream);
 
 // Elements per thread (log2) of the energy kernel for a transform of length 2^log2m: 8, or 16 at
 // M = 4096, so that a line is at most 256 threads.

@@ -346,16 +346,24 @@ struct sfac_plan_s {
     unsigned char* energy_dev = nullptr;  // [0, 16): the two energy sums; then per-axis tables
     size_t energy_bytes = 0;
     EnergyAxis eax[3];
-    unsigned char* trace_dev = nullptr;   // per-step record: [0, 8) the step index, then trace_cap entries
-    long long trace_cap = 0;
+    // per-step record: [0, 8) the step index, then trace_cap entries, then one slot per
+    // wavefront of the last pass
+    unsigned char* trace_dev = nullptr;
+    long long trace_cap = 0, trace_parts = 0;
+    int trace_wpb = 0;
 
     long long* trace_step() { return reinterpret_cast<long long*>(trace_dev); }
     unsigned long long* trace_rec() { return reinterpret_cast<unsigned long long*>(trace_dev + 8); }
+    unsigned long long* trace_slots() { return trace_rec() + trace_cap; }
     void set_trace() {
         for (int a = 0; a < in.dims; ++a) {
-            d64[a].trace = d32[a].trace = trace_dev ? trace_rec() : nullptr;
-            d64[a].trace_step = d32[a].trace_step = trace_dev ? trace_step() : nullptr;
-            d64[a].trace_cap = d32[a].trace_cap = trace_dev ? trace_cap : 0;
+            d64[a].trace_part = d32[a].trace_part = nullptr;
+            d64[a].trace_wpb = d32[a].trace_wpb = 0;
+        }
+        if (trace_dev) {
+            const int a = in.dims - 1;            // the pass that stores (and folds) the statistics
+            d64[a].trace_part = d32[a].trace_part = trace_slots();
+            d64[a].trace_wpb = d32[a].trace_wpb = trace_wpb;
         }
     }
 
@@ -380,7 +388,8 @@ struct sfac_plan_s {
                 if (e != hipSuccess) return e;
             }
             if (trace_dev) {
-                hipError_t e = sfac::launch_trace_advance(trace_step(), s);
+                hipError_t e = sfac::launch_trace_collect(trace_slots(), trace_parts, trace_rec(), trace_step(),
+                                                          trace_cap, s);
                 if (e != hipSuccess) return e;
             }
         }
@@ -631,8 +640,8 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
             // plain launches outside sfac_step: not part of the per-step record
             sfac::PassDesc<double> d64 = p->d64[a];
             sfac::PassDesc<float> d32 = p->d32[a];
-            d64.trace = nullptr;
-            d32.trace = nullptr;
+            d64.trace_part = nullptr;
+            d32.trace_part = nullptr;
             e = p->in.dt == SFAC_FP64 ? launch_pass(d64, p->in.ax[a].lds, p->stream)
                                       : launch_pass(d32, p->in.ax[a].lds, p->stream);
             if (e != hipSuccess) break;
@@ -706,8 +715,15 @@ sfac_status sfac_plan_trace(sfac_plan p, int64_t capacity) {
     if (p->trace_dev) (void)hipFree(p->trace_dev);
     p->trace_dev = nullptr;
     p->trace_cap = 0;
+    p->trace_parts = 0;
     if (capacity > 0) {
-        const size_t bytes = 8 + 8 * (size_t)capacity;
+        // one slot per wavefront of the last pass's launch
+        const int a = p->in.dims - 1;
+        const int blocks = p->in.dt == SFAC_FP64 ? sfac::pass_blocks(p->d64[a]) : sfac::pass_blocks(p->d32[a]);
+        const int threads = p->in.dt == SFAC_FP64 ? p->d64[a].threads : p->d32[a].threads;
+        p->trace_wpb = (threads + 63) / 64;
+        p->trace_parts = (long long)blocks * p->trace_wpb;
+        const size_t bytes = 8 + 8 * (size_t)capacity + 8 * (size_t)p->trace_parts;
         e = hipMalloc(&p->trace_dev, bytes);
         if (e != hipSuccess) {
             p->trace_dev = nullptr;
