@@ -189,3 +189,24 @@ def served_stream(count=2000, rate=200.0, seed=5, n2=(63, 1023), n3=(31, 255),
             inst.seed = useed
         out.append(Request(rid, t, inst, dt))
     return out
+
+
+def example3(dims, alphas, seed, steps=None):
+    """Sec. 5, Example 3 (phase separation and coarsening): (0, 1)^d, eps = 0.01, tau = 0.1,
+    u0 uniform in [-0.9, 0.9]; 255^2 nodes in 2D (t to 100), 127^3 in 3D (t to 200)."""
+    n = 255 if dims == 2 else 127
+    ns = (n,) * dims
+    steps = steps if steps is not None else (1000 if dims == 2 else 2000)
+    inst = Instance(ns, tuple(alphas), 0.01, 0.1, tuple(1.0 / (n + 1) for _ in ns), steps)
+    inst.u0 = uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed)
+    return inst
+
+
+def example4(dims, alphas, seed, steps):
+    """Sec. 5, Example 4 (the discrete maximum principle): Example 3's meshes with eps = 0.1,
+    tau = 0.01 and u0 = 0.95 rand + 0.05 (rand uniform in (0, 1))."""
+    n = 255 if dims == 2 else 127
+    ns = (n,) * dims
+    inst = Instance(ns, tuple(alphas), 0.1, 0.01, tuple(1.0 / (n + 1) for _ in ns), steps)
+    inst.u0 = 0.95 * uniform_field(tuple(reversed(ns)), 0.0, 1.0, seed) + 0.05
+    return inst
