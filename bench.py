@@ -12,7 +12,10 @@ the autotuner picked on an MI355X for this shape, read from the table that ships
 package (`--tune-cache none` tunes afresh on the device at hand).
 
 Besides the headline value the JSON line carries: the FP32 rate of the same workload, the
-roofline of the dominant axis-pass kernel, and the CPU oracle timed on a bounded sample.
+roofline of the dominant axis-pass kernel, the CPU oracle timed on a bounded sample, and (FP64,
+N <= 1024 per axis) the one-level scheme with the exact exponential that the paper compares the
+two-level scheme with, run on the GPU over the same steps: its step time, the rate of its dense
+products and how far its final state lies from the two-level one.
 
 Roofline. Each axis pass reads and writes the state once (2 x points x element bytes) and does
 the conventional FFT count of flops on every point: 6 transforms of 5 L log2 L flops per complex
@@ -166,6 +169,45 @@ def diagnostics(plan, u0, u, k):
         return {"unavailable": str(err)}
 
 
+def one_level_exact(inst, steps, two_level_state, two_level_ms):
+    """The one-level scheme (eq. (strang)) with e^{tau B} per axis as a dense FP64 product on the
+    GPU (SFAC_METHOD_EXACT) over the bench's steps: plan creation (host eigendecomposition),
+    step time, the products' flop rate (2 N flops per point and axis) and the max-norm distance
+    of its final state from the two-level scheme's."""
+    import numpy as np
+    import torch
+    from paper_2209_08437_amd import sfac
+    if max(inst.ns) > 1024:
+        return {"unavailable": "N above 1024"}
+    u0 = torch.tensor(inst.u0, dtype=torch.float64, device="cuda")
+    u = u0.clone()
+    t = time.perf_counter()
+    plan = sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, "f64", method="exact")
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t) * 1e3
+    try:
+        plan.step(u, 5)
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        plan.step(u, steps)
+        ev[1].record()
+        torch.cuda.synchronize()
+        step_ms = ev[0].elapsed_time(ev[1]) / steps
+        flags, vmax = plan.flags()
+    finally:
+        plan.close()
+    flops = sum(2.0 * n * inst.points for n in inst.ns)
+    diff = float(np.abs(u.cpu().numpy() - two_level_state).max())
+    log(f"[bench] one-level exact: {step_ms * 1e3:.1f} us/step ({flops / step_ms / 1e9:.1f} TFLOP/s products), "
+        f"plan {create_ms:.0f} ms, max|diff| to two-level {diff:.3e}")
+    return {"ms_per_step": round(step_ms, 5), "plan_create_ms": round(create_ms, 1),
+            "product_flops_per_step": flops, "product_TFLOPs": round(flops / step_ms / 1e9, 3),
+            "two_level_speedup": round(step_ms / two_level_ms, 2),
+            "max_abs_diff_vs_two_level": diff, "max_abs": vmax, "flags": flags}
+
+
 def batched_run(args):
     """All instances of the batched workload stepped together (sfac_batch_step), against the
     same instances stepped one after another with plain FP64 plans."""
@@ -303,6 +345,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-exact", action="store_true", help="skip the one-level exact-exponential comparison")
     ap.add_argument("--pass-reps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="default schedules instead of autotuned ones")
     ap.add_argument("--tune-cache", default=None,
@@ -396,6 +439,8 @@ def main():
     out["max_abs"] = main_r["max_abs"]
     out["flags"] = main_r["flags"]
     out["diagnostics"] = main_r["diagnostics"]
+    if args.dtype == "f64" and not args.no_exact:
+        out["one_level_exact"] = one_level_exact(inst, steps, main_r["state"], main_r["wall_s"] * 1e3 / steps)
     if not args.no_cpu:
         log(f"[bench] timing the CPU oracle for about {args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)

@@ -56,8 +56,21 @@ typedef enum { SFAC_FP64 = 0, SFAC_FP32 = 1 } sfac_dtype;
  *                     each is applied as a linear convolution by its first column, computed
  *                     with one forward and one inverse length-M transform, M = 2^k >= 2N - 1.
  *                     Works for every N.
- *  SFAC_METHOD_AUTO:  the library picks per axis (the faster of the two for N and dtype). */
-typedef enum { SFAC_METHOD_AUTO = 0, SFAC_METHOD_DIAG = 1, SFAC_METHOD_EMBED = 2 } sfac_method;
+ *  SFAC_METHOD_AUTO:  the library picks per axis (the faster of the two for N and dtype).
+ *  SFAC_METHOD_EXACT: not the two-level scheme but the one-level scheme of eq. (strang), the
+ *                     one the paper compares with (Tables 2 and 4): the whole linear step is
+ *                     e^{tau A}, A the Kronecker sum of the axes' matrices B of eq. (B), applied as
+ *                     one dense product per axis with e^{tau B} (computed once in FP64 on the
+ *                     host, see sfac_exact_exponential). O(N) work per point and axis instead of
+ *                     O(log N): a reference scheme, not a fast path. Every axis of the plan must
+ *                     ask for it; SFAC_FP64 only; N_l <= 1024; single plans only (not groups or
+ *                     batches); kernel, elems_log2 and lines_per_block are ignored. */
+typedef enum {
+    SFAC_METHOD_AUTO = 0,
+    SFAC_METHOD_DIAG = 1,
+    SFAC_METHOD_EMBED = 2,
+    SFAC_METHOD_EXACT = 3
+} sfac_method;
 
 typedef struct sfac_plan_s* sfac_plan;
 typedef struct sfac_batch_s* sfac_batch;
@@ -107,8 +120,11 @@ typedef struct {
  *                and rounded once for SFAC_FP32).
  *   hip_stream : hipStream_t the steps are ordered on; NULL means the legacy default stream.
  *   opt        : NULL or settings as above.
- * Errors: SFAC_EINVAL for arguments out of range, SFAC_EUNSUPPORTED for N_l above 4096
- * (diagonal method) or 2048 (embedded method), SFAC_ENOMEM, SFAC_EDEVICE.
+ * Errors: SFAC_EINVAL for arguments out of range or SFAC_METHOD_EXACT on some axes only,
+ * SFAC_EUNSUPPORTED for N_l above 4096 (diagonal method), 2048 (embedded method) or 1024 (exact
+ * exponential), or SFAC_METHOD_EXACT with SFAC_FP32, SFAC_ENOMEM, SFAC_EDEVICE.
+ * A plan of SFAC_METHOD_EXACT also holds a state-sized FP64 scratch buffer (the per-axis
+ * products alternate between it and the state).
  */
 sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis,
                              const double* alpha_axis, double eps, double tau,
@@ -147,7 +163,7 @@ sfac_status sfac_plan_reset_flags(sfac_plan p);
  * plain launches, a HIP event pair recorded on the plan's stream around every pass, and write
  * the mean duration of each axis' pass in milliseconds to ms[0 .. dims-1]. The state advances
  * by `reps` steps exactly as sfac_step would advance it. Synchronizes the plan's stream.
- * Errors: SFAC_EINVAL, SFAC_EDEVICE.
+ * Errors: SFAC_EINVAL, SFAC_EUNSUPPORTED (a plan of SFAC_METHOD_EXACT), SFAC_EDEVICE.
  */
 sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float* ms);
 
@@ -190,8 +206,9 @@ sfac_status sfac_plan_trace(sfac_plan p, int64_t capacity);
  */
 sfac_status sfac_plan_read_trace(sfac_plan p, double* out, int64_t capacity, int64_t* recorded);
 
-/* sfac_plan_method - the method (SFAC_METHOD_DIAG or SFAC_METHOD_EMBED) and transform length
- * the plan uses on axis `axis` (1-based). Errors: SFAC_EINVAL. */
+/* sfac_plan_method - the method (SFAC_METHOD_DIAG, SFAC_METHOD_EMBED or SFAC_METHOD_EXACT) and
+ * transform length (N_l for SFAC_METHOD_EXACT) the plan uses on axis `axis` (1-based).
+ * Errors: SFAC_EINVAL. */
 sfac_status sfac_plan_method(sfac_plan p, int32_t axis, int32_t* method, int32_t* length);
 
 /*
@@ -209,6 +226,18 @@ sfac_status sfac_plan_method(sfac_plan p, int32_t axis, int32_t* method, int32_t
 sfac_status sfac_axis_tables(int32_t n, double alpha, double eps, double tau, double h, int32_t method,
                              int32_t* length, double* scale_c, double* scale_s, int32_t* radices,
                              int32_t* nstages);
+
+/*
+ * sfac_exact_exponential - host-only: the exact exponential e^{tau B} of one axis, B the
+ * symmetric Toeplitz matrix of eq. (B) (N = n interior nodes, mesh width h), as the one-level
+ * scheme of eq. (strang) uses it per axis (the exponential of the Kronecker sum A of the axes is
+ * the Kronecker product of these). Computed in FP64 from an eigendecomposition of B (Householder
+ * reduction to tridiagonal form, then implicit QR steps with the Wilkinson shift):
+ * e^{tau B} = V diag(e^{tau lambda}) V^T. P receives n * n doubles, row-major (the matrix is
+ * symmetric). No device call. Errors: SFAC_EINVAL (arguments as for sfac_plan_create, NULL P),
+ * SFAC_EUNSUPPORTED (n > 1024).
+ */
+sfac_status sfac_exact_exponential(int32_t n, double alpha, double eps, double tau, double h, double* P);
 
 /* sfac_last_error - message for the last non-OK status returned on this thread ("" if none).
  * The string stays valid until the next library call on the same thread. */
@@ -232,7 +261,7 @@ sfac_status sfac_group_create(sfac_group* out, void* hip_stream);
  * step is fused across plans or steps). Waits for the group's previous call to finish (its
  * launch descriptors are rewritten), then queues the work asynchronously on the group's stream.
  * Errors: SFAC_EINVAL (NULL arguments, a repeated plan, negative steps, misaligned state),
- * SFAC_ENOMEM, SFAC_EDEVICE.
+ * SFAC_EUNSUPPORTED (a plan of SFAC_METHOD_EXACT), SFAC_ENOMEM, SFAC_EDEVICE.
  */
 sfac_status sfac_group_step(sfac_group g, int32_t count, const sfac_plan* plans, void* const* u_dev,
                             const int64_t* nsteps);

@@ -81,4 +81,11 @@ struct EnergyTables {
 };
 std::string build_energy_tables(const AxisParams& p, int log2e, EnergyTables* out);
 
+// e^{tau B} for one axis (eq. (linear_operator) per axis: the exact exponential of the one-level
+// scheme, eq. (strang)), a dense symmetric N x N matrix in row-major order, from the symmetric
+// eigendecomposition of B (Householder tridiagonal reduction, implicit shifted QR). Returns an
+// error message if the QR iteration does not converge.
+constexpr int kMaxExactLength = 1024;
+std::string build_exact_exponential(const AxisParams& p, std::vector<double>* P);
+
 }  // namespace sfac

@@ -848,6 +848,94 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
 }
 
 namespace {
+// Row-major batched FP64 product, 64 x 64 tile of C per block of 256 threads (4 x 4 per thread),
+// K in steps of 16 through LDS; every load and store is guarded, so any M, N, K work.
+constexpr int kGemmTile = 64, kGemmK = 16;
+__global__ void __launch_bounds__(256) exact_gemm(const double* __restrict__ X, const double* __restrict__ Y,
+                                                  double* __restrict__ C, int M, int N, int K, long long ldx,
+                                                  long long ldy, long long ldc, long long sx, long long sy,
+                                                  long long sc) {
+    __shared__ double xs[kGemmK][kGemmTile + 1];   // xs[k][m]
+    __shared__ double ys[kGemmK][kGemmTile + 1];   // ys[k][n]
+    const long long b = blockIdx.z;
+    X += b * sx;
+    Y += b * sy;
+    C += b * sc;
+    const int m0 = blockIdx.y * kGemmTile, n0 = blockIdx.x * kGemmTile;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += kGemmK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int idx = threadIdx.x + r * 256;
+            const int mm = idx >> 4, kk = idx & 15;            // 16 consecutive k of one row
+            const int gm = m0 + mm, gk = k0 + kk;
+            xs[kk][mm] = (gm < M && gk < K) ? X[(long long)gm * ldx + gk] : 0.0;
+            const int kk2 = idx >> 6, nn = idx & 63;           // 64 consecutive n of one row
+            const int gk2 = k0 + kk2, gn = n0 + nn;
+            ys[kk2][nn] = (gk2 < K && gn < N) ? Y[(long long)gk2 * ldy + gn] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGemmK; ++kk) {
+            double xa[4], yb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xa[i] = xs[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) yb[j] = ys[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(xa[i], yb[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
+            if (gm < M && gn < N) C[(long long)gm * ldc + gn] = acc[i][j];
+        }
+}
+
+__global__ void __launch_bounds__(kExactNlThreads) exact_nl(double* dst, const double* src, long long n, double decay,
+                                                            int stats, PassDesc<double> d) {
+    const long long i = (long long)blockIdx.x * kExactNlThreads + threadIdx.x;
+    double vmax = 0.0;
+    unsigned int bad = 0;
+    if (i < n) {
+        const double z = nonlinear_half_step(src[i], decay, 0.0);
+        dst[i] = z;
+        const double az = fabs(z);
+        if (!(az <= 1.7976931348623157e308))
+            bad |= SFAC_FLAG_NONFINITE;
+        else
+            vmax = az;
+    }
+    if (stats) publish_stats(vmax, bad, d);
+}
+}  // namespace
+
+hipError_t launch_exact_gemm(const double* X, const double* Y, double* C, int M, int N, int K, long long ldx,
+                             long long ldy, long long ldc, long long sx, long long sy, long long sc, int batch,
+                             hipStream_t stream) {
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    const dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile, batch);
+    hipLaunchKernelGGL(exact_gemm, grid, dim3(256), 0, stream, X, Y, C, M, N, K, ldx, ldy, ldc, sx, sy, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_nl(double* dst, const double* src, long long n, double decay, bool stats,
+                           const PassDesc<double>& d, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const long long blocks = (n + kExactNlThreads - 1) / kExactNlThreads;
+    hipLaunchKernelGGL(exact_nl, dim3((unsigned)blocks), dim3(kExactNlThreads), 0, stream, dst, src, n, decay,
+                       stats ? 1 : 0, d);
+    return hipGetLastError();
+}
+
+namespace {
 constexpr int kCollectThreads = 1024;
 __global__ void __launch_bounds__(kCollectThreads) trace_collect(unsigned long long* parts, long long nparts,
                                                                  unsigned long long* rec, long long* step,

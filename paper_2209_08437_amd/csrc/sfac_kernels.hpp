@@ -97,6 +97,19 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
 hipError_t launch_trace_collect(unsigned long long* parts, long long nparts, unsigned long long* rec, long long* step,
                                 long long cap, hipStream_t stream);
 
+// The one-level scheme with the exact exponential (eq. (strang)), FP64.
+// Batched row-major product C[b] = X[b] Y[b] (M x K times K x N; leading dimensions ldx, ldy, ldc
+// and batch strides sx, sy, sc in elements; any sizes).
+hipError_t launch_exact_gemm(const double* X, const double* Y, double* C, int M, int N, int K, long long ldx,
+                             long long ldy, long long ldc, long long sx, long long sy, long long sc, int batch,
+                             hipStream_t stream);
+// dst[i] = J^Q_{tau/2}(src[i]) for i < n (dst may be src); with `stats`, the largest |u| and the
+// non-finite flag are folded into d.stat_max / d.stat_flags (and d.trace_part) as by the last pass
+// of the two-level scheme. Blocks of 256 threads.
+constexpr int kExactNlThreads = 256;
+hipError_t launch_exact_nl(double* dst, const double* src, long long n, double decay, bool stats,
+                           const PassDesc<double>& d, hipStream_t stream);
+
 // Elements per thread (log2) of the energy kernel for a transform of length 2^log2m: 8, or 16 at
 // M = 4096, so that a line is at most 256 threads.
 constexpr int energy_log2e(int log2m) { return log2m >= 12 ? 4 : 3; }

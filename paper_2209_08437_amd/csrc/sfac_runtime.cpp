@@ -351,6 +351,10 @@ struct sfac_plan_s {
     unsigned char* trace_dev = nullptr;
     long long trace_cap = 0, trace_parts = 0;
     int trace_wpb = 0;
+    // one-level scheme with the exact exponential (SFAC_METHOD_EXACT): e^{tau B} per axis and a
+    // state-sized scratch buffer in dev
+    int exact = 0;
+    size_t off_P[3] = {0, 0, 0}, off_scratch = 0;
 
     long long* trace_step() { return reinterpret_cast<long long*>(trace_dev); }
     unsigned long long* trace_rec() { return reinterpret_cast<unsigned long long*>(trace_dev + 8); }
@@ -380,8 +384,44 @@ struct sfac_plan_s {
         graph_u = nullptr;
     }
 
+    // eq. (strang): J^Q_{tau/2} e^{tau A} J^Q_{tau/2}, e^{tau A} one dense product per axis, alternating
+    // between the state and the scratch buffer; the closing half-step writes the state
+    hipError_t exact_step(hipStream_t s) {
+        double* u = d64[0].u;
+        double* scratch = reinterpret_cast<double*>(dev + off_scratch);
+        const long long pts = in.points();
+        const double decay = std::exp(-in.tau);
+        const sfac::PassDesc<double>& stats = d64[in.dims - 1];
+        hipError_t e = sfac::launch_exact_nl(u, u, pts, decay, false, stats, s);
+        double* cur = u;
+        double* other = scratch;
+        for (int a = 0; a < in.dims && e == hipSuccess; ++a) {
+            const long long n = in.n[a];
+            long long inner = 1, outer = 1;
+            for (int b = 0; b < a; ++b) inner *= in.n[b];
+            for (int b = a + 1; b < in.dims; ++b) outer *= in.n[b];
+            const double* P = reinterpret_cast<const double*>(dev + off_P[a]);
+            if (inner == 1)   // rows: C = X P (P symmetric)
+                e = sfac::launch_exact_gemm(cur, P, other, (int)outer, (int)n, (int)n, n, n, n, 0, 0, 0, 1, s);
+            else              // per slower index o: C_o = P X_o
+                e = sfac::launch_exact_gemm(P, cur, other, (int)n, (int)inner, (int)n, n, inner, inner, 0,
+                                            n * inner, n * inner, (int)outer, s);
+            std::swap(cur, other);
+        }
+        if (e == hipSuccess) e = sfac::launch_exact_nl(u, cur, pts, decay, true, stats, s);
+        return e;
+    }
+
     hipError_t launch_steps(hipStream_t s, int64_t nsteps) {
         for (int64_t k = 0; k < nsteps; ++k) {
+            if (exact) {
+                hipError_t e = exact_step(s);
+                if (e != hipSuccess) return e;
+                if (trace_dev) e = sfac::launch_trace_collect(trace_slots(), trace_parts, trace_rec(), trace_step(),
+                                                               trace_cap, s);
+                if (e != hipSuccess) return e;
+                continue;
+            }
             for (int a = 0; a < in.dims; ++a) {
                 hipError_t e = in.dt == SFAC_FP64 ? launch_pass(d64[a], in.ax[a].lds, s)
                                                   : launch_pass(d32[a], in.ax[a].lds, s);
@@ -514,6 +554,68 @@ extern "C" {
 
 const char* sfac_last_error(void) { return g_error.c_str(); }
 
+}  // extern "C"
+
+// A plan of the one-level scheme with the exact exponential: every axis SFAC_METHOD_EXACT, FP64.
+static sfac_status exact_plan_create(sfac_plan p, int32_t dims, const int32_t* n, const double* alpha, double eps,
+                                     double tau, const double* h, sfac_dtype dt, void* hip_stream,
+                                     const sfac_options* opt) {
+    sfac_status st = validate_instance(dims, n, alpha, eps, tau, h, "");
+    if (st != SFAC_OK) return st;
+    for (int a = 0; a < dims; ++a)
+        if (opt->method[a] != SFAC_METHOD_EXACT)
+            return fail(SFAC_EINVAL, "axis %d: the exact exponential replaces the whole linear step, so every axis "
+                        "must use SFAC_METHOD_EXACT", a + 1);
+    if (dt != SFAC_FP64) return fail(SFAC_EUNSUPPORTED, "the exact exponential is FP64 only");
+    Instance& in = p->in;
+    in.dims = dims;
+    in.eps = eps;
+    in.tau = tau;
+    in.dt = dt;
+    std::vector<std::vector<double>> P(dims);
+    size_t off = 0;
+    for (int a = 0; a < dims; ++a) {
+        in.n[a] = n[a];
+        in.alpha[a] = alpha[a];
+        in.h[a] = h[a];
+        const std::string err = sfac::build_exact_exponential(sfac::AxisParams{n[a], alpha[a], eps, tau, h[a]}, &P[a]);
+        if (!err.empty()) return fail(SFAC_EUNSUPPORTED, "axis %d: %s", a + 1, err.c_str());
+        p->off_P[a] = off;
+        off = align_up(off + sizeof(double) * P[a].size(), 256);
+    }
+    p->exact = 1;
+    p->off_scratch = off;
+    p->off_stat = align_up(off + sizeof(double) * (size_t)in.points(), 256);
+    p->dev_bytes = p->off_stat + 256;
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    p->use_graph = opt->use_graph ? 1 : 0;
+    if (opt->graph_chunk > 0) p->chunk = opt->graph_chunk;
+    std::vector<unsigned char> host(off, 0);
+    for (int a = 0; a < dims; ++a) memcpy(host.data() + p->off_P[a], P[a].data(), sizeof(double) * P[a].size());
+    hipError_t e = hipMalloc(&p->dev, p->dev_bytes);
+    if (e != hipSuccess) {
+        p->dev = nullptr;
+        return e == hipErrorOutOfMemory ? fail(SFAC_ENOMEM, "hipMalloc(%zu): %s", p->dev_bytes, hipGetErrorString(e))
+                                        : hip_fail(e, "hipMalloc");
+    }
+    e = hipMemcpy(p->dev, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->dev + p->off_stat, 0, 256);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipFree(p->dev);
+        p->dev = nullptr;
+        return hip_fail(e, "exact plan set-up");
+    }
+    for (int a = 0; a < dims; ++a) {
+        p->d64[a] = sfac::PassDesc<double>{};
+        p->d64[a].stat_max = p->stat_max();
+        p->d64[a].stat_flags = p->stat_flags();
+    }
+    return SFAC_OK;
+}
+
+extern "C" {
+
 sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis, const double* alpha_axis,
                              double eps, double tau, const double* h_axis, sfac_dtype dt, void* hip_stream,
                              const sfac_options* opt) {
@@ -525,7 +627,7 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
         if (opt->graph_chunk < 0 || opt->graph_chunk > 1024)
             return fail(SFAC_EINVAL, "graph_chunk = %d, expected 1..1024 (0 = default)", opt->graph_chunk);
         for (int a = 0; a < 3; ++a) {
-            if (opt->method[a] < SFAC_METHOD_AUTO || opt->method[a] > SFAC_METHOD_EMBED)
+            if (opt->method[a] < SFAC_METHOD_AUTO || opt->method[a] > SFAC_METHOD_EXACT)
                 return fail(SFAC_EINVAL, "unknown method %d for axis %d", opt->method[a], a + 1);
             if (opt->lines_per_block[a] < 0 || opt->lines_per_block[a] > 256)
                 return fail(SFAC_EINVAL, "lines_per_block = %d for axis %d, expected 0..256",
@@ -534,6 +636,14 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
     }
     std::unique_ptr<sfac_plan_s> p(new (std::nothrow) sfac_plan_s());
     if (!p) return fail(SFAC_ENOMEM, "host allocation failed");
+    bool exact = false;
+    for (int a = 0; opt && a < dims && a < 3; ++a) exact = exact || opt->method[a] == SFAC_METHOD_EXACT;
+    if (exact) {
+        sfac_status st = exact_plan_create(p.get(), dims, n_axis, alpha_axis, eps, tau, h_axis, dt, hip_stream, opt);
+        if (st != SFAC_OK) return st;
+        *out = p.release();
+        return SFAC_OK;
+    }
     sfac_status st = build_instance(&p->in, dims, n_axis, alpha_axis, eps, tau, h_axis, dt, opt, "");
     if (st != SFAC_OK) return st;
     p->stream = static_cast<hipStream_t>(hip_stream);
@@ -621,6 +731,7 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
     g_error.clear();
     if (!p) return fail(SFAC_EINVAL, "NULL plan");
     if (!u_dev || !ms || reps < 1) return fail(SFAC_EINVAL, "NULL state or output, or reps < 1");
+    if (p->exact) return fail(SFAC_EUNSUPPORTED, "a plan of the exact exponential has no per-axis passes to time");
     const size_t es = p->in.dt == SFAC_FP64 ? 8 : 4;
     if (reinterpret_cast<uintptr_t>(u_dev) % es) return fail(SFAC_EINVAL, "state pointer not aligned to %zu bytes", es);
     const int d = p->in.dims;
@@ -719,8 +830,12 @@ sfac_status sfac_plan_trace(sfac_plan p, int64_t capacity) {
     if (capacity > 0) {
         // one slot per wavefront of the last pass's launch
         const int a = p->in.dims - 1;
-        const int blocks = p->in.dt == SFAC_FP64 ? sfac::pass_blocks(p->d64[a]) : sfac::pass_blocks(p->d32[a]);
-        const int threads = p->in.dt == SFAC_FP64 ? p->d64[a].threads : p->d32[a].threads;
+        long long blocks = p->in.dt == SFAC_FP64 ? sfac::pass_blocks(p->d64[a]) : sfac::pass_blocks(p->d32[a]);
+        int threads = p->in.dt == SFAC_FP64 ? p->d64[a].threads : p->d32[a].threads;
+        if (p->exact) {   // the closing nonlinear half-step kernel stores the statistics
+            threads = sfac::kExactNlThreads;
+            blocks = (p->in.points() + threads - 1) / threads;
+        }
         p->trace_wpb = (threads + 63) / 64;
         p->trace_parts = (long long)blocks * p->trace_wpb;
         const size_t bytes = 8 + 8 * (size_t)capacity + 8 * (size_t)p->trace_parts;
@@ -794,8 +909,8 @@ sfac_status sfac_plan_method(sfac_plan p, int32_t axis, int32_t* method, int32_t
     g_error.clear();
     if (!p) return fail(SFAC_EINVAL, "NULL plan");
     if (axis < 1 || axis > p->in.dims) return fail(SFAC_EINVAL, "axis %d outside 1..%d", axis, p->in.dims);
-    if (method) *method = p->in.ax[axis - 1].host.method;
-    if (length) *length = p->in.ax[axis - 1].host.length;
+    if (method) *method = p->exact ? SFAC_METHOD_EXACT : p->in.ax[axis - 1].host.method;
+    if (length) *length = p->exact ? p->in.n[axis - 1] : p->in.ax[axis - 1].host.length;
     return SFAC_OK;
 }
 
@@ -818,6 +933,20 @@ sfac_status sfac_axis_tables(int32_t n, double alpha, double eps, double tau, do
     if (scale_s) std::copy(t.scale_s.begin(), t.scale_s.end(), scale_s);
     if (radices) std::copy(t.radices.begin(), t.radices.end(), radices);
     if (nstages) *nstages = (int32_t)t.radices.size();
+    return SFAC_OK;
+}
+
+sfac_status sfac_exact_exponential(int32_t n, double alpha, double eps, double tau, double h, double* P) {
+    g_error.clear();
+    if (!P) return fail(SFAC_EINVAL, "NULL output");
+    int32_t ns[1] = {n};
+    double al[1] = {alpha}, hs[1] = {h};
+    sfac_status st = validate_instance(1, ns, al, eps, tau, hs, "");
+    if (st != SFAC_OK) return st;
+    std::vector<double> m;
+    const std::string err = sfac::build_exact_exponential(sfac::AxisParams{n, alpha, eps, tau, h}, &m);
+    if (!err.empty()) return fail(SFAC_EUNSUPPORTED, "%s", err.c_str());
+    std::copy(m.begin(), m.end(), P);
     return SFAC_OK;
 }
 
@@ -1006,6 +1135,7 @@ sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void*
     for (int32_t i = 0; i < count; ++i) {
         sfac_plan p = plans[i];
         if (!p) return fail(SFAC_EINVAL, "plan %d is NULL", i);
+        if (p->exact) return fail(SFAC_EUNSUPPORTED, "plan %d: a plan of the exact exponential steps alone", i);
         if (nsteps[i] < 0) return fail(SFAC_EINVAL, "plan %d: nsteps = %lld", i, (long long)nsteps[i]);
         if (nsteps[i] == 0) continue;
         const size_t es = p->in.dt == SFAC_FP64 ? 8 : 4;
@@ -1128,6 +1258,12 @@ sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instanc
         sfac_options opt{};
         if (opts) opt = opts[i];
         opt.use_graph = 0;   // a batch steps through its group, never through a plan's graphs
+        for (int a = 0; a < 3; ++a)
+            if (opt.method[a] == SFAC_METHOD_EXACT) {
+                for (sfac_plan q : b->plans) sfac_plan_destroy(q);
+                return fail(SFAC_EUNSUPPORTED, "instance %d: the exact exponential is available to single plans only",
+                            i);
+            }
         sfac_plan p = nullptr;
         sfac_status st = sfac_plan_create(&p, d.dims, d.n, d.alpha, d.eps, d.tau, d.h, dt, hip_stream, &opt);
         if (st != SFAC_OK) {

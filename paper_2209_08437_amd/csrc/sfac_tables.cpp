@@ -16,6 +16,8 @@
 // columns placed as circular convolution kernels, divided by M.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -139,6 +141,140 @@ static std::vector<ld> first_column_B(const AxisParams& p) {
     if (N >= 2) b[1] = kappa * (w[0] + w[2]);
     for (int k = 2; k < N; ++k) b[k] = kappa * w[k + 1];
     return b;
+}
+
+std::string build_exact_exponential(const AxisParams& p, std::vector<double>* P) {
+    const int N = p.n;
+    if (N < 1) return "N must be >= 1";
+    if (N > kMaxExactLength) {
+        char msg[128];
+        snprintf(msg, sizeof msg, "N = %d exceeds the exact exponential's limit %d", N, kMaxExactLength);
+        return msg;
+    }
+    // B (eq. (B)) as a dense symmetric matrix and its eigendecomposition B = V diag(lambda) V^T,
+    // then e^{tau B} = V diag(e^{tau lambda}) V^T. The eigendecomposition is the textbook
+    // symmetric one: Householder reduction to tridiagonal form B = Q T Q^T, then implicit QR
+    // steps with the Wilkinson shift on T, each a chase of Givens rotations, accumulated into
+    // the rows of V^T (rows stay contiguous, so every update walks memory in order).
+    const std::vector<ld> b = first_column_B(p);
+    std::vector<double> a((size_t)N * N), q((size_t)N * N, 0.0);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) a[(size_t)i * N + j] = (double)b[(size_t)std::abs(i - j)];
+    for (int i = 0; i < N; ++i) q[(size_t)i * N + i] = 1.0;
+    auto A = [&](int i, int j) -> double& { return a[(size_t)i * N + j]; };
+    std::vector<double> d(N), e(N, 0.0), v(N), w(N);
+    // Householder: step k maps column k below the diagonal onto a multiple of e_{k+1} with
+    // H = I - beta u u^T acting on indices k+1..N-1; the trailing block S becomes H S H, which is
+    // S - u z^T - z u^T for y = beta S u and z = y - (beta u^T y / 2) u
+    for (int k = 0; k + 2 < N; ++k) {
+        const int m = N - k - 1;
+        double* x = &A(k, k + 1);
+        double nrm2 = 0.0;
+        for (int j = 0; j < m; ++j) nrm2 += x[j] * x[j];
+        const double nrm = std::sqrt(nrm2);
+        if (nrm == 0.0) {
+            e[k] = 0.0;
+            continue;
+        }
+        const double alpha = x[0] > 0 ? -nrm : nrm;
+        for (int j = 0; j < m; ++j) v[j] = x[j];
+        v[0] -= alpha;
+        const double beta = 2.0 / (nrm2 - x[0] * alpha - x[0] * alpha + alpha * alpha);
+        double uy = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double* row = &A(k + 1 + i, k + 1);
+            double acc = 0.0;
+            for (int j = 0; j < m; ++j) acc += row[j] * v[j];
+            w[i] = beta * acc;
+            uy += v[i] * w[i];
+        }
+        const double kk = 0.5 * beta * uy;
+        for (int i = 0; i < m; ++i) w[i] -= kk * v[i];
+        for (int i = 0; i < m; ++i) {
+            double* row = &A(k + 1 + i, k + 1);
+            const double vi = v[i], wi = w[i];
+            for (int j = 0; j < m; ++j) row[j] -= vi * w[j] + wi * v[j];
+        }
+        e[k] = alpha;
+        // Q = Q H: every row of Q against u
+        for (int i = 0; i < N; ++i) {
+            double* row = &q[(size_t)i * N + k + 1];
+            double acc = 0.0;
+            for (int j = 0; j < m; ++j) acc += row[j] * v[j];
+            acc *= beta;
+            for (int j = 0; j < m; ++j) row[j] -= acc * v[j];
+        }
+    }
+    for (int k = 0; k < N; ++k) d[k] = A(k, k);
+    if (N >= 2) e[N - 2] = A(N - 2, N - 1);
+    // V^T starts as Q^T; row r of V^T is the eigenvector of d[r] at the end
+    std::vector<double> vt((size_t)N * N);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) vt[(size_t)j * N + i] = q[(size_t)i * N + j];
+    auto rotate = [&](int k, double c, double s) {   // V <- V R on columns k, k+1
+        double* r0 = &vt[(size_t)k * N];
+        double* r1 = r0 + N;
+        for (int j = 0; j < N; ++j) {
+            const double x0 = r0[j], x1 = r1[j];
+            r0[j] = c * x0 - s * x1;
+            r1[j] = s * x0 + c * x1;
+        }
+    };
+    const double eps = std::numeric_limits<double>::epsilon();
+    long long iters = 0;
+    for (int hi = N - 1; hi > 0;) {
+        // the unreduced block [lo, hi]: off-diagonals below the rounding of their neighbours are zero
+        int lo = hi;
+        while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+        if (lo == hi) {
+            e[hi - 1] = 0.0;
+            --hi;
+            continue;
+        }
+        if (++iters > 60LL * N) return "the symmetric QR iteration did not converge";
+        // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer to d[hi]
+        const double dd = 0.5 * (d[hi - 1] - d[hi]);
+        const double eh = e[hi - 1];
+        const double mu = d[hi] - eh * eh / (dd + (dd >= 0 ? 1.0 : -1.0) * std::hypot(dd, eh));
+        double x = d[lo] - mu, z = e[lo];
+        for (int k = lo; k < hi; ++k) {
+            // R = [[c, s], [-s, c]] on (k, k+1) with s x + c z = 0 zeroes the bulge (k-1, k+1);
+            // for k = lo it brings in the shift
+            const double r = std::hypot(x, z);
+            const double c = r == 0.0 ? 1.0 : x / r, s = r == 0.0 ? 0.0 : -z / r;
+            if (k > lo) e[k - 1] = r;
+            const double p0 = d[k], p1 = d[k + 1], ek = e[k];
+            d[k] = c * c * p0 - 2.0 * c * s * ek + s * s * p1;
+            d[k + 1] = s * s * p0 + 2.0 * c * s * ek + c * c * p1;
+            e[k] = c * s * (p0 - p1) + (c * c - s * s) * ek;
+            if (k + 1 < hi) {
+                const double f = e[k + 1];
+                z = -s * f;            // the new bulge (k, k+2)
+                e[k + 1] = c * f;
+                x = e[k];
+            }
+            rotate(k, c, s);
+        }
+    }
+    std::vector<double> ev(N);
+    for (int j = 0; j < N; ++j) ev[j] = std::exp(p.tau * d[j]);
+    // P = V diag(ev) V^T, entry (i, j) a weighted dot product of columns i and j of V^T, taken
+    // from the rows of V
+    std::vector<double> vr((size_t)N * N);
+    for (int r = 0; r < N; ++r)
+        for (int i = 0; i < N; ++i) vr[(size_t)i * N + r] = vt[(size_t)r * N + i];
+    P->assign((size_t)N * N, 0.0);
+    for (int i = 0; i < N; ++i) {
+        const double* ri = &vr[(size_t)i * N];
+        for (int r = 0; r < N; ++r) w[r] = ri[r] * ev[r];
+        for (int j = i; j < N; ++j) {
+            const double* rj = &vr[(size_t)j * N];
+            double acc = 0.0;
+            for (int r = 0; r < N; ++r) acc += w[r] * rj[r];
+            (*P)[(size_t)i * N + j] = (*P)[(size_t)j * N + i] = acc;
+        }
+    }
+    return std::string();
 }
 
 std::string build_energy_tables(const AxisParams& p, int log2e, EnergyTables* out) {

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libsfac.so")
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, EBUDGET = range(6)
 FP64, FP32 = 0, 1
-METHOD_AUTO, METHOD_DIAG, METHOD_EMBED = 0, 1, 2
+METHOD_AUTO, METHOD_DIAG, METHOD_EMBED, METHOD_EXACT = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_ABOVE_ONE = 1, 2
 _STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSUPPORTED", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUDGET"}
 
@@ -22,7 +22,7 @@ EXPORTS = [
     "sfac_batch_create", "sfac_batch_step", "sfac_batch_destroy", "sfac_batch_device_bytes",
     "sfac_axis_tables", "sfac_plan_time_passes", "sfac_group_create", "sfac_group_step",
     "sfac_group_destroy", "sfac_group_device_bytes", "sfac_batch_plan", "sfac_plan_energy",
-    "sfac_plan_trace", "sfac_plan_read_trace",
+    "sfac_plan_trace", "sfac_plan_read_trace", "sfac_exact_exponential",
 ]
 
 
@@ -77,6 +77,7 @@ def lib():
     L.sfac_plan_time_passes.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_float)]
     L.sfac_plan_energy.argtypes = [vp, vp, ctypes.POINTER(dbl)]
     L.sfac_plan_trace.argtypes = [vp, i64]
+    L.sfac_exact_exponential.argtypes = [i32, dbl, dbl, dbl, dbl, ctypes.POINTER(dbl)]
     L.sfac_plan_read_trace.argtypes = [vp, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)]
     L.sfac_group_create.argtypes = [ctypes.POINTER(vp), vp]
     L.sfac_group_step.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64)]
@@ -88,7 +89,7 @@ def lib():
     for name in ["sfac_group_create", "sfac_group_step", "sfac_group_destroy", "sfac_plan_time_passes", "sfac_axis_tables", "sfac_plan_create", "sfac_step", "sfac_plan_destroy", "sfac_plan_flags",
                  "sfac_plan_reset_flags", "sfac_plan_method", "sfac_batch_create",
                  "sfac_batch_step", "sfac_batch_destroy", "sfac_plan_energy",
-                 "sfac_plan_trace", "sfac_plan_read_trace"]:
+                 "sfac_plan_trace", "sfac_plan_read_trace", "sfac_exact_exponential"]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -158,12 +159,23 @@ def axis_tables(n, alpha, eps, tau, h, method=None):
     return length.value, sc, ss, list(rad[: nst.value])
 
 
+def exact_exponential(n, alpha, eps, tau, h):
+    """e^{tau B} of one axis (host-only, FP64), an n x n numpy array."""
+    import numpy as np
+    out = np.zeros((n, n), dtype=np.float64)
+    _check(lib().sfac_exact_exponential(int(n), float(alpha), float(eps), float(tau), float(h),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
 def fill_options(opt, dims, method=None, elems_log2=None, lines_per_block=None, kernel=None):
     """Write a kernel schedule into an Options struct: each argument is None (automatic), one
-    value for every axis or a per-axis sequence (method: None, "auto", "diag" or "embed")."""
+    value for every axis or a per-axis sequence (method: None, "auto", "diag", "embed" or
+    "exact"; "exact" on every axis or none)."""
     def per_axis(v, a):
         return v[a] if isinstance(v, (list, tuple)) else v
-    codes = {None: METHOD_AUTO, "auto": METHOD_AUTO, "diag": METHOD_DIAG, "embed": METHOD_EMBED}
+    codes = {None: METHOD_AUTO, "auto": METHOD_AUTO, "diag": METHOD_DIAG, "embed": METHOD_EMBED,
+             "exact": METHOD_EXACT}
     for a in range(3):
         opt.method[a] = codes[per_axis(method, a)] if a < dims else METHOD_AUTO
     for a in range(min(3, dims)):
@@ -180,7 +192,8 @@ class Plan:
     """sfac_plan_create / sfac_step / sfac_plan_destroy for one instance.
 
     ns, alphas, hs: per-axis sequences, axis 1 first. dtype: "f64" or "f32".
-    method: None (automatic), "diag" or "embed" (one for all axes) or a per-axis sequence.
+    method: None (automatic), "diag" or "embed" (one for all axes) or a per-axis sequence;
+    "exact" (every axis, FP64) for the one-level scheme with the exact exponential.
     elems_log2, lines_per_block: kernel schedule per axis (None or 0 = automatic; see
     sfac_options in include/sfac.h and autotune.py)."""
 
@@ -258,7 +271,7 @@ class Plan:
         m = ctypes.c_int32()
         n = ctypes.c_int32()
         _check(lib().sfac_plan_method(self._h, int(axis), ctypes.byref(m), ctypes.byref(n)))
-        return {METHOD_DIAG: "diag", METHOD_EMBED: "embed"}[m.value], n.value
+        return {METHOD_DIAG: "diag", METHOD_EMBED: "embed", METHOD_EXACT: "exact"}[m.value], n.value
 
     @property
     def device_bytes(self):

@@ -197,3 +197,59 @@ def test_plain_c_client_compiles_links_and_runs(sfac_lib, tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stderr + r.stdout
     assert "ok" in r.stdout
+
+
+def test_exact_method_is_validated(sfac_lib):
+    """SFAC_METHOD_EXACT: every axis or none, FP64 only, N <= 1024, single plans only; all of it
+    is checked before any device call."""
+    import ctypes
+    opt = sfac.Options()
+    opt.method[0] = sfac.METHOD_EXACT
+    st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EINVAL and not h.value and "every axis" in msg
+    opt.method[1] = sfac.METHOD_EXACT
+    st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], dt=sfac.FP32, opt=opt)
+    assert st == sfac.EUNSUPPORTED and not h.value and "FP64" in msg
+    st, h, msg = _create(2, [1025, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EUNSUPPORTED and not h.value and "1024" in msg
+    opt.method[2] = 7
+    st, h, msg = _create(2, [63, 8], [1.5, 1.5], 0.1, 0.01, [0.1, 0.1], opt=opt)
+    assert st == sfac.EINVAL and "unknown method" in msg, msg
+    arr = (sfac.InstanceDesc * 1)()
+    arr[0].dims = 1
+    arr[0].n[0] = 63
+    arr[0].alpha[0] = 1.5
+    arr[0].h[0] = 2.0 / 64
+    arr[0].eps = 0.1
+    arr[0].tau = 0.01
+    opts = (sfac.Options * 1)()
+    opts[0].method[0] = sfac.METHOD_EXACT
+    b = ctypes.c_void_p()
+    st = sfac.lib().sfac_batch_create(ctypes.byref(b), 1, arr, sfac.FP64, None, opts)
+    assert st == sfac.EUNSUPPORTED and not b.value
+    assert "single plans" in sfac.lib().sfac_last_error().decode()
+
+
+@pytest.mark.parametrize("n,alpha,eps,tau", [(1, 1.5, 0.1, 0.01), (2, 1.2, 0.1, 0.05), (63, 1.5, 0.1, 0.01),
+                                             (200, 1.9, 0.05, 0.02), (255, 1.2, 0.1, 0.005),
+                                             (1023, 1.9, 0.1, 0.01)])
+def test_exact_exponential_matches_pade(sfac_lib, n, alpha, eps, tau):
+    """The host e^{tau B} (Householder + implicit QR eigendecomposition) against scipy's scaling-and-squaring Pade
+    expm of the same B (eq. (B)), plus what holds for the negative definite B: P symmetric with
+    its spectrum in (0, 1), and P(tau)^2 = P(2 tau)."""
+    from scipy.linalg import expm
+    from oracle import sfac_oracle as O
+    h = 2.0 / (n + 1)
+    P = sfac.exact_exponential(n, alpha, eps, tau, h)
+    P2 = sfac.exact_exponential(n, alpha, eps, 2 * tau, h)
+    B = O.matrix_B(alpha, eps, h, n)
+    ref = expm(tau * B)
+    assert P.shape == (n, n)
+    assert np.abs(P - ref).max() <= 1e-13
+    assert np.array_equal(P, P.T)
+    assert np.abs(P @ P - P2).max() <= 1e-13
+    # B is negative definite: the spectrum of P lies in (0, 1) (its low end may round to 0)
+    lam = np.linalg.eigvalsh(P)
+    assert lam.min() > -1e-13 and lam.max() < 1.0
+    if n == 1:   # B is a scalar: e^{tau B} is its exponential
+        assert P[0, 0] == pytest.approx(np.exp(tau * B[0, 0]), rel=1e-15)

@@ -1,0 +1,171 @@
+"""The one-level scheme with the exact exponential (eq. (strang)) on the GPU, SFAC_METHOD_EXACT.
+
+This is the scheme the paper sets the two-level method against in Tables 2 and 4: one step is
+J^Q_{tau/2} e^{tau A} J^Q_{tau/2}, and e^{tau A} (A the Kronecker sum of the axes' B) is the
+product of the per-axis factors e^{tau B_l}, each one dense FP64 product along its axis.
+
+* parity with the oracle's strang_solve, element by element, at sizes with several 64-wide
+  product tiles and ragged tails, in 1D, 2D and 3D;
+* bitwise the same with and without graphs and across split calls;
+* the paper's printed Strang columns: Table 2 (2D, 255^2) and Table 4 (3D, 63^3);
+* the per-step max|u| record and the energy work on such a plan as on the two-level one.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import sfac_oracle as O
+from paper_2209_08437_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+FP64_TOL = 1e-12     # relative to max|u|, as for the two-level FP64 path
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _run(u0, ns, alphas, eps, hs, tau, steps, splits=None, use_graph=True):
+    import torch
+    from paper_2209_08437_amd import sfac
+    u = torch.tensor(np.ascontiguousarray(u0), dtype=torch.float64, device="cuda")
+    with sfac.Plan(ns, alphas, eps, tau, hs, "f64", method="exact", use_graph=use_graph) as p:
+        for a in range(len(ns)):
+            assert p.method(a + 1) == ("exact", ns[a])
+        for k in (splits or [steps]):
+            p.step(u, k)
+        flags, vmax = p.flags()
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), flags, vmax
+
+
+@pytest.mark.parametrize("ns,alphas,eps,tau", [
+    ((200,), (1.7,), 0.1, 0.01),
+    ((63, 130), (1.3, 1.8), 0.1, 0.01),          # 1 and 3 tiles of 64, ragged
+    ((17, 9, 33), (1.3, 1.6, 1.9), 0.3, 0.02),   # every axis below or just over one tile
+    ((70, 5, 66), (1.2, 1.5, 1.1), 0.05, 0.05),
+], ids=lambda v: str(v))
+def test_exact_parity_with_oracle(sfac_lib, ns, alphas, eps, tau):
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.95, 0.95, seed=7 + len(ns))
+    steps = 12
+    ref = O.strang_solve(u0, ns, alphas, eps, hs, tau, steps)
+    _say(f"case exact {ns} {alphas}")
+    got, flags, vmax = _run(u0, ns, alphas, eps, hs, tau, steps)
+    rel = np.abs(got - ref).max() / np.abs(ref).max()
+    _say(f"  max rel diff {rel:.2e}, flags {flags}, max|u| {vmax:.6f}")
+    assert rel <= FP64_TOL
+    assert flags == 0 and vmax >= np.abs(got).max()
+    # split calls and plain launches give the same bits
+    split, _, _ = _run(u0, ns, alphas, eps, hs, tau, steps, splits=[5, 0, 7])
+    plain, _, _ = _run(u0, ns, alphas, eps, hs, tau, steps, use_graph=False)
+    assert np.array_equal(split, got) and np.array_equal(plain, got)
+
+
+def test_exact_eps0_is_the_nonlinear_flow(sfac_lib):
+    """eps = 0: B = 0, e^{tau B} = I, and a step is the closed-form ODE flow over tau."""
+    ns = (65, 40)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=3)
+    tau, steps = 0.05, 10
+    got, flags, _ = _run(u0, ns, (1.5, 1.5), 0.0, W.mesh_widths(ns), tau, steps)
+    t = tau * steps
+    ref = u0 / np.sqrt(u0 ** 2 + (1 - u0 ** 2) * np.exp(-2 * t))
+    assert np.abs(got - ref).max() <= 1e-13
+    assert flags == 0
+
+
+def test_table2_strang_column(sfac_lib):
+    """Sec. 5, Example 1, Table 2 (Strang column): ||u(h, tau) - u(h, tau/2)||_inf on 255 x 255
+    interior nodes, T = 1, for all four alpha pairs and tau = 1/100, 1/200."""
+    g = _golden("table2_example1_temporal.json")
+    n, L, eps, T = g["n"], g["domain_length"], g["eps"], g["T"]
+    h = L / (n + 1)
+    u0 = W.two_gaussians_2d(n, L)
+    cache = {}
+
+    def run(alpha, tau):
+        key = (tuple(alpha), tau)
+        if key not in cache:
+            u, flags, _ = _run(u0, (n, n), alpha, eps, (h, h), tau, int(round(T / tau)))
+            assert flags == 0
+            cache[key] = u
+        return cache[key]
+
+    for row in g["rows"]:
+        a, tau = row["alpha"], row["tau"]
+        e = np.abs(run(a, tau) - run(a, tau / 2)).max()
+        _say(f"case table 2 Strang alpha {a} tau {tau}: {e:.5e} (printed {row['strang']:.5e})")
+        assert abs(e - row["strang"]) <= 5e-4 * row["strang"], (a, tau, e, row["strang"])
+
+
+def test_table4_strang_column(sfac_lib):
+    """Sec. 5, Example 2, Table 4 (Strang column): the same temporal error on 63^3 interior
+    nodes of (0, 1)^3, T = 1, tau = 0.05."""
+    g = _golden("table4_example2_strang.json")
+    n, L, eps = g["n"], g["domain_length"], g["eps"]
+    h = L / (n + 1)
+    u0 = W.two_gaussians_3d(n, L)
+    for row in g["rows"]:
+        a, tau = row["alpha"], row["tau"]
+        steps = int(round(g["T"] / tau))
+        u1, f1, _ = _run(u0, (n,) * 3, a, eps, (h,) * 3, tau, steps)
+        u2, f2, _ = _run(u0, (n,) * 3, a, eps, (h,) * 3, tau / 2, 2 * steps)
+        e = np.abs(u1 - u2).max()
+        _say(f"case table 4 Strang alpha {a}: {e:.5e} (printed {row['strang']:.5e})")
+        assert f1 == 0 and f2 == 0
+        assert abs(e - row["strang"]) <= 5e-4 * row["strang"], (a, e, row["strang"])
+
+
+def test_exact_trace_and_energy(sfac_lib):
+    """The per-step max|u| record and the discrete energy on a plan of the exact exponential,
+    against the oracle's one-level states."""
+    import torch
+    from paper_2209_08437_amd import sfac
+    ns, alphas, eps, tau = (63, 130), (1.4, 1.7), 0.1, 0.02
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.95, 0.95, seed=19)
+    ops = O.axis_operators(ns, alphas, eps, hs, tau)
+    steps = 40
+    maxes, u = [], np.array(u0)
+    for _ in range(steps):
+        u = O.strang_step(u, ops, tau)
+        maxes.append(np.abs(u).max())
+    e_ref = O.discrete_energy(u, ops, hs)
+    d = torch.tensor(u0, device="cuda")
+    with sfac.Plan(ns, alphas, eps, tau, hs, "f64", method="exact") as p:
+        p.trace(steps)
+        p.step(d, 25)
+        p.step(d, 15)
+        rec, n = p.read_trace()
+        energy = p.energy(d)
+        _, vmax = p.flags()
+    assert n == steps
+    assert np.abs(rec - np.array(maxes)).max() <= FP64_TOL
+    assert rec.max() == vmax
+    # the state differs from the oracle's by the FP64 parity bound; the energy is smooth in it
+    assert abs(energy - e_ref) <= 1e-11 * abs(e_ref)
+
+
+def test_exact_plan_rejects_pass_timing_and_groups(sfac_lib):
+    import torch
+    from paper_2209_08437_amd import sfac
+    ns = (31, 31)
+    u = torch.zeros(ns, dtype=torch.float64, device="cuda")
+    g = sfac.Group()
+    try:
+        with sfac.Plan(ns, (1.5, 1.5), 0.1, 0.01, W.mesh_widths(ns), "f64", method="exact") as p:
+            with pytest.raises(sfac.SfacError, match="exact exponential"):
+                p.time_passes(u, 2)
+            with pytest.raises(sfac.SfacError, match="exact exponential"):
+                g.step([p], [u], [1])
+    finally:
+        g.close()
