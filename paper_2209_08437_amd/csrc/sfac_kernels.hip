@@ -850,53 +850,75 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
 namespace {
 // Row-major batched FP64 product, 64 x 64 tile of C per block of 256 threads (4 x 4 per thread),
 // K in steps of 16 through LDS; every load and store is guarded, so any M, N, K work.
-constexpr int kGemmTile = 64, kGemmK = 16;
-__global__ void __launch_bounds__(256) exact_gemm(const double* __restrict__ X, const double* __restrict__ Y,
-                                                  double* __restrict__ C, int M, int N, int K, long long ldx,
-                                                  long long ldy, long long ldc, long long sx, long long sy,
-                                                  long long sc) {
-    __shared__ double xs[kGemmK][kGemmTile + 1];   // xs[k][m]
-    __shared__ double ys[kGemmK][kGemmTile + 1];   // ys[k][n]
+// Dense FP64 product C = X Y (per batch index), on the matrix cores: v_mfma_f64_16x16x4 takes
+// A (16 x 4) as lane l -> row l % 16, k = l / 16, B (4 x 16) as lane l -> column l % 16,
+// k = l / 16, and returns D (16 x 16) in four registers, register i of lane l holding row
+// 4 i + l / 16, column l % 16. A block of four wavefronts owns a 32 x 32 tile of C, one 16 x 16
+// quarter per wavefront; K advances in slabs of 32 staged through LDS (X transposed, so both
+// operands are read along m or n by consecutive lanes), the next slab loaded into registers
+// while the current one is multiplied.
+constexpr int kGemmTile = 32, kGemmK = 32, kGemmThreads = 256;
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kGemmThreads) exact_gemm(const double* __restrict__ X, const double* __restrict__ Y,
+                                                           double* __restrict__ C, int M, int N, int K, long long ldx,
+                                                           long long ldy, long long ldc, long long sx, long long sy,
+                                                           long long sc) {
+    __shared__ double xs[2][kGemmK][kGemmTile + 1];   // xs[k][m]
+    __shared__ double ys[2][kGemmK][kGemmTile + 1];   // ys[k][n]
     const long long b = blockIdx.z;
     X += b * sx;
     Y += b * sy;
     C += b * sc;
     const int m0 = blockIdx.y * kGemmTile, n0 = blockIdx.x * kGemmTile;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < K; k0 += kGemmK) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;
+    constexpr int kPer = kGemmTile * kGemmK / kGemmThreads;   // elements of each slab per thread
+    double xr[kPer], yr[kPer];
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int idx = threadIdx.x + r * 256;
-            const int mm = idx >> 4, kk = idx & 15;            // 16 consecutive k of one row
+        for (int r = 0; r < kPer; ++r) {
+            const int idx = t + r * kGemmThreads;
+            const int mm = idx / kGemmK, kk = idx % kGemmK;    // consecutive threads along a row of X
             const int gm = m0 + mm, gk = k0 + kk;
-            xs[kk][mm] = (gm < M && gk < K) ? X[(long long)gm * ldx + gk] : 0.0;
-            const int kk2 = idx >> 6, nn = idx & 63;           // 64 consecutive n of one row
+            xr[r] = (gm < M && gk < K) ? X[(long long)gm * ldx + gk] : 0.0;
+            const int kk2 = idx / kGemmTile, nn = idx % kGemmTile;   // along a row of Y
             const int gk2 = k0 + kk2, gn = n0 + nn;
-            ys[kk2][nn] = (gk2 < K && gn < N) ? Y[(long long)gk2 * ldy + gn] : 0.0;
+            yr[r] = (gk2 < K && gn < N) ? Y[(long long)gk2 * ldy + gn] : 0.0;
         }
-        __syncthreads();
+    };
+    auto stash = [&](int buf) {
 #pragma unroll
-        for (int kk = 0; kk < kGemmK; ++kk) {
-            double xa[4], yb[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) xa[i] = xs[kk][ty * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) yb[j] = ys[kk][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(xa[i], yb[j], acc[i][j]);
+        for (int r = 0; r < kPer; ++r) {
+            const int idx = t + r * kGemmThreads;
+            xs[buf][idx % kGemmK][idx / kGemmK] = xr[r];
+            ys[buf][idx / kGemmTile][idx % kGemmTile] = yr[r];
         }
+    };
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    load(0);
+    stash(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += kGemmK) {
+        const bool more = k0 + kGemmK < K;
+        if (more) load(k0 + kGemmK);
+#pragma unroll
+        for (int k4 = 0; k4 < kGemmK; k4 += 4) {
+            const double a = xs[buf][k4 + (lane >> 4)][wm + (lane & 15)];
+            const double bb = ys[buf][k4 + (lane >> 4)][wn + (lane & 15)];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        }
+        if (more) stash(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
+    const int gn = n0 + wn + (lane & 15);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
-            if (gm < M && gn < N) C[(long long)gm * ldc + gn] = acc[i][j];
-        }
+    for (int i = 0; i < 4; ++i) {
+        const int gm = m0 + wm + 4 * i + (lane >> 4);
+        if (gm < M && gn < N) C[(long long)gm * ldc + gn] = acc[i];
+    }
 }
 
 __global__ void __launch_bounds__(kExactNlThreads) exact_nl(double* dst, const double* src, long long n, double decay,
@@ -922,7 +944,7 @@ hipError_t launch_exact_gemm(const double* X, const double* Y, double* C, int M,
                              hipStream_t stream) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     const dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile, batch);
-    hipLaunchKernelGGL(exact_gemm, grid, dim3(256), 0, stream, X, Y, C, M, N, K, ldx, ldy, ldc, sx, sy, sc);
+    hipLaunchKernelGGL(exact_gemm, grid, dim3(kGemmThreads), 0, stream, X, Y, C, M, N, K, ldx, ldy, ldc, sx, sy, sc);
     return hipGetLastError();
 }
 
