@@ -86,6 +86,25 @@ def trace_axis_means(trace_csv, dims):
     return out
 
 
+def exact_axis_means(trace_csv, ns):
+    """The one-level scheme's dense products in a kernel trace: mean duration (us) per axis (the
+    d-periodic dispatch order) and the flop rate, 2 N_axis flops per grid point."""
+    rows = sorted(_rows(trace_csv), key=lambda r: int(r["Start_Timestamp"]))
+    v = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows if "exact_gemm" in r["Kernel_Name"]]
+    pts = 1
+    for n in ns:
+        pts *= n
+    out = []
+    for a in range(len(ns)):
+        xs = v[a::len(ns)]
+        if not xs:
+            continue
+        mean = sum(xs) / len(xs) / 1e3
+        out.append({"axis": a + 1, "dispatches": len(xs), "mean_us": mean, "min_us": min(xs) / 1e3,
+                    "max_us": max(xs) / 1e3, "tflops": 2.0 * ns[a] * pts / (mean * 1e-6) / 1e12})
+    return out
+
+
 def stats_markdown(stats_csv, top=8):
     rows = _rows(stats_csv)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
@@ -160,7 +179,7 @@ SQ_SETS = (("A", "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_
            ("B", "SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU "
                  "SQ_ACTIVE_INST_ANY SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64"))
 SQ_COMMAND = ("timeout -s KILL 90 rocprofv3 --pmc $COUNTERS --output-format csv -d $O/$SET_$W -o run -- "
-              "python3 $R/bench.py --workload $W --dtype f64 --no-cpu --no-fp32 --steps 10 --warmup 2 --pass-reps 2")
+              "python3 $R/bench.py --workload $W --dtype f64 --no-cpu --no-fp32 --no-exact --steps 10 --warmup 2 --pass-reps 2")
 # MI355X: 256 CUs of 4 SIMDs; a SIMD issues one wavefront VALU instruction (FP64, or FP32 unpacked) every
 # 4 cycles at 2.4 GHz
 VALU_WAVE_INSTR_PER_US = 256 * 4 / 4 * 2400.0
@@ -240,8 +259,8 @@ def load_traffic(path, workload, dtype, schedule=None):
 COMMANDS = """\
 python3 -m paper_2209_08437_amd.autotune --fresh --out $R/paper_2209_08437_amd/tuned_mi355x.json large_2d_1023 large_3d_255 plain_2d_63 batched_2d   # the packaged schedule table, tuned on an MI355X beforehand; every run below uses it
 rocprofv3 --kernel-trace --stats --output-format csv -d $O/trace_$W -o run -- python3 $R/bench.py --workload $W --no-cpu
-rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --steps 20 --warmup 2 --pass-reps 2
-rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-exact --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-exact --steps 20 --warmup 2 --pass-reps 2
 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/copy_FETCH_SIZE -o run -- python3 $R/bench.py --copy-probe
 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/copy_WRITE_SIZE -o run -- python3 $R/bench.py --copy-probe"""
 
@@ -292,6 +311,18 @@ def _main():
         for r in res:
             lines.append(f"| {et} | {r['axis']} | `{r['kernel']}` | {r['dispatches']} | {r['mean_us']:.2f} | "
                          f"{r['min_us']:.2f} | {r['max_us']:.2f} |")
+    ex = exact_axis_means(os.path.join(d, f"trace_{w}", "run_kernel_trace.csv"), bench["config"]["grid"])
+    if ex:
+        lines += ["", "One-level scheme with the exact exponential (`exact_gemm`, FP64 matrix cores; "
+                  "2 N flops per point and axis; peak 78.6 TFLOP/s):", "",
+                  "| axis | dispatches | mean us | min us | max us | TFLOP/s | frac |", "|---|---|---|---|---|---|---|"]
+        for r in ex:
+            lines.append(f"| {r['axis']} | {r['dispatches']} | {r['mean_us']:.2f} | {r['min_us']:.2f} | "
+                         f"{r['max_us']:.2f} | {r['tflops']:.1f} | {r['tflops'] / 78.6:.3f} |")
+        one = bench.get("one_level_exact", {})
+        if "ms_per_step" in one:
+            lines += ["", f"bench.py in the same session: {one['ms_per_step'] * 1e3:.1f} us per one-level step "
+                      f"({one['product_TFLOPs']} TFLOP/s over the step), plan creation {one['plan_create_ms']:.0f} ms."]
     lines += ["", f"bench.py in the same session (no profiler): FP64 {bench['ms_per_step'] * 1e3:.2f} us/step, "
               f"pass us {[round(x * 1e3, 2) for x in bench['roofline']['pass_ms']]}; FP32 "
               f"{bench['fp32']['ms_per_step'] * 1e3:.2f} us/step, pass us "

@@ -123,3 +123,23 @@ def test_sq_axis_means(tmp_path):
     assert a1["SQ_WAVES"] == 2048.0 and a2["SQ_WAVES"] == 2048.0
     assert a1["SQ_INSTS_VALU"] == 15.0 and a2["SQ_INSTS_VALU"] == 40.0
     assert a1["kernel"] == "embed_pass_single<double, 11, 3>"
+
+
+def test_exact_axis_means(tmp_path):
+    # a 2D one-level run: products alternate axis 1, axis 2; other kernels are skipped
+    path = str(tmp_path / "trace.csv")
+    fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    gemm = "sfac::(anonymous namespace)::exact_gemm(double const*, double const*, double*, int, int, int)"
+    nl = "sfac::(anonymous namespace)::exact_nl(double*, double const*, long long, double, int)"
+    rows = [(nl, 0, 500), (gemm, 1000, 3000), (gemm, 3000, 7000), (nl, 7000, 7500),
+            (gemm, 9000, 13000), (gemm, 13000, 19000), (PASS, 20000, 21000)]
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(fields, r)))
+    a1, a2 = P.exact_axis_means(path, [100, 50])
+    assert a1["dispatches"] == a2["dispatches"] == 2
+    assert a1["mean_us"] == pytest.approx(3.0) and a2["mean_us"] == pytest.approx(5.0)
+    assert a1["tflops"] == pytest.approx(2 * 100 * 5000 / 3e-6 / 1e12)
+    assert a2["tflops"] == pytest.approx(2 * 50 * 5000 / 5e-6 / 1e12)
