@@ -14,10 +14,17 @@ result: every state sees exactly the kernels and order of a lone sfac_step call.
 
 The executor does the device work; `GpuExecutor` uses the library. Anything with the same four
 methods can stand in (the tests use a CPU stand-in to check the scheduling).
+
+Two front ends share that policy: `Server.run` replays a list of timed requests (the benchmark's
+arrival stream), and `Service` is the online form: `submit` from any thread returns a future,
+and one worker thread owns the executor and runs the ticks.
 """
 from collections import deque
+from concurrent.futures import Future
 from dataclasses import dataclass, field
 import math
+import queue
+import threading
 import time
 
 import numpy as np
@@ -49,6 +56,8 @@ class GpuExecutor:
     their shape when the schedule table (`schedule_table`: a cache file path; default the
     packaged MI355X table; False for automatic schedules only) holds it; nothing is tuned
     while serving."""
+
+    on_device = True
 
     def __init__(self, stream=None, schedule_table=None):
         import torch
@@ -196,3 +205,167 @@ class Server:
             "admit_total_s": float(adm.sum()),
         }
         return [tickets[r.rid] for r in sorted(reqs, key=lambda r: r.rid)], summary
+
+
+class Service:
+    """Online solve service: `submit(inst, dtype)` from any thread returns a
+    concurrent.futures.Future of (final state as an FP64 array, sticky flags, max|u|).
+
+    One worker thread creates the executor (`executor_factory()`, e.g. GpuExecutor) and does
+    all device work. Between ticks it takes new submissions, admits queued requests first come
+    first served while their device memory fits `budget_bytes`, and advances every admitted
+    request by up to `tick_steps` steps in one grouped step; requests that finish are read back
+    and their futures completed at the tick boundary. A request larger than the whole budget,
+    or one whose admission or step fails, gets the exception in its future. A future cancelled
+    before admission is dropped. `close()` stops taking submissions, lets the admitted and
+    queued requests finish, and joins the worker.
+
+    Not enabled for device executors (`on_device`, e.g. GpuExecutor): the one run of this
+    service with the device executor on its worker thread ended in a host segmentation fault
+    whose cause has not been found, so such an executor is refused with an error until it is.
+    Device serving goes through `Server.run`, which does its device work on the calling thread."""
+
+    _STOP = object()
+
+    _DEVICE_REFUSED = ("the online service is not enabled for device executors: its one run with the "
+                       "device executor on a worker thread ended in a host segmentation fault of unknown cause; "
+                       "serve through Server.run")
+
+    def __init__(self, executor_factory, budget_bytes, tick_steps=50, max_active=256):
+        if isinstance(executor_factory, type) and getattr(executor_factory, "on_device", False):
+            raise RuntimeError(self._DEVICE_REFUSED)
+        self.budget = int(budget_bytes)
+        self.tick_steps = int(tick_steps)
+        self.max_active = int(max_active)
+        self._inbox = queue.Queue()
+        self._closed = False
+        self._lock = threading.Lock()
+        self._stats = {"submitted": 0, "completed": 0, "rejected": 0, "failed": 0, "ticks": 0,
+                       "peak_active": 0, "peak_bytes": 0}
+        self._ready = threading.Event()
+        self._start_error = None
+        self._thread = threading.Thread(target=self._loop, args=(executor_factory,), daemon=True)
+        self._thread.start()
+        self._ready.wait()
+        if self._start_error is not None:
+            raise self._start_error
+
+    def submit(self, inst, dtype="f64"):
+        if dtype not in ("f64", "f32"):
+            raise ValueError(f"dtype {dtype!r}, expected 'f64' or 'f32'")
+        fut = Future()
+        with self._lock:
+            if self._closed:
+                raise RuntimeError("the service is closed")
+            self._stats["submitted"] += 1
+            self._inbox.put((inst, dtype, fut))
+        return fut
+
+    def stats(self):
+        with self._lock:
+            return dict(self._stats)
+
+    def close(self):
+        with self._lock:
+            if self._closed:
+                return
+            self._closed = True
+            self._inbox.put(self._STOP)
+        self._thread.join()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _count(self, key, n=1):
+        with self._lock:
+            self._stats[key] += n
+
+    def _loop(self, executor_factory):
+        try:
+            ex = executor_factory()
+            if getattr(ex, "on_device", False):
+                raise RuntimeError(self._DEVICE_REFUSED)
+        except Exception as err:        # reported by the constructor
+            self._start_error = err
+            self._ready.set()
+            return
+        self._ready.set()
+        pending = deque()
+        active = []            # [future, handle, remaining steps, bytes]
+        used = 0
+        stopping = False
+        while True:
+            # new submissions: wait for one when there is nothing else to do
+            idle = not active and not pending
+            while True:
+                try:
+                    item = self._inbox.get(block=idle and not stopping)
+                except queue.Empty:
+                    break
+                idle = False
+                if item is self._STOP:
+                    stopping = True
+                else:
+                    pending.append(item)
+            while pending and len(active) < self.max_active:
+                inst, dtype, fut = pending[0]
+                need = ex.bytes_needed(inst, dtype)
+                if need <= self.budget and used + need > self.budget:
+                    break
+                pending.popleft()
+                if not fut.set_running_or_notify_cancel():
+                    continue
+                if need > self.budget:
+                    fut.set_exception(ValueError(f"request needs {need} bytes, more than the budget {self.budget}"))
+                    self._count("rejected")
+                    continue
+                if int(inst.steps) == 0:
+                    fut.set_result((np.array(inst.u0, dtype=np.float64, copy=True), 0,
+                                    float(np.abs(np.asarray(inst.u0)).max()) if np.size(inst.u0) else 0.0))
+                    self._count("completed")
+                    continue
+                try:
+                    handle = ex.admit(inst, dtype)
+                except Exception as err:
+                    fut.set_exception(err)
+                    self._count("failed")
+                    continue
+                active.append([fut, handle, int(inst.steps), need])
+                used += need
+            with self._lock:
+                self._stats["peak_active"] = max(self._stats["peak_active"], len(active))
+                self._stats["peak_bytes"] = max(self._stats["peak_bytes"], used)
+            if active:
+                k = [min(self.tick_steps, a[2]) for a in active]
+                try:
+                    ex.step([a[1] for a in active], k)
+                except Exception as err:
+                    for a in active:
+                        a[0].set_exception(err)
+                        try:
+                            ex.retire(a[1])
+                        except Exception:
+                            pass
+                    self._count("failed", len(active))
+                    active, used = [], 0
+                    continue
+                self._count("ticks")
+                still = []
+                for a, kk in zip(active, k):
+                    a[2] -= kk
+                    if a[2] == 0:
+                        try:
+                            a[0].set_result(ex.retire(a[1]))
+                            self._count("completed")
+                        except Exception as err:
+                            a[0].set_exception(err)
+                            self._count("failed")
+                        used -= a[3]
+                    else:
+                        still.append(a)
+                active = still
+            elif stopping and not pending:
+                return

@@ -55,3 +55,42 @@ def test_served_results_equal_lone_solves(sfac_lib):
         if r.dtype == "f64" and r.rid < 6:
             ref = O.two_level_solve(i.u0, i.ns, i.alphas, i.eps, i.hs, i.tau, i.steps)
             assert np.abs(tk.result - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.skip(reason="the one run of the online service with the device executor on its worker thread "
+                         "ended in a host segmentation fault whose cause has not been found; the service "
+                         "refuses device executors until it is")
+def test_online_service_results_equal_lone_solves(sfac_lib):
+    """The online form: submissions from two threads, the worker thread owning the device
+    executor; each future's state is bitwise the lone solve's."""
+    import threading
+    import torch
+    from paper_2209_08437_amd import serve, sfac
+    reqs = _stream(count=8, seed=23)
+    sizes = [serve.GpuExecutor.bytes_needed(None, r.inst, r.dtype) for r in reqs]
+    budget = max(sizes) + min(sizes)
+    print(f"case online service, {len(reqs)} requests, budget {budget} B", flush=True)
+    futs = {}
+    with serve.Service(serve.GpuExecutor, budget_bytes=budget, tick_steps=6) as svc:
+        def worker(part):
+            for r in part:
+                futs[r.rid] = svc.submit(r.inst, r.dtype)
+        threads = [threading.Thread(target=worker, args=(reqs[i::2],)) for i in range(2)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        results = {rid: f.result(timeout=120) for rid, f in futs.items()}
+    st = svc.stats()
+    print(st, flush=True)
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["peak_bytes"] <= budget
+    for r in reqs:
+        i = r.inst
+        tdt = torch.float64 if r.dtype == "f64" else torch.float32
+        u = torch.tensor(i.u0, dtype=tdt, device="cuda")
+        with sfac.Plan(i.ns, i.alphas, i.eps, i.tau, i.hs, r.dtype) as p:
+            p.step(u, i.steps)
+        torch.cuda.synchronize()
+        out, flags, vmax = results[r.rid]
+        assert np.array_equal(out, u.double().cpu().numpy()), r.rid
+        assert flags == 0 and vmax <= 1.0

@@ -114,3 +114,88 @@ def test_fifo_admission_and_continuous_joining():
     assert joined
     # every grouped step advanced each active request by at most the tick size
     assert all(k <= 3 for tick in ex.log for _, k in tick)
+
+
+def test_online_service_futures_from_several_threads():
+    """Service: submissions from two threads, results through futures, bitwise equal to lone
+    solves; an oversize request fails its future alone; close() drains; no submit afterwards."""
+    import threading
+    clock = SimClock()
+    reqs = _requests(count=12, seed=11)
+    big = W.Instance((40, 40), (1.5, 1.5), 0.1, 0.01, W.mesh_widths((40, 40)), 5)
+    big.u0 = W.uniform_field(big.shape, -0.5, 0.5, seed=1)
+    zero = W.Instance((9, 9), (1.5, 1.5), 0.1, 0.01, W.mesh_widths((9, 9)), 0)
+    zero.u0 = W.uniform_field(zero.shape, -0.5, 0.5, seed=2)
+    futs = {}
+    need = max(int(np.prod(r.inst.ns)) * 8 for r in reqs)
+    budget = 12000                    # every small request fits (a few at a time); the big one never
+    assert need <= budget < 8 * 40 * 40
+    with serve.Service(lambda: OracleExecutor(clock), budget_bytes=budget, tick_steps=5) as svc:
+        def worker(part):
+            for r in part:
+                futs[r.rid] = svc.submit(r.inst, r.dtype)
+        threads = [threading.Thread(target=worker, args=(reqs[i::2],)) for i in range(2)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        f_big = svc.submit(big, "f64")
+        f_zero = svc.submit(zero, "f32")
+        with pytest.raises(ValueError):
+            svc.submit(zero, "bf16")
+    with pytest.raises(RuntimeError):
+        svc.submit(zero, "f64")
+    for r in reqs:
+        i = r.inst
+        out, flags, vmax = futs[r.rid].result(timeout=0)
+        alone = O.two_level_solve(i.u0, i.ns, i.alphas, i.eps, i.hs, i.tau, i.steps)
+        assert np.array_equal(out, alone) and flags == 0 and vmax == np.abs(alone).max()
+    with pytest.raises(ValueError, match="budget"):
+        f_big.result(timeout=0)
+    assert np.array_equal(f_zero.result(timeout=0)[0], zero.u0)
+    st = svc.stats()
+    assert st["submitted"] == 14 and st["completed"] == 13 and st["rejected"] == 1 and st["failed"] == 0
+    assert st["peak_bytes"] <= budget
+
+
+def test_online_service_step_failure_reaches_futures():
+    """A failing grouped step fails the futures of the requests in it and the service goes on."""
+    clock = SimClock()
+
+    class Flaky(OracleExecutor):
+        calls = 0
+
+        def step(self, handles, nsteps):
+            Flaky.calls += 1
+            if Flaky.calls == 1:
+                raise RuntimeError("device step failed")
+            super().step(handles, nsteps)
+
+    r1, r2 = _requests(count=2, seed=5)
+    with serve.Service(lambda: Flaky(clock), budget_bytes=10 ** 9, tick_steps=100) as svc:
+        f1 = svc.submit(r1.inst, "f64")
+        with pytest.raises(RuntimeError, match="device step failed"):
+            f1.result(timeout=30)
+        f2 = svc.submit(r2.inst, "f64")
+        out, _, _ = f2.result(timeout=30)
+    i = r2.inst
+    assert np.array_equal(out, O.two_level_solve(i.u0, i.ns, i.alphas, i.eps, i.hs, i.tau, i.steps))
+    assert svc.stats()["failed"] == 1
+
+
+def test_online_service_reports_executor_start_failure():
+    def broken():
+        raise RuntimeError("no device")
+    with pytest.raises(RuntimeError, match="no device"):
+        serve.Service(broken, budget_bytes=1)
+
+
+def test_online_service_refuses_device_executors():
+    """Device executors stay off the online service (see Service's docstring)."""
+    class DeviceStandIn(OracleExecutor):
+        on_device = True
+
+    with pytest.raises(RuntimeError, match="not enabled for device executors"):
+        serve.Service(serve.GpuExecutor, budget_bytes=1)
+    with pytest.raises(RuntimeError, match="not enabled for device executors"):
+        serve.Service(lambda: DeviceStandIn(SimClock()), budget_bytes=1)
