@@ -71,6 +71,20 @@ def test_exact_parity_with_oracle(sfac_lib, ns, alphas, eps, tau):
     assert np.array_equal(split, got) and np.array_equal(plain, got)
 
 
+@pytest.mark.parametrize("which,steps", [("large_2d_1023", 20), ("large_3d_255", 3)])
+def test_exact_parity_full_size(sfac_lib, which, steps):
+    """The benchmark workloads at full size (1023^2 and 255^3 FP64), every element against the
+    oracle's one-level solve: the products then span 32 and 8 tiles of 32 per axis, with the
+    ragged last tile, and the 3D strided axes run as batches of 255."""
+    inst = getattr(W, which)()
+    ref = O.strang_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, steps)
+    _say(f"case exact full size {which}, {steps} steps")
+    got, flags, _ = _run(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, steps)
+    rel = np.abs(got - ref).max() / np.abs(ref).max()
+    _say(f"  max rel diff {rel:.2e}")
+    assert rel <= FP64_TOL and flags == 0
+
+
 def test_exact_eps0_is_the_nonlinear_flow(sfac_lib):
     """eps = 0: B = 0, e^{tau B} = I, and a step is the closed-form ODE flow over tau."""
     ns = (65, 40)
