@@ -42,6 +42,7 @@ if ROOT not in sys.path:
 METRIC = "grid-point-steps/s (N^d·steps/s) FP64 vs FP32 + HBM GB/s; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}     # MI355X published vector peaks
+MFMA_F64_PEAK_TFLOPS = 78.6                         # MI355X published dense FP64 matrix peak
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -169,11 +170,13 @@ def diagnostics(plan, u0, u, k):
         return {"unavailable": str(err)}
 
 
-def one_level_exact(inst, steps, two_level_state, two_level_ms):
+def one_level_exact(inst, steps, two_level_state, two_level_ms, workload_name, pass_reps):
     """The one-level scheme (eq. (strang)) with e^{tau B} per axis as a dense FP64 product on the
     GPU (SFAC_METHOD_EXACT) over the bench's steps: plan creation (host eigendecomposition),
-    step time, the products' flop rate (2 N flops per point and axis) and the max-norm distance
-    of its final state from the two-level scheme's."""
+    step time, the products' flop rate (2 N flops per point and axis), the max-norm distance
+    of its final state from the two-level scheme's, and the roofline of the dense product with
+    the longest mean duration (HIP events around each product on the plan's stream, against
+    the FP64 matrix-core peak; traffic from the committed counter record when it matches)."""
     import numpy as np
     import torch
     from paper_2209_08437_amd import sfac
@@ -196,16 +199,28 @@ def one_level_exact(inst, steps, two_level_state, two_level_ms):
         torch.cuda.synchronize()
         step_ms = ev[0].elapsed_time(ev[1]) / steps
         flags, vmax = plan.flags()
+        prod_ms = plan.time_passes(u0.clone(), pass_reps)
     finally:
         plan.close()
     flops = sum(2.0 * n * inst.points for n in inst.ns)
+    a = max(range(inst.dims), key=lambda i: prod_ms[i])
+    fl = 2.0 * inst.ns[a] * inst.points
+    tf = fl / (prod_ms[a] * 1e-3) / 1e12
+    from paper_2209_08437_amd import profiling
+    rec = profiling.load_traffic(TRAFFIC_RECORD, workload_name, "exact")
+    roof = {"bound": "mfma", "achieved": round(tf, 3), "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / MFMA_F64_PEAK_TFLOPS, 4),
+            "traffic": rec["per_axis"][a]["bytes"] if rec else None,
+            "kernel": f"exact_gemm (FP64 matrix cores), axis {a + 1}", "flops_per_launch": fl,
+            "algorithmic_bytes_per_launch": 8 * (2 * inst.points + inst.ns[a] ** 2),
+            "product_ms": [round(x, 5) for x in prod_ms]}
     diff = float(np.abs(u.cpu().numpy() - two_level_state).max())
     log(f"[bench] one-level exact: {step_ms * 1e3:.1f} us/step ({flops / step_ms / 1e9:.1f} TFLOP/s products), "
         f"plan {create_ms:.0f} ms, max|diff| to two-level {diff:.3e}")
     return {"ms_per_step": round(step_ms, 5), "plan_create_ms": round(create_ms, 1),
             "product_flops_per_step": flops, "product_TFLOPs": round(flops / step_ms / 1e9, 3),
             "two_level_speedup": round(step_ms / two_level_ms, 2),
-            "max_abs_diff_vs_two_level": diff, "max_abs": vmax, "flags": flags}
+            "max_abs_diff_vs_two_level": diff, "max_abs": vmax, "flags": flags, "roofline": roof}
 
 
 def batched_run(args):
@@ -440,7 +455,8 @@ def main():
     out["flags"] = main_r["flags"]
     out["diagnostics"] = main_r["diagnostics"]
     if args.dtype == "f64" and not args.no_exact:
-        out["one_level_exact"] = one_level_exact(inst, steps, main_r["state"], main_r["wall_s"] * 1e3 / steps)
+        out["one_level_exact"] = one_level_exact(inst, steps, main_r["state"], main_r["wall_s"] * 1e3 / steps,
+                                                 args.workload, args.pass_reps)
     if not args.no_cpu:
         log(f"[bench] timing the CPU oracle for about {args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)

@@ -146,8 +146,9 @@ sfac_status sfac_step(sfac_plan p, void* u_dev, int64_t nsteps);
  * Waits for the plan's queued work first. */
 sfac_status sfac_plan_destroy(sfac_plan p);
 
-/* sfac_plan_device_bytes - device memory the plan holds (tables, flags), excluding the
- * caller's state; 0 for NULL. */
+/* sfac_plan_device_bytes - device memory the plan holds (tables, flags; for SFAC_METHOD_EXACT the
+ * per-axis exponentials and a state-sized scratch buffer), excluding the caller's state; 0 for
+ * NULL. */
 size_t sfac_plan_device_bytes(sfac_plan p);
 
 /* sfac_plan_flags - synchronize the plan's stream and read its sticky status: *flags gets
@@ -163,7 +164,9 @@ sfac_status sfac_plan_reset_flags(sfac_plan p);
  * plain launches, a HIP event pair recorded on the plan's stream around every pass, and write
  * the mean duration of each axis' pass in milliseconds to ms[0 .. dims-1]. The state advances
  * by `reps` steps exactly as sfac_step would advance it. Synchronizes the plan's stream.
- * Errors: SFAC_EINVAL, SFAC_EUNSUPPORTED (a plan of SFAC_METHOD_EXACT), SFAC_EDEVICE.
+ * For a plan of SFAC_METHOD_EXACT, ms[a] is the mean duration of axis a+1's dense product (the
+ * nonlinear half-steps run between the event pairs, untimed).
+ * Errors: SFAC_EINVAL, SFAC_EDEVICE.
  */
 sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float* ms);
 

@@ -848,29 +848,40 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Pass
 }
 
 namespace {
-// Row-major batched FP64 product, 64 x 64 tile of C per block of 256 threads (4 x 4 per thread),
-// K in steps of 16 through LDS; every load and store is guarded, so any M, N, K work.
-// Dense FP64 product C = X Y (per batch index), on the matrix cores: v_mfma_f64_16x16x4 takes
+// Dense FP64 product C = X Y (row-major, per batch index), on the matrix cores: v_mfma_f64_16x16x4 takes
 // A (16 x 4) as lane l -> row l % 16, k = l / 16, B (4 x 16) as lane l -> column l % 16,
 // k = l / 16, and returns D (16 x 16) in four registers, register i of lane l holding row
 // 4 i + l / 16, column l % 16. A block of four wavefronts owns a 32 x 32 tile of C, one 16 x 16
 // quarter per wavefront; K advances in slabs of 32 staged through LDS (X transposed, so both
 // operands are read along m or n by consecutive lanes), the next slab loaded into registers
-// while the current one is multiplied.
-constexpr int kGemmTile = 32, kGemmK = 32, kGemmThreads = 256;
+// while the current one is multiplied. Every load and store is guarded, so any M, N, K work.
+//
+// Tiles to XCDs: workgroup L of a launch runs on XCD L mod 8, and each XCD has its own L2. The
+// tile grid of one batch index is cut into gy x gx rectangles of rm x rn tiles, one per XCD,
+// with (gy, gx) chosen so that an XCD reads as few row bands of X and column bands of Y as
+// possible (an operand shared by every batch index costs nothing: it stays in the L2 across the
+// batch); inside a rectangle the shorter side runs fastest, so workgroups dispatched one after
+// another share the band of the longer side while they read it. Slots beyond the grid exit.
+constexpr int kGemmTile = 32, kGemmK = 32, kGemmThreads = 256, kXcds = 8;
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(kGemmThreads) exact_gemm(const double* __restrict__ X, const double* __restrict__ Y,
                                                            double* __restrict__ C, int M, int N, int K, long long ldx,
                                                            long long ldy, long long ldc, long long sx, long long sy,
-                                                           long long sc) {
+                                                           long long sc, int tiles_m, int tiles_n, int gx, int rm,
+                                                           int rn) {
     __shared__ double xs[2][kGemmK][kGemmTile + 1];   // xs[k][m]
     __shared__ double ys[2][kGemmK][kGemmTile + 1];   // ys[k][n]
-    const long long b = blockIdx.z;
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const bool n_fast = rn <= rm;
+    const int tm = (xcd / gx) * rm + (n_fast ? slot / rn : slot % rm);
+    const int tn = (xcd % gx) * rn + (n_fast ? slot % rn : slot / rm);
+    if (tm >= tiles_m || tn >= tiles_n) return;   // the whole block, before any barrier
+    const long long b = blockIdx.y;
     X += b * sx;
     Y += b * sy;
     C += b * sc;
-    const int m0 = blockIdx.y * kGemmTile, n0 = blockIdx.x * kGemmTile;
+    const int m0 = tm * kGemmTile, n0 = tn * kGemmTile;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;
     constexpr int kPer = kGemmTile * kGemmK / kGemmThreads;   // elements of each slab per thread
@@ -943,8 +954,23 @@ hipError_t launch_exact_gemm(const double* X, const double* Y, double* C, int M,
                              long long ldy, long long ldc, long long sx, long long sy, long long sc, int batch,
                              hipStream_t stream) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-    const dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile, batch);
-    hipLaunchKernelGGL(exact_gemm, grid, dim3(kGemmThreads), 0, stream, X, Y, C, M, N, K, ldx, ldy, ldc, sx, sy, sc);
+    const int tiles_m = (M + kGemmTile - 1) / kGemmTile, tiles_n = (N + kGemmTile - 1) / kGemmTile;
+    const bool x_shared = sx == 0 && batch > 1, y_shared = sy == 0 && batch > 1;
+    int gx = 1, rm = 0, rn = 0, best = 0;
+    for (int g = 1; g <= kXcds; g *= 2) {   // gx column groups, kXcds / gx row groups
+        const int m = (tiles_m + kXcds / g - 1) / (kXcds / g), n = (tiles_n + g - 1) / g;
+        const int cost = (x_shared ? 0 : m) + (y_shared ? 0 : n);
+        if (rm == 0 || cost < best || (cost == best && m + n < rm + rn)) {
+            gx = g;
+            rm = m;
+            rn = n;
+            best = cost;
+        }
+    }
+    // grid.x a multiple of 8: workgroup (x, b) runs on XCD x mod 8 for every batch index b
+    const dim3 grid((unsigned)kXcds * rm * rn, batch, 1);
+    hipLaunchKernelGGL(exact_gemm, grid, dim3(kGemmThreads), 0, stream, X, Y, C, M, N, K, ldx, ldy, ldc, sx, sy, sc,
+                       tiles_m, tiles_n, gx, rm, rn);
     return hipGetLastError();
 }
 

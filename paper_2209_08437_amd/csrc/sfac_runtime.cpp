@@ -385,13 +385,13 @@ struct sfac_plan_s {
     }
 
     // eq. (strang): J^Q_{tau/2} e^{tau A} J^Q_{tau/2}, e^{tau A} one dense product per axis, alternating
-    // between the state and the scratch buffer; the closing half-step writes the state
-    hipError_t exact_step(hipStream_t s) {
+    // between the state and the scratch buffer; the closing half-step writes the state and the
+    // statistics of `stats`. With `ev` (2 per axis), each product is bracketed by an event pair.
+    hipError_t exact_step(hipStream_t s, const sfac::PassDesc<double>& stats, hipEvent_t* ev = nullptr) {
         double* u = d64[0].u;
         double* scratch = reinterpret_cast<double*>(dev + off_scratch);
         const long long pts = in.points();
         const double decay = std::exp(-in.tau);
-        const sfac::PassDesc<double>& stats = d64[in.dims - 1];
         hipError_t e = sfac::launch_exact_nl(u, u, pts, decay, false, stats, s);
         double* cur = u;
         double* other = scratch;
@@ -401,11 +401,14 @@ struct sfac_plan_s {
             for (int b = 0; b < a; ++b) inner *= in.n[b];
             for (int b = a + 1; b < in.dims; ++b) outer *= in.n[b];
             const double* P = reinterpret_cast<const double*>(dev + off_P[a]);
+            if (ev) e = hipEventRecord(ev[2 * a], s);
+            if (e != hipSuccess) break;
             if (inner == 1)   // rows: C = X P (P symmetric)
                 e = sfac::launch_exact_gemm(cur, P, other, (int)outer, (int)n, (int)n, n, n, n, 0, 0, 0, 1, s);
             else              // per slower index o: C_o = P X_o
                 e = sfac::launch_exact_gemm(P, cur, other, (int)n, (int)inner, (int)n, n, inner, inner, 0,
                                             n * inner, n * inner, (int)outer, s);
+            if (ev && e == hipSuccess) e = hipEventRecord(ev[2 * a + 1], s);
             std::swap(cur, other);
         }
         if (e == hipSuccess) e = sfac::launch_exact_nl(u, cur, pts, decay, true, stats, s);
@@ -415,7 +418,7 @@ struct sfac_plan_s {
     hipError_t launch_steps(hipStream_t s, int64_t nsteps) {
         for (int64_t k = 0; k < nsteps; ++k) {
             if (exact) {
-                hipError_t e = exact_step(s);
+                hipError_t e = exact_step(s, d64[in.dims - 1]);
                 if (e != hipSuccess) return e;
                 if (trace_dev) e = sfac::launch_trace_collect(trace_slots(), trace_parts, trace_rec(), trace_step(),
                                                                trace_cap, s);
@@ -731,7 +734,6 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
     g_error.clear();
     if (!p) return fail(SFAC_EINVAL, "NULL plan");
     if (!u_dev || !ms || reps < 1) return fail(SFAC_EINVAL, "NULL state or output, or reps < 1");
-    if (p->exact) return fail(SFAC_EUNSUPPORTED, "a plan of the exact exponential has no per-axis passes to time");
     const size_t es = p->in.dt == SFAC_FP64 ? 8 : 4;
     if (reinterpret_cast<uintptr_t>(u_dev) % es) return fail(SFAC_EINVAL, "state pointer not aligned to %zu bytes", es);
     const int d = p->in.dims;
@@ -744,6 +746,12 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
     void* keep = p->graph_u;
     p->set_u(u_dev);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        if (p->exact) {   // whole steps, each axis' dense product bracketed by its event pair
+            sfac::PassDesc<double> quiet = p->d64[d - 1];
+            quiet.trace_part = nullptr;
+            e = p->exact_step(p->stream, quiet, &ev[2 * (size_t)r * d]);
+            continue;
+        }
         for (int a = 0; a < d && e == hipSuccess; ++a) {
             const size_t i = 2 * ((size_t)r * d + a);
             e = hipEventRecord(ev[i], p->stream);

@@ -117,13 +117,17 @@ def stats_markdown(stats_csv, top=8):
     return "\n".join(out)
 
 
-def _pass_counters(pmc_csv, counter, dims):
-    """Mean counter value (KiB) per axis over the pass-kernel dispatches of one --pmc run."""
+EXACT_KERNEL_TAGS = ("exact_gemm",)
+
+
+def _pass_counters(pmc_csv, counter, dims, tags=PASS_KERNEL_TAGS):
+    """Mean counter value (KiB) per axis over the dispatches of the kernels named by `tags`
+    (the axis passes by default) in one --pmc run; the axis is the place in the d-periodic order."""
     rows = [r for r in _rows(pmc_csv) if r["Counter_Name"] == counter]
     per_dispatch = {}
     names = {}
     for r in rows:
-        if not any(t in r["Kernel_Name"] for t in PASS_KERNEL_TAGS):
+        if not any(t in r["Kernel_Name"] for t in tags):
             continue
         d = int(r["Dispatch_Id"])
         per_dispatch[d] = per_dispatch.get(d, 0.0) + float(r["Counter_Value"])
@@ -144,7 +148,7 @@ def _copy_counter(pmc_csv, counter):
     """Mean counter value (KiB) over the copy kernel's dispatches of a --copy-probe run."""
     vals = {}
     for r in _rows(pmc_csv):
-        if r["Counter_Name"] != counter or any(t in r["Kernel_Name"] for t in PASS_KERNEL_TAGS):
+        if r["Counter_Name"] != counter or any(t in r["Kernel_Name"] for t in PASS_KERNEL_TAGS + EXACT_KERNEL_TAGS):
             continue
         d = int(r["Dispatch_Id"])
         vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
@@ -153,10 +157,11 @@ def _copy_counter(pmc_csv, counter):
     return sum(big) / len(big)
 
 
-def traffic_from_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, dims):
-    """Calibrated HBM bytes per pass launch: counter KiB x 1024 x (copy bytes / copy counter bytes)."""
-    f, nf, kf = _pass_counters(fetch_csv, "FETCH_SIZE", dims)
-    w, nw, _ = _pass_counters(write_csv, "WRITE_SIZE", dims)
+def traffic_from_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, dims, tags=PASS_KERNEL_TAGS):
+    """Calibrated HBM bytes per launch of the pass kernels (or the kernels named by `tags`):
+    counter KiB x 1024 x (copy bytes / copy counter bytes)."""
+    f, nf, kf = _pass_counters(fetch_csv, "FETCH_SIZE", dims, tags)
+    w, nw, _ = _pass_counters(write_csv, "WRITE_SIZE", dims, tags)
     cf = _copy_counter(copy_fetch_csv, "FETCH_SIZE") * 1024.0
     cw = _copy_counter(copy_write_csv, "WRITE_SIZE") * 1024.0
     scale_f = copy_bytes / cf
@@ -259,8 +264,8 @@ def load_traffic(path, workload, dtype, schedule=None):
 COMMANDS = """\
 python3 -m paper_2209_08437_amd.autotune --fresh --out $R/paper_2209_08437_amd/tuned_mi355x.json large_2d_1023 large_3d_255 plain_2d_63 batched_2d   # the packaged schedule table, tuned on an MI355X beforehand; every run below uses it
 rocprofv3 --kernel-trace --stats --output-format csv -d $O/trace_$W -o run -- python3 $R/bench.py --workload $W --no-cpu
-rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-exact --steps 20 --warmup 2 --pass-reps 2
-rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-exact --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --steps 20 --warmup 2 --pass-reps 2
 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/copy_FETCH_SIZE -o run -- python3 $R/bench.py --copy-probe
 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/copy_WRITE_SIZE -o run -- python3 $R/bench.py --copy-probe"""
 
@@ -352,6 +357,30 @@ def _main():
                          f"{r['bytes']} | {alg} | {r['bytes'] / alg:.3f} |")
         rec_all[f"{w}:{dt}"] = {"source_hash": source_hash(), "profile": os.path.basename(a.out),
                                 "algorithmic_bytes": alg, "schedule": scheds.get(dt), **t}
+    ex_t = None
+    try:
+        ex_t = traffic_from_pmc(os.path.join(d, f"FETCH_SIZE_{w}_f64", "run_counter_collection.csv"),
+                                os.path.join(d, f"WRITE_SIZE_{w}_f64", "run_counter_collection.csv"),
+                                os.path.join(d, "copy_FETCH_SIZE", "run_counter_collection.csv"),
+                                os.path.join(d, "copy_WRITE_SIZE", "run_counter_collection.csv"), 512 << 20, a.dims,
+                                tags=EXACT_KERNEL_TAGS)
+    except (TypeError, ZeroDivisionError, OSError):
+        ex_t = None
+    if ex_t and all(r["dispatches"] for r in ex_t["per_axis"]):
+        grid = bench["config"]["grid"]
+        pts = 1
+        for n in grid:
+            pts *= n
+        lines += ["", "One-level scheme's dense products (`exact_gemm`, FP64; algorithmic bytes: read the state and "
+                  "e^{tau B}, write the product):", "",
+                  "| axis | FETCH KiB | WRITE KiB | calibrated bytes | algorithmic bytes | ratio |", "|---|---|---|---|---|---|"]
+        for r in ex_t["per_axis"]:
+            alg = 8 * (2 * pts + grid[r["axis"] - 1] ** 2)
+            r["algorithmic_bytes"] = alg
+            lines.append(f"| {r['axis']} | {r['fetch_kib_raw']} | {r['write_kib_raw']} | {r['bytes']} | {alg} | "
+                         f"{r['bytes'] / alg:.3f} |")
+        rec_all[f"{w}:exact"] = {"source_hash": source_hash(), "profile": os.path.basename(a.out),
+                                 "schedule": None, **ex_t}
     lines += ["", f"Copy calibration: FETCH_SIZE read {t['copy_fetch_kib_raw']} KiB and WRITE_SIZE "
               f"{t['copy_write_kib_raw']} KiB per 512 MiB copy (scales {t['fetch_scale']:.4f}, "
               f"{t['write_scale']:.4f}).", f"Device-code source hash: `{source_hash()}`.", ""]

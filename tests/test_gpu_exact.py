@@ -228,17 +228,28 @@ def test_exact_trace_and_energy(sfac_lib):
     assert abs(energy - e_ref) <= 1e-11 * abs(e_ref)
 
 
-def test_exact_plan_rejects_pass_timing_and_groups(sfac_lib):
+def test_exact_plan_product_timing_and_groups(sfac_lib):
+    """sfac_plan_time_passes on an exact plan times each axis' dense product and advances the
+    state exactly as sfac_step does; groups refuse exact plans."""
     import torch
     from paper_2209_08437_amd import sfac
-    ns = (31, 31)
-    u = torch.zeros(ns, dtype=torch.float64, device="cuda")
+    ns = (31, 47, 9)
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=5)
+    args = (ns, (1.5, 1.3, 1.8), 0.1, 0.01, hs, "f64")
+    a = torch.tensor(u0, device="cuda")
+    b = torch.tensor(u0, device="cuda")
     g = sfac.Group()
     try:
-        with sfac.Plan(ns, (1.5, 1.5), 0.1, 0.01, W.mesh_widths(ns), "f64", method="exact") as p:
+        with sfac.Plan(*args, method="exact") as p:
+            p.trace(10)
+            ms = p.time_passes(a, 4)
+            assert len(ms) == 3 and all(t > 0 for t in ms)
+            assert p.read_trace()[1] == 0          # timing is not part of the per-step record
+            p.step(b, 4)
             with pytest.raises(sfac.SfacError, match="exact exponential"):
-                p.time_passes(u, 2)
-            with pytest.raises(sfac.SfacError, match="exact exponential"):
-                g.step([p], [u], [1])
+                g.step([p], [b], [1])
     finally:
         g.close()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
