@@ -862,38 +862,54 @@ namespace {
 // possible (an operand shared by every batch index costs nothing: it stays in the L2 across the
 // batch); inside a rectangle the shorter side runs fastest, so workgroups dispatched one after
 // another share the band of the longer side while they read it. Slots beyond the grid exit.
-constexpr int kGemmTile = 32, kGemmK = 32, kGemmThreads = 256, kXcds = 8;
+// A batch of at least 8 products sharing X (rm == 0) is dealt by whole products instead:
+// product b on XCD b mod 8, its tiles one after another, so each Y slab is read by one L2.
+constexpr int kGemmThreads = 256, kXcds = 8;
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+// W x W matrix-core tiles of 16 x 16 per wavefront: the block tile is 32 W x 32 W, K advances in
+// slabs of BK.
+template <int W, int BK>
 __global__ void __launch_bounds__(kGemmThreads) exact_gemm(const double* __restrict__ X, const double* __restrict__ Y,
                                                            double* __restrict__ C, int M, int N, int K, long long ldx,
                                                            long long ldy, long long ldc, long long sx, long long sy,
                                                            long long sc, int tiles_m, int tiles_n, int gx, int rm,
-                                                           int rn) {
-    __shared__ double xs[2][kGemmK][kGemmTile + 1];   // xs[k][m]
-    __shared__ double ys[2][kGemmK][kGemmTile + 1];   // ys[k][n]
+                                                           int rn, int batch) {
+    constexpr int kTile = 32 * W;
+    __shared__ double xs[2][BK][kTile + 1];   // xs[k][m]
+    __shared__ double ys[2][BK][kTile + 1];   // ys[k][n]
     const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
-    const bool n_fast = rn <= rm;
-    const int tm = (xcd / gx) * rm + (n_fast ? slot / rn : slot % rm);
-    const int tn = (xcd % gx) * rn + (n_fast ? slot % rn : slot / rm);
-    if (tm >= tiles_m || tn >= tiles_n) return;   // the whole block, before any barrier
-    const long long b = blockIdx.y;
+    int tm, tn;
+    long long b;
+    if (rm == 0) {   // whole products per XCD
+        const int per = tiles_m * tiles_n;
+        b = (long long)(slot / per) * kXcds + xcd;
+        tm = (slot % per) % tiles_m;
+        tn = (slot % per) / tiles_m;
+        if (b >= batch) return;   // the whole block, before any barrier
+    } else {
+        const bool n_fast = rn <= rm;
+        tm = (xcd / gx) * rm + (n_fast ? slot / rn : slot % rm);
+        tn = (xcd % gx) * rn + (n_fast ? slot % rn : slot / rm);
+        b = blockIdx.y;
+        if (tm >= tiles_m || tn >= tiles_n) return;   // the whole block, before any barrier
+    }
     X += b * sx;
     Y += b * sy;
     C += b * sc;
-    const int m0 = tm * kGemmTile, n0 = tn * kGemmTile;
+    const int m0 = tm * kTile, n0 = tn * kTile;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;
-    constexpr int kPer = kGemmTile * kGemmK / kGemmThreads;   // elements of each slab per thread
+    const int wm = (wave >> 1) * 16 * W, wn = (wave & 1) * 16 * W;
+    constexpr int kPer = kTile * BK / kGemmThreads;   // elements of each slab per thread
     double xr[kPer], yr[kPer];
     auto load = [&](int k0) {
 #pragma unroll
         for (int r = 0; r < kPer; ++r) {
             const int idx = t + r * kGemmThreads;
-            const int mm = idx / kGemmK, kk = idx % kGemmK;    // consecutive threads along a row of X
+            const int mm = idx / BK, kk = idx % BK;          // consecutive threads along a row of X
             const int gm = m0 + mm, gk = k0 + kk;
             xr[r] = (gm < M && gk < K) ? X[(long long)gm * ldx + gk] : 0.0;
-            const int kk2 = idx / kGemmTile, nn = idx % kGemmTile;   // along a row of Y
+            const int kk2 = idx / kTile, nn = idx % kTile;   // along a row of Y
             const int gk2 = k0 + kk2, gn = n0 + nn;
             yr[r] = (gk2 < K && gn < N) ? Y[(long long)gk2 * ldy + gn] : 0.0;
         }
@@ -902,33 +918,48 @@ __global__ void __launch_bounds__(kGemmThreads) exact_gemm(const double* __restr
 #pragma unroll
         for (int r = 0; r < kPer; ++r) {
             const int idx = t + r * kGemmThreads;
-            xs[buf][idx % kGemmK][idx / kGemmK] = xr[r];
-            ys[buf][idx / kGemmTile][idx % kGemmTile] = yr[r];
+            xs[buf][idx % BK][idx / BK] = xr[r];
+            ys[buf][idx / kTile][idx % kTile] = yr[r];
         }
     };
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    double4_t acc[W][W];
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
     load(0);
     stash(0);
     __syncthreads();
     int buf = 0;
-    for (int k0 = 0; k0 < K; k0 += kGemmK) {
-        const bool more = k0 + kGemmK < K;
-        if (more) load(k0 + kGemmK);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        const bool more = k0 + BK < K;
+        if (more) load(k0 + BK);
 #pragma unroll
-        for (int k4 = 0; k4 < kGemmK; k4 += 4) {
-            const double a = xs[buf][k4 + (lane >> 4)][wm + (lane & 15)];
-            const double bb = ys[buf][k4 + (lane >> 4)][wn + (lane & 15)];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        for (int k4 = 0; k4 < BK; k4 += 4) {
+            double a[W], bb[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) a[i] = xs[buf][k4 + (lane >> 4)][wm + 16 * i + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < W; ++j) bb[j] = ys[buf][k4 + (lane >> 4)][wn + 16 * j + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+#pragma unroll
+                for (int j = 0; j < W; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
         }
         if (more) stash(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
-    const int gn = n0 + wn + (lane & 15);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int gm = m0 + wm + 4 * i + (lane >> 4);
-        if (gm < M && gn < N) C[(long long)gm * ldc + gn] = acc[i];
+    for (int j = 0; j < W; ++j) {
+        const int gn = n0 + wn + 16 * j + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + 16 * i + 4 * r + (lane >> 4);
+                if (gm < M && gn < N) C[(long long)gm * ldc + gn] = acc[i][j][r];
+            }
     }
 }
 
@@ -954,7 +985,12 @@ hipError_t launch_exact_gemm(const double* X, const double* Y, double* C, int M,
                              long long ldy, long long ldc, long long sx, long long sy, long long sc, int batch,
                              hipStream_t stream) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-    const int tiles_m = (M + kGemmTile - 1) / kGemmTile, tiles_n = (N + kGemmTile - 1) / kGemmTile;
+    // 64 x 64 block tiles (2 x 2 matrix-core tiles per wavefront, half the LDS reads per product)
+    // where they still give every SIMD several wavefronts (at least 8 blocks per CU); 32 x 32
+    // otherwise (on 1023^2 the 64 x 64 tiles leave one wavefront per SIMD and are slower)
+    const long long big = (long long)((M + 63) / 64) * ((N + 63) / 64) * batch;
+    const int tile = big >= 8LL * 256 ? 64 : 32;
+    const int tiles_m = (M + tile - 1) / tile, tiles_n = (N + tile - 1) / tile;
     const bool x_shared = sx == 0 && batch > 1, y_shared = sy == 0 && batch > 1;
     int gx = 1, rm = 0, rn = 0, best = 0;
     for (int g = 1; g <= kXcds; g *= 2) {   // gx column groups, kXcds / gx row groups
@@ -968,9 +1004,17 @@ hipError_t launch_exact_gemm(const double* X, const double* Y, double* C, int M,
         }
     }
     // grid.x a multiple of 8: workgroup (x, b) runs on XCD x mod 8 for every batch index b
-    const dim3 grid((unsigned)kXcds * rm * rn, batch, 1);
-    hipLaunchKernelGGL(exact_gemm, grid, dim3(kGemmThreads), 0, stream, X, Y, C, M, N, K, ldx, ldy, ldc, sx, sy, sc,
-                       tiles_m, tiles_n, gx, rm, rn);
+    dim3 grid((unsigned)kXcds * rm * rn, batch, 1);
+    if (x_shared && batch >= kXcds) {   // whole products per XCD (rm = 0 selects it)
+        grid = dim3((unsigned)kXcds * tiles_m * tiles_n * ((batch + kXcds - 1) / kXcds), 1, 1);
+        rm = rn = 0;
+    }
+    if (tile == 64)
+        hipLaunchKernelGGL((exact_gemm<2, 16>), grid, dim3(kGemmThreads), 0, stream, X, Y, C, M, N, K, ldx, ldy, ldc,
+                           sx, sy, sc, tiles_m, tiles_n, gx, rm, rn, batch);
+    else
+        hipLaunchKernelGGL((exact_gemm<1, 32>), grid, dim3(kGemmThreads), 0, stream, X, Y, C, M, N, K, ldx, ldy, ldc,
+                           sx, sy, sc, tiles_m, tiles_n, gx, rm, rn, batch);
     return hipGetLastError();
 }
 
