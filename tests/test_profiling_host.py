@@ -143,3 +143,30 @@ def test_exact_axis_means(tmp_path):
     assert a1["mean_us"] == pytest.approx(3.0) and a2["mean_us"] == pytest.approx(5.0)
     assert a1["tflops"] == pytest.approx(2 * 100 * 5000 / 3e-6 / 1e12)
     assert a2["tflops"] == pytest.approx(2 * 50 * 5000 / 5e-6 / 1e12)
+
+
+def test_exact_traffic_attribution(tmp_path):
+    # a 2D run with both the pass kernels and the one-level products: each kind is attributed on
+    # its own, and neither counts as the copy probe
+    gemm = "void sfac::(anonymous namespace)::exact_gemm<1, 32>(double const*, double const*, double*)"
+    fetch = [(1, PASS, "FETCH_SIZE", 100.0), (2, PASS, "FETCH_SIZE", 200.0),
+             (3, gemm, "FETCH_SIZE", 50.0), (3, gemm, "FETCH_SIZE", 50.0), (4, gemm, "FETCH_SIZE", 300.0),
+             (5, gemm, "FETCH_SIZE", 110.0), (6, gemm, "FETCH_SIZE", 290.0)]
+    write = [(1, PASS, "WRITE_SIZE", 10.0), (2, PASS, "WRITE_SIZE", 20.0),
+             (3, gemm, "WRITE_SIZE", 30.0), (4, gemm, "WRITE_SIZE", 40.0),
+             (5, gemm, "WRITE_SIZE", 30.0), (6, gemm, "WRITE_SIZE", 40.0)]
+    copy_bytes = 1 << 20
+    cf = [(i, COPY, "FETCH_SIZE", copy_bytes / 1024) for i in range(1, 21)] + [(21, gemm, "FETCH_SIZE", 1e9)]
+    cw = [(i, COPY, "WRITE_SIZE", copy_bytes / 1024) for i in range(1, 21)] + [(21, gemm, "WRITE_SIZE", 1e9)]
+    paths = {}
+    for key, rows in (("f", fetch), ("w", write), ("cf", cf), ("cw", cw)):
+        paths[key] = str(tmp_path / f"{key}.csv")
+        _write_pmc(paths[key], rows)
+    ex = P.traffic_from_pmc(paths["f"], paths["w"], paths["cf"], paths["cw"], copy_bytes, 2, tags=P.EXACT_KERNEL_TAGS)
+    assert ex["fetch_scale"] == pytest.approx(1.0) and ex["write_scale"] == pytest.approx(1.0)
+    a1, a2 = ex["per_axis"]
+    assert a1["fetch_kib_raw"] == 105.0 and a2["fetch_kib_raw"] == 295.0
+    assert a1["write_kib_raw"] == 30.0 and a2["write_kib_raw"] == 40.0
+    assert a1["kernel"] == "exact_gemm<1, 32>"
+    ps = P.traffic_from_pmc(paths["f"], paths["w"], paths["cf"], paths["cw"], copy_bytes, 2)
+    assert [r["fetch_kib_raw"] for r in ps["per_axis"]] == [100.0, 200.0]
