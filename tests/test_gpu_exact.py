@@ -85,6 +85,18 @@ def test_exact_parity_full_size(sfac_lib, which, steps):
     assert rel <= FP64_TOL and flags == 0
 
 
+def test_exact_maximum_length(sfac_lib):
+    """N = 1024, the longest axis an exact plan takes, on both the contiguous and the strided
+    axis (1024 x 3 and 3 x 1024), against the oracle."""
+    for ns in ((1024, 3), (3, 1024)):
+        hs = W.mesh_widths(ns)
+        u0 = W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=sum(ns))
+        ref = O.strang_solve(u0, ns, (1.9, 1.2), 0.1, hs, 0.01, 5)
+        got, flags, _ = _run(u0, ns, (1.9, 1.2), 0.1, hs, 0.01, 5)
+        _say(f"case exact maximum length {ns}: {np.abs(got - ref).max() / np.abs(ref).max():.2e}")
+        assert flags == 0 and np.abs(got - ref).max() <= FP64_TOL * np.abs(ref).max()
+
+
 def test_exact_eps0_is_the_nonlinear_flow(sfac_lib):
     """eps = 0: B = 0, e^{tau B} = I, and a step is the closed-form ODE flow over tau."""
     ns = (65, 40)
