@@ -170,6 +170,30 @@ def diagnostics(plan, u0, u, k):
         return {"unavailable": str(err)}
 
 
+def pass_roofline(inst, dtype, r, workload_name):
+    """Roofline of the axis pass with the longest mean duration of one gpu_rate result: the
+    conventional flop count over the duration against the dtype's vector peak, the HBM rate of
+    its algorithmic bytes, and the counter-measured traffic when the committed record matches."""
+    from paper_2209_08437_amd import profiling
+    esize = 8 if dtype == "f64" else 4
+    pass_ms = r["pass_ms"]
+    a = max(range(len(pass_ms)), key=lambda i: pass_ms[i])
+    fl = pass_flops(inst, a)
+    tf = fl / (pass_ms[a] * 1e-3) / 1e12
+    peak = VALU_PEAK_TFLOPS[dtype]
+    byt = 2 * inst.points * esize
+    gbps = byt / (pass_ms[a] * 1e-3) / 1e9
+    rec = profiling.load_traffic(TRAFFIC_RECORD, workload_name, dtype, r["schedule"] or None)
+    meth, length = r["methods"][a]
+    return {"bound": "alu", "achieved": round(tf, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+            "traffic": rec["per_axis"][a]["bytes"] if rec else None,
+            "kernel": f"{meth} axis pass ({'double' if esize == 8 else 'float'}, transform length {length}), "
+                      f"axis {a + 1}",
+            "flops_per_launch": round(fl),
+            "hbm": {"achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4),
+                    "bytes_per_launch": byt}}
+
+
 def one_level_exact(inst, steps, two_level_state, two_level_ms, workload_name, pass_reps):
     """The one-level scheme (eq. (strang)) with e^{tau B} per axis as a dense FP64 product on the
     GPU (SFAC_METHOD_EXACT) over the bench's steps: plan creation (host eigendecomposition),
@@ -450,7 +474,8 @@ def main():
                        "rel_err_vs_fp64_gpu": float(np.abs(r32["state"] - ref).max() / np.abs(ref).max()),
                        "max_abs": r32["max_abs"], "flags": r32["flags"],
                        "pass_ms": [round(x, 5) for x in r32["pass_ms"]], "schedule": r32["schedule"],
-                       "plan_create_ms": round(r32["plan_create_ms"], 3)}
+                       "plan_create_ms": round(r32["plan_create_ms"], 3),
+                       "roofline": pass_roofline(inst, "f32", r32, args.workload)}
     out["max_abs"] = main_r["max_abs"]
     out["flags"] = main_r["flags"]
     out["diagnostics"] = main_r["diagnostics"]
