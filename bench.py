@@ -119,6 +119,18 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None):
     # per-pass kernel durations: HIP events on the plan's stream around each launch give the
     # passes' shares; an event pair per launch adds a few microseconds to each, so the timed
     # region's step time (graph replays, events only at its ends) is split by those shares
+    # the same timed region repeated (state reset from u0 outside each), for the spread
+    reps = []
+    for _ in range(5):
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.step(u, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1) / steps)
     uu = u0.clone()
     pass_ev = plan.time_passes(uu, pass_reps)
     torch.cuda.synchronize()
@@ -128,7 +140,7 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None):
     result = {
         "wall_s": wall, "gpu_ms": gpu_ms, "flags": flags, "max_abs": vmax,
         "pass_ms": pass_ms, "pass_ms_events": pass_ev, "methods": methods, "state": u.double().cpu().numpy(), "schedule": sched,
-        "plan_create_ms": plan_ms, "warmup_ms": warm_ms, "diagnostics": diag,
+        "plan_create_ms": plan_ms, "warmup_ms": warm_ms, "diagnostics": diag, "repeat_ms_per_step": reps,
     }
     plan.close()
     return result
@@ -476,6 +488,11 @@ def main():
                        "pass_ms": [round(x, 5) for x in r32["pass_ms"]], "schedule": r32["schedule"],
                        "plan_create_ms": round(r32["plan_create_ms"], 3),
                        "roofline": pass_roofline(inst, "f32", r32, args.workload)}
+    import statistics
+    rp = main_r["repeat_ms_per_step"]
+    out["repeats"] = {"n": len(rp), "median_ms_per_step": round(statistics.median(rp), 5),
+                      "min_ms_per_step": round(min(rp), 5), "max_ms_per_step": round(max(rp), 5),
+                      "note": "the timed region repeated after it (HIP events, state reset outside); value is the first"}
     out["max_abs"] = main_r["max_abs"]
     out["flags"] = main_r["flags"]
     out["diagnostics"] = main_r["diagnostics"]
