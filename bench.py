@@ -379,11 +379,28 @@ def cpu_baseline(inst, seconds):
         u = O.two_level_step(u, ops, inst.tau)
     dt = time.perf_counter() - t0
     pts = inst.points
-    return {
+    out = {
         "value": pts * k / dt, "unit": "grid-point-steps/s", "cores": int(threads), "kind": "oracle",
         "sample": f"{k} steps of the same {'x'.join(map(str, inst.ns))} workload after 1 untimed step "
                   f"(dense per-axis exponentials, numpy/OpenBLAS FP64); table set-up {setup:.2f} s not included",
     }
+    # the same oracle on one thread, over a fifth of the budget
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            u = O.two_level_step(u, ops, inst.tau)
+            one1 = time.perf_counter() - t0
+            k1 = max(1, min(inst.steps - 1, int(seconds / 5 / max(one1, 1e-6))))
+            t0 = time.perf_counter()
+            for _ in range(k1):
+                u = O.two_level_step(u, ops, inst.tau)
+            dt1 = time.perf_counter() - t0
+        out["single_thread"] = {"value": pts * k1 / dt1, "unit": "grid-point-steps/s", "cores": 1,
+                                "sample": f"{k1} steps after 1 untimed step"}
+    except ImportError:
+        pass
+    return out
 
 
 def main():
