@@ -292,7 +292,7 @@ typedef struct {
  * opts is NULL (automatic schedules) or `count` per-instance options (the kernel schedules an
  * autotuner picked; use_graph and graph_chunk are ignored). Every instance is validated as by
  * sfac_plan_create; the first invalid one fails the call with its index in the message.
- * Errors as sfac_plan_create.
+ * Errors as sfac_plan_create; SFAC_EUNSUPPORTED for SFAC_METHOD_EXACT (single plans only).
  */
 sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instance_desc* desc,
                               sfac_dtype dt, void* hip_stream, const sfac_options* opts);
