@@ -45,6 +45,27 @@ int main(void) {
     int32_t prime[2] = {127, 8};
     CHECK(sfac_plan_create(&p, 2, prime, alpha, 0.1, 0.01, h, SFAC_FP64, NULL, &opt) == SFAC_EUNSUPPORTED);
 
+    /* the exact exponential of one axis (host only): symmetric, entries in (-1, 1], rows of a
+     * contraction (B is negative definite); the exact method asks for every axis and FP64 */
+    static double P[31 * 31];
+    CHECK(sfac_exact_exponential(31, 1.7, 0.1, 0.05, 2.0 / 32, P) == SFAC_OK);
+    for (int i = 0; i < 31; ++i) {
+        double row = 0.0;
+        for (int j = 0; j < 31; ++j) {
+            CHECK(P[i * 31 + j] == P[j * 31 + i]);
+            row += fabs(P[i * 31 + j]);
+        }
+        CHECK(P[i * 31 + i] > 0.0 && P[i * 31 + i] <= 1.0);
+        CHECK(row > 0.0 && row <= sqrt(31.0));
+    }
+    CHECK(sfac_exact_exponential(1025, 1.5, 0.1, 0.01, 2.0 / 1026, P) == SFAC_EUNSUPPORTED);
+    CHECK(sfac_exact_exponential(31, 1.5, 0.1, 0.01, 2.0 / 32, NULL) == SFAC_EINVAL);
+    memset(&opt, 0, sizeof opt);
+    opt.method[0] = SFAC_METHOD_EXACT;
+    CHECK(sfac_plan_create(&p, 2, n, alpha, 0.1, 0.01, h, SFAC_FP64, NULL, &opt) == SFAC_EINVAL);
+    opt.method[1] = SFAC_METHOD_EXACT;
+    CHECK(sfac_plan_create(&p, 2, n, alpha, 0.1, 0.01, h, SFAC_FP32, NULL, &opt) == SFAC_EUNSUPPORTED);
+
     /* NULL handles */
     CHECK(sfac_step(NULL, NULL, 1) == SFAC_EINVAL);
     CHECK(sfac_plan_destroy(NULL) == SFAC_OK);
