@@ -11,6 +11,8 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <system_error>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -575,14 +577,42 @@ static sfac_status exact_plan_create(sfac_plan p, int32_t dims, const int32_t* n
     in.eps = eps;
     in.tau = tau;
     in.dt = dt;
+    // e^{tau B} per axis: an axis with the same (N, alpha, h) as an earlier one reuses its matrix;
+    // the others are built on threads of their own (each an O(N^3) eigendecomposition)
     std::vector<std::vector<double>> P(dims);
+    std::vector<std::string> errs(dims);
+    int same[3] = {-1, -1, -1};
+    for (int a = 0; a < dims; ++a)
+        for (int b = 0; b < a && same[a] < 0; ++b)
+            if (same[b] < 0 && n[b] == n[a] && alpha[b] == alpha[a] && h[b] == h[a]) same[a] = b;
+    auto build = [&](int a) {
+        try {
+            errs[a] = sfac::build_exact_exponential(sfac::AxisParams{n[a], alpha[a], eps, tau, h[a]}, &P[a]);
+        } catch (const std::bad_alloc&) {
+            errs[a] = "host allocation failed";
+        }
+    };
+    std::vector<std::thread> workers;
+    for (int a = 1; a < dims; ++a) {
+        if (same[a] >= 0) continue;
+        try {
+            workers.emplace_back(build, a);
+        } catch (const std::system_error&) {
+            build(a);   // no thread to be had: build it here
+        }
+    }
+    build(0);
+    for (auto& w : workers) w.join();
     size_t off = 0;
     for (int a = 0; a < dims; ++a) {
         in.n[a] = n[a];
         in.alpha[a] = alpha[a];
         in.h[a] = h[a];
-        const std::string err = sfac::build_exact_exponential(sfac::AxisParams{n[a], alpha[a], eps, tau, h[a]}, &P[a]);
-        if (!err.empty()) return fail(SFAC_EUNSUPPORTED, "axis %d: %s", a + 1, err.c_str());
+        if (same[a] >= 0) {
+            p->off_P[a] = p->off_P[same[a]];
+            continue;
+        }
+        if (!errs[a].empty()) return fail(SFAC_EUNSUPPORTED, "axis %d: %s", a + 1, errs[a].c_str());
         p->off_P[a] = off;
         off = align_up(off + sizeof(double) * P[a].size(), 256);
     }
@@ -594,7 +624,8 @@ static sfac_status exact_plan_create(sfac_plan p, int32_t dims, const int32_t* n
     p->use_graph = opt->use_graph ? 1 : 0;
     if (opt->graph_chunk > 0) p->chunk = opt->graph_chunk;
     std::vector<unsigned char> host(off, 0);
-    for (int a = 0; a < dims; ++a) memcpy(host.data() + p->off_P[a], P[a].data(), sizeof(double) * P[a].size());
+    for (int a = 0; a < dims; ++a)
+        if (same[a] < 0) memcpy(host.data() + p->off_P[a], P[a].data(), sizeof(double) * P[a].size());
     hipError_t e = hipMalloc(&p->dev, p->dev_bytes);
     if (e != hipSuccess) {
         p->dev = nullptr;

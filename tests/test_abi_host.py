@@ -253,3 +253,19 @@ def test_exact_exponential_matches_pade(sfac_lib, n, alpha, eps, tau):
     assert lam.min() > -1e-13 and lam.max() < 1.0
     if n == 1:   # B is a scalar: e^{tau B} is its exponential
         assert P[0, 0] == pytest.approx(np.exp(tau * B[0, 0]), rel=1e-15)
+
+
+def test_exact_plan_tables_built_on_threads(sfac_lib):
+    """An exact plan builds its per-axis exponentials (on threads, an axis equal to an earlier one
+    reusing its matrix) before any device call; without a device the call then fails at the
+    device allocation, with no handle. Run under a sanitizer build, this is the path that
+    exercises the threads."""
+    opt = sfac.Options()
+    for a in range(3):
+        opt.method[a] = sfac.METHOD_EXACT
+    st, h, msg = _create(3, [40, 33, 40], [1.5, 1.7, 1.5], 0.1, 0.01, [0.05, 0.06, 0.05], opt=opt)
+    if st == sfac.OK:                      # a device is present: the plan is real
+        assert sfac.lib().sfac_plan_destroy(h) == sfac.OK
+        return
+    assert st in (sfac.EDEVICE, sfac.ENOMEM) and not h.value, msg
+    assert "hipMalloc" in msg
