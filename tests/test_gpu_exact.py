@@ -265,3 +265,27 @@ def test_exact_plan_product_timing_and_groups(sfac_lib):
         g.close()
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_exact_flags_report_nonfinite_and_above_one(sfac_lib):
+    """The closing half-step of the exact scheme keeps the sticky status as the two-level passes
+    do: a NaN in the state and |u| above 1 (|u0| > 1 leaves Theorem 1's premise) are reported."""
+    import torch
+    from paper_2209_08437_amd import sfac
+    ns = (16, 20, 3)
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=1)
+    with sfac.Plan(ns, (1.5, 1.5, 1.2), 0.1, 0.01, hs, "f64", method="exact") as p:
+        u = torch.tensor(u0, device="cuda")
+        p.step(u, 3)
+        f, m = p.flags()
+        assert f == 0 and 0 < m <= 1
+        u[1, 3, 4] = float("nan")
+        p.step(u, 1)
+        f, _ = p.flags()
+        assert f & sfac.FLAG_NONFINITE
+        p.reset_flags()
+        u = torch.tensor(u0 * 1.5, device="cuda")
+        p.step(u, 1)
+        f, m = p.flags()
+        assert f & sfac.FLAG_ABOVE_ONE and m > 1
