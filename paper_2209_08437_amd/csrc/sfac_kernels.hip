@@ -987,7 +987,8 @@ hipError_t launch_exact_gemm(const double* X, const double* Y, double* C, int M,
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     // 64 x 64 block tiles (2 x 2 matrix-core tiles per wavefront, half the LDS reads per product)
     // where they still give every SIMD several wavefronts (at least 8 blocks per CU); 32 x 32
-    // otherwise (on 1023^2 the 64 x 64 tiles leave one wavefront per SIMD and are slower)
+    // otherwise (on 1023^2 the 64 x 64 tiles leave one wavefront per SIMD, and 32 x 64 tiles
+    // two, and both are slower)
     const long long big = (long long)((M + 63) / 64) * ((N + 63) / 64) * batch;
     const int tile = big >= 8LL * 256 ? 64 : 32;
     const int tiles_m = (M + tile - 1) / tile, tiles_n = (N + tile - 1) / tile;
