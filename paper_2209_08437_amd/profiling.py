@@ -6,7 +6,9 @@
 * `sq_markdown()` summarises shader-sequencer counter runs (VALU and LDS work, waits, occupancy).
 * `traffic_from_pmc()` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of a workload and
   the same two counters read on a plain copy kernel of known size into calibrated HBM bytes
-  per launch of each axis-pass kernel.
+  per launch of each axis-pass kernel (or of the one-level scheme's dense products).
+* `exact_axis_means()` and `mfma_markdown()` summarise the dense products' trace and their
+  matrix-core counters.
 
 The axis of a pass-kernel dispatch is recovered from the dispatch order: every step launches
 the passes of axes 1..d in order, and the profiled command launches nothing else with the
@@ -190,12 +192,13 @@ SQ_COMMAND = ("timeout -s KILL 90 rocprofv3 --pmc $COUNTERS --output-format csv 
 VALU_WAVE_INSTR_PER_US = 256 * 4 / 4 * 2400.0
 
 
-def sq_axis_means(csv_path, dims):
-    """Mean value per axis of every counter in one --pmc run, over the pass-kernel dispatches
-    (a dispatch's rows are summed), with the kernel name of each axis."""
+def sq_axis_means(csv_path, dims, tags=PASS_KERNEL_TAGS):
+    """Mean value per axis of every counter in one --pmc run, over the dispatches of the kernels
+    named by `tags` (the pass kernels by default; a dispatch's rows are summed), with the kernel
+    name of each axis."""
     per, names = {}, {}
     for r in _rows(csv_path):
-        if not any(t in r["Kernel_Name"] for t in PASS_KERNEL_TAGS):
+        if not any(t in r["Kernel_Name"] for t in tags):
             continue
         d = int(r["Dispatch_Id"])
         c = per.setdefault(d, {})
@@ -239,6 +242,54 @@ def sq_markdown(directory, workload, dims):
             f"{c.get('SQ_WAIT_INST_ANY', 0) / wc:.3f} | {c.get('SQ_INSTS_LDS', 0):.3g} | "
             f"{c.get('SQ_LDS_BANK_CONFLICT', 0):.3g} | {c.get('SQ_INSTS_VMEM_RD', 0):.3g} / "
             f"{c.get('SQ_INSTS_VMEM_WR', 0):.3g} |")
+    lines += ["", f"Device-code source hash: `{source_hash()}`.", ""]
+    return "\n".join(lines)
+
+
+# Matrix-core counters of the one-level scheme's dense products (bench.py runs with the exact
+# comparison on)
+MFMA_COUNTERS = ("SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU_MFMA_F64 SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_LDS "
+                 "SQ_LDS_BANK_CONFLICT SQ_INSTS_VMEM_RD")
+MFMA_COMMAND = ("timeout -s KILL 120 rocprofv3 --pmc " + MFMA_COUNTERS + " --output-format csv -d $O/$W -o run -- "
+                "python3 $R/bench.py --workload $W --no-cpu --no-fp32 --steps 10 --warmup 2 --pass-reps 2")
+SIMDS = 1024                      # MI355X: 256 CUs of 4 SIMDs
+CLOCK_MHZ = 2400.0
+
+
+def mfma_markdown(directory, workloads):
+    """Markdown summary of the matrix-core counter runs of the exact-exponential products: per
+    workload and axis, FP64 MFMA instructions per dispatch, cycles per instruction, and the share
+    of every SIMD's time the matrix core is busy over the dispatch's mean duration (taken from
+    the trace of the same counter run)."""
+    lines = ["# Matrix-core counters of the one-level scheme's dense products (`exact_gemm`, FP64)", "",
+             "Commands (run from /tmp on one MI355X; `$R` is the repository root, `$O` the output directory):", "",
+             "```"]
+    lines += [MFMA_COMMAND.replace("$W", w) for w, _ in workloads]
+    lines += ["```", "",
+              "Per axis, means over the product dispatches of a run. The MFMA-busy share is "
+              "SQ_VALU_MFMA_BUSY_CYCLES over (1024 SIMDs x the dispatch's duration in 2.4 GHz cycles); "
+              "the duration is the mean of the same dispatches' timestamps in the counter run, which counter "
+              "collection lengthens (the kernel-trace means in axis_pass_*.md are the plain durations).", "",
+              "| workload | axis | kernel | waves | MFMA F64 instr. | cycles per MFMA | mean us | MFMA-busy share | "
+              "LDS instr. | bank conflicts |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for w, dims in workloads:
+        path = os.path.join(directory, w, "run_counter_collection.csv")
+        means = sq_axis_means(path, dims, tags=EXACT_KERNEL_TAGS)
+        # durations per axis from the rows' timestamps (one value per dispatch)
+        spans = {}
+        for r in _rows(path):
+            if any(t in r["Kernel_Name"] for t in EXACT_KERNEL_TAGS):
+                spans[int(r["Dispatch_Id"])] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        order = sorted(spans)
+        for a, c in enumerate(means):
+            ds = order[a::dims]
+            us = sum(spans[d] for d in ds) / len(ds) / 1e3 if ds else float("nan")
+            n = c.get("SQ_INSTS_VALU_MFMA_F64", 0.0)
+            busy = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+            lines.append(f"| {w} | {a + 1} | `{c['kernel']}` | {c.get('SQ_WAVES', 0):.0f} | {n:.4g} | "
+                         f"{busy / n if n else float('nan'):.1f} | {us:.2f} | "
+                         f"{busy / (SIMDS * us * CLOCK_MHZ):.3f} | {c.get('SQ_INSTS_LDS', 0):.3g} | "
+                         f"{c.get('SQ_LDS_BANK_CONFLICT', 0):.3g} |")
     lines += ["", f"Device-code source hash: `{source_hash()}`.", ""]
     return "\n".join(lines)
 
@@ -294,7 +345,13 @@ def _main():
     ap.add_argument("--out", help="markdown summary to write")
     ap.add_argument("--traffic", help="JSON traffic record to update")
     ap.add_argument("--sq", help="write the SQ counter summary (SQ_SETS runs) to this file instead")
+    ap.add_argument("--mfma", help="write the matrix-core counter summary of the exact products (MFMA_COMMAND runs of "
+                                   "large_2d_1023 and large_3d_255 under --dir) to this file instead")
     a = ap.parse_args()
+    if a.mfma:
+        with open(a.mfma, "w") as f:
+            f.write(mfma_markdown(a.dir, [("large_2d_1023", 2), ("large_3d_255", 3)]))
+        return
     d, w = a.dir, a.workload
     if a.sq:
         with open(a.sq, "w") as f:

@@ -170,3 +170,28 @@ def test_exact_traffic_attribution(tmp_path):
     assert a1["kernel"] == "exact_gemm<1, 32>"
     ps = P.traffic_from_pmc(paths["f"], paths["w"], paths["cf"], paths["cw"], copy_bytes, 2)
     assert [r["fetch_kib_raw"] for r in ps["per_axis"]] == [100.0, 200.0]
+
+
+def test_mfma_markdown(tmp_path):
+    # one 2D run with two product dispatches per axis (rows per XCD summed) and a pass kernel in
+    # between that is not counted; one 3D run absent from the summary's other table is not needed
+    gemm = "void sfac::(anonymous namespace)::exact_gemm<1, 32>(double const*)"
+    fields = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    for d, (t0, t1) in enumerate([(0, 10000), (20000, 30000), (40000, 50000), (60000, 70000)], start=1):
+        rows += [(d, gemm, "SQ_INSTS_VALU_MFMA_F64", 500.0, t0, t1), (d, gemm, "SQ_INSTS_VALU_MFMA_F64", 500.0, t0, t1),
+                 (d, gemm, "SQ_VALU_MFMA_BUSY_CYCLES", 64000.0, t0, t1), (d, gemm, "SQ_WAVES", 64.0, t0, t1)]
+    rows.append((9, PASS, "SQ_INSTS_VALU_MFMA_F64", 1e9, 0, 1))
+    for w in ("large_2d_1023", "large_3d_255"):
+        os.makedirs(tmp_path / w)
+        with open(tmp_path / w / "run_counter_collection.csv", "w", newline="") as f:
+            wr = csv.DictWriter(f, fieldnames=fields)
+            wr.writeheader()
+            for r in rows:
+                wr.writerow(dict(zip(fields, r)))
+    md = P.mfma_markdown(str(tmp_path), [("large_2d_1023", 2)])
+    line = [l for l in md.splitlines() if l.startswith("| large_2d_1023 | 1 |")][0]
+    cells = [c.strip() for c in line.split("|")]
+    assert cells[5] == "1000" and cells[6] == "64.0" and cells[7] == "10.00"
+    # busy share: 64000 / (1024 SIMDs x 10 us x 2400 cycles per us)
+    assert float(cells[8]) == pytest.approx(64000 / (1024 * 10 * 2400), abs=1e-3)
