@@ -253,6 +253,8 @@ class Service:
     def submit(self, inst, dtype="f64"):
         if dtype not in ("f64", "f32"):
             raise ValueError(f"dtype {dtype!r}, expected 'f64' or 'f32'")
+        if int(inst.steps) < 0:
+            raise ValueError(f"steps = {inst.steps}, expected >= 0")
         fut = Future()
         with self._lock:
             if self._closed:

@@ -143,6 +143,10 @@ def test_online_service_futures_from_several_threads():
         f_zero = svc.submit(zero, "f32")
         with pytest.raises(ValueError):
             svc.submit(zero, "bf16")
+        neg = W.Instance((9, 9), (1.5, 1.5), 0.1, 0.01, W.mesh_widths((9, 9)), -1)
+        neg.u0 = zero.u0
+        with pytest.raises(ValueError, match="steps"):
+            svc.submit(neg, "f64")
     with pytest.raises(RuntimeError):
         svc.submit(zero, "f64")
     for r in reqs:
