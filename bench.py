@@ -2,30 +2,33 @@
 
 A bench step is one time step of the solver (J^Q_{tau/2}, e^{tau/2 C} e^{tau S} e^{tau/2 C}
 along every axis, J^Q_{tau/2}) over the whole grid of the workload. The default workload is
-the 2D single large instance (N = 1023 per axis, alpha = (1.3, 1.7), eps = 0.05, tau = 1e-3,
-FP64) and the default K = 1000 timed steps is its full run. The state is resident in HBM before
-the timed region starts; the timed region is one sfac_step call of K steps (HIP graph replays)
-bracketed by device synchronizations.
+the largest single-GPU instance: 3D, N = 255 per axis (16.6 M points), alpha = (1.2, 1.5, 1.8),
+eps = 0.08, tau = 5e-3, FP64, and the default K = 200 timed steps is its full run. The state is
+resident in HBM before the timed region starts; the timed region is one sfac_step call of K
+steps (HIP graph replays: K / 32 replays of a 32-step graph and one replay per set bit of the
+rest) bracketed by device synchronizations.
 
 Each axis pass runs the schedule (method, kernel, elements per thread, lines per block) that
 the autotuner picked on an MI355X for this shape, read from the table that ships with the
 package (`--tune-cache none` tunes afresh on the device at hand).
 
-Besides the headline value the JSON line carries: the FP32 rate of the same workload, the
-roofline of the dominant axis-pass kernel, the CPU oracle timed on a bounded sample, and (FP64,
-N <= 1024 per axis) the one-level scheme with the exact exponential that the paper compares the
-two-level scheme with, run on the GPU over the same steps: its step time, the rate of its dense
-products and how far its final state lies from the two-level one.
+Besides the headline value the JSON line carries: the FP32 rate of the same workload, the 2D
+1023^2 instance (FP64 and FP32) as a sub-object, the roofline of the dominant axis-pass kernel
+of each, the CPU oracle timed on a bounded sample with the max-norm error of the GPU results
+against it (the 63^3 subsample of the 3D instance over all its steps, and the 1023^2 instance
+over all its steps), and the one-level scheme with the exact exponential that the paper
+compares the two-level scheme with, run on the GPU over the same steps.
 
 Roofline. Each axis pass reads and writes the state once (2 x points x element bytes) and does
 the conventional FFT count of flops on every point: 6 transforms of 5 L log2 L flops per complex
 line of 2 real lines, i.e. 15 log2 N flops per point, plus 9 for the three spectrum scalings and
 the two psi twiddles, plus the nonlinear half-steps (about 20 flops per point per step, split
-over the d passes). At these intensities (about 14 flop/byte in FP64, 28 in FP32) the pass is
-bound by vector arithmetic, not by HBM (the MI355X ridge is 78.6 TFLOP/s / 8 TB/s = 9.8
-flop/byte), so the roofline reported is the arithmetic one: algorithmic flops per launch over
-the kernel's mean launch duration (HIP events on the plan's stream), against the vector peak of
-the dtype. The HBM figure of the same launch is reported beside it, and `traffic` is the HBM
+over the d passes). Whichever of the two takes longer at the published peaks (8 TB/s HBM; 78.6
+FP64 / 157.3 FP32 TFLOP/s vector) bounds the pass: 3D N = 255 in FP64 moves 16 B per point for
+136 flops (8.5 flop/B, below the 9.8 flop/B ridge), so it is bound by HBM; 2D N = 1023 does 169
+flops on the same bytes (10.6 flop/B), bound by arithmetic. `achieved` is the algorithmic bytes
+(or flops) per launch over the kernel's mean launch duration, measured here with HIP events
+around a graph of back-to-back launches of that pass on the plan's stream. `traffic` is the HBM
 bytes per launch measured with hardware counters (rocprofv3 FETCH_SIZE and WRITE_SIZE,
 calibrated on a plain copy kernel) when the committed record matches the current kernel sources.
 """
@@ -67,7 +70,7 @@ def pass_flops(inst, axis):
     return inst.points * (15.0 * math.log2(inst.ns[axis]) + 9.0 + 20.0 / inst.dims)
 
 
-def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None):
+def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None, with_diagnostics=True):
     import numpy as np
     import torch
     from paper_2209_08437_amd import autotune, sfac
@@ -116,9 +119,6 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None):
     flags, vmax = plan.flags()
     log(f"[bench] {dtype}: {steps} steps in {wall * 1e3:.2f} ms wall ({gpu_ms:.2f} ms events), "
         f"max|u| {vmax:.6f}, flags {flags}")
-    # per-pass kernel durations: HIP events on the plan's stream around each launch give the
-    # passes' shares; an event pair per launch adds a few microseconds to each, so the timed
-    # region's step time (graph replays, events only at its ends) is split by those shares
     # the same timed region repeated (state reset from u0 outside each), for the spread
     reps = []
     for _ in range(5):
@@ -131,15 +131,17 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None):
         e1.record()
         torch.cuda.synchronize()
         reps.append(e0.elapsed_time(e1) / steps)
+    # per-pass kernel durations: each axis' pass launched pass_reps times back to back from a
+    # captured graph, HIP events around the replay on the plan's stream (on a scratch copy)
     uu = u0.clone()
-    pass_ev = plan.time_passes(uu, pass_reps)
+    pass_ms = plan.time_passes(uu, pass_reps)
+    del uu
     torch.cuda.synchronize()
-    step_ms = gpu_ms / steps
-    pass_ms = [step_ms * t / sum(pass_ev) for t in pass_ev]
-    diag = diagnostics(plan, u0, u, min(steps, 200))
+    state = u.double().cpu().numpy()
+    diag = diagnostics(plan, u0, u, min(steps, 200)) if with_diagnostics else None
     result = {
         "wall_s": wall, "gpu_ms": gpu_ms, "flags": flags, "max_abs": vmax,
-        "pass_ms": pass_ms, "pass_ms_events": pass_ev, "methods": methods, "state": u.double().cpu().numpy(), "schedule": sched,
+        "pass_ms": pass_ms, "methods": methods, "state": state, "schedule": sched,
         "plan_create_ms": plan_ms, "warmup_ms": warm_ms, "diagnostics": diag, "repeat_ms_per_step": reps,
     }
     plan.close()
@@ -183,27 +185,41 @@ def diagnostics(plan, u0, u, k):
 
 
 def pass_roofline(inst, dtype, r, workload_name):
-    """Roofline of the axis pass with the longest mean duration of one gpu_rate result: the
-    conventional flop count over the duration against the dtype's vector peak, the HBM rate of
-    its algorithmic bytes, and the counter-measured traffic when the committed record matches."""
+    """Roofline of the axis pass with the longest mean launch duration of one gpu_rate result.
+    The bound is whichever of the pass's algorithmic bytes (one read and one write of the state)
+    and algorithmic flops takes longer at the published peaks; `achieved` is that quantity per
+    launch over the mean launch duration. The other figure is reported beside it, and `traffic`
+    is the counter-measured HBM bytes per launch when the committed record matches."""
     from paper_2209_08437_amd import profiling
     esize = 8 if dtype == "f64" else 4
     pass_ms = r["pass_ms"]
     a = max(range(len(pass_ms)), key=lambda i: pass_ms[i])
     fl = pass_flops(inst, a)
-    tf = fl / (pass_ms[a] * 1e-3) / 1e12
-    peak = VALU_PEAK_TFLOPS[dtype]
     byt = 2 * inst.points * esize
-    gbps = byt / (pass_ms[a] * 1e-3) / 1e9
+    sec = pass_ms[a] * 1e-3
+    peak_tf = VALU_PEAK_TFLOPS[dtype]
+    tf = fl / sec / 1e12
+    gbps = byt / sec / 1e9
+    hbm = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbps / HBM_PEAK_GBS, 4)}
+    alu = {"bound": "alu", "achieved": round(tf, 3), "peak": peak_tf, "unit": "TFLOP/s",
+           "frac": round(tf / peak_tf, 4)}
+    hbm_bound = byt / (HBM_PEAK_GBS * 1e9) >= fl / (peak_tf * 1e12)
+    out = dict(hbm if hbm_bound else alu)
     rec = profiling.load_traffic(TRAFFIC_RECORD, workload_name, dtype, r["schedule"] or None)
     meth, length = r["methods"][a]
-    return {"bound": "alu", "achieved": round(tf, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4),
-            "traffic": rec["per_axis"][a]["bytes"] if rec else None,
-            "kernel": f"{meth} axis pass ({'double' if esize == 8 else 'float'}, transform length {length}), "
-                      f"axis {a + 1}",
-            "flops_per_launch": round(fl),
-            "hbm": {"achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4),
-                    "bytes_per_launch": byt}}
+    out.update({
+        "traffic": rec["per_axis"][a]["bytes"] if rec else None,
+        "kernel": f"{meth} axis pass ({'double' if esize == 8 else 'float'}, transform length {length}), "
+                  f"axis {a + 1}",
+        "algorithmic_bytes_per_launch": byt, "flops_per_launch": round(fl),
+        "mean_launch_ms": round(pass_ms[a], 5), "pass_ms": [round(x, 5) for x in pass_ms],
+        "timing": "HIP events around a graph of back-to-back launches of each pass on the plan's stream",
+        "alu" if hbm_bound else "hbm": alu if hbm_bound else hbm,
+        "traffic_record": (f"profiles/traffic.json ({rec['profile']})" if rec else
+                           "none for the current kernel sources"),
+    })
+    return out
 
 
 def one_level_exact(inst, steps, two_level_state, two_level_ms, workload_name, pass_reps):
@@ -356,9 +372,11 @@ def served_run(args):
     }
 
 
-def cpu_baseline(inst, seconds):
-    """The CPU oracle as it stands, on a bounded sample of the same workload: table set-up
-    (dense per-axis exponentials) timed apart, then as many whole steps as fit the budget."""
+def cpu_leg(inst, seconds, checks=()):
+    """The CPU oracle as it stands: (1) timed on a bounded sample of the workload (table set-up,
+    the dense per-axis exponentials, timed apart; then as many whole steps as fit the budget, on
+    all host threads and on one); (2) the max-norm error of GPU results against it: each check is
+    (name, instance, {dtype: final GPU state}) and the oracle runs the instance's full step count."""
     import numpy as np
     from oracle import sfac_oracle as O
     try:
@@ -400,7 +418,51 @@ def cpu_baseline(inst, seconds):
                                 "sample": f"{k1} steps after 1 untimed step"}
     except ImportError:
         pass
-    return out
+    acc = {}
+    for name, cinst, states in checks:
+        t0 = time.perf_counter()
+        ref = O.two_level_solve(cinst.u0, cinst.ns, cinst.alphas, cinst.eps, cinst.hs, cinst.tau, cinst.steps)
+        scale = float(np.abs(ref).max())
+        acc[name] = {"steps": cinst.steps, "grid": list(cinst.ns), "oracle_s": round(time.perf_counter() - t0, 2),
+                     "oracle_max_abs": scale}
+        for dt_, st in states.items():
+            acc[name][f"{dt_}_rel_err_vs_oracle"] = float(np.abs(st - ref).max() / scale)
+        log(f"[bench] oracle check {name}: " + ", ".join(f"{k2} {v:.3e}" for k2, v in acc[name].items()
+                                                          if k2.endswith("oracle")))
+    return out, acc
+
+
+def sub_workload(name, steps, args):
+    """FP64 and FP32 runs of another single-instance workload, for a sub-object of the line."""
+    inst, desc = workload(name)
+    steps = steps if steps is not None else inst.steps
+    r64 = gpu_rate(inst, "f64", steps, args.warmup, args.pass_reps, tune=not args.no_tune,
+                   tune_cache=args.tune_cache, with_diagnostics=False)
+    r32 = gpu_rate(inst, "f32", steps, args.warmup, args.pass_reps, tune=not args.no_tune,
+                   tune_cache=args.tune_cache, with_diagnostics=False)
+    out = {"workload": desc, "steps": steps}
+    for dt_, r in (("f64", r64), ("f32", r32)):
+        out[dt_] = {"value": round(inst.points * steps / r["wall_s"], 1), "unit": "grid-point-steps/s",
+                    "ms_per_step": round(r["wall_s"] * 1e3 / steps, 5), "max_abs": r["max_abs"], "flags": r["flags"],
+                    "schedule": r["schedule"], "roofline": pass_roofline(inst, dt_, r, name)}
+    return inst, out, {"f64": r64["state"], "f32": r32["state"]}
+
+
+def subsample_states(big, args):
+    """GPU FP64 and FP32 results of the 63^3 companion of the 3D instance (all its steps)."""
+    import torch
+    from paper_2209_08437_amd import sfac, workloads as W
+    inst = W.subsample_3d_63(big)
+    states = {}
+    for dt_ in ("f64", "f32"):
+        tdt = torch.float64 if dt_ == "f64" else torch.float32
+        u = torch.tensor(inst.u0, dtype=tdt, device="cuda")
+        with sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dt_) as p:
+            p.step(u, inst.steps)
+            flags, vmax = p.flags()
+        states[dt_] = u.double().cpu().numpy()
+        log(f"[bench] 63^3 subsample {dt_}: {inst.steps} steps, max|u| {vmax:.6f}, flags {flags}")
+    return inst, states
 
 
 def main():
@@ -408,11 +470,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="large_2d_1023")
+    ap.add_argument("--workload", default="large_3d_255")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-sub", action="store_true", help="skip the 1023^2 sub-object of the 3D line")
+    ap.add_argument("--no-oracle-checks", action="store_true",
+                    help="skip the oracle runs behind the error figures (the 1023^2 one takes about a minute)")
     ap.add_argument("--no-exact", action="store_true", help="skip the one-level exact-exponential comparison")
     ap.add_argument("--pass-reps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="default schedules instead of autotuned ones")
@@ -459,28 +524,6 @@ def main():
     main_r = gpu_rate(inst, args.dtype, steps, args.warmup, args.pass_reps, tune=not args.no_tune,
                       tune_cache=args.tune_cache)
     value = pts * steps / main_r["wall_s"]
-    # roofline of the dominant kernel: the axis pass with the largest mean duration
-    pass_ms = main_r["pass_ms"]
-    a_dom = max(range(len(pass_ms)), key=lambda a: pass_ms[a])
-    flops_per_launch = pass_flops(inst, a_dom)
-    tflops = flops_per_launch / (pass_ms[a_dom] * 1e-3) / 1e12
-    peak = VALU_PEAK_TFLOPS[args.dtype]
-    bytes_per_launch = 2 * pts * esize           # one read and one write of the state
-    gbps = bytes_per_launch / (pass_ms[a_dom] * 1e-3) / 1e9
-    from paper_2209_08437_amd import profiling
-    rec = profiling.load_traffic(TRAFFIC_RECORD, args.workload, args.dtype, main_r["schedule"] or None)
-    traffic = rec["per_axis"][a_dom]["bytes"] if rec else None
-    meth, length = main_r["methods"][a_dom]
-    roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(tflops / peak, 4), "traffic": traffic,
-            "kernel": f"{meth} axis pass ({'double' if esize == 8 else 'float'}, transform length {length}), "
-                      f"axis {a_dom + 1}",
-            "flops_per_launch": round(flops_per_launch), "pass_ms": [round(x, 5) for x in pass_ms],
-            "pass_ms_events": [round(x, 5) for x in main_r["pass_ms_events"]],
-            "hbm": {"achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbps / HBM_PEAK_GBS, 4), "bytes_per_launch": bytes_per_launch},
-            "traffic_record": (f"profiles/traffic.json ({rec['profile']})" if rec else
-                               "none for the current kernel sources")}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "grid-point-steps/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup,
@@ -491,18 +534,21 @@ def main():
                    "effective_GBps": round(value * 2 * inst.dims * esize / 1e9, 2),
                    "plan_create_ms": round(main_r["plan_create_ms"], 3),
                    "warmup_ms": round(main_r["warmup_ms"], 3)},
-        "roofline": roof,
+        "roofline": pass_roofline(inst, args.dtype, main_r, args.workload),
     }
+    out["roofline"]["step_ms_timed_region"] = round(main_r["gpu_ms"] / steps, 5)
+    checks = []
+    r32 = None
     if not args.no_fp32 and args.dtype == "f64":
         r32 = gpu_rate(inst, "f32", steps, args.warmup, args.pass_reps, tune=not args.no_tune,
-                       tune_cache=args.tune_cache)
+                       tune_cache=args.tune_cache, with_diagnostics=False)
         import numpy as np
         ref = main_r["state"]
         out["fp32"] = {"value": round(pts * steps / r32["wall_s"], 1), "unit": "grid-point-steps/s",
                        "ms_per_step": round(r32["wall_s"] * 1e3 / steps, 5),
+                       "speedup_vs_fp64": round(main_r["wall_s"] / r32["wall_s"], 3),
                        "rel_err_vs_fp64_gpu": float(np.abs(r32["state"] - ref).max() / np.abs(ref).max()),
-                       "max_abs": r32["max_abs"], "flags": r32["flags"],
-                       "pass_ms": [round(x, 5) for x in r32["pass_ms"]], "schedule": r32["schedule"],
+                       "max_abs": r32["max_abs"], "flags": r32["flags"], "schedule": r32["schedule"],
                        "plan_create_ms": round(r32["plan_create_ms"], 3),
                        "roofline": pass_roofline(inst, "f32", r32, args.workload)}
     import statistics
@@ -513,12 +559,21 @@ def main():
     out["max_abs"] = main_r["max_abs"]
     out["flags"] = main_r["flags"]
     out["diagnostics"] = main_r["diagnostics"]
+    if args.workload == "large_3d_255":
+        sub_inst, sstates = subsample_states(inst, args)
+        if steps == inst.steps:
+            checks.append(("subsample_3d_63", sub_inst, sstates))
+    if args.workload == "large_3d_255" and not args.no_sub:
+        c2_inst, out["large_2d_1023"], c2_states = sub_workload("large_2d_1023", None, args)
+        checks.append(("large_2d_1023", c2_inst, c2_states))
     if args.dtype == "f64" and not args.no_exact:
         out["one_level_exact"] = one_level_exact(inst, steps, main_r["state"], main_r["wall_s"] * 1e3 / steps,
                                                  args.workload, args.pass_reps)
     if not args.no_cpu:
         log(f"[bench] timing the CPU oracle for about {args.cpu_seconds:.0f} s")
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+        out["cpu_baseline"], acc = cpu_leg(inst, args.cpu_seconds, [] if args.no_oracle_checks else checks)
+        if acc:
+            out["accuracy_vs_oracle"] = acc
     print(json.dumps(out), flush=True)
 
 

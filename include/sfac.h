@@ -79,7 +79,9 @@ typedef struct sfac_batch_s* sfac_batch;
 typedef struct {
     int32_t method[3];          /* sfac_method per axis (axis 1 first); default SFAC_METHOD_AUTO */
     int32_t use_graph;          /* 1 (default): replay steps from captured HIP graphs; 0: plain launches */
-    int32_t graph_chunk;        /* steps captured per graph replay (default 32, 1..1024) */
+    int32_t graph_chunk;        /* steps captured per graph replay (default 32, 1..1024); sfac_step
+                                   replays that graph nsteps / graph_chunk times and graphs of
+                                   1, 2, 4, .. steps for the remainder (one per set bit) */
     int32_t elems_log2[3];      /* embedded method: log2 of the elements each thread holds, 2, 3 or 4
                                    (0 = automatic; 2 only for transform lengths 64..2048); fewer
                                    elements means more threads per line */
@@ -160,13 +162,15 @@ sfac_status sfac_plan_flags(sfac_plan p, uint32_t* flags, double* max_abs);
 sfac_status sfac_plan_reset_flags(sfac_plan p);
 
 /*
- * sfac_plan_time_passes - measure the axis-pass kernels: run `reps` >= 1 steps on u_dev with
- * plain launches, a HIP event pair recorded on the plan's stream around every pass, and write
- * the mean duration of each axis' pass in milliseconds to ms[0 .. dims-1]. The state advances
- * by `reps` steps exactly as sfac_step would advance it. Synchronizes the plan's stream.
- * For a plan of SFAC_METHOD_EXACT, ms[a] is the mean duration of axis a+1's dense product (the
- * nonlinear half-steps run between the event pairs, untimed).
- * Errors: SFAC_EINVAL, SFAC_EDEVICE.
+ * sfac_plan_time_passes - measure the axis-pass kernels: for each axis, `reps` >= 1 launches of
+ * that axis' pass alone on u_dev, captured into a graph and replayed once between a pair of HIP
+ * events on the plan's stream; ms[0 .. dims-1] receives the mean duration per launch in
+ * milliseconds (back-to-back launches, as inside the step graphs). u_dev is overwritten with
+ * intermediate values: it holds no state of the scheme afterwards. Synchronizes the plan's
+ * stream. For a plan of SFAC_METHOD_EXACT, `reps` whole steps run instead, with an event pair
+ * around every dense product, and ms[a] is the mean duration of axis a+1's product (the
+ * nonlinear half-steps run between the event pairs, untimed); the state advances by `reps`
+ * steps. Errors: SFAC_EINVAL, SFAC_EDEVICE.
  */
 sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float* ms);
 
@@ -248,8 +252,11 @@ const char* sfac_last_error(void);
 
 /* ---------------------------------------------------------------- grouped stepping
  * Several independent plans stepped together: every axis pass of every plan that needs it is
- * one launch per kernel variant (transform length and arithmetic) and pass, instead of one
- * launch per plan. Used for batched solves and by the solve server's continuous batching. */
+ * one launch per kernel variant (transform length and arithmetic) and pass (up to 64 plans per
+ * launch), instead of one launch per plan. Used for batched solves and by the solve server's
+ * continuous batching. A launch carries its plans in its kernel arguments, so a group holds no
+ * device memory; the captured step graphs are kept per set of (plan, state) pairs (the 32 most
+ * recently used), so repeated calls with the same plans and states replay them. */
 typedef struct sfac_group_s* sfac_group;
 
 /* sfac_group_create - a launch workspace ordered on hip_stream (NULL = legacy default stream).
@@ -261,8 +268,9 @@ sfac_status sfac_group_create(sfac_group* out, void* hip_stream);
  * sfac_group_step - advance plans[i]'s state u_dev[i] by nsteps[i] >= 0 steps, i < count. A plan
  * may appear once. Plans of both arithmetics may be mixed. Each state ends bitwise equal to
  * stepping its plan alone with sfac_step: the same kernels run on it in the same order (no
- * step is fused across plans or steps). Waits for the group's previous call to finish (its
- * launch descriptors are rewritten), then queues the work asynchronously on the group's stream.
+ * step is fused across plans or steps). Asynchronous on the group's stream: it returns once the
+ * work is queued and does not wait for earlier calls (dropping a cached graph when the cache is
+ * full waits for the stream). The plans must stay alive until the work has run.
  * Errors: SFAC_EINVAL (NULL arguments, a repeated plan, negative steps, misaligned state),
  * SFAC_EUNSUPPORTED (a plan of SFAC_METHOD_EXACT), SFAC_ENOMEM, SFAC_EDEVICE.
  */
@@ -272,7 +280,8 @@ sfac_status sfac_group_step(sfac_group g, int32_t count, const sfac_plan* plans,
 /* sfac_group_destroy - waits for the group's work and frees it; NULL is accepted. */
 sfac_status sfac_group_destroy(sfac_group g);
 
-/* sfac_group_device_bytes - device memory of the group's launch workspace. */
+/* sfac_group_device_bytes - device memory the group itself holds: 0 (launches carry their plans in
+ * their kernel arguments; the plans' own memory is counted by sfac_plan_device_bytes). */
 size_t sfac_group_device_bytes(sfac_group g);
 
 /* ---------------------------------------------------------------- batched form
@@ -301,7 +310,7 @@ sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instanc
  * sfac_batch_step - advance instance i by nsteps[i] steps (>= 0) in place; u_dev[i] is its
  * state as for sfac_step. Instances with fewer steps drop out of the launches once done.
  * An instance's result is bitwise the same as stepping it alone with sfac_step.
- * Asynchronous on the batch's stream (waits for the batch's previous call first).
+ * Asynchronous on the batch's stream.
  * Errors: SFAC_EINVAL, SFAC_ENOMEM, SFAC_EDEVICE.
  */
 sfac_status sfac_batch_step(sfac_batch b, void* const* u_dev, const int64_t* nsteps);

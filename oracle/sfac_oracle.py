@@ -18,12 +18,18 @@ What it computes, in the paper's order and notation (Sec. 2):
   J^Q_{tau/2} e^{tau/2 C_a} e^{tau S_a} e^{tau/2 C_a} J^Q_{tau/2}, where C_a and S_a are the
   Kronecker sums of eq. (2DA) / (3DA) form, so each exponential is the product of the
   per-axis exponentials (all axes' C factors, then all S factors, then all C factors);
+* the same step with the per-axis factors multiplied out once (P_l = e^{tau/2 C_l} e^{tau S_l}
+  e^{tau/2 C_l}, one dense product per axis, axes in reverse order): a second FP64 evaluation
+  order of eq. (finalstrang), used to measure the rounding floor of long runs;
+* the same step with every factor applied through Remark 1's diagonalisation by a library FFT
+  (a third FP64 evaluation order, for the same measurement);
 * eq. (strang) with eq. (linear_operator): the one-level scheme with the exact exponential
   e^{tau A}, used only to reproduce the paper's "Strang splitting" table columns;
 * Sec. 5, Example 5: the discrete free energy prod(h) (1/4 |u^2 - 1|^2 - 1/2 u^T A u).
 
 Every linear factor is a dense N x N matrix applied by a dense product along one axis of
-the state; there is no FFT, blocking or fusion. Arrays are C-order with axis 1 (the paper's
+the state (the FFT evaluation order above aside, which exists only to measure rounding); there
+is no blocking or fusion. Arrays are C-order with axis 1 (the paper's
 x^(1), index i) fastest, i.e. shape (N2, N1) in 2D and (N3, N2, N1) in 3D, as the state
 vector ordering of Sec. 2.1 prescribes.
 
@@ -38,7 +44,9 @@ __all__ = [
     "toeplitz_column", "circulant_skew_split", "fourier_matrix", "skew_diagonal",
     "circulant_spectrum", "skew_spectrum", "exp_circulant", "exp_skew",
     "exp_symmetric", "nonlinear_flow", "AxisOperators", "axis_operators",
-    "apply_along_axis", "two_level_step", "two_level_solve", "strang_step",
+    "apply_along_axis", "two_level_step", "two_level_solve", "composed_operators",
+    "two_level_solve_composed", "apply_exp_circulant_fft", "apply_exp_skew_fft",
+    "two_level_solve_fft", "rounding_spread", "strang_step",
     "strang_solve", "discrete_energy",
 ]
 
@@ -258,6 +266,89 @@ def two_level_solve(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, observe=None
         if observe is not None:
             observe(n + 1, u)
     return u
+
+
+def composed_operators(ops):
+    """Per axis the dense product P_l = e^{tau/2 C_l} e^{tau S_l} e^{tau/2 C_l}, formed once. The
+    Kronecker-sum exponentials of eq. (finalstrang) factor per axis and factors on different axes
+    commute, so the linear part of a step is the product over the axes of these P_l."""
+    return [op.EC @ op.ES @ op.EC for op in ops]
+
+
+def two_level_solve_composed(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, reverse_axes=True):
+    """The scheme of two_level_solve evaluated in another FP64 order: each step applies the
+    composed per-axis operators P_l (one dense product per axis), the last axis first when
+    `reverse_axes` is set. Equal to two_level_solve in exact arithmetic; the two differ only by
+    rounding, which measures how reproducible an FP64 evaluation of a long run is at all."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    if ops is None:
+        ops = axis_operators(ns, alphas, eps, hs, tau)
+    P = composed_operators(ops)
+    d = u.ndim
+    order = range(d, 0, -1) if reverse_axes else range(1, d + 1)
+    for _ in range(nsteps):
+        u = nonlinear_flow(u, 0.5 * tau)
+        for ax in order:
+            u = apply_along_axis(P[ax - 1], u, ax)
+        u = nonlinear_flow(u, 0.5 * tau)
+    return u
+
+
+def apply_exp_circulant_fft(x, lam, t, axis):
+    """e^{t C} along the paper's axis `axis` through Remark 1 with a library FFT: C = F* Lambda F
+    with F = sqrt(N) ifft (the e^{+2 pi i j k / N} / sqrt(N) of Remark 1) and F* = fft / sqrt(N)."""
+    ax = x.ndim - axis
+    shape = [1] * x.ndim
+    shape[ax] = -1
+    return np.fft.fft(np.exp(t * lam).reshape(shape) * np.fft.ifft(x, axis=ax), axis=ax).real
+
+
+def apply_exp_skew_fft(x, mu, t, axis):
+    """e^{t S} along `axis` through Remark 1 with a library FFT: S = Psi* F* Lambda_S F Psi."""
+    ax = x.ndim - axis
+    N = x.shape[ax]
+    shape = [1] * x.ndim
+    shape[ax] = -1
+    psi = skew_diagonal(N).reshape(shape)
+    y = np.fft.ifft(psi * x, axis=ax)
+    return (np.conj(psi) * np.fft.fft(np.exp(t * mu).reshape(shape) * y, axis=ax)).real
+
+
+def two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=None):
+    """The scheme of two_level_solve evaluated a third way: every factor applied through the
+    diagonalisation of Remark 1 with a library FFT instead of a dense product, in the paper's
+    factor order. Equal to two_level_solve in exact arithmetic; used beside
+    two_level_solve_composed to measure how far FP64 evaluations of a long run spread."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    if ops is None:
+        ops = axis_operators(ns, alphas, eps, hs, tau)
+    lams = [circulant_spectrum(op.C) for op in ops]
+    mus = [skew_spectrum(op.S) for op in ops]
+    d = u.ndim
+    for _ in range(nsteps):
+        u = nonlinear_flow(u, 0.5 * tau)
+        for ax in range(1, d + 1):
+            u = apply_exp_circulant_fft(u, lams[ax - 1], 0.5 * tau, ax)
+        for ax in range(1, d + 1):
+            u = apply_exp_skew_fft(u, mus[ax - 1], tau, ax)
+        for ax in range(1, d + 1):
+            u = apply_exp_circulant_fft(u, lams[ax - 1], 0.5 * tau, ax)
+        u = nonlinear_flow(u, 0.5 * tau)
+    return u
+
+
+def rounding_spread(u0, ns, alphas, eps, hs, tau, nsteps, ref, ops=None):
+    """Largest relative max-norm distance of the two other FP64 evaluation orders
+    (two_level_solve_composed, two_level_solve_fft) from `ref`, the result of two_level_solve on
+    the same input: the spread below which FP64 evaluations of this run are not reproducible."""
+    if ops is None:
+        ops = axis_operators(ns, alphas, eps, hs, tau)
+    scale = max(float(np.abs(ref).max()), 1e-300)
+    out = 0.0
+    for alt in (two_level_solve_composed(u0, ns, alphas, eps, hs, tau, nsteps, ops=ops),
+                two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=ops)):
+        out = max(out, float(np.abs(alt - ref).max()) / scale)
+    return out
 
 
 def strang_step(u, ops, tau):

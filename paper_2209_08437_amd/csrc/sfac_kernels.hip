@@ -568,23 +568,31 @@ __global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_single(PassDesc<T
     run_embed_tile<T, LOG2M, LE, STAGE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
-// Several instances with the same transform length in one launch (batched form).
-template <typename T, int LOG2M, int LE, bool STAGE>
-__global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_multi(const PassDesc<T>* __restrict__ descs,
-                                                                  const int* __restrict__ block_start,
-                                                                  int ndesc) {
-    extern __shared__ unsigned char smem_raw[];
-    int lo = 0, hi = ndesc;
-    const int b = blockIdx.x;
+// The instance of a grouped launch that owns block b (the last entry whose first block is at
+// most b) and its descriptor, with the state pointer of the launch; *local gets the block's
+// index within that instance's pass.
+template <typename T>
+__device__ __forceinline__ PassDesc<T> group_desc(const GroupArgs<T>& g, int b, int* local) {
+    int lo = 0, hi = g.n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (block_start[mid] <= b)
+        if (g.start[mid] <= b)
             lo = mid;
         else
             hi = mid;
     }
-    const PassDesc<T> d = descs[lo];
-    const int local = b - block_start[lo];
+    PassDesc<T> d = *g.desc[lo];
+    d.u = g.u[lo];
+    *local = b - g.start[lo];
+    return d;
+}
+
+// Several instances with the same transform length in one launch (batched form).
+template <typename T, int LOG2M, int LE, bool STAGE>
+__global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_multi(const GroupArgs<T> g) {
+    extern __shared__ unsigned char smem_raw[];
+    int local;
+    const PassDesc<T> d = group_desc(g, blockIdx.x, &local);
     const int tile = d.xcd_remap ? xcd_tile(local, d.ntiles) : local;
     if (tile >= d.ntiles) return;
     // the block has the group's largest size; threads beyond d.lpb lines hold no line (their
@@ -609,21 +617,10 @@ __global__ void __launch_bounds__(kBlockThreads, (diag2_min_waves<T, A, B, WA>()
 }
 
 template <typename T, int A, int B, bool WA>
-__global__ void __launch_bounds__(kBlockThreads, (diag2_min_waves<T, A, B, WA>())) diag2_pass_multi(const PassDesc<T>* __restrict__ descs,
-                                                                  const int* __restrict__ block_start,
-                                                                  int ndesc) {
+__global__ void __launch_bounds__(kBlockThreads, (diag2_min_waves<T, A, B, WA>())) diag2_pass_multi(const GroupArgs<T> g) {
     extern __shared__ unsigned char smem_raw[];
-    int lo = 0, hi = ndesc;
-    const int b = blockIdx.x;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (block_start[mid] <= b)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const PassDesc<T> d = descs[lo];
-    const int local = b - block_start[lo];
+    int local;
+    const PassDesc<T> d = group_desc(g, blockIdx.x, &local);
     const int tile = d.xcd_remap ? xcd_tile(local, d.ntiles) : local;
     if (tile >= d.ntiles) return;
     run_diag2_tile<T, A, B, WA>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
@@ -698,22 +695,10 @@ const void* embed_fn(int log2m, int le, bool multi, bool stage) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlockThreads) axis_pass_multi(const PassDesc<T>* __restrict__ descs,
-                                                                 const int* __restrict__ block_start,
-                                                                 int ndesc) {
+__global__ void __launch_bounds__(kBlockThreads) axis_pass_multi(const GroupArgs<T> g) {
     extern __shared__ unsigned char smem_raw[];
-    // find the descriptor whose block range holds this block (block_start has ndesc + 1 entries)
-    int lo = 0, hi = ndesc;
-    const int b = blockIdx.x;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (block_start[mid] <= b)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const PassDesc<T> d = descs[lo];
-    const int local = b - block_start[lo];
+    int local;
+    const PassDesc<T> d = group_desc(g, blockIdx.x, &local);
     const int tile = d.xcd_remap ? xcd_tile(local, d.ntiles) : local;
     if (tile >= d.ntiles) return;
     cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -831,19 +816,19 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
 }
 
 template <typename T>
-hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const PassDesc<T>* descs_dev,
-                                  const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
+hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const GroupArgs<T>& args, size_t lds_bytes,
                                   hipStream_t stream) {
+    if (args.n < 1 || args.n > kGroupSlots) return hipErrorInvalidValue;
+    const int total_blocks = args.start[args.n];
     if (total_blocks <= 0) return hipSuccess;
     if (kind == 1 || kind == 2) {
         const void* fn = kind == 1 ? embed_fn<T>((variant % 128) / 8, variant % 8, true, variant >= 128)
                                    : diag2_fn<T>((variant % 4096) / 64, variant % 64, true, variant >= 4096);
         if (!fn) return hipErrorInvalidValue;
-        void* args[] = {&descs_dev, &block_start_dev, &ndesc};
-        return hipLaunchKernel(fn, dim3(total_blocks), dim3(threads), args, lds_bytes, stream);
+        void* kargs[] = {const_cast<GroupArgs<T>*>(&args)};
+        return hipLaunchKernel(fn, dim3(total_blocks), dim3(threads), kargs, lds_bytes, stream);
     }
-    hipLaunchKernelGGL(axis_pass_multi<T>, dim3(total_blocks), dim3(kBlockThreads), lds_bytes, stream,
-                       descs_dev, block_start_dev, ndesc);
+    hipLaunchKernelGGL(axis_pass_multi<T>, dim3(total_blocks), dim3(kBlockThreads), lds_bytes, stream, args);
     return hipGetLastError();
 }
 
@@ -1060,6 +1045,25 @@ hipError_t launch_trace_collect(unsigned long long* parts, long long nparts, uns
     return hipGetLastError();
 }
 
+namespace {
+// An empty one-wavefront kernel whose name carries a number: launched around the timed launches
+// of sfac_plan_time_passes, it tells a kernel trace or counter record which axis the pass
+// dispatches that follow belong to (0: the timed launches are over).
+template <int AXIS>
+__global__ void __launch_bounds__(64) pass_timing_mark() {}
+}  // namespace
+
+hipError_t launch_timing_mark(int axis, hipStream_t stream) {
+    switch (axis) {
+        case 0: hipLaunchKernelGGL(pass_timing_mark<0>, dim3(1), dim3(64), 0, stream); break;
+        case 1: hipLaunchKernelGGL(pass_timing_mark<1>, dim3(1), dim3(64), 0, stream); break;
+        case 2: hipLaunchKernelGGL(pass_timing_mark<2>, dim3(1), dim3(64), 0, stream); break;
+        case 3: hipLaunchKernelGGL(pass_timing_mark<3>, dim3(1), dim3(64), 0, stream); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_energy_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream) {
     const int blocks = pass_blocks(d);
@@ -1113,10 +1117,8 @@ template int pass_blocks<double>(const PassDesc<double>&);
 template int pass_blocks<float>(const PassDesc<float>&);
 template hipError_t launch_axis_pass<double>(const PassDesc<double>&, size_t, hipStream_t);
 template hipError_t launch_axis_pass<float>(const PassDesc<float>&, size_t, hipStream_t);
-template hipError_t launch_axis_pass_multi<double>(int, int, int, const PassDesc<double>*, const int*, int, int,
-                                                   size_t, hipStream_t);
-template hipError_t launch_axis_pass_multi<float>(int, int, int, const PassDesc<float>*, const int*, int, int,
-                                                  size_t, hipStream_t);
+template hipError_t launch_axis_pass_multi<double>(int, int, int, const GroupArgs<double>&, size_t, hipStream_t);
+template hipError_t launch_axis_pass_multi<float>(int, int, int, const GroupArgs<float>&, size_t, hipStream_t);
 template hipError_t launch_energy_pass<double>(const PassDesc<double>&, size_t, hipStream_t);
 template hipError_t launch_energy_pass<float>(const PassDesc<float>&, size_t, hipStream_t);
 template hipError_t allow_lds<double>(size_t);

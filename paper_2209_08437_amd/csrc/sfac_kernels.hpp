@@ -83,19 +83,36 @@ int pass_blocks(const PassDesc<T>& d);
 template <typename T>
 hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t stream);
 
+// The instances of one grouped launch, passed by value as the kernel's argument (so a launch
+// needs no device memory of its own and a captured graph node carries everything it reads):
+// entry i is the device copy of a plan's pass descriptor (its `u` field unused), the state it
+// steps, and its first block; start[n] is the launch's block count. A launch holds at most
+// kGroupSlots instances (about 1.3 KB of kernel arguments); larger sets take several launches.
+constexpr int kGroupSlots = 64;
+template <typename T>
+struct GroupArgs {
+    const PassDesc<T>* desc[kGroupSlots];
+    T* u[kGroupSlots];
+    int start[kGroupSlots + 1];
+    int n;
+};
+
 // One launch over several instances' tiles of one pass; every descriptor of the launch uses the
 // same kernel variant; `threads` is the block size (the group's largest).
 // kind: 0 generic, 1 embedded (variant = log2m * 8 + log2e, plus 128 for the LDS-staged tile),
 // 2 two-step diagonal (variant = a * 64 + b, plus 4096 for the wavefront-aligned line layout)
 template <typename T>
-hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const PassDesc<T>* descs_dev,
-                                  const int* block_start_dev, int ndesc, int total_blocks, size_t lds_bytes,
+hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const GroupArgs<T>& args, size_t lds_bytes,
                                   hipStream_t stream);
 
 // After the last pass of a step: reduce the nparts per-wavefront slots of the step's largest |u|
 // into rec[*step] (if *step < cap), clear the slots and advance *step by one.
 hipError_t launch_trace_collect(unsigned long long* parts, long long nparts, unsigned long long* rec, long long* step,
                                 long long cap, hipStream_t stream);
+
+// An empty kernel named for `axis` (1..3, or 0 after the last): sfac_plan_time_passes launches
+// one before each axis' timed launches, so that profiles attribute those dispatches to their axis.
+hipError_t launch_timing_mark(int axis, hipStream_t stream);
 
 // The one-level scheme with the exact exponential (eq. (strang)), FP64.
 // Batched row-major product C[b] = X[b] Y[b] (M x K times K x N; leading dimensions ldx, ldy, ldc

@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <list>
 #include <memory>
 #include <new>
 #include <string>
@@ -331,20 +333,33 @@ struct EnergyAxis {
     size_t lds = 0;
 };
 
+namespace {
+// A captured sequence of `steps` whole steps of a plan, replayed by sfac_step.
+struct StepGraph {
+    int64_t steps;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+std::atomic<unsigned long long> g_next_plan_id{1};
+}  // namespace
+
 struct sfac_plan_s {
     Instance in;
+    unsigned long long id = g_next_plan_id.fetch_add(1);   // never reused (groups key graphs by it)
     hipStream_t stream = nullptr;      // caller's stream (may be the legacy default stream)
     hipStream_t capture = nullptr;     // private stream used only to capture graphs
-    unsigned char* dev = nullptr;      // tables + status words
+    unsigned char* dev = nullptr;      // tables, status words, pass descriptors
     size_t dev_bytes = 0;
     size_t off_stat = 0;
+    size_t off_desc = 0;               // device copies of d64 (FP64) or d32 (FP32), state pointer unset
     sfac::PassDesc<double> d64[3];
     sfac::PassDesc<float> d32[3];
     int use_graph = 1;
     int chunk = 32;
     void* graph_u = nullptr;           // state pointer the graphs were captured for
-    hipGraphExec_t exec_chunk = nullptr, exec_one = nullptr;
-    hipGraph_t graph_chunk = nullptr, graph_one = nullptr;
+    // graphs of `chunk` steps and of powers of two below it, each captured on first use
+    std::vector<StepGraph> graphs;
     unsigned char* energy_dev = nullptr;  // [0, 16): the two energy sums; then per-axis tables
     size_t energy_bytes = 0;
     EnergyAxis eax[3];
@@ -377,13 +392,17 @@ struct sfac_plan_s {
     unsigned int* stat_flags() { return reinterpret_cast<unsigned int*>(dev + off_stat + 8); }
 
     void drop_graphs() {
-        if (exec_chunk) (void)hipGraphExecDestroy(exec_chunk);
-        if (exec_one) (void)hipGraphExecDestroy(exec_one);
-        if (graph_chunk) (void)hipGraphDestroy(graph_chunk);
-        if (graph_one) (void)hipGraphDestroy(graph_one);
-        exec_chunk = exec_one = nullptr;
-        graph_chunk = graph_one = nullptr;
+        for (auto& sg : graphs) {
+            (void)hipGraphExecDestroy(sg.exec);
+            (void)hipGraphDestroy(sg.graph);
+        }
+        graphs.clear();
         graph_u = nullptr;
+    }
+
+    template <typename T>
+    const sfac::PassDesc<T>* device_desc(int a) const {
+        return reinterpret_cast<const sfac::PassDesc<T>*>(dev + off_desc) + a;
     }
 
     // eq. (strang): J^Q_{tau/2} e^{tau A} J^Q_{tau/2}, e^{tau A} one dense product per axis, alternating
@@ -449,14 +468,39 @@ struct sfac_plan_s {
     }
 
     sfac_status capture_graph(int64_t steps, hipGraph_t* g, hipGraphExec_t* x) {
+        *g = nullptr;
+        *x = nullptr;
         hipError_t e = hipStreamBeginCapture(capture, hipStreamCaptureModeRelaxed);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         hipError_t le = launch_steps(capture, steps);
         e = hipStreamEndCapture(capture, g);
-        if (le != hipSuccess) return hip_fail(le, "kernel launch during capture");
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        if (le != hipSuccess || e != hipSuccess) {
+            if (e == hipSuccess && *g) (void)hipGraphDestroy(*g);
+            *g = nullptr;
+            return le != hipSuccess ? hip_fail(le, "kernel launch during capture") : hip_fail(e, "hipStreamEndCapture");
+        }
         e = hipGraphInstantiate(x, *g, nullptr, nullptr, 0);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(*g);
+            *g = nullptr;
+            *x = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        return SFAC_OK;
+    }
+
+    // the graph of `steps` steps for the current state pointer, captured on first use
+    sfac_status graph_for(int64_t steps, hipGraphExec_t* x) {
+        for (const auto& sg : graphs)
+            if (sg.steps == steps) {
+                *x = sg.exec;
+                return SFAC_OK;
+            }
+        StepGraph sg{steps, nullptr, nullptr};
+        const sfac_status st = capture_graph(steps, &sg.graph, &sg.exec);
+        if (st != SFAC_OK) return st;
+        graphs.push_back(sg);
+        *x = sg.exec;
         return SFAC_OK;
     }
 };
@@ -686,7 +730,9 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
         if (opt->graph_chunk > 0) p->chunk = opt->graph_chunk;
     }
     p->off_stat = align_up(p->in.table_bytes, 256);
-    p->dev_bytes = p->off_stat + 256;
+    p->off_desc = p->off_stat + 256;
+    const size_t desc_bytes = dt == SFAC_FP64 ? sizeof(sfac::PassDesc<double>) : sizeof(sfac::PassDesc<float>);
+    p->dev_bytes = align_up(p->off_desc + 3 * desc_bytes, 256);
     std::vector<unsigned char> host(p->dev_bytes, 0);
     for (int a = 0; a < p->in.dims; ++a) {
         if (dt == SFAC_FP64)
@@ -700,6 +746,15 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
         return e == hipErrorOutOfMemory ? fail(SFAC_ENOMEM, "hipMalloc(%zu): %s", p->dev_bytes, hipGetErrorString(e))
                                         : hip_fail(e, "hipMalloc");
     }
+    for (int a = 0; a < p->in.dims; ++a) {
+        p->d64[a] = make_desc<double>(p->in, a, p->dev, nullptr, p->stat_max(), p->stat_flags());
+        p->d32[a] = make_desc<float>(p->in, a, p->dev, nullptr, p->stat_max(), p->stat_flags());
+    }
+    // the descriptors grouped launches read (the state pointer comes with each launch)
+    if (dt == SFAC_FP64)
+        memcpy(host.data() + p->off_desc, p->d64, sizeof(sfac::PassDesc<double>) * p->in.dims);
+    else
+        memcpy(host.data() + p->off_desc, p->d32, sizeof(sfac::PassDesc<float>) * p->in.dims);
     e = hipMemcpy(p->dev, host.data(), p->dev_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(p->dev);
@@ -716,10 +771,6 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
     if (e != hipSuccess) {
         (void)hipFree(p->dev);
         return hip_fail(e, "hipStreamCreate");
-    }
-    for (int a = 0; a < p->in.dims; ++a) {
-        p->d64[a] = make_desc<double>(p->in, a, p->dev, nullptr, p->stat_max(), p->stat_flags());
-        p->d32[a] = make_desc<float>(p->in, a, p->dev, nullptr, p->stat_max(), p->stat_flags());
     }
     *out = p.release();
     return SFAC_OK;
@@ -741,21 +792,26 @@ sfac_status sfac_step(sfac_plan p, void* u_dev, int64_t nsteps) {
     if (p->graph_u != u_dev) {
         p->drop_graphs();
         p->set_u(u_dev);
-        sfac_status st = p->capture_graph(p->chunk, &p->graph_chunk, &p->exec_chunk);
-        if (st == SFAC_OK) st = p->capture_graph(1, &p->graph_one, &p->exec_one);
-        if (st != SFAC_OK) {
-            p->drop_graphs();
-            return st;
-        }
         p->graph_u = u_dev;
     }
+    // nsteps / chunk replays of the chunk-step graph, then one replay per set bit of the rest:
+    // a call of fewer than chunk steps costs at most log2(chunk) + 1 graph launches
     const int64_t full = nsteps / p->chunk, rest = nsteps % p->chunk;
-    for (int64_t k = 0; k < full; ++k) {
-        hipError_t e = hipGraphLaunch(p->exec_chunk, p->stream);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    hipGraphExec_t x = nullptr;
+    if (full > 0) {
+        const sfac_status st = p->graph_for(p->chunk, &x);
+        if (st != SFAC_OK) return st;
+        for (int64_t k = 0; k < full; ++k) {
+            hipError_t e = hipGraphLaunch(x, p->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        }
     }
-    for (int64_t k = 0; k < rest; ++k) {
-        hipError_t e = hipGraphLaunch(p->exec_one, p->stream);
+    for (int b = 62; b >= 0; --b) {
+        const int64_t part = int64_t(1) << b;
+        if (!(rest & part)) continue;
+        const sfac_status st = p->graph_for(part, &x);
+        if (st != SFAC_OK) return st;
+        hipError_t e = hipGraphLaunch(x, p->stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     }
     return SFAC_OK;
@@ -768,7 +824,10 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
     const size_t es = p->in.dt == SFAC_FP64 ? 8 : 4;
     if (reinterpret_cast<uintptr_t>(u_dev) % es) return fail(SFAC_EINVAL, "state pointer not aligned to %zu bytes", es);
     const int d = p->in.dims;
-    std::vector<hipEvent_t> ev(2 * (size_t)d * reps, nullptr);
+    const bool exact = p->exact != 0;
+    // exact plans: an event pair around every dense product of `reps` whole steps; two-level
+    // plans: one event pair around `reps` launches of one axis' pass replayed from a graph
+    std::vector<hipEvent_t> ev(exact ? 2 * (size_t)d * reps : 2, nullptr);
     hipError_t e = hipSuccess;
     for (auto& x : ev) {
         e = hipEventCreate(&x);
@@ -776,31 +835,14 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
     }
     void* keep = p->graph_u;
     p->set_u(u_dev);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) {
-        if (p->exact) {   // whole steps, each axis' dense product bracketed by its event pair
+    if (exact) {
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
             sfac::PassDesc<double> quiet = p->d64[d - 1];
             quiet.trace_part = nullptr;
             e = p->exact_step(p->stream, quiet, &ev[2 * (size_t)r * d]);
-            continue;
         }
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
         for (int a = 0; a < d && e == hipSuccess; ++a) {
-            const size_t i = 2 * ((size_t)r * d + a);
-            e = hipEventRecord(ev[i], p->stream);
-            if (e != hipSuccess) break;
-            // plain launches outside sfac_step: not part of the per-step record
-            sfac::PassDesc<double> d64 = p->d64[a];
-            sfac::PassDesc<float> d32 = p->d32[a];
-            d64.trace_part = nullptr;
-            d32.trace_part = nullptr;
-            e = p->in.dt == SFAC_FP64 ? launch_pass(d64, p->in.ax[a].lds, p->stream)
-                                      : launch_pass(d32, p->in.ax[a].lds, p->stream);
-            if (e != hipSuccess) break;
-            e = hipEventRecord(ev[i + 1], p->stream);
-        }
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-    if (e == hipSuccess) {
-        for (int a = 0; a < d; ++a) {
             double acc = 0;
             for (int r = 0; r < reps && e == hipSuccess; ++r) {
                 const size_t i = 2 * ((size_t)r * d + a);
@@ -811,9 +853,39 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
             ms[a] = (float)(acc / reps);
         }
     }
+    if (!exact) e = hipStreamSynchronize(p->stream);
+    for (int a = 0; a < d && !exact && e == hipSuccess; ++a) {
+        // plain launches outside sfac_step: not part of the per-step record
+        sfac::PassDesc<double> d64 = p->d64[a];
+        sfac::PassDesc<float> d32 = p->d32[a];
+        d64.trace_part = nullptr;
+        d32.trace_part = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) break;
+        hipError_t le = hipSuccess;
+        for (int r = 0; r < reps && le == hipSuccess; ++r)
+            le = p->in.dt == SFAC_FP64 ? launch_pass(d64, p->in.ax[a].lds, p->capture)
+                                       : launch_pass(d32, p->in.ax[a].lds, p->capture);
+        e = hipStreamEndCapture(p->capture, &graph);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = sfac::launch_timing_mark(a + 1, p->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[0], p->stream);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, p->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        float t = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+        if (e == hipSuccess) ms[a] = t / reps;
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    if (!exact && e == hipSuccess) e = sfac::launch_timing_mark(0, p->stream);
     for (auto& x : ev)
         if (x) (void)hipEventDestroy(x);
-    // the captured graphs keep their own copies of the launch arguments
+    // the captured step graphs keep their own copies of the launch arguments
     if (keep) p->set_u(keep);
     return e == hipSuccess ? SFAC_OK : hip_fail(e, "timed pass launches");
 }
@@ -992,25 +1064,44 @@ sfac_status sfac_exact_exponential(int32_t n, double alpha, double eps, double t
 }  // extern "C"
 
 // ===================================================================== groups
-// A group is a reusable launch workspace: sfac_group_step advances any set of plans together,
-// with one launch per (pass, arithmetic, kernel variant) covering every plan that needs it.
+// A group steps any set of plans together, with one launch per (pass, arithmetic, kernel
+// variant) covering every plan that needs it. A launch's instances travel in its kernel
+// arguments (sfac::GroupArgs: the device copy of each plan's pass descriptor and its state), so
+// a group owns no device memory, a call never waits for the previous one, and a captured step
+// graph stays valid for as long as its plans live. Step graphs are cached per set of (plan,
+// state) pairs: a served tick with the same requests as the one before replays the same graph.
+namespace {
+
+struct GroupLaunch {
+    int pass = 0, fp64 = 0, kind = 0, variant = 0, threads = 0;
+    size_t lds = 0;
+    sfac::GroupArgs<double> a64{};
+    sfac::GroupArgs<float> a32{};
+};
+
+// One cached step graph: the (plan id, state) pairs of a phase, in call order.
+struct GroupGraph {
+    std::vector<std::pair<unsigned long long, void*>> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
 struct sfac_group_s {
-    static constexpr int kAux = 4;        // streams the launches of one pass fan out to
+    static constexpr int kAux = 4;         // streams the launches of one pass fan out to
+    static constexpr size_t kCache = 32;   // step graphs kept (most recently used first)
     hipStream_t stream = nullptr;
-    unsigned char* arena = nullptr;        // descriptors and block offsets of the current call
-    size_t arena_bytes = 0;
-    std::vector<unsigned char> host;
     hipStream_t capture = nullptr;         // private streams used only while capturing a step
     hipStream_t aux[kAux] = {};
     hipEvent_t fork = nullptr, join[kAux] = {};
-    std::vector<hipGraph_t> graphs;        // the current call's step graphs (one per phase)
-    std::vector<hipGraphExec_t> execs;
+    std::list<GroupGraph> cache;
 
-    void drop_graphs() {
-        for (auto x : execs) (void)hipGraphExecDestroy(x);
-        for (auto x : graphs) (void)hipGraphDestroy(x);
-        execs.clear();
-        graphs.clear();
+    static void destroy(GroupGraph& gg) {
+        if (gg.exec) (void)hipGraphExecDestroy(gg.exec);
+        if (gg.graph) (void)hipGraphDestroy(gg.graph);
+        gg.exec = nullptr;
+        gg.graph = nullptr;
     }
     hipError_t ensure_streams() {
         hipError_t e = hipSuccess;
@@ -1023,154 +1114,196 @@ struct sfac_group_s {
         return e;
     }
     void release() {
-        drop_graphs();
+        for (auto& gg : cache) destroy(gg);
+        cache.clear();
         if (fork) (void)hipEventDestroy(fork);
         for (int k = 0; k < kAux; ++k) {
             if (join[k]) (void)hipEventDestroy(join[k]);
             if (aux[k]) (void)hipStreamDestroy(aux[k]);
         }
         if (capture) (void)hipStreamDestroy(capture);
-        if (arena) (void)hipFree(arena);
     }
 };
 
 namespace {
 
-struct GroupLaunch {
-    size_t off_desc, off_start;
-    int ndesc, blocks;
-    int64_t reps;
-    int phase, pass;
-    int fp64, kind, variant, threads;
-    size_t lds;
+// The plans of a phase that step (in call order), with their states.
+struct PhaseEntry {
+    sfac_plan plan;
+    void* u;
 };
 
-// Appends the launches of the plans of one arithmetic type. Phases are the maximal step ranges
-// with a fixed set of active plans; inside a phase every step issues pass 0, 1, 2 in order, so
-// each plan sees exactly the launch sequence sfac_step would give it.
 template <typename T>
-void group_plan(std::vector<GroupLaunch>* out, std::vector<unsigned char>* host,
-                const std::vector<int64_t>& bounds, const std::vector<sfac_plan>& plans,
-                const std::vector<void*>& us, const std::vector<int64_t>& steps) {
-    auto push = [&](const void* p, size_t n) {
-        size_t off = align_up(host->size(), 256);
-        host->resize(off + n);
-        memcpy(host->data() + off, p, n);
-        return off;
-    };
-    int64_t done = 0;
-    for (size_t ph = 0; ph < bounds.size(); ++ph) {
-        const int64_t bound = bounds[ph];
-        for (int pass = 0; pass < 3; ++pass) {
-            std::vector<std::pair<int, int>> keys;   // (kernel kind, variant): see launch_axis_pass_multi
-            std::vector<std::vector<sfac::PassDesc<T>>> groups;
-            std::vector<size_t> glds;
-            for (size_t i = 0; i < plans.size(); ++i) {
-                sfac_plan p = plans[i];
-                if (steps[i] < bound || pass >= p->in.dims) continue;
-                sfac::PassDesc<T> d = make_desc<T>(p->in, pass, p->dev, static_cast<T*>(us[i]), p->stat_max(),
-                                                   p->stat_flags());
-                const int kind = d.method == SFAC_METHOD_EMBED ? 1 : (d.d2a > 0 ? 2 : 0);
-                const int variant = kind == 1 ? d.log2m * 8 + d.log2e + (d.stage ? 128 : 0)
-                                              : (kind == 2 ? d.d2a * 64 + d.d2b + (d.d2wave ? 4096 : 0) : 0);
-                const std::pair<int, int> key(kind, variant);
-                size_t g = std::find(keys.begin(), keys.end(), key) - keys.begin();
-                if (g == keys.size()) {
-                    keys.push_back(key);
-                    groups.emplace_back();
-                    glds.push_back(0);
-                }
-                groups[g].push_back(d);
-                glds[g] = std::max(glds[g], p->in.ax[pass].lds);
+const sfac::PassDesc<T>& host_desc(const sfac_plan_s* p, int a) {
+    if constexpr (std::is_same<T, double>::value)
+        return p->d64[a];
+    else
+        return p->d32[a];
+}
+template <typename T>
+sfac::GroupArgs<T>& launch_args(GroupLaunch& l) {
+    if constexpr (std::is_same<T, double>::value)
+        return l.a64;
+    else
+        return l.a32;
+}
+
+// The launches of one step of a phase for the plans of arithmetic T: for pass 0, 1, 2 in turn,
+// one launch per kernel variant (at most kGroupSlots instances each), so every plan sees the
+// launch sequence a lone sfac_step gives it.
+template <typename T>
+void phase_launches(const std::vector<PhaseEntry>& entries, std::vector<GroupLaunch>* out) {
+    constexpr bool f64 = std::is_same<T, double>::value;
+    for (int pass = 0; pass < 3; ++pass) {
+        std::vector<std::pair<int, int>> keys;   // (kernel kind, variant): see launch_axis_pass_multi
+        std::vector<std::vector<const PhaseEntry*>> members;
+        for (const PhaseEntry& e : entries) {
+            sfac_plan p = e.plan;
+            if ((p->in.dt == SFAC_FP64) != f64 || pass >= p->in.dims) continue;
+            const sfac::PassDesc<T>& d = host_desc<T>(p, pass);
+            const int kind = d.method == SFAC_METHOD_EMBED ? 1 : (d.d2a > 0 ? 2 : 0);
+            const int variant = kind == 1 ? d.log2m * 8 + d.log2e + (d.stage ? 128 : 0)
+                                          : (kind == 2 ? d.d2a * 64 + d.d2b + (d.d2wave ? 4096 : 0) : 0);
+            const std::pair<int, int> key(kind, variant);
+            const size_t g = std::find(keys.begin(), keys.end(), key) - keys.begin();
+            if (g == keys.size()) {
+                keys.push_back(key);
+                members.emplace_back();
             }
-            for (size_t g = 0; g < groups.size(); ++g) {
-                std::vector<int> starts(1, 0);
-                int threads = sfac::kBlockThreads;
-                if (keys[g].first == 1) {
-                    threads = 0;
-                    for (const auto& d : groups[g]) threads = std::max(threads, d.threads);
-                    const int E = 1 << sfac::embed_log2e((keys[g].second % 128) / 8, keys[g].second % 8);
-                    glds[g] = (size_t)threads * E * sizeof(sfac::cplx<T>);
-                } else if (keys[g].first == 2) {
-                    // a full block of P-thread lines (or of wavefronts of 64/P lines); lines beyond
-                    // a descriptor's lpb idle
-                    threads = 0;
-                    for (const auto& d : groups[g]) threads = std::max(threads, d.threads);
-                    const int v = keys[g].second % 4096;
-                    const int A = v / 64, B = v % 64, P = std::max(A, B);
-                    const int lines = keys[g].second >= 4096 ? (threads / 64) * (64 / P) : threads / P;
-                    glds[g] = (size_t)lines * sfac::diag2_line_stride(A, B, sizeof(sfac::cplx<T>)) * sizeof(sfac::cplx<T>);
-                }
-                for (const auto& d : groups[g]) starts.push_back(starts.back() + sfac::pass_blocks(d));
+            members[g].push_back(&e);
+        }
+        for (size_t g = 0; g < keys.size(); ++g) {
+            for (size_t first = 0; first < members[g].size(); first += sfac::kGroupSlots) {
+                const size_t last = std::min(members[g].size(), first + sfac::kGroupSlots);
                 GroupLaunch l;
-                l.off_desc = push(groups[g].data(), groups[g].size() * sizeof(sfac::PassDesc<T>));
-                l.off_start = push(starts.data(), starts.size() * sizeof(int));
-                l.ndesc = (int)groups[g].size();
-                l.blocks = starts.back();
-                l.reps = bound - done;
-                l.phase = (int)ph;
                 l.pass = pass;
-                l.fp64 = std::is_same<T, double>::value;
+                l.fp64 = f64;
                 l.kind = keys[g].first;
                 l.variant = keys[g].second;
+                sfac::GroupArgs<T>& args = launch_args<T>(l);
+                args.n = (int)(last - first);
+                args.start[0] = 0;
+                size_t lds = 0;
+                int threads = l.kind == 0 ? sfac::kBlockThreads : 0;
+                for (size_t i = first; i < last; ++i) {
+                    sfac_plan p = members[g][i]->plan;
+                    const sfac::PassDesc<T>& d = host_desc<T>(p, pass);
+                    const int k = (int)(i - first);
+                    args.desc[k] = p->template device_desc<T>(pass);
+                    args.u[k] = static_cast<T*>(members[g][i]->u);
+                    args.start[k + 1] = args.start[k] + sfac::pass_blocks(d);
+                    lds = std::max(lds, p->in.ax[pass].lds);
+                    if (l.kind != 0) threads = std::max(threads, d.threads);
+                }
+                if (l.kind == 1) {
+                    const int E = 1 << sfac::embed_log2e((l.variant % 128) / 8, l.variant % 8);
+                    lds = (size_t)threads * E * sizeof(sfac::cplx<T>);
+                } else if (l.kind == 2) {
+                    // a full block of P-thread lines (or of wavefronts of 64/P lines); lines beyond
+                    // a descriptor's lpb idle
+                    const int v = l.variant % 4096;
+                    const int A = v / 64, B = v % 64, P = std::max(A, B);
+                    const int lines = l.variant >= 4096 ? (threads / 64) * (64 / P) : threads / P;
+                    lds = (size_t)lines * sfac::diag2_line_stride(A, B, sizeof(sfac::cplx<T>)) * sizeof(sfac::cplx<T>);
+                }
                 l.threads = threads;
-                l.lds = glds[g];
+                l.lds = lds;
                 out->push_back(l);
             }
         }
-        done = bound;
     }
 }
 
-template <typename T>
-hipError_t group_launch(sfac_group g, const GroupLaunch& l, hipStream_t s) {
-    return sfac::launch_axis_pass_multi<T>(l.kind, l.variant, l.threads,
-                                           reinterpret_cast<const sfac::PassDesc<T>*>(g->arena + l.off_desc),
-                                           reinterpret_cast<const int*>(g->arena + l.off_start), l.ndesc,
-                                           l.blocks, l.lds, s);
+hipError_t group_launch(const GroupLaunch& l, hipStream_t s) {
+    return l.fp64 ? sfac::launch_axis_pass_multi<double>(l.kind, l.variant, l.threads, l.a64, l.lds, s)
+                  : sfac::launch_axis_pass_multi<float>(l.kind, l.variant, l.threads, l.a32, l.lds, s);
 }
 
 // Captures one step of a phase: pass after pass; the launches of one pass (different kernel
 // variants and arithmetic, disjoint plans) fan out over the auxiliary streams and join before
 // the next pass, so every plan still sees its passes in order.
-sfac_status capture_step(sfac_group g, const GroupLaunch* first, const GroupLaunch* last, hipGraph_t* graph) {
+sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch>& launches, hipGraph_t* graph) {
+    *graph = nullptr;
     hipError_t e = hipStreamBeginCapture(g->capture, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     hipError_t le = hipSuccess;
     for (int pass = 0; pass < 3 && le == hipSuccess; ++pass) {
         std::vector<const GroupLaunch*> ls;
-        for (const GroupLaunch* l = first; l != last; ++l)
-            if (l->pass == pass) ls.push_back(l);
+        for (const GroupLaunch& l : launches)
+            if (l.pass == pass) ls.push_back(&l);
         if (ls.empty()) continue;
         if (ls.size() == 1) {
-            le = ls[0]->fp64 ? group_launch<double>(g, *ls[0], g->capture) : group_launch<float>(g, *ls[0], g->capture);
+            le = group_launch(*ls[0], g->capture);
             continue;
         }
         le = hipEventRecord(g->fork, g->capture);
         const int used = (int)std::min<size_t>(ls.size(), sfac_group_s::kAux);
         for (int k = 0; k < used && le == hipSuccess; ++k) le = hipStreamWaitEvent(g->aux[k], g->fork, 0);
-        for (size_t k = 0; k < ls.size() && le == hipSuccess; ++k) {
-            hipStream_t s = g->aux[k % sfac_group_s::kAux];
-            le = ls[k]->fp64 ? group_launch<double>(g, *ls[k], s) : group_launch<float>(g, *ls[k], s);
-        }
+        for (size_t k = 0; k < ls.size() && le == hipSuccess; ++k) le = group_launch(*ls[k], g->aux[k % sfac_group_s::kAux]);
         for (int k = 0; k < used && le == hipSuccess; ++k) le = hipEventRecord(g->join[k], g->aux[k]);
         for (int k = 0; k < used && le == hipSuccess; ++k) le = hipStreamWaitEvent(g->capture, g->join[k], 0);
     }
     e = hipStreamEndCapture(g->capture, graph);
-    if (le != hipSuccess) {
+    if (le != hipSuccess || e != hipSuccess) {
         if (e == hipSuccess && *graph) (void)hipGraphDestroy(*graph);
-        return hip_fail(le, "grouped kernel launch during capture");
+        *graph = nullptr;
+        return le != hipSuccess ? hip_fail(le, "grouped kernel launch during capture")
+                                : hip_fail(e, "hipStreamEndCapture");
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    return SFAC_OK;
+}
+
+// The step graph of a phase: from the cache, or captured and instantiated (the least recently
+// used graph is dropped once the cache is full, after the stream has finished with it).
+sfac_status phase_graph(sfac_group g, const std::vector<PhaseEntry>& entries, hipGraphExec_t* exec) {
+    std::vector<std::pair<unsigned long long, void*>> key;
+    key.reserve(entries.size());
+    for (const PhaseEntry& e : entries) key.emplace_back(e.plan->id, e.u);
+    for (auto it = g->cache.begin(); it != g->cache.end(); ++it)
+        if (it->key == key) {
+            g->cache.splice(g->cache.begin(), g->cache, it);
+            *exec = g->cache.front().exec;
+            return SFAC_OK;
+        }
+    std::vector<GroupLaunch> launches;
+    phase_launches<double>(entries, &launches);
+    phase_launches<float>(entries, &launches);
+    size_t lds_need = 0;
+    for (const auto& l : launches) lds_need = std::max(lds_need, l.lds);
+    if (lds_need > 64 * 1024) {
+        hipError_t e = sfac::allow_lds<double>(lds_need);
+        if (e == hipSuccess) e = sfac::allow_lds<float>(lds_need);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
+    }
+    hipError_t e = g->ensure_streams();
+    if (e != hipSuccess) return hip_fail(e, "group streams and events");
+    GroupGraph gg;
+    gg.key = std::move(key);
+    sfac_status st = capture_step(g, launches, &gg.graph);
+    if (st != SFAC_OK) return st;
+    e = hipGraphInstantiate(&gg.exec, gg.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        sfac_group_s::destroy(gg);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    if (g->cache.size() >= sfac_group_s::kCache) {
+        e = hipStreamSynchronize(g->stream);   // the dropped graph may still be running
+        if (e != hipSuccess) {
+            sfac_group_s::destroy(gg);
+            return hip_fail(e, "hipStreamSynchronize");
+        }
+        sfac_group_s::destroy(g->cache.back());
+        g->cache.pop_back();
+    }
+    g->cache.push_front(std::move(gg));
+    *exec = g->cache.front().exec;
     return SFAC_OK;
 }
 
 sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void* const* u_dev,
                       const int64_t* nsteps) {
-    std::vector<sfac_plan> p64, p32;
-    std::vector<void*> u64, u32;
-    std::vector<int64_t> s64, s32, bounds;
-    size_t lds_need = 0;
+    std::vector<PhaseEntry> all;
+    std::vector<int64_t> steps, bounds;
     for (int32_t i = 0; i < count; ++i) {
         sfac_plan p = plans[i];
         if (!p) return fail(SFAC_EINVAL, "plan %d is NULL", i);
@@ -1182,62 +1315,28 @@ sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void*
         if (reinterpret_cast<uintptr_t>(u_dev[i]) % es) return fail(SFAC_EINVAL, "plan %d: misaligned state", i);
         for (int32_t j = 0; j < i; ++j)
             if (plans[j] == p && nsteps[j] > 0) return fail(SFAC_EINVAL, "plan %d appears twice", i);
-        (p->in.dt == SFAC_FP64 ? p64 : p32).push_back(p);
-        (p->in.dt == SFAC_FP64 ? u64 : u32).push_back(u_dev[i]);
-        (p->in.dt == SFAC_FP64 ? s64 : s32).push_back(nsteps[i]);
+        all.push_back(PhaseEntry{p, u_dev[i]});
+        steps.push_back(nsteps[i]);
         bounds.push_back(nsteps[i]);
-        lds_need = std::max(lds_need, p->in.lds_max);
     }
     if (bounds.empty()) return SFAC_OK;
     std::sort(bounds.begin(), bounds.end());
     bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
-    std::vector<GroupLaunch> plan;
-    g->host.clear();
-    group_plan<double>(&plan, &g->host, bounds, p64, u64, s64);
-    group_plan<float>(&plan, &g->host, bounds, p32, u32, s32);
-    for (const auto& l : plan) lds_need = std::max(lds_need, l.lds);
-    if (lds_need > 64 * 1024) {
-        hipError_t e = sfac::allow_lds<double>(lds_need);
-        if (e == hipSuccess) e = sfac::allow_lds<float>(lds_need);
-        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
-    }
-    // the arena (and the previous call's graphs) may still be in use by the previous call
-    hipError_t e = hipStreamSynchronize(g->stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    g->drop_graphs();
-    e = g->ensure_streams();
-    if (e != hipSuccess) return hip_fail(e, "group streams and events");
-    if (g->host.size() > g->arena_bytes) {
-        if (g->arena) (void)hipFree(g->arena);
-        g->arena = nullptr;
-        g->arena_bytes = 0;
-        e = hipMalloc(&g->arena, g->host.size());
-        if (e != hipSuccess)
-            return fail(SFAC_ENOMEM, "hipMalloc(%zu) for the launch arena: %s", g->host.size(), hipGetErrorString(e));
-        g->arena_bytes = g->host.size();
-    }
-    e = hipMemcpy(g->arena, g->host.data(), g->host.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy launch arena");
-    // phase after phase; one captured step per phase, replayed for the phase's steps
-    std::stable_sort(plan.begin(), plan.end(),
-                     [](const GroupLaunch& a, const GroupLaunch& b) { return a.phase < b.phase; });
-    size_t li = 0;
-    while (li < plan.size()) {
-        size_t lj = li;
-        while (lj < plan.size() && plan[lj].phase == plan[li].phase) ++lj;
-        hipGraph_t graph = nullptr;
-        sfac_status st = capture_step(g, plan.data() + li, plan.data() + lj, &graph);
-        if (st != SFAC_OK) return st;
-        g->graphs.push_back(graph);
+    // phase after phase (the maximal step ranges with a fixed set of active plans); one step
+    // graph per phase, replayed for the phase's steps
+    int64_t done = 0;
+    for (const int64_t bound : bounds) {
+        std::vector<PhaseEntry> active;
+        for (size_t i = 0; i < all.size(); ++i)
+            if (steps[i] >= bound) active.push_back(all[i]);
         hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-        g->execs.push_back(exec);
-        for (int64_t r = 0; r < plan[li].reps; ++r) {
-            e = hipGraphLaunch(exec, g->stream);
+        const sfac_status st = phase_graph(g, active, &exec);
+        if (st != SFAC_OK) return st;
+        for (int64_t r = done; r < bound; ++r) {
+            const hipError_t e = hipGraphLaunch(exec, g->stream);
             if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
         }
-        li = lj;
+        done = bound;
     }
     return SFAC_OK;
 }
@@ -1281,7 +1380,7 @@ sfac_status sfac_group_destroy(sfac_group g) {
     return SFAC_OK;
 }
 
-size_t sfac_group_device_bytes(sfac_group g) { return g ? g->arena_bytes : 0; }
+size_t sfac_group_device_bytes(sfac_group) { return 0; }
 
 sfac_status sfac_batch_create(sfac_batch* out, int32_t count, const sfac_instance_desc* desc, sfac_dtype dt,
                               void* hip_stream, const sfac_options* opts) {

@@ -66,23 +66,57 @@ def short_name(name):
     return s.strip()
 
 
+MARK_TAG = "pass_timing_mark<"
+
+
+def axis_labels(names, dims, tags=PASS_KERNEL_TAGS):
+    """Axis (0-based) of every dispatch named by `tags` in a time-ordered list of kernel names,
+    None for the others. Steps launch the passes of axes 1..d in turn (the d-periodic order); the
+    timed launches of sfac_plan_time_passes run one axis at a time, each block preceded by a
+    marker kernel named pass_timing_mark<axis> and the last followed by pass_timing_mark<0>.
+    Counts of the periodic order are kept per element type."""
+    out = []
+    periodic = {}
+    timing = None
+    for nm in names:
+        if MARK_TAG in nm:
+            a = int(nm.split(MARK_TAG, 1)[1].split(">", 1)[0])
+            timing = a - 1 if a > 0 else None
+            out.append(None)
+        elif any(t in nm for t in tags):
+            if timing is not None:
+                out.append(timing)
+            else:
+                et = "double" if "<double" in nm else "float"
+                k = periodic.get(et, 0)
+                out.append(k % dims)
+                periodic[et] = k + 1
+        else:
+            out.append(None)
+    return out
+
+
 def trace_axis_means(trace_csv, dims):
     """Mean duration (us) per (kernel, axis) of the pass-kernel dispatches in a kernel trace, one
-    list per element type; the axis is the dispatch's place in the d-periodic launch order."""
+    list per element type; the axis comes from axis_labels."""
     rows = sorted(_rows(trace_csv), key=lambda r: int(r["Start_Timestamp"]))
+    labels = axis_labels([r["Kernel_Name"] for r in rows], dims)
     seq = {}
-    for r in rows:
-        k = r["Kernel_Name"]
-        if not any(t in k for t in PASS_KERNEL_TAGS):
+    for r, a in zip(rows, labels):
+        if a is None:
             continue
+        k = r["Kernel_Name"]
         et = "double" if "<double" in k else "float"
-        seq.setdefault(et, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), short_name(k)))
+        seq.setdefault(et, [[] for _ in range(dims)])[a].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), short_name(k)))
     out = {}
-    for et, v in seq.items():
+    for et, per in seq.items():
         res = []
         for a in range(dims):
-            xs = [v[i][0] for i in range(a, len(v), dims)]
-            res.append({"axis": a + 1, "kernel": v[a][1], "dispatches": len(xs),
+            xs = [x for x, _ in per[a]]
+            if not xs:
+                continue
+            res.append({"axis": a + 1, "kernel": per[a][0][1], "dispatches": len(xs),
                         "mean_us": sum(xs) / len(xs) / 1e3, "min_us": min(xs) / 1e3, "max_us": max(xs) / 1e3})
         out[et] = res
     return out
@@ -129,20 +163,22 @@ def _pass_counters(pmc_csv, counter, dims, tags=PASS_KERNEL_TAGS):
     per_dispatch = {}
     names = {}
     for r in rows:
-        if not any(t in r["Kernel_Name"] for t in tags):
+        if not (any(t in r["Kernel_Name"] for t in tags) or MARK_TAG in r["Kernel_Name"]):
             continue
         d = int(r["Dispatch_Id"])
         per_dispatch[d] = per_dispatch.get(d, 0.0) + float(r["Counter_Value"])
-        names[d] = short_name(r["Kernel_Name"])
+        names[d] = r["Kernel_Name"]
     order = sorted(per_dispatch)
+    labels = axis_labels([names[d] for d in order], dims, tags)
     sums = [0.0] * dims
     counts = [0] * dims
     kern = [None] * dims
-    for i, d in enumerate(order):
-        a = i % dims
+    for d, a in zip(order, labels):
+        if a is None:
+            continue
         sums[a] += per_dispatch[d]
         counts[a] += 1
-        kern[a] = names[d]
+        kern[a] = short_name(names[d])
     return [s / c if c else None for s, c in zip(sums, counts)], counts, kern
 
 
@@ -388,7 +424,7 @@ def _main():
     lines += ["", f"bench.py in the same session (no profiler): FP64 {bench['ms_per_step'] * 1e3:.2f} us/step, "
               f"pass us {[round(x * 1e3, 2) for x in bench['roofline']['pass_ms']]}; FP32 "
               f"{bench['fp32']['ms_per_step'] * 1e3:.2f} us/step, pass us "
-              f"{[round(x * 1e3, 2) for x in bench['fp32']['pass_ms']]}.", ""]
+              f"{[round(x * 1e3, 2) for x in bench['fp32']['roofline']['pass_ms']]}.", ""]
     scheds = _schedules(os.path.join(d, f"bench_{w}.err"))
     rec_all = {}
     try:

@@ -50,12 +50,33 @@ class Ticket:
         return None if self.finished is None else self.finished - self.arrival
 
 
+def initial_flags(u0):
+    """(flags, max|u|) of a state no step has touched: the same sticky bits the library sets
+    (non-finite values; some |u| > 1)."""
+    from .sfac import FLAG_ABOVE_ONE, FLAG_NONFINITE
+    a = np.abs(np.asarray(u0, dtype=np.float64))
+    if a.size == 0:
+        return 0, 0.0
+    flags = 0 if np.all(np.isfinite(a)) else FLAG_NONFINITE
+    fin = a[np.isfinite(a)]
+    vmax = float(fin.max()) if fin.size else 0.0
+    if vmax > 1.0:
+        flags |= FLAG_ABOVE_ONE
+    return flags, vmax
+
+
 class GpuExecutor:
     """Device side of the server: one plan and one device-resident state per admitted request,
     one group for the grouped steps, all on one stream. Plans take the autotuned schedule of
     their shape when the schedule table (`schedule_table`: a cache file path; default the
     packaged MI355X table; False for automatic schedules only) holds it; nothing is tuned
-    while serving."""
+    while serving.
+
+    A request's device memory is what the library reports for its plan
+    (sfac_plan_device_bytes: tables, status, descriptors) plus its state; the plan is built when
+    the server first asks for that figure and kept for the admission. `step` only queues the
+    grouped launches (the host goes on admitting while the device runs); `retire` waits for the
+    request's work and reads its state back."""
 
     on_device = True
 
@@ -68,39 +89,56 @@ class GpuExecutor:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.group = sfac.Group(self.stream)
         self.table = {} if schedule_table is False else autotune.load_table(schedule_table)
+        self._built = {}          # id(inst) -> (inst, dtype, plan), plans built for bytes_needed
+
+    def _plan(self, inst, dtype):
+        key = id(inst)
+        hit = self._built.get(key)
+        if hit is not None and hit[0] is inst and hit[1] == dtype:
+            return hit[2]
+        sched = self.autotune.lookup(inst.ns, dtype, table=self.table) if self.table else None
+        plan = self.sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype,
+                              stream=self.stream, use_graph=False, **(sched or {}))
+        if len(self._built) >= 4:                 # requests that were measured but never admitted
+            old = next(iter(self._built))
+            self._built.pop(old)[2].close()
+        self._built[key] = (inst, dtype, plan)
+        return plan
 
     def bytes_needed(self, inst, dtype):
         esize = 8 if dtype == "f64" else 4
-        tables = 0
-        for n in inst.ns:
-            m = 2
-            while m < 2 * n - 1:
-                m *= 2
-            tables += 4 * m * 2 * esize + 1024        # twiddles, two spectra, alignment
-        return int(np.prod(inst.ns)) * esize + tables + 256
+        return int(np.prod(inst.ns)) * esize + int(self._plan(inst, dtype).device_bytes)
 
     def admit(self, inst, dtype):
         torch = self.torch
         tdt = torch.float64 if dtype == "f64" else torch.float32
-        sched = self.autotune.lookup(inst.ns, dtype, table=self.table) if self.table else None
+        plan = self._plan(inst, dtype)
+        self._built.pop(id(inst), None)
+        # the upload is queued behind the grouped steps already on the stream (pinned source,
+        # kept alive with the handle), so admitting does not wait for them
+        host = torch.as_tensor(np.asarray(inst.u0), dtype=tdt).pin_memory()
         with torch.cuda.stream(self.stream):
-            plan = self.sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype,
-                                  stream=self.stream, use_graph=False, **(sched or {}))
-            u = torch.as_tensor(np.asarray(inst.u0), dtype=tdt).to("cuda", non_blocking=False)
-        return (plan, u)
+            u = host.to("cuda", non_blocking=True)
+        return (plan, u, host)
 
     def step(self, handles, nsteps):
         plans = [h[0] for h in handles]
         states = [h[1] for h in handles]
         self.group.step(plans, states, nsteps)
-        self.stream.synchronize()
 
     def retire(self, handle):
-        plan, u = handle
-        flags, vmax = plan.flags()
-        out = u.double().cpu().numpy()
+        plan, u, _ = handle
+        flags, vmax = plan.flags()                # waits for the plan's stream
+        with self.torch.cuda.stream(self.stream):
+            out = u.double().cpu().numpy()
         plan.close()
         return out, flags, vmax
+
+    def close(self):
+        for _, _, plan in self._built.values():
+            plan.close()
+        self._built.clear()
+        self.group.close()
 
 
 class Server:
@@ -131,16 +169,16 @@ class Server:
         t0 = self.clock()
         busy = 0.0
         admit_s = []         # per admitted request: plan tables, device upload of state and tables
-        while nxt < len(reqs) or queue or active:
-            now = self.clock() - t0
-            while nxt < len(reqs) and reqs[nxt].arrival <= now:
-                queue.append(reqs[nxt])
-                nxt += 1
-            # admission: first come first served while the head fits the budget
+
+        def admit(used):
             while queue and len(active) < self.max_active:
                 r = queue[0]
-                need = self.ex.bytes_needed(r.inst, r.dtype)
                 tk = tickets[r.rid]
+                if tk.steps < 0:                  # not a solve: refused, the stream goes on
+                    queue.popleft()
+                    tk.rejected = True
+                    continue
+                need = self.ex.bytes_needed(r.inst, r.dtype) if tk.steps > 0 else 0
                 if need > self.budget:
                     queue.popleft()
                     tk.rejected = True
@@ -152,12 +190,22 @@ class Server:
                 if tk.steps == 0:
                     tk.finished = tk.admitted
                     tk.result = np.array(r.inst.u0, dtype=np.float64, copy=True)
+                    tk.flags, tk.max_abs = initial_flags(tk.result)
                     continue
                 ta = self.clock()
                 handle = self.ex.admit(r.inst, r.dtype)
                 admit_s.append(self.clock() - ta)
                 active.append([tk, handle, tk.steps, need])
                 used += need
+            return used
+
+        while nxt < len(reqs) or queue or active:
+            now = self.clock() - t0
+            while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                queue.append(reqs[nxt])
+                nxt += 1
+            # admission: first come first served while the head fits the budget
+            used = admit(used)
             peak_active = max(peak_active, len(active))
             peak_bytes = max(peak_bytes, used)
             if active:
@@ -166,17 +214,31 @@ class Server:
                 self.ex.step([a[1] for a in active], k)
                 busy += self.clock() - ts
                 ticks += 1
+                # while the device runs the tick: take arrivals and admit what still fits (they
+                # join the next tick; the requests this tick finishes still hold their memory)
+                now = self.clock() - t0
+                while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                    queue.append(reqs[nxt])
+                    nxt += 1
+                n_before = len(active)
+                used = admit(used)
+                peak_bytes = max(peak_bytes, used)
+                joined = active[n_before:]
+                active = active[:n_before]
                 still = []
                 for a, kk in zip(active, k):
                     a[2] -= kk
                     if a[2] == 0:
                         tk = a[0]
+                        tr = self.clock()
                         tk.result, tk.flags, tk.max_abs = self.ex.retire(a[1])
+                        busy += self.clock() - tr
                         tk.finished = self.clock() - t0
                         used -= a[3]
                     else:
                         still.append(a)
-                active = still
+                active = still + joined
+                peak_active = max(peak_active, len(active))
             elif nxt < len(reqs) and not queue:
                 wait = reqs[nxt].arrival - (self.clock() - t0)
                 if wait > 0:
@@ -325,8 +387,8 @@ class Service:
                     self._count("rejected")
                     continue
                 if int(inst.steps) == 0:
-                    fut.set_result((np.array(inst.u0, dtype=np.float64, copy=True), 0,
-                                    float(np.abs(np.asarray(inst.u0)).max()) if np.size(inst.u0) else 0.0))
+                    u0 = np.array(inst.u0, dtype=np.float64, copy=True)
+                    fut.set_result((u0,) + initial_flags(u0))
                     self._count("completed")
                     continue
                 try:

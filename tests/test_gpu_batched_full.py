@@ -1,0 +1,96 @@
+"""The batched workload at its configured size: 64 independent 2D instances, n drawn from
+{63, 127, 255, 511, 1023} (seed 4), 500 steps each, through one batch (grouped launches of the
+embedded-method kernels at transform lengths 128 to 2048, with the packaged autotuned
+schedules, as bench.py runs it). Every instance ends bitwise equal to its lone plan; instances
+with n <= 255 and a seeded sample of the larger ones are checked against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sfac_oracle as O
+from paper_2209_08437_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+# FP32 over 500 steps with tau up to 1e-2 (T up to 5): the rounding of the FP32 transforms
+# accumulates every step and the nonlinear flow amplifies it near u = 0 by up to e^T
+FP32_TOL_BATCH = 1.5e-3
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(a, ref):
+    return float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+_ORACLE = {}
+
+
+def _oracle(i, inst):
+    """Oracle result of instance i and the spread of its FP64 evaluation orders (the floor below
+    which no FP64 evaluation of the run is reproducible; the FP64 bound is 1e-12 or twice it)."""
+    if i not in _ORACLE:
+        ops = O.axis_operators(inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau)
+        _say(f"    oracle for instance {i} (n = {inst.ns[0]}, {inst.steps} steps, three evaluation orders)")
+        ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps, ops=ops)
+        spread = O.rounding_spread(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps, ref,
+                                   ops=ops)
+        _ORACLE[i] = (ref, spread)
+    return _ORACLE[i]
+
+
+def _checked(insts):
+    """Every instance with n <= 255, plus one instance of each larger n (seeded choice)."""
+    rng = np.random.default_rng(40)
+    out = [i for i, inst in enumerate(insts) if inst.ns[0] <= 255]
+    for n in (511, 1023):
+        idx = [i for i, inst in enumerate(insts) if inst.ns[0] == n]
+        if idx:
+            out.append(int(rng.choice(idx)))
+    return out
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batched_workload_full_size(sfac_lib, dtype):
+    import torch
+    from paper_2209_08437_amd import autotune, sfac
+    insts = W.batched_2d()
+    sizes = sorted(set(i.ns[0] for i in insts))
+    _say(f"case batched workload {dtype}: {len(insts)} instances, n in {sizes}, {insts[0].steps} steps")
+    assert 511 in sizes and 1023 in sizes
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    sched = autotune.schedules(insts, dtype, path=None)
+    states = [torch.tensor(i.u0, dtype=tdt, device="cuda") for i in insts]
+    b = sfac.Batch(insts, dtype, schedules=sched)
+    b.step(states, [i.steps for i in insts])
+    torch.cuda.synchronize()
+    flags = [b.flags(k) for k in range(len(insts))]
+    b.close()
+    got = [u.double().cpu().numpy() for u in states]
+    del states
+    # every instance bitwise equal to a lone plan with the same schedule
+    for k, (inst, sch) in enumerate(zip(insts, sched)):
+        u = torch.tensor(inst.u0, dtype=tdt, device="cuda")
+        with sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dtype, **(sch or {})) as p:
+            p.step(u, inst.steps)
+        torch.cuda.synchronize()
+        assert np.array_equal(u.double().cpu().numpy(), got[k]), (dtype, k, inst.ns)
+        assert flags[k][0] == 0 and flags[k][1] <= 1.0, (k, flags[k])
+    _say(f"  all {len(insts)} bitwise equal to lone plans")
+    worst = 0.0
+    for k in _checked(insts):
+        inst = insts[k]
+        ref, floor = _oracle(k, inst)
+        e = rel_err(got[k], ref)
+        worst = max(worst, e)
+        tol = max(FP64_TOL, 4 * floor) if dtype == "f64" else FP32_TOL_BATCH
+        _say(f"  instance {k} n={inst.ns[0]} tau={inst.tau:.4f} T={inst.tau * inst.steps:.2f}: rel err {e:.3e} "
+             f"(oracle floor {floor:.2e}, bound {tol:.2e})")
+        assert e <= tol, (k, inst.ns, e, tol)
+    _say(f"  worst rel err against the oracle {worst:.3e}")

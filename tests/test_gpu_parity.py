@@ -24,8 +24,8 @@ from paper_2209_08437_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
-FP64_TOL_LONG = 1e-11
 FP32_TOL = 3e-4
+FP32_TOL_C2 = 5e-4
 
 
 def _torch():
@@ -442,15 +442,109 @@ def test_batch_with_schedules_matches_lone_plans(sfac_lib):
         b.close()
 
 
+_C2_ORACLE = {}
+
+
+def _c2_oracle():
+    """The 1023^2 workload over all 1000 steps by the oracle, and the spread of its three FP64
+    evaluation orders (dense factors in the paper's order, per-axis operators multiplied out,
+    Remark 1 through a library FFT) over the same run."""
+    if not _C2_ORACLE:
+        inst = W.large_2d_1023()
+        _say("  oracle, 1023^2 x 1000 steps, three evaluation orders (a minute or two on the host)")
+        ops = O.axis_operators(inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau)
+        def progress(k, _):
+            if k % 250 == 0:
+                _say(f"    oracle step {k}")
+        _C2_ORACLE["ref"] = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau,
+                                              inst.steps, ops=ops, observe=progress)
+        _C2_ORACLE["floor"] = O.rounding_spread(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau,
+                                                inst.steps, _C2_ORACLE["ref"], ops=ops)
+        _say(f"  oracle rounding floor (spread of its FP64 evaluation orders) {_C2_ORACLE['floor']:.3e}")
+    return _C2_ORACLE["ref"], _C2_ORACLE["floor"]
+
+
+@pytest.mark.timeout(900)
 def test_large_2d_1023_all_steps_fp64(sfac_lib):
     """The benchmark workload at full size and full length (1000 steps), in the launch
-    configuration bench.py times (packaged autotuned schedule, graph replays), against the oracle."""
+    configuration bench.py times (packaged autotuned schedule, graph replays), against the oracle.
+    Bound: 1e-12, or twice the spread of the oracle's own FP64 evaluation orders over the same
+    run when that is larger (the floor below which no FP64 evaluation is reproducible)."""
     inst = W.large_2d_1023()
     s = _bench_schedule(inst, "f64")
-    _say(f"case large_2d_1023 fp64 all {inst.steps} steps schedule {s} (oracle on the host, about a minute)")
+    _say(f"case large_2d_1023 fp64 all {inst.steps} steps schedule {s}")
     got, (flags, vmax) = gpu_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps, sched=s)
-    ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
+    ref, floor = _c2_oracle()
     e = rel_err(got, ref)
-    _say(f"  rel err {e:.3e} max|u| {vmax:.6f}")
-    assert e <= FP64_TOL_LONG
+    tol = max(FP64_TOL, 2 * floor)
+    _say(f"  rel err {e:.3e} (bound {tol:.3e}) max|u| {vmax:.6f}")
+    assert e <= tol
     assert flags == 0 and vmax <= 1.0
+
+
+@pytest.mark.timeout(900)
+def test_large_2d_1023_all_steps_fp32(sfac_lib):
+    """FP32 at full size and full length against the oracle, in bench.py's schedule."""
+    inst = W.large_2d_1023()
+    s = _bench_schedule(inst, "f32")
+    _say(f"case large_2d_1023 fp32 all {inst.steps} steps schedule {s}")
+    got, (flags, vmax) = gpu_solve(inst.u0.astype(np.float32), inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau,
+                                   inst.steps, "f32", sched=s)
+    ref, _ = _c2_oracle()
+    e = rel_err(got, ref)
+    _say(f"  fp32 rel err {e:.3e} (bound {FP32_TOL_C2:.1e}) max|u| {vmax:.6f}")
+    assert e <= FP32_TOL_C2
+    assert flags == 0 and vmax <= 1.0
+
+
+def test_group_graph_cache_and_plan_churn(sfac_lib):
+    """Grouped steps replay step graphs cached per (plan, state) set: repeated calls with the same
+    set, a new state for one plan, and plans closed and replaced between calls (a new plan may
+    reuse a closed one's host address) all end bitwise equal to lone plans."""
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    insts = W.batched_2d(count=10, steps=6, seed=31, sizes=(31, 63, 100, 127))
+    _say("case group graph cache and plan churn")
+
+    def lone(inst, dt, steps):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        u = torch.tensor(inst.u0, dtype=tdt, device="cuda")
+        with sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dt) as p:
+            p.step(u, steps)
+        torch.cuda.synchronize()
+        return u
+
+    dts = ["f64", "f32", "f64", "f32"]
+    g = sfac.Group()
+    live = []                                     # [inst, dtype, plan, state, steps done]
+    for k in range(4):
+        inst, dt = insts[k], dts[k]
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        live.append([inst, dt, sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dt),
+                     torch.tensor(inst.u0, dtype=tdt, device="cuda"), 0])
+    nxt = 4
+    for rnd in range(6):
+        ks = [2 + (rnd + j) % 3 for j in range(len(live))]
+        for _ in range(2):                        # the second call replays the cached graphs
+            g.step([e[2] for e in live], [e[3] for e in live], ks)
+            for e, kk in zip(live, ks):
+                e[4] += kk
+        torch.cuda.synchronize()
+        for e in live:
+            assert torch.equal(e[3], lone(e[0], e[1], e[4])), (rnd, e[0].ns, e[1])
+        if rnd == 2:                              # same plan, a fresh state tensor
+            e = live[0]
+            fresh = e[3].clone()
+            e[3] = fresh
+        # retire the oldest plan and admit a new instance in its place
+        old = live.pop(0)
+        old[2].close()
+        inst = insts[nxt % len(insts)]
+        dt = dts[nxt % 4]
+        nxt += 1
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        live.append([inst, dt, sfac.Plan(inst.ns, inst.alphas, inst.eps, inst.tau, inst.hs, dt),
+                     torch.tensor(inst.u0, dtype=tdt, device="cuda"), 0])
+    for e in live:
+        e[2].close()
+    g.close()

@@ -57,6 +57,44 @@ def test_served_results_equal_lone_solves(sfac_lib):
             assert np.abs(tk.result - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.timeout(600)
+def test_served_full_size_requests_equal_lone_solves(sfac_lib):
+    """Requests at the served stream's largest sizes (a 255^3 FP64 and a 1023^2 FP32 solve)
+    beside small ones, under a budget that holds both large ones at once: each result bitwise
+    equal to its lone solve."""
+    import torch
+    from paper_2209_08437_amd import autotune, serve, sfac
+    rng = np.random.default_rng(77)
+    reqs = []
+    specs = [((255, 255, 255), "f64", 30), ((1023, 1023), "f32", 60), ((40, 40, 40), "f32", 25),
+             ((300, 300), "f64", 45), ((31, 31, 31), "f64", 12)]
+    t = 0.0
+    for rid, (ns, dt, steps) in enumerate(specs):
+        t += 0.002
+        inst = W.Instance(ns, tuple(float(a) for a in rng.uniform(1.1, 1.9, len(ns))), float(rng.uniform(0.02, 0.2)),
+                          float(rng.uniform(1e-3, 1e-2)), W.mesh_widths(ns), steps)
+        inst.u0 = W.uniform_field(inst.shape, -0.9, 0.9, seed=300 + rid)
+        reqs.append(W.Request(rid, t, inst, dt))
+    ex = serve.GpuExecutor()
+    sizes = [ex.bytes_needed(r.inst, r.dtype) for r in reqs]
+    print(f"case served full-size requests, bytes {sizes}", flush=True)
+    srv = serve.Server(ex, budget_bytes=sum(sizes), tick_steps=20)
+    tickets, summ = srv.run(reqs)
+    ex.close()
+    assert summ["completed"] == len(reqs) and summ["peak_bytes"] <= sum(sizes)
+    for r, tk in zip(reqs, tickets):
+        i = r.inst
+        tdt = torch.float64 if r.dtype == "f64" else torch.float32
+        u = torch.tensor(i.u0, dtype=tdt, device="cuda")
+        # the server's plans take the packaged schedule of their shape (1023^2 has one)
+        sched = autotune.lookup(i.ns, r.dtype) or {}
+        with sfac.Plan(i.ns, i.alphas, i.eps, i.tau, i.hs, r.dtype, **sched) as p:
+            p.step(u, i.steps)
+        torch.cuda.synchronize()
+        assert np.array_equal(tk.result, u.double().cpu().numpy()), r.rid
+        assert tk.flags == 0 and tk.max_abs <= 1.0
+
+
 @pytest.mark.skip(reason="the one run of the online service with the device executor on its worker thread "
                          "ended in a host segmentation fault whose cause has not been found; the service "
                          "refuses device executors until it is")
@@ -67,7 +105,9 @@ def test_online_service_results_equal_lone_solves(sfac_lib):
     import torch
     from paper_2209_08437_amd import serve, sfac
     reqs = _stream(count=8, seed=23)
-    sizes = [serve.GpuExecutor.bytes_needed(None, r.inst, r.dtype) for r in reqs]
+    ex0 = serve.GpuExecutor()
+    sizes = [ex0.bytes_needed(r.inst, r.dtype) for r in reqs]
+    ex0.close()
     budget = max(sizes) + min(sizes)
     print(f"case online service, {len(reqs)} requests, budget {budget} B", flush=True)
     futs = {}

@@ -245,6 +245,60 @@ def test_step_matches_dense_kronecker(ns):
     assert np.allclose(O.strang_step(u0, ops, tau), ref1, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("ns", [(4, 3), (5, 5), (2, 3, 4), (3, 3, 3)])
+def test_composed_order_matches_dense_kronecker(ns):
+    """The second evaluation order (per-axis operators multiplied out, axes reversed) against the
+    same dense Kronecker brute force, over two steps."""
+    alphas = (1.25, 1.7, 1.45)[: len(ns)]
+    eps, tau = 0.35, 0.04
+    hs = W.mesh_widths(ns)
+    ops = O.axis_operators(ns, alphas, eps, hs, tau)
+    Ca = _kron_sum([o.C for o in ops])
+    Sa = _kron_sum([o.S for o in ops])
+    P = scipy.linalg.expm(0.5 * tau * Ca) @ scipy.linalg.expm(tau * Sa) @ scipy.linalg.expm(0.5 * tau * Ca)
+    u0 = W.uniform_field(tuple(reversed(ns)), -1, 1, seed=8)
+    f = lambda x: x / np.sqrt(x * x + (1 - x * x) * math.exp(-tau))
+    v = u0.reshape(-1)
+    for _ in range(2):
+        v = f(P @ f(v))
+    for rev in (True, False):
+        got = O.two_level_solve_composed(u0, ns, alphas, eps, hs, tau, 2, reverse_axes=rev)
+        assert np.allclose(got, v.reshape(u0.shape), rtol=0, atol=1e-13)
+    got = O.two_level_solve_fft(u0, ns, alphas, eps, hs, tau, 2)
+    assert np.allclose(got, v.reshape(u0.shape), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("N", [1, 2, 5, 16, 33])
+def test_fft_factors_match_dense_exponentials(N):
+    """Remark 1 through a library FFT against the dense e^{tC}, e^{tS} (themselves pinned to
+    scipy's expm), on every column of the identity, along either axis of a 2D array."""
+    op = O.AxisOperators(N, 1.35, 0.3, 2.0 / (N + 1), 0.07)
+    lam, mu = O.circulant_spectrum(op.C), O.skew_spectrum(op.S)
+    eye = np.eye(N)
+    assert np.allclose(O.apply_exp_circulant_fft(eye, lam, 0.5 * op.tau, 2), op.EC, rtol=0, atol=1e-14)
+    assert np.allclose(O.apply_exp_skew_fft(eye, mu, op.tau, 2), op.ES, rtol=0, atol=1e-14)
+    # axis 1 (the last array dimension) applies the matrix to rows: E X^T = (X E^T)^T
+    assert np.allclose(O.apply_exp_skew_fft(eye, mu, op.tau, 1), op.ES.T, rtol=0, atol=1e-14)
+
+
+def test_composed_order_agrees_with_paper_order_to_rounding():
+    """The three FP64 orders of eq. (finalstrang) on a 2D grid over 20 steps: the same values up
+    to the rounding of the evaluations (a few units of 1e-15 relative per step; a wrong factor
+    would differ by many orders of magnitude more)."""
+    ns = (40, 33)
+    alphas, eps, tau = (1.3, 1.7), 0.2, 0.01
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field((33, 40), -0.9, 0.9, seed=9)
+    a = O.two_level_solve(u0, ns, alphas, eps, hs, tau, 20)
+    b = O.two_level_solve_composed(u0, ns, alphas, eps, hs, tau, 20)
+    c = O.two_level_solve_fft(u0, ns, alphas, eps, hs, tau, 20)
+    for alt in (b, c):
+        rel = np.abs(a - alt).max() / np.abs(a).max()
+        assert 0 < rel < 20 * 2.5e-15
+    spread = O.rounding_spread(u0, ns, alphas, eps, hs, tau, 20, a)
+    assert spread == max(np.abs(a - b).max(), np.abs(a - c).max()) / np.abs(a).max()
+
+
 # --------------------------------------------------------------- invariants (P9)
 def test_invariants_2d():
     ns = (12, 9)

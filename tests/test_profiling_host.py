@@ -94,6 +94,40 @@ def test_trace_axis_means(tmp_path):
     assert m[0]["min_us"] == pytest.approx(2.0) and m[1]["max_us"] == pytest.approx(5.0)
 
 
+def test_axis_labels_follow_timing_marks():
+    """Steps give the d-periodic order; the timed launches of sfac_plan_time_passes come in
+    blocks, one axis each, announced by pass_timing_mark<axis> and closed by pass_timing_mark<0>."""
+    A = "void sfac::(anonymous namespace)::diag2_pass_single<double, 15, 17, true>(sfac::PassDesc<double>)"
+    B = "void sfac::(anonymous namespace)::diag2_pass_single<double, 15, 17, false>(sfac::PassDesc<double>)"
+    F = "void sfac::(anonymous namespace)::diag2_pass_single<float, 15, 17, false>(sfac::PassDesc<float>)"
+    mark = lambda a: f"void sfac::(anonymous namespace)::pass_timing_mark<{a}>()"
+    names = [A, B, B, F, A, B, B, COPY, F,
+             mark(1), A, A, mark(2), B, B, mark(3), B, B, mark(0),
+             F, A, B, B]
+    got = P.axis_labels(names, 3)
+    assert got == [0, 1, 2, 0, 0, 1, 2, None, 1,
+                   None, 0, 0, None, 1, 1, None, 2, 2, None,
+                   2, 0, 1, 2]
+
+
+def test_trace_axis_means_with_timed_blocks(tmp_path):
+    path = str(tmp_path / "trace.csv")
+    fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
+    mark = lambda a: f"void sfac::(anonymous namespace)::pass_timing_mark<{a}>()"
+    rows = [(PASS, 0, 2000), (PASS, 2000, 6000),                                    # one step
+            (mark(1), 6000, 6100), (PASS, 6100, 8100), (PASS, 8100, 10100),       # axis 1 timed
+            (mark(2), 10100, 10200), (PASS, 10200, 14200), (mark(0), 14200, 14300),
+            (PASS, 14300, 16300), (PASS, 16300, 20300)]                          # one more step
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(fields, r)))
+    m = P.trace_axis_means(path, 2)["double"]
+    assert [r["dispatches"] for r in m] == [4, 3]
+    assert m[0]["mean_us"] == pytest.approx(2.0) and m[1]["mean_us"] == pytest.approx(4.0)
+
+
 def test_traffic_record_used_only_for_current_code_and_schedule(tmp_path):
     sched = {"method": ["embed", "embed"], "elems_log2": [3, 3], "lines_per_block": [4, 4], "kernel": [0, 0]}
     rec = {"source_hash": P.source_hash(), "schedule": sched, "per_axis": [{"axis": 1, "bytes": 1}]}

@@ -116,6 +116,34 @@ def test_fifo_admission_and_continuous_joining():
     assert all(k <= 3 for tick in ex.log for _, k in tick)
 
 
+def test_server_refuses_negative_steps_and_flags_untouched_states():
+    """A request with negative steps is refused without stopping the stream; a zero-step
+    request returns its initial state with the flags the library would set for it."""
+    from paper_2209_08437_amd import sfac
+    clock = SimClock()
+    ex = OracleExecutor(clock)
+    reqs = _requests(4, seed=9)
+    reqs[1].inst.steps = -2
+    reqs[2].inst.steps = 0
+    reqs[2].inst.u0 = reqs[2].inst.u0 * 1.5            # |u0| > 1: outside the DMP's premise
+    srv = serve.Server(ex, budget_bytes=10 ** 9, tick_steps=5, clock=clock, sleep=clock.sleep)
+    tickets, summ = srv.run(reqs)
+    assert tickets[1].rejected and tickets[1].finished is None
+    assert summ["completed"] == 3 and summ["rejected"] == 1
+    t2 = tickets[2]
+    assert np.array_equal(t2.result, reqs[2].inst.u0)
+    assert t2.flags == sfac.FLAG_ABOVE_ONE and t2.max_abs == np.abs(reqs[2].inst.u0).max() > 1
+    bad = np.array(reqs[2].inst.u0)
+    bad[0, 0] = np.nan
+    f, m = serve.initial_flags(bad)
+    assert f & sfac.FLAG_NONFINITE and f & sfac.FLAG_ABOVE_ONE and np.isfinite(m)
+    assert serve.initial_flags(np.zeros((3, 3))) == (0, 0.0)
+    for i in (0, 3):
+        inst = reqs[i].inst
+        alone = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
+        assert np.array_equal(tickets[i].result, alone)
+
+
 def test_online_service_futures_from_several_threads():
     """Service: submissions from two threads, results through futures, bitwise equal to lone
     solves; an oversize request fails its future alone; close() drains; no submit afterwards."""
