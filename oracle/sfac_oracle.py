@@ -22,7 +22,10 @@ What it computes, in the paper's order and notation (Sec. 2):
   e^{tau/2 C_l}, one dense product per axis, axes in reverse order): a second FP64 evaluation
   order of eq. (finalstrang), used to measure the rounding floor of long runs;
 * the same step with every factor applied through Remark 1's diagonalisation by a library FFT
-  (a third FP64 evaluation order, for the same measurement);
+  (a third FP64 evaluation order, for the same measurement), and that evaluation carried out in
+  extended precision (numpy's longdouble, every table included): the reference long FP64 runs
+  are measured against, since the FP64 orders above differ from it by about as much as they
+  differ from each other;
 * eq. (strang) with eq. (linear_operator): the one-level scheme with the exact exponential
   e^{tau A}, used only to reproduce the paper's "Strang splitting" table columns;
 * Sec. 5, Example 5: the discrete free energy prod(h) (1/4 |u^2 - 1|^2 - 1/2 u^T A u).
@@ -46,56 +49,65 @@ __all__ = [
     "exp_symmetric", "nonlinear_flow", "AxisOperators", "axis_operators",
     "apply_along_axis", "two_level_step", "two_level_solve", "composed_operators",
     "two_level_solve_composed", "apply_exp_circulant_fft", "apply_exp_skew_fft",
-    "two_level_solve_fft", "rounding_spread", "strang_step",
+    "two_level_solve_fft", "extended_solve", "rounding_spread", "strang_step",
     "strang_solve", "discrete_energy",
 ]
 
 
 # ----------------------------------------------------------------------------- weights
-def g_coefficients(alpha, count):
+def _pi(dtype):
+    """pi in the precision of `dtype` (numpy's np.pi is a float64 constant)."""
+    return np.arccos(dtype(-1))
+
+
+def g_coefficients(alpha, count, dtype=np.float64):
     """g_0 .. g_{count-1} by the recursion of eq. (g_coe), Sec. 2.1:
-    g_0 = 1, g_{k+1} = (1 - (alpha + 1)/(k + 1)) g_k."""
-    g = np.empty(count, dtype=np.float64)
+    g_0 = 1, g_{k+1} = (1 - (alpha + 1)/(k + 1)) g_k. `dtype` is the arithmetic (float64, or
+    numpy's longdouble for the extended-precision reference)."""
+    alpha = dtype(alpha)
+    g = np.empty(count, dtype=dtype)
     g[0] = 1.0
     for k in range(count - 1):
         g[k + 1] = (1.0 - (alpha + 1.0) / (k + 1.0)) * g[k]
     return g
 
 
-def omega_weights(alpha, count):
+def omega_weights(alpha, count, dtype=np.float64):
     """omega_0 .. omega_{count-1} of eq. (omega_coe), Sec. 2.1:
     omega_0 = (alpha/2) g_0, omega_{k+1} = (alpha/2) g_{k+1} + ((2 - alpha)/2) g_k."""
-    g = g_coefficients(alpha, count)
-    w = np.empty(count, dtype=np.float64)
+    g = g_coefficients(alpha, count, dtype)
+    alpha = dtype(alpha)
+    w = np.empty(count, dtype=dtype)
     w[0] = 0.5 * alpha * g[0]
     for k in range(count - 1):
         w[k + 1] = 0.5 * alpha * g[k + 1] + 0.5 * (2.0 - alpha) * g[k]
     return w
 
 
-def riesz_factor(alpha, eps, h):
+def riesz_factor(alpha, eps, h, dtype=np.float64):
     """The scalar -eps^2 / (2 h^alpha cos(alpha pi / 2)) that multiplies D + D^T in eq. (B)
     (it is the factor of both sums in eq. (disFAC))."""
-    return -(eps * eps) / (2.0 * h ** alpha * np.cos(alpha * np.pi / 2.0))
+    alpha, eps, h = dtype(alpha), dtype(eps), dtype(h)
+    return -(eps * eps) / (2 * h ** alpha * np.cos(alpha * _pi(dtype) / 2))
 
 
 # ---------------------------------------------------------------------- Toeplitz matrix
-def matrix_D(alpha, N):
+def matrix_D(alpha, N, dtype=np.float64):
     """D_alpha of Sec. 2.1 as an N x N dense matrix (N = m - 1 interior nodes):
     entry (i, j) is omega_{i - j + 1} when i - j + 1 >= 0 and zero otherwise, i.e.
     omega_1 on the diagonal, omega_0 on the superdiagonal, omega_2, omega_3, ... below."""
-    w = omega_weights(alpha, N + 1)
+    w = omega_weights(alpha, N + 1, dtype)
     i = np.arange(N)[:, None]
     j = np.arange(N)[None, :]
     k = i - j + 1
-    D = np.where(k >= 0, w[np.clip(k, 0, N)], 0.0)
+    D = np.where(k >= 0, w[np.clip(k, 0, N)], dtype(0))
     return D
 
 
-def matrix_B(alpha, eps, h, N):
+def matrix_B(alpha, eps, h, N, dtype=np.float64):
     """B_alpha = kappa (D_alpha + D_alpha^T), eq. (B) of Sec. 2.1 (symmetric Toeplitz)."""
-    D = matrix_D(alpha, N)
-    return riesz_factor(alpha, eps, h) * (D + D.T)
+    D = matrix_D(alpha, N, dtype)
+    return riesz_factor(alpha, eps, h, dtype) * (D + D.T)
 
 
 def toeplitz_column(B):
@@ -138,35 +150,37 @@ def circulant_skew_split(B):
 
 
 # -------------------------------------------------------------------------- Remark 1
-def fourier_matrix(N):
+def fourier_matrix(N, dtype=np.float64):
     """The unitary Fourier matrix of Remark 1: F[j, k] = exp(2 pi i j k / N) / sqrt(N).
     The angle is reduced exactly in integers (j k mod N) before the trigonometric call."""
     j = np.arange(N, dtype=np.int64)[:, None]
     k = np.arange(N, dtype=np.int64)[None, :]
     r = (j * k) % N
-    ang = 2.0 * np.pi * r.astype(np.float64) / N
-    return (np.cos(ang) + 1j * np.sin(ang)) / np.sqrt(N)
+    ang = 2 * _pi(dtype) * r.astype(dtype) / dtype(N)
+    return (np.cos(ang) + 1j * np.sin(ang)) / np.sqrt(dtype(N))
 
 
-def skew_diagonal(N):
+def skew_diagonal(N, dtype=np.float64):
     """Psi = diag(1, e^{-i pi/N}, ..., e^{-i pi (N-1)/N}) of Remark 1, as a vector."""
-    k = np.arange(N, dtype=np.float64)
-    ang = -np.pi * k / N
+    k = np.arange(N, dtype=dtype)
+    ang = -_pi(dtype) * k / dtype(N)
     return np.cos(ang) + 1j * np.sin(ang)
 
 
 def circulant_spectrum(C):
     """Eigenvalues of the circulant C by Remark 1: F C e_1 = Lambda_C 1 / sqrt(N), so
-    lambda = sqrt(N) F (C e_1). C is symmetric, so lambda is real."""
+    lambda = sqrt(N) F (C e_1). C is symmetric, so lambda is real. Computed in C's precision."""
     N = C.shape[0]
-    lam = np.sqrt(N) * (fourier_matrix(N) @ C[:, 0])
+    dt = C.dtype.type
+    lam = np.sqrt(dt(N)) * (fourier_matrix(N, dt) @ C[:, 0])
     return lam.real
 
 
 def skew_spectrum(S):
     """Eigenvalues of the skew-circulant S by Remark 1: F Psi S e_1 = Lambda_S 1 / sqrt(N)."""
     N = S.shape[0]
-    mu = np.sqrt(N) * (fourier_matrix(N) @ (skew_diagonal(N) * S[:, 0]))
+    dt = S.dtype.type
+    mu = np.sqrt(dt(N)) * (fourier_matrix(N, dt) @ (skew_diagonal(N, dt) * S[:, 0]))
     return mu.real
 
 
@@ -201,22 +215,38 @@ def exp_symmetric(B, t):
 def nonlinear_flow(v, t):
     """J^Q_t of eq. (nonlinear_operator): v / sqrt(v^2 + (1 - v^2) e^{-2t}), the exact flow
     of the Bernoulli equation v' = v - v^3, applied pointwise."""
-    v = np.asarray(v, dtype=np.float64)
-    return v / np.sqrt(v * v + (1.0 - v * v) * np.exp(-2.0 * t))
+    v = np.asarray(v)
+    if v.dtype != np.longdouble:
+        v = v.astype(np.float64)
+    t = v.dtype.type(t)
+    return v / np.sqrt(v * v + (1 - v * v) * np.exp(-2 * t))
 
 
 # ---------------------------------------------------------------------- per-axis factors
 class AxisOperators:
     """Dense per-axis matrices for one axis: B, C, S and the factors exp(tau/2 C), exp(tau S),
-    plus the exact exp(tau B) on request."""
+    plus the exact exp(tau B) on request. `dtype` float64, or numpy's longdouble for the
+    extended-precision reference (which uses only B, C, S and the spectra: the dense factors
+    are formed on first use)."""
 
-    def __init__(self, N, alpha, eps, h, tau):
+    def __init__(self, N, alpha, eps, h, tau, dtype=np.float64):
         self.N, self.alpha, self.eps, self.h, self.tau = N, alpha, eps, h, tau
-        self.B = matrix_B(alpha, eps, h, N)
+        self.dtype = dtype
+        self.B = matrix_B(alpha, eps, h, N, dtype)
         self.C, self.S = circulant_skew_split(self.B)
-        self.EC = exp_circulant(self.C, 0.5 * tau)
-        self.ES = exp_skew(self.S, tau)
-        self._EB = None
+        self._EC = self._ES = self._EB = None
+
+    @property
+    def EC(self):
+        if self._EC is None:
+            self._EC = exp_circulant(self.C, 0.5 * self.tau)
+        return self._EC
+
+    @property
+    def ES(self):
+        if self._ES is None:
+            self._ES = exp_skew(self.S, self.tau)
+        return self._ES
 
     @property
     def EB(self):
@@ -225,9 +255,9 @@ class AxisOperators:
         return self._EB
 
 
-def axis_operators(ns, alphas, eps, hs, tau):
+def axis_operators(ns, alphas, eps, hs, tau, dtype=np.float64):
     """AxisOperators for axes 1..d (ns, alphas, hs are per-axis sequences, axis 1 first)."""
-    return [AxisOperators(int(n), float(a), float(eps), float(h), float(tau))
+    return [AxisOperators(int(n), float(a), float(eps), float(h), float(tau), dtype)
             for n, a, h in zip(ns, alphas, hs)]
 
 
@@ -294,13 +324,26 @@ def two_level_solve_composed(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, rev
     return u
 
 
+def _fft_module(x):
+    """numpy's FFT for float64 data; scipy's (which keeps numpy's longdouble) for the extended
+    reference, split over the host's threads."""
+    if x.dtype in (np.longdouble, np.clongdouble):
+        import os
+        import scipy.fft as sfft
+        w = os.cpu_count() or 1
+        return (lambda a, axis: sfft.fft(a, axis=axis, workers=w)), (lambda a, axis: sfft.ifft(a, axis=axis, workers=w))
+    return np.fft.fft, np.fft.ifft
+
+
 def apply_exp_circulant_fft(x, lam, t, axis):
     """e^{t C} along the paper's axis `axis` through Remark 1 with a library FFT: C = F* Lambda F
     with F = sqrt(N) ifft (the e^{+2 pi i j k / N} / sqrt(N) of Remark 1) and F* = fft / sqrt(N)."""
     ax = x.ndim - axis
     shape = [1] * x.ndim
     shape[ax] = -1
-    return np.fft.fft(np.exp(t * lam).reshape(shape) * np.fft.ifft(x, axis=ax), axis=ax).real
+    fft, ifft = _fft_module(x)
+    e = np.exp(lam.dtype.type(t) * lam).reshape(shape)
+    return fft(e * ifft(x, axis=ax), axis=ax).real
 
 
 def apply_exp_skew_fft(x, mu, t, axis):
@@ -309,32 +352,43 @@ def apply_exp_skew_fft(x, mu, t, axis):
     N = x.shape[ax]
     shape = [1] * x.ndim
     shape[ax] = -1
-    psi = skew_diagonal(N).reshape(shape)
-    y = np.fft.ifft(psi * x, axis=ax)
-    return (np.conj(psi) * np.fft.fft(np.exp(t * mu).reshape(shape) * y, axis=ax)).real
+    fft, ifft = _fft_module(x)
+    psi = skew_diagonal(N, x.dtype.type).reshape(shape)
+    e = np.exp(mu.dtype.type(t) * mu).reshape(shape)
+    y = ifft(psi * x, axis=ax)
+    return (np.conj(psi) * fft(e * y, axis=ax)).real
 
 
-def two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=None):
-    """The scheme of two_level_solve evaluated a third way: every factor applied through the
-    diagonalisation of Remark 1 with a library FFT instead of a dense product, in the paper's
-    factor order. Equal to two_level_solve in exact arithmetic; used beside
-    two_level_solve_composed to measure how far FP64 evaluations of a long run spread."""
-    u = np.array(u0, dtype=np.float64, copy=True)
-    if ops is None:
-        ops = axis_operators(ns, alphas, eps, hs, tau)
+def two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, dtype=np.float64):
+    """The scheme of two_level_solve evaluated through Remark 1's diagonalisation with a library
+    FFT instead of dense products, in the paper's factor order. In float64 it is a third
+    evaluation order (used beside two_level_solve_composed to measure how far FP64 evaluations
+    of a long run spread). With dtype=numpy.longdouble every table (g, omega, B, C, S, the
+    spectra, Psi) and every operation is carried in extended precision (64-bit significand on
+    x86, unit roundoff 2^-64): the reference the FP64 results are measured against, about 2000
+    times more precise than any FP64 evaluation. Returns an array of `dtype`."""
+    u = np.array(u0, dtype=dtype, copy=True)
+    if ops is None or ops[0].dtype != dtype:
+        ops = axis_operators(ns, alphas, eps, hs, tau, dtype)
     lams = [circulant_spectrum(op.C) for op in ops]
     mus = [skew_spectrum(op.S) for op in ops]
     d = u.ndim
+    half = dtype(tau) / 2
     for _ in range(nsteps):
-        u = nonlinear_flow(u, 0.5 * tau)
+        u = nonlinear_flow(u, half)
         for ax in range(1, d + 1):
-            u = apply_exp_circulant_fft(u, lams[ax - 1], 0.5 * tau, ax)
+            u = apply_exp_circulant_fft(u, lams[ax - 1], half, ax)
         for ax in range(1, d + 1):
-            u = apply_exp_skew_fft(u, mus[ax - 1], tau, ax)
+            u = apply_exp_skew_fft(u, mus[ax - 1], dtype(tau), ax)
         for ax in range(1, d + 1):
-            u = apply_exp_circulant_fft(u, lams[ax - 1], 0.5 * tau, ax)
-        u = nonlinear_flow(u, 0.5 * tau)
+            u = apply_exp_circulant_fft(u, lams[ax - 1], half, ax)
+        u = nonlinear_flow(u, half)
     return u
+
+
+def extended_solve(u0, ns, alphas, eps, hs, tau, nsteps):
+    """two_level_solve_fft in numpy's longdouble: the extended-precision reference."""
+    return two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, dtype=np.longdouble)
 
 
 def rounding_spread(u0, ns, alphas, eps, hs, tau, nsteps, ref, ops=None):

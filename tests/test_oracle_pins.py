@@ -268,6 +268,72 @@ def test_composed_order_matches_dense_kronecker(ns):
     assert np.allclose(got, v.reshape(u0.shape), rtol=0, atol=1e-13)
 
 
+def test_extended_precision_is_in_effect():
+    """The extended-precision reference needs a wider type than float64 (x86's 80-bit long
+    double: 64-bit significand); its Fourier matrix is unitary to that precision."""
+    assert np.finfo(np.longdouble).eps < 1e-18
+    F = O.fourier_matrix(33, np.longdouble)
+    assert F.dtype == np.clongdouble
+    err = np.abs(F @ F.conj().T - np.eye(33)).max()
+    assert err < 1e-17
+    # the same spectra as the float64 tables, to float64 rounding
+    op64 = O.AxisOperators(37, 1.45, 0.2, 2.0 / 38, 0.01)
+    opx = O.AxisOperators(37, 1.45, 0.2, 2.0 / 38, 0.01, np.longdouble)
+    for f in (lambda o: O.circulant_spectrum(o.C), lambda o: O.skew_spectrum(o.S)):
+        a, b = f(op64), f(opx)
+        assert b.dtype == np.longdouble
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+
+
+def test_extended_solve_eps0_closed_form():
+    """eps = 0 in extended precision: the linear part is the identity up to the rounding of the
+    transforms, so the run reproduces the Bernoulli closed form to long-double accuracy."""
+    ns = (12, 7)
+    u0 = W.uniform_field((7, 12), -0.99, 0.99, seed=14)
+    steps, tau = 30, 0.02
+    got = O.extended_solve(u0, ns, (1.5, 1.7), 0.0, W.mesh_widths(ns), tau, steps)
+    assert got.dtype == np.longdouble
+    u = u0.astype(np.longdouble)
+    closed = u / np.sqrt(u * u + (1 - u * u) * np.exp(-2 * np.longdouble(steps) * np.longdouble(tau)))
+    assert np.abs(got - closed).max() < 5e-17
+
+
+@pytest.mark.parametrize("ns", [(4, 3), (3, 3, 3)])
+def test_extended_solve_matches_dense_kronecker(ns):
+    """The extended-precision evaluation against the same dense Kronecker brute force (FP64)."""
+    alphas = (1.25, 1.7, 1.45)[: len(ns)]
+    eps, tau = 0.35, 0.04
+    hs = W.mesh_widths(ns)
+    ops = O.axis_operators(ns, alphas, eps, hs, tau)
+    Ca = _kron_sum([o.C for o in ops])
+    Sa = _kron_sum([o.S for o in ops])
+    P = scipy.linalg.expm(0.5 * tau * Ca) @ scipy.linalg.expm(tau * Sa) @ scipy.linalg.expm(0.5 * tau * Ca)
+    u0 = W.uniform_field(tuple(reversed(ns)), -1, 1, seed=8)
+    f = lambda x: x / np.sqrt(x * x + (1 - x * x) * math.exp(-tau))
+    v = u0.reshape(-1)
+    for _ in range(2):
+        v = f(P @ f(v))
+    got = O.extended_solve(u0, ns, alphas, eps, hs, tau, 2)
+    assert np.allclose(got.astype(np.float64), v.reshape(u0.shape), rtol=0, atol=1e-13)
+
+
+def test_fp64_orders_spread_around_the_extended_reference():
+    """Over a 300-step run the three FP64 evaluation orders each land within a few units of
+    1e-13 of the extended-precision result (their rounding, accumulated), and closer to it
+    than the run's own scale by far: the reference is what FP64 results are measured against."""
+    ns = (45, 31)
+    alphas, eps, tau = (1.3, 1.75), 0.15, 0.004
+    hs = W.mesh_widths(ns)
+    u0 = W.uniform_field((31, 45), -0.9, 0.9, seed=21)
+    x = O.extended_solve(u0, ns, alphas, eps, hs, tau, 300)
+    m = float(np.abs(x).max())
+    for alt in (O.two_level_solve(u0, ns, alphas, eps, hs, tau, 300),
+                O.two_level_solve_composed(u0, ns, alphas, eps, hs, tau, 300),
+                O.two_level_solve_fft(u0, ns, alphas, eps, hs, tau, 300)):
+        rel = float(np.abs(alt - x).max()) / m
+        assert 0 < rel < 1e-12
+
+
 @pytest.mark.parametrize("N", [1, 2, 5, 16, 33])
 def test_fft_factors_match_dense_exponentials(N):
     """Remark 1 through a library FFT against the dense e^{tC}, e^{tS} (themselves pinned to
