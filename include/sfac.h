@@ -325,6 +325,34 @@ sfac_status sfac_batch_destroy(sfac_batch b);
 /* sfac_batch_device_bytes - device memory the batch holds, excluding the states. */
 size_t sfac_batch_device_bytes(sfac_batch b);
 
+/* ---------------------------------------------------------------- solve without allocation
+ * For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): sfac_plan_create + sfac_step + sfac_plan_flags + sfac_plan_destroy in one call that
+ * allocates nothing on the device. The instance's tables and status words live in a workspace of
+ * 512 KiB that the library reserves in each device's memory once (held until the process ends);
+ * there is one workspace per device, shared by every call on it.
+ *
+ * sfac_solve_noalloc - advance u_dev by nsteps steps of eq. (finalstrang), in place, with the
+ * kernels and launch order sfac_step uses (the result is bitwise that of a plan with the same
+ * options), by plain launches on hip_stream.
+ *   dims .. dt, hip_stream, opt : as for sfac_plan_create (use_graph and graph_chunk ignored;
+ *                 SFAC_METHOD_EXACT is refused: it needs a state-sized buffer).
+ *   u_dev, nsteps : as for sfac_step.
+ *   flags, max_abs : if either is not NULL, the call waits for its work and writes the sticky
+ *                 status of this call's steps (as sfac_plan_flags); if both are NULL the call
+ *                 returns once the work is queued.
+ * The tables are built on the host at every call (milliseconds for N <= 1023) and copied into the
+ * workspace, ordered on hip_stream after the work already queued there. Calls that overlap on one
+ * device (different streams, or different host threads without ordering) race on the workspace:
+ * order them on one stream.
+ * Errors: as sfac_plan_create and sfac_step; SFAC_EUNSUPPORTED when the tables of the instance need
+ * more than the workspace holds (up to 192 KiB per axis: every 1D and 2D instance fits, and 3D
+ * instances with N_l <= 1023; three axes of N_l = 2048 do not).
+ */
+sfac_status sfac_solve_noalloc(int32_t dims, const int32_t* n_axis, const double* alpha_axis, double eps,
+                               double tau, const double* h_axis, sfac_dtype dt, void* u_dev, int64_t nsteps,
+                               void* hip_stream, const sfac_options* opt, uint32_t* flags, double* max_abs);
+
 #ifdef __cplusplus
 }
 #endif

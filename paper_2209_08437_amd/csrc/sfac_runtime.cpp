@@ -11,6 +11,7 @@
 #include <cstring>
 #include <list>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <system_error>
@@ -1449,3 +1450,121 @@ size_t sfac_batch_device_bytes(sfac_batch b) {
 }
 
 }  // extern "C"
+
+// ===================================================================== solve without allocation
+// sfac_solve_noalloc keeps an instance's tables and its status words in `scratch`, a fixed
+// array in device memory that the library image brings along (one copy per device, held until
+// the process ends), so the call allocates nothing on the device. Host code reaches it only
+// through the address hipGetSymbolAddress returns on each device: the array's name is a host
+// stand-in, not a device address.
+namespace {
+constexpr size_t kScratchBytes = size_t(512) << 10;
+constexpr int kScratchDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_lock;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+sfac_status scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kScratchDevices) return fail(SFAC_EUNSUPPORTED, "device %d: too many devices", dev);
+    std::lock_guard<std::mutex> guard(g_scratch_lock);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(SFAC_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SFAC_OK;
+}
+
+template <typename T>
+sfac_status noalloc_run(const Instance& in, unsigned char* base, size_t off_stat, T* u, int64_t nsteps,
+                        hipStream_t s) {
+    sfac::PassDesc<T> d[3];
+    auto* smax = reinterpret_cast<unsigned long long*>(base + off_stat);
+    auto* sflags = reinterpret_cast<unsigned int*>(base + off_stat + 8);
+    for (int a = 0; a < in.dims; ++a) d[a] = make_desc<T>(in, a, base, u, smax, sflags);
+    for (int64_t k = 0; k < nsteps; ++k)
+        for (int a = 0; a < in.dims; ++a) {
+            const hipError_t e = launch_pass(d[a], in.ax[a].lds, s);
+            if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        }
+    return SFAC_OK;
+}
+}  // namespace
+
+extern "C" sfac_status sfac_solve_noalloc(int32_t dims, const int32_t* n_axis, const double* alpha_axis, double eps,
+                                          double tau, const double* h_axis, sfac_dtype dt, void* u_dev, int64_t nsteps,
+                                          void* hip_stream, const sfac_options* opt, uint32_t* flags,
+                                          double* max_abs) {
+    g_error.clear();
+    if (dt != SFAC_FP64 && dt != SFAC_FP32) return fail(SFAC_EINVAL, "unknown dtype %d", (int)dt);
+    if (nsteps < 0) return fail(SFAC_EINVAL, "nsteps = %lld, expected >= 0", (long long)nsteps);
+    if (!u_dev) return fail(SFAC_EINVAL, "NULL state pointer");
+    const size_t es = dt == SFAC_FP64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(u_dev) % es) return fail(SFAC_EINVAL, "state pointer not aligned to %zu bytes", es);
+    if (opt) {
+        for (int a = 0; a < 3; ++a) {
+            if (opt->method[a] == SFAC_METHOD_EXACT)
+                return fail(SFAC_EUNSUPPORTED, "the exact exponential needs a plan (its scratch state is allocated)");
+            if (opt->method[a] < SFAC_METHOD_AUTO || opt->method[a] > SFAC_METHOD_EXACT)
+                return fail(SFAC_EINVAL, "unknown method %d for axis %d", opt->method[a], a + 1);
+            if (opt->lines_per_block[a] < 0 || opt->lines_per_block[a] > 256)
+                return fail(SFAC_EINVAL, "lines_per_block = %d for axis %d, expected 0..256", opt->lines_per_block[a],
+                            a + 1);
+        }
+    }
+    Instance in;
+    sfac_status st = build_instance(&in, dims, n_axis, alpha_axis, eps, tau, h_axis, dt, opt, "");
+    if (st != SFAC_OK) return st;
+    const size_t off_stat = align_up(in.table_bytes, 256);
+    const size_t total = off_stat + 256;
+    if (total > kScratchBytes)
+        return fail(SFAC_EUNSUPPORTED, "the tables need %zu bytes, more than the %zu bytes of the static workspace",
+                    total, kScratchBytes);
+    void* base = nullptr;
+    st = scratch_address(&base);
+    if (st != SFAC_OK) return st;
+    // tables and zeroed status words in one copy from host memory, ordered on the stream after
+    // the work already queued there (an earlier call's passes read the same workspace)
+    std::vector<unsigned char> host(total, 0);
+    for (int a = 0; a < in.dims; ++a) {
+        if (dt == SFAC_FP64)
+            axis_table_fill<double>(in.ax[a].host, in.ax[a], host.data());
+        else
+            axis_table_fill<float>(in.ax[a].host, in.ax[a], host.data());
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipMemcpyAsync(base, host.data(), total, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync tables");
+    if (in.lds_max > 64 * 1024) {
+        e = dt == SFAC_FP64 ? sfac::allow_lds<double>(in.lds_max) : sfac::allow_lds<float>(in.lds_max);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
+    }
+    unsigned char* b = static_cast<unsigned char*>(base);
+    st = dt == SFAC_FP64 ? noalloc_run<double>(in, b, off_stat, static_cast<double*>(u_dev), nsteps, s)
+                         : noalloc_run<float>(in, b, off_stat, static_cast<float*>(u_dev), nsteps, s);
+    if (st != SFAC_OK) return st;
+    if (flags || max_abs) {
+        unsigned char buf[16];
+        e = hipMemcpyAsync(buf, b + off_stat, 16, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "status read-back");
+        unsigned long long bits;
+        unsigned int fl;
+        memcpy(&bits, buf, 8);
+        memcpy(&fl, buf + 8, 4);
+        if (flags) *flags = fl;
+        if (max_abs) memcpy(max_abs, &bits, 8);
+    }
+    return SFAC_OK;
+}

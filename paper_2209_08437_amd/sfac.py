@@ -22,7 +22,7 @@ EXPORTS = [
     "sfac_batch_create", "sfac_batch_step", "sfac_batch_destroy", "sfac_batch_device_bytes",
     "sfac_axis_tables", "sfac_plan_time_passes", "sfac_group_create", "sfac_group_step",
     "sfac_group_destroy", "sfac_group_device_bytes", "sfac_batch_plan", "sfac_plan_energy",
-    "sfac_plan_trace", "sfac_plan_read_trace", "sfac_exact_exponential",
+    "sfac_plan_trace", "sfac_plan_read_trace", "sfac_exact_exponential", "sfac_solve_noalloc",
 ]
 
 
@@ -86,6 +86,10 @@ def lib():
     L.sfac_group_device_bytes.restype = ctypes.c_size_t
     L.sfac_batch_plan.argtypes = [vp, i32]
     L.sfac_batch_plan.restype = vp
+    L.sfac_solve_noalloc.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), dbl, dbl, ctypes.POINTER(dbl),
+                                     ctypes.c_int, vp, i64, vp, ctypes.POINTER(Options),
+                                     ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(dbl)]
+    L.sfac_solve_noalloc.restype = ctypes.c_int
     for name in ["sfac_group_create", "sfac_group_step", "sfac_group_destroy", "sfac_plan_time_passes", "sfac_axis_tables", "sfac_plan_create", "sfac_step", "sfac_plan_destroy", "sfac_plan_flags",
                  "sfac_plan_reset_flags", "sfac_plan_method", "sfac_batch_create",
                  "sfac_batch_step", "sfac_batch_destroy", "sfac_plan_energy",
@@ -186,6 +190,26 @@ def fill_options(opt, dims, method=None, elems_log2=None, lines_per_block=None, 
         if kernel is not None:
             opt.kernel[a] = int(per_axis(kernel, a) or 0)
     return opt
+
+
+def solve_noalloc(u, ns, alphas, eps, tau, hs, nsteps, dtype="f64", stream=None, method=None,
+                  elems_log2=None, lines_per_block=None, kernel=None):
+    """sfac_solve_noalloc: advance the GPU tensor u in place by nsteps steps without a plan and
+    without device allocation; returns (flags, max_abs) of those steps (waits for the work)."""
+    dims = len(ns)
+    dt = _dtype_code(dtype)
+    _check_state(u, tuple(reversed([int(n) for n in ns])), dt)
+    opt = Options()
+    fill_options(opt, dims, method=method, elems_log2=elems_log2, lines_per_block=lines_per_block, kernel=kernel)
+    n_arr = (ctypes.c_int32 * dims)(*[int(n) for n in ns])
+    a_arr = (ctypes.c_double * dims)(*[float(a) for a in alphas])
+    h_arr = (ctypes.c_double * dims)(*[float(h) for h in hs])
+    f = ctypes.c_uint32()
+    m = ctypes.c_double()
+    _check(lib().sfac_solve_noalloc(dims, n_arr, a_arr, float(eps), float(tau), h_arr, dt,
+                                    ctypes.c_void_p(u.data_ptr()), int(nsteps), _stream_handle(stream),
+                                    ctypes.byref(opt), ctypes.byref(f), ctypes.byref(m)))
+    return f.value, m.value
 
 
 class Plan:
