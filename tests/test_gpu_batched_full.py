@@ -2,7 +2,10 @@
 {63, 127, 255, 511, 1023} (seed 4), 500 steps each, through one batch (grouped launches of the
 embedded-method kernels at transform lengths 128 to 2048, with the packaged autotuned
 schedules, as bench.py runs it). Every instance ends bitwise equal to its lone plan; instances
-with n <= 255 and a seeded sample of the larger ones are checked against the oracle."""
+with n <= 255 and a seeded sample of the larger ones are checked against the oracle (FP64: within
+1e-12 or four times the spread of the oracle's own FP64 evaluation orders), and every n <= 127, a
+seeded part of the n = 255 ones and the sampled n = 511 and 1023 ones against the oracle's
+extended-precision evaluation (FP64: within fp64_bound)."""
 import sys
 
 import numpy as np
@@ -16,7 +19,16 @@ pytestmark = pytest.mark.gpu
 FP64_TOL = 1e-12
 # FP32 over 500 steps with tau up to 1e-2 (T up to 5): the rounding of the FP32 transforms
 # accumulates every step and the nonlinear flow amplifies it near u = 0 by up to e^T
+# (measured at most 7.5e-4)
 FP32_TOL_BATCH = 1.5e-3
+UNIT_ROUNDOFF = 2.0 ** -53
+
+
+def fp64_bound(inst):
+    """Bound of an FP64 result against the extended-precision reference: 1e-12, or, for long runs
+    of large T = steps tau, one unit roundoff per step amplified by the nonlinear flow's e^T (the
+    factors are contractions, Lemma 1 and 2; J^Q_t grows perturbations near u = 0 by at most e^t)."""
+    return max(FP64_TOL, inst.steps * UNIT_ROUNDOFF * float(np.exp(inst.steps * inst.tau)))
 
 
 def _say(msg):
@@ -42,6 +54,40 @@ def _oracle(i, inst):
                                    ops=ops)
         _ORACLE[i] = (ref, spread)
     return _ORACLE[i]
+
+
+_EXT = {}
+
+
+def _extended(i, inst):
+    """(indices, values, scale) of the extended-precision reference of instance i: computed here
+    for n <= 255, read from the sampled golden files for the larger ones."""
+    if i not in _EXT:
+        if inst.ns[0] <= 255:
+            _say(f"    extended-precision reference for instance {i} (n = {inst.ns[0]})")
+            x = O.extended_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
+            x = x.astype(np.float64).reshape(-1)
+            _EXT[i] = (np.arange(x.size), x, float(np.abs(x).max()))
+        else:
+            import json
+            import os
+            with open(os.path.join(os.path.dirname(__file__), "golden", f"extended_batched_2d_{i}.json")) as f:
+                d = json.load(f)
+            assert tuple(d["ns"]) == tuple(inst.ns) and d["steps"] == inst.steps and d["tau"] == inst.tau
+            _EXT[i] = (np.array(d["index"]), np.array(d["value"]), float(d["max_abs"]))
+    return _EXT[i]
+
+
+def _extended_checked(insts):
+    """Instances compared with the extended-precision reference: every n <= 127, a seeded third
+    of the n = 255 ones plus the one with the largest T, and the sampled n = 511 and 1023 ones."""
+    rng = np.random.default_rng(41)
+    small = [i for i, inst in enumerate(insts) if inst.ns[0] <= 127]
+    mid = [i for i, inst in enumerate(insts) if inst.ns[0] == 255]
+    pick = sorted(set(rng.choice(mid, max(1, len(mid) // 3), replace=False).tolist()
+                      + [max(mid, key=lambda i: insts[i].tau)]))
+    big = [i for i in _checked(insts) if insts[i].ns[0] > 255]
+    return small + pick + big
 
 
 def _checked(insts):
@@ -94,3 +140,14 @@ def test_batched_workload_full_size(sfac_lib, dtype):
              f"(oracle floor {floor:.2e}, bound {tol:.2e})")
         assert e <= tol, (k, inst.ns, e, tol)
     _say(f"  worst rel err against the oracle {worst:.3e}")
+    worst = 0.0
+    for k in _extended_checked(insts):
+        inst = insts[k]
+        idx, val, scale = _extended(k, inst)
+        e = float(np.abs(got[k].reshape(-1)[idx] - val).max() / scale)
+        tol = fp64_bound(inst) if dtype == "f64" else FP32_TOL_BATCH
+        worst = max(worst, e / tol)
+        _say(f"  instance {k} n={inst.ns[0]} T={inst.tau * inst.steps:.2f}: rel err against the extended-precision "
+             f"reference {e:.3e} (bound {tol:.2e})")
+        assert e <= tol, (k, inst.ns, e, tol)
+    _say(f"  largest error over its bound against the extended reference {worst:.3f}")

@@ -1,17 +1,18 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, element by element on
 seeded inputs, plus the invariants that hold at any size.
 
-Tolerances (relative max-norm, max|gpu - oracle| / max|oracle|):
-  FP64: 1e-12 for runs of up to a few hundred steps (measured <= 5.2e-13 at 200 steps).
-  FP64, the 1000-step 1023^2 run: 1e-11. Both sides round every transform; the rounding of one
-        step's operator is a fixed perturbation of size ~ u log2(M) per factor (u = 2^-53), and
-        with contractive factors (Lemma 1, 2) and the nonlinear Lipschitz factor e^{tau/2} per
-        half-step the deviation grows at most like steps * that size * e^T: about 6e-12 for 1000
-        steps of 6 length-2048 factor pairs at T = 1 (measured 3.3e-12).
-  FP32: 3e-4 for runs of up to a few hundred steps. The error is the random rounding of the
-        transform arithmetic, the same mechanism as in FP64 scaled by the unit-roundoff ratio
-        2^-24 / 2^-53 = 2^29: the FP64 path's <= 5.2e-13 becomes ~2.8e-4 (measured 2.5e-5 ..
-        1.0e-4); table rounding is not the dominant term (hi/lo tables did not reduce it).
+Tolerances (relative max-norm, max|gpu - reference| / max|reference|):
+  FP64: 1e-12 against the oracle for runs of up to a few hundred steps (measured <= 5.7e-13 at
+        200 steps). Over long runs an FP64 oracle cannot certify 1e-12: its own evaluation orders
+        (dense factors, per-axis operators multiplied out, Remark 1 through a library FFT) differ
+        from each other by their fixed rounding, which every step applies again and the nonlinear
+        flow amplifies near u = 0 by up to e^T (4.5e-12 over the 1000-step 1023^2 run). There the
+        bound against the FP64 oracle is twice that measured spread, and the benchmark spec's 1e-12 is
+        checked against the oracle's extended-precision evaluation (sampled, tests/golden).
+  FP32: per configuration, from the measured error with a margin of about two: 3e-4 for runs of up
+        to a few hundred steps (measured 2.5e-5 .. 1.0e-4), 5e-4 for the 1000-step 1023^2 run
+        (measured 2.5e-4). The error is the rounding of the FP32 transform arithmetic, accumulated
+        over the steps and amplified by the nonlinear flow.
 """
 import sys
 
@@ -445,6 +446,25 @@ def test_batch_with_schedules_matches_lone_plans(sfac_lib):
 _C2_ORACLE = {}
 
 
+class _extended:
+    """A sampled extended-precision reference from tests/golden (written by
+    make_extended_references.py, which calls only the oracle): rel_err(state) is the largest
+    deviation at the sampled positions over the reference state's max-norm."""
+
+    def __init__(self, name, inst):
+        import json
+        import os
+        with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+            d = json.load(f)
+        assert tuple(d["ns"]) == tuple(inst.ns) and d["steps"] == inst.steps and d["tau"] == inst.tau
+        self.index = np.array(d["index"], dtype=np.int64)
+        self.value = np.array(d["value"], dtype=np.float64)
+        self.scale = float(d["max_abs"])
+
+    def rel_err(self, state):
+        return float(np.abs(np.asarray(state).reshape(-1)[self.index] - self.value).max() / self.scale)
+
+
 def _c2_oracle():
     """The 1023^2 workload over all 1000 steps by the oracle, and the spread of its three FP64
     evaluation orders (dense factors in the paper's order, per-axis operators multiplied out,
@@ -480,6 +500,12 @@ def test_large_2d_1023_all_steps_fp64(sfac_lib):
     _say(f"  rel err {e:.3e} (bound {tol:.3e}) max|u| {vmax:.6f}")
     assert e <= tol
     assert flags == 0 and vmax <= 1.0
+    # against the extended-precision reference (sampled): the benchmark spec's bound itself
+    ext = _extended("extended_large_2d_1023.json", inst)
+    e_ext = ext.rel_err(got)
+    e_orc = ext.rel_err(ref)
+    _say(f"  sampled rel err against the extended-precision reference {e_ext:.3e} (the FP64 oracle's own: {e_orc:.3e})")
+    assert e_ext <= FP64_TOL
 
 
 @pytest.mark.timeout(900)
@@ -492,8 +518,10 @@ def test_large_2d_1023_all_steps_fp32(sfac_lib):
                                    inst.steps, "f32", sched=s)
     ref, _ = _c2_oracle()
     e = rel_err(got, ref)
-    _say(f"  fp32 rel err {e:.3e} (bound {FP32_TOL_C2:.1e}) max|u| {vmax:.6f}")
-    assert e <= FP32_TOL_C2
+    e_ext = _extended("extended_large_2d_1023.json", inst).rel_err(got)
+    _say(f"  fp32 rel err {e:.3e} (bound {FP32_TOL_C2:.1e}; sampled against the extended reference {e_ext:.3e}) "
+         f"max|u| {vmax:.6f}")
+    assert e <= FP32_TOL_C2 and e_ext <= FP32_TOL_C2
     assert flags == 0 and vmax <= 1.0
 
 
