@@ -80,7 +80,7 @@ def candidates(n):
     pair = [(a, b) for a, b in DIAG2_PAIRS if a * b == n]
     if pair:
         full = 256 // max(pair[0])          # lines of a whole 256-thread block
-        for lpb in sorted({0, 2, 5, 7, 10, full}):
+        for lpb in sorted({0, 2, 3, 4, 5, 6, 7, 10, full}):
             out.append(("diag", 0, lpb, 2))
         lpw = 64 // max(pair[0])
         for w in (0, 1, 2, 4):

@@ -111,13 +111,17 @@ struct Diag2Line {
         }
     }
 
+    // The eigenvalue factors are loaded after the forward transform, not before it: held across
+    // the transform they would keep B more values live at its peak and cost the kernel a third
+    // wavefront per SIMD (FP64 15 x 17: 202 against 156 VGPRs); their load latency is covered by
+    // the other wavefronts that the smaller register budget lets in.
     template <bool SKEW>
     __device__ __forceinline__ void factor(const Spec<T>* __restrict__ gpos, const cplx<T>* __restrict__ psipos,
                                            cplx<T>* line, int t) {
-        Spec<T> gv[B];
-        load_scale(gpos, gv, t);
         if constexpr (SKEW) psi_mul<false>(psipos, t);
         forward(line, t);
+        Spec<T> gv[B];
+        load_scale(gpos, gv, t);
         scale(gv, t);
         inverse(line, t);
         if constexpr (SKEW) psi_mul<true>(psipos, t);

@@ -600,12 +600,12 @@ __global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_multi(const Group
     run_embed_tile<T, LOG2M, LE, STAGE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
-// Waves per SIMD the register budget is cut for. The FP64 15 x 17 kernel with block barriers
-// holds 2.5 waves per SIMD at its tuned 7 lines per block (LDS); with the registers of two waves
-// it spills nothing and runs 4% faster on MI355X. The wavefront-aligned one keeps three.
+// Waves per SIMD the register budget is cut for: three (at most 168 VGPRs). Every pair fits
+// without spilling (FP64 15 x 17: 156 VGPRs); with six lines per block or the wavefront-aligned
+// layout the FP64 15 x 17 tiles also fit three wavefronts per SIMD in the LDS.
 template <typename T, int A, int B, bool WA>
 constexpr int diag2_min_waves() {
-    return (sizeof(T) == 8 && !WA && A * B == 255) ? 2 : 3;
+    return 3;
 }
 
 template <typename T, int A, int B, bool WA>

@@ -222,7 +222,8 @@ SQ_SETS = (("A", "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_
            ("B", "SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU "
                  "SQ_ACTIVE_INST_ANY SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64"))
 SQ_COMMAND = ("timeout -s KILL 90 rocprofv3 --pmc $COUNTERS --output-format csv -d $O/$SET_$W -o run -- "
-              "python3 $R/bench.py --workload $W --dtype f64 --no-cpu --no-fp32 --no-exact --steps 10 --warmup 2 --pass-reps 2")
+              "python3 $R/bench.py --workload $W --dtype f64 --no-cpu --no-fp32 --no-exact --no-sub --steps 10 --warmup 2 "
+              "--pass-reps 2")
 # MI355X: 256 CUs of 4 SIMDs; a SIMD issues one wavefront VALU instruction (FP64, or FP32 unpacked) every
 # 4 cycles at 2.4 GHz
 VALU_WAVE_INSTR_PER_US = 256 * 4 / 4 * 2400.0
@@ -234,16 +235,18 @@ def sq_axis_means(csv_path, dims, tags=PASS_KERNEL_TAGS):
     name of each axis."""
     per, names = {}, {}
     for r in _rows(csv_path):
-        if not any(t in r["Kernel_Name"] for t in tags):
+        if not (any(t in r["Kernel_Name"] for t in tags) or MARK_TAG in r["Kernel_Name"]):
             continue
         d = int(r["Dispatch_Id"])
         c = per.setdefault(d, {})
         c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
-        names[d] = short_name(r["Kernel_Name"])
+        names[d] = r["Kernel_Name"]
     order = sorted(per)
+    labels = axis_labels([names[d] for d in order], dims, tags)
+    names = {d: short_name(n) for d, n in names.items()}
     out = []
     for a in range(dims):
-        ds = order[a::dims]
+        ds = [d for d, lab in zip(order, labels) if lab == a]
         keys = set().union(*(per[d] for d in ds)) if ds else set()
         out.append({"kernel": names[ds[0]] if ds else None, "dispatches": len(ds),
                     **{k: sum(per[d].get(k, 0.0) for d in ds) / len(ds) for k in keys}})
@@ -350,9 +353,9 @@ def load_traffic(path, workload, dtype, schedule=None):
 # O the output directory; DT is f64 and f32 in turn)
 COMMANDS = """\
 python3 -m paper_2209_08437_amd.autotune --fresh --out $R/paper_2209_08437_amd/tuned_mi355x.json large_2d_1023 large_3d_255 plain_2d_63 batched_2d   # the packaged schedule table, tuned on an MI355X beforehand; every run below uses it
-rocprofv3 --kernel-trace --stats --output-format csv -d $O/trace_$W -o run -- python3 $R/bench.py --workload $W --no-cpu
-rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --steps 20 --warmup 2 --pass-reps 2
-rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --kernel-trace --stats --output-format csv -d $O/trace_$W -o run -- python3 $R/bench.py --workload $W --no-cpu --no-sub
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --steps 20 --warmup 2 --pass-reps 2
 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/copy_FETCH_SIZE -o run -- python3 $R/bench.py --copy-probe
 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/copy_WRITE_SIZE -o run -- python3 $R/bench.py --copy-probe"""
 
