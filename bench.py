@@ -347,29 +347,116 @@ def batched_run(args):
     }
 
 
-def served_run(args):
-    """A bounded sample of the served stream through the continuous-batching server."""
-    import numpy as np
-    from paper_2209_08437_amd import serve, workloads as W
-    reqs = W.served_stream(count=args.serve_count)
-    ex = serve.GpuExecutor()
-    srv = serve.Server(ex, budget_bytes=int(args.serve_budget_gb * 2 ** 30), tick_steps=args.tick_steps)
+class _StreamExecutor:
+    """The device executor for long served streams: a request's initial state is drawn from its
+    seed when it is admitted (not held for the whole stream) and results are not read back
+    (flags and max|u| only), so host memory stays bounded."""
+
+    def __init__(self):
+        from paper_2209_08437_amd import serve
+        self.ex = serve.GpuExecutor(keep_states=False)
+        self.on_device = True
+
+    def bytes_needed(self, inst, dtype):
+        return self.ex.bytes_needed(inst, dtype)
+
+    def admit(self, inst, dtype):
+        from paper_2209_08437_amd import workloads as W
+        inst.u0 = W.uniform_field(inst.shape, -0.9, 0.9, inst.seed)
+        try:
+            return self.ex.admit(inst, dtype)
+        finally:
+            inst.u0 = None
+
+    def step(self, handles, nsteps):
+        self.ex.step(handles, nsteps)
+
+    def retire(self, handle):
+        return self.ex.retire(handle)
+
+    def close(self):
+        self.ex.close()
+
+
+def _serve(reqs, args):
+    from paper_2209_08437_amd import serve
+    ex = _StreamExecutor()
+    def progress(done, total):
+        if done % 100 == 0 or done == total:
+            log(f"[bench]   {done}/{total} requests finished")
+    srv = serve.Server(ex, budget_bytes=int(args.serve_budget_gb * 2 ** 30), tick_steps=args.tick_steps,
+                       progress=progress)
     tickets, summ = srv.run(reqs)
+    ex.close()
+    return tickets, summ, srv
+
+
+def sustainable_rate(args):
+    """Highest arrival rate the server keeps up with, by bisection on the logarithm of the rate:
+    a stream of args.serve_probe_count requests of the served workload's mix is served at each
+    trial rate; the server keeps up when it serves at least 90% of the offered grid-point-steps
+    per second (the rest is the drain of the last requests). Each trial runs in a process of its
+    own (one server, one executor per process), started before this process touches the GPU."""
+    import math
+    import subprocess
+    lo, hi = args.serve_rate_lo, args.serve_rate
+    trials = []
+    for k in range(args.serve_bisect):
+        r = math.sqrt(lo * hi)
+        cmd = [sys.executable, os.path.abspath(__file__), "--workload", "served", "--serve-count",
+               str(args.serve_probe_count), "--serve-rate", repr(r), "--serve-seed", str(50 + k), "--serve-bisect",
+               "0", "--serve-budget-gb", repr(args.serve_budget_gb), "--tick-steps", str(args.tick_steps)]
+        res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+        if res.returncode != 0:
+            log(res.stderr[-2000:])
+            raise SystemExit(f"served probe at {r:.2f} req/s failed with status {res.returncode}")
+        summ = json.loads(res.stdout.strip().splitlines()[-1])
+        ratio = summ["served_fraction_of_offered"]
+        ok = ratio >= 0.9
+        trials.append({"rate": round(r, 2), "served_over_offered": round(ratio, 3), "keeps_up": ok,
+                       "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
+                       "makespan_s": round(summ["summary"]["makespan_s"], 2)})
+        log(f"[bench] served probe at {r:.1f} req/s: served/offered {ratio:.3f}, p99 {summ['p99_latency_s']:.2f} s")
+        if ok:
+            lo = r
+        else:
+            hi = r
+    return {"sustainable_rate_req_per_s": round(lo, 2), "first_rate_not_sustained": round(hi, 2),
+            "probe_requests": args.serve_probe_count, "criterion": "served >= 0.9 x offered grid-point-steps/s",
+            "trials": trials}
+
+
+def served_run(args):
+    """The served workload: the seeded Poisson stream (mean args.serve_rate req/s) of
+    args.serve_count requests through the continuous-batching server, then the highest
+    sustainable arrival rate by bisection."""
+    from paper_2209_08437_amd import workloads as W
+    sustainable = sustainable_rate(args) if args.serve_bisect > 0 else None
+    reqs = W.served_stream(count=args.serve_count, rate=args.serve_rate, seed=args.serve_seed, materialize=False)
     n3 = sum(1 for r in reqs if r.inst.dims == 3)
+    nf = sum(1 for r in reqs if r.dtype == "f32")
+    log(f"[bench] serving {len(reqs)} requests ({n3} 3D, {nf} FP32) arriving over {reqs[-1].arrival:.1f} s")
+    tickets, summ, srv = _serve(reqs, args)
+    bad = sum(1 for t in tickets if t.flags)
+    vmax = max((t.max_abs for t in tickets if t.finished is not None), default=0.0)
     log(f"[bench] served {summ['completed']}/{len(reqs)} requests in {summ['makespan_s']:.2f} s, "
         f"p50 {summ['p50_latency_s']:.3f} s p99 {summ['p99_latency_s']:.3f} s")
-    return {
+    out = {
         "metric": METRIC, "value": round(summ["throughput_gps"], 1), "unit": "grid-point-steps/s", "n_gpus": 1,
         "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": f"served solve stream: first {len(reqs)} requests of the seeded Poisson stream "
-                               f"(mean 200 req/s; {n3} 3D n in [31,255], {len(reqs) - n3} 2D n in [63,1023]; "
-                               "steps in [50,2000]; FP64:FP32 1:1)",
+        "config": {"workload": f"served solve stream: {len(reqs)} requests of the seeded Poisson stream "
+                               f"(mean {args.serve_rate:g} req/s; {n3} 3D n in [31,255], {len(reqs) - n3} 2D n in "
+                               f"[63,1023]; steps in [50,2000]; {nf} FP32, {len(reqs) - nf} FP64)",
                    "budget_bytes": srv.budget, "tick_steps": srv.tick_steps},
         "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
         "offered_gps": summ["offered_gps"], "served_fraction_of_offered": summ["throughput_gps"] / summ["offered_gps"],
+        "requests_flagged": bad, "max_abs": vmax,
         "summary": {k: v for k, v in summ.items() if k not in ("p50_latency_s", "p99_latency_s")},
     }
+    if sustainable is not None:
+        out["sustainable"] = sustainable
+    return out
 
 
 def cpu_leg(inst, seconds, checks=()):
@@ -486,7 +573,13 @@ def main():
                          "the schedules measured on an MI355X that ship with the package, read only; "
                          "'none': tune every axis afresh)")
     ap.add_argument("--batch-count", type=int, default=64)
-    ap.add_argument("--serve-count", type=int, default=48)
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrival rate of the served stream (req/s)")
+    ap.add_argument("--serve-bisect", type=int, default=6,
+                    help="bisection steps for the highest sustainable arrival rate (0: skip)")
+    ap.add_argument("--serve-rate-lo", type=float, default=2.0)
+    ap.add_argument("--serve-probe-count", type=int, default=150)
+    ap.add_argument("--serve-seed", type=int, default=5, help="seed of the served stream")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--tick-steps", type=int, default=50)
     ap.add_argument("--copy-probe", action="store_true",
@@ -497,17 +590,18 @@ def main():
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design note, not part of this build)", flush=True)
         sys.exit(2)
-    import torch
     from paper_2209_08437_amd import sfac, build_lib
     if not os.path.exists(sfac.LIB_PATH):
         build_lib.build()
+    if args.workload == "served":
+        # its rate probes run as child processes, started before this process touches the GPU
+        print(json.dumps(served_run(args)), flush=True)
+        return
+    import torch
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     if args.workload == "batched_2d":
         print(json.dumps(batched_run(args)), flush=True)
-        return
-    if args.workload == "served":
-        print(json.dumps(served_run(args)), flush=True)
         return
     inst, desc = workload(args.workload)
     steps = args.steps if args.steps is not None else inst.steps

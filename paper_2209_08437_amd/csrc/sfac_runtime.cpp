@@ -468,10 +468,18 @@ struct sfac_plan_s {
         }
     }
 
+    // the private capture stream, created on first use (plans stepped only through groups, or
+    // with plain launches, never hold one)
+    hipError_t capture_stream() {
+        return capture ? hipSuccess : hipStreamCreateWithFlags(&capture, hipStreamNonBlocking);
+    }
+
     sfac_status capture_graph(int64_t steps, hipGraph_t* g, hipGraphExec_t* x) {
         *g = nullptr;
         *x = nullptr;
-        hipError_t e = hipStreamBeginCapture(capture, hipStreamCaptureModeRelaxed);
+        hipError_t e = capture_stream();
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        e = hipStreamBeginCapture(capture, hipStreamCaptureModeRelaxed);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         hipError_t le = launch_steps(capture, steps);
         e = hipStreamEndCapture(capture, g);
@@ -679,7 +687,6 @@ static sfac_status exact_plan_create(sfac_plan p, int32_t dims, const int32_t* n
     }
     e = hipMemcpy(p->dev, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->dev + p->off_stat, 0, 256);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipFree(p->dev);
         p->dev = nullptr;
@@ -768,11 +775,6 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
             return hip_fail(e, "hipFuncSetAttribute(max dynamic LDS)");
         }
     }
-    e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        (void)hipFree(p->dev);
-        return hip_fail(e, "hipStreamCreate");
-    }
     *out = p.release();
     return SFAC_OK;
 }
@@ -855,6 +857,7 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
         }
     }
     if (!exact) e = hipStreamSynchronize(p->stream);
+    if (!exact && e == hipSuccess) e = p->capture_stream();
     for (int a = 0; a < d && !exact && e == hipSuccess; ++a) {
         // plain launches outside sfac_step: not part of the per-step record
         sfac::PassDesc<double> d64 = p->d64[a];

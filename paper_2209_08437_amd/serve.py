@@ -76,11 +76,17 @@ class GpuExecutor:
     (sfac_plan_device_bytes: tables, status, descriptors) plus its state; the plan is built when
     the server first asks for that figure and kept for the admission. `step` only queues the
     grouped launches (the host goes on admitting while the device runs); `retire` waits for the
-    request's work and reads its state back."""
+    request's work and reads its state back.
+
+    An admitted state is uploaded on a copy stream of its own, from the caller's (pageable)
+    array: the host waits for that copy only, not for the grouped steps queued on the
+    executor's stream, which is then ordered after the copy. No host staging buffer outlives the
+    call (keeping a page-locked copy of every admitted state until it retired held gigabytes of
+    locked host memory on long streams)."""
 
     on_device = True
 
-    def __init__(self, stream=None, schedule_table=None):
+    def __init__(self, stream=None, schedule_table=None, keep_states=True):
         import torch
         from . import autotune, sfac
         self.torch = torch
@@ -89,6 +95,8 @@ class GpuExecutor:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.group = sfac.Group(self.stream)
         self.table = {} if schedule_table is False else autotune.load_table(schedule_table)
+        self.keep_states = keep_states   # False: retire reports flags and max|u| only (no read-back)
+        self.copy_stream = torch.cuda.Stream(device=self.stream.device)
         self._built = {}          # id(inst) -> (inst, dtype, plan), plans built for bytes_needed
 
     def _plan(self, inst, dtype):
@@ -114,12 +122,13 @@ class GpuExecutor:
         tdt = torch.float64 if dtype == "f64" else torch.float32
         plan = self._plan(inst, dtype)
         self._built.pop(id(inst), None)
-        # the upload is queued behind the grouped steps already on the stream (pinned source,
-        # kept alive with the handle), so admitting does not wait for them
-        host = torch.as_tensor(np.asarray(inst.u0), dtype=tdt).pin_memory()
-        with torch.cuda.stream(self.stream):
-            u = host.to("cuda", non_blocking=True)
-        return (plan, u, host)
+        # a synchronous copy on the copy stream (runs beside the queued grouped steps); the
+        # executor's stream waits for it before the request's first step
+        with torch.cuda.stream(self.copy_stream):
+            u = torch.as_tensor(np.asarray(inst.u0), dtype=tdt).to(self.stream.device, non_blocking=False)
+        self.stream.wait_stream(self.copy_stream)
+        u.record_stream(self.stream)
+        return (plan, u)
 
     def step(self, handles, nsteps):
         plans = [h[0] for h in handles]
@@ -127,10 +136,12 @@ class GpuExecutor:
         self.group.step(plans, states, nsteps)
 
     def retire(self, handle):
-        plan, u, _ = handle
+        plan, u = handle
         flags, vmax = plan.flags()                # waits for the plan's stream
-        with self.torch.cuda.stream(self.stream):
-            out = u.double().cpu().numpy()
+        out = None
+        if self.keep_states:
+            with self.torch.cuda.stream(self.stream):
+                out = u.double().cpu().numpy()
         plan.close()
         return out, flags, vmax
 
@@ -145,13 +156,14 @@ class Server:
     """Admission by device-memory budget, FIFO, continuous batching in ticks of `tick_steps`."""
 
     def __init__(self, executor, budget_bytes, tick_steps=50, max_active=256,
-                 clock=time.perf_counter, sleep=time.sleep):
+                 clock=time.perf_counter, sleep=time.sleep, progress=None):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.tick_steps = int(tick_steps)
         self.max_active = int(max_active)
         self.clock = clock
         self.sleep = sleep
+        self.progress = progress      # called with (finished requests, all requests) after each retire
 
     def run(self, requests):
         """Serve `requests` (objects with rid, arrival, inst, dtype; arrival in seconds from the
@@ -168,6 +180,7 @@ class Server:
         peak_bytes = 0
         t0 = self.clock()
         busy = 0.0
+        finished = 0
         admit_s = []         # per admitted request: plan tables, device upload of state and tables
 
         def admit(used):
@@ -235,6 +248,9 @@ class Server:
                         busy += self.clock() - tr
                         tk.finished = self.clock() - t0
                         used -= a[3]
+                        finished += 1
+                        if self.progress is not None:
+                            self.progress(finished, len(reqs))
                     else:
                         still.append(a)
                 active = still + joined
