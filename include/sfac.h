@@ -64,13 +64,20 @@ typedef enum { SFAC_FP64 = 0, SFAC_FP32 = 1 } sfac_dtype;
  *                     host, see sfac_exact_exponential). O(N) work per point and axis instead of
  *                     O(log N): a reference scheme, not a fast path. Every axis of the plan must
  *                     ask for it; SFAC_FP64 only; N_l <= 1024; single plans only (not groups or
- *                     batches); kernel, elems_log2 and lines_per_block are ignored. */
+ *                     batches); kernel, elems_log2 and lines_per_block are ignored.
+ * Precision: SFAC_FP64 plans apply each factor K as written. SFAC_FP32 plans apply it in
+ * increment form, x + (K - I) x, with tables of K - I (expm1 of the eigenvalue exponents): the
+ * same operator, but the transforms round the increment instead of the state, which keeps the
+ * error of long FP32 runs near the single-step rounding of smooth states. */
 typedef enum {
     SFAC_METHOD_AUTO = 0,
     SFAC_METHOD_DIAG = 1,
     SFAC_METHOD_EMBED = 2,
     SFAC_METHOD_EXACT = 3
 } sfac_method;
+
+/* sfac_axis_tables flag: the increment-form tables (of K - I) that SFAC_FP32 plans use. */
+#define SFAC_TABLES_INCREMENT 0x100
 
 typedef struct sfac_plan_s* sfac_plan;
 typedef struct sfac_batch_s* sfac_batch;
@@ -228,7 +235,9 @@ sfac_status sfac_plan_method(sfac_plan p, int32_t axis, int32_t* method, int32_t
  *               e^{tau/2 C} placed as a symmetric circular kernel, divided by M;
  *   scale_s   : likewise for e^{tau S} (DIAG: mu_j = sum_k s_k e^{-i pi k (2j+1)/N});
  *   radices   : if not NULL, up to 12 stage radices, *nstages their count.
- * Call it once with NULL arrays to learn L. Errors as sfac_plan_create.
+ * method | SFAC_TABLES_INCREMENT gives the tables of e^{tau/2 C} - I and e^{tau S} - I instead
+ * (DIAG: expm1(tau/2 lambda_j)/N, ...; EMBED: spectra of the first columns of the factors minus
+ * the identity). Call it once with NULL arrays to learn L. Errors as sfac_plan_create.
  */
 sfac_status sfac_axis_tables(int32_t n, double alpha, double eps, double tau, double h, int32_t method,
                              int32_t* length, double* scale_c, double* scale_s, int32_t* radices,

@@ -115,9 +115,17 @@ struct Diag2Line {
     // the transform they would keep B more values live at its peak and cost the kernel a third
     // wavefront per SIMD (FP64 15 x 17: 202 against 156 VGPRs); their load latency is covered by
     // the other wavefronts that the smaller register budget lets in.
+    // In the increment form (FP32) the tables hold the factor minus the identity and the factor's
+    // input, kept in registers across it, is added back at the end.
     template <bool SKEW>
     __device__ __forceinline__ void factor(const Spec<T>* __restrict__ gpos, const cplx<T>* __restrict__ psipos,
                                            cplx<T>* line, int t) {
+        constexpr bool INC = increment_form<T>();
+        cplx<T> x0[INC ? A : 1];
+        if constexpr (INC) {
+#pragma unroll
+            for (int k = 0; k < A; ++k) x0[k] = a[k];
+        }
         if constexpr (SKEW) psi_mul<false>(psipos, t);
         forward(line, t);
         Spec<T> gv[B];
@@ -125,6 +133,12 @@ struct Diag2Line {
         scale(gv, t);
         inverse(line, t);
         if constexpr (SKEW) psi_mul<true>(psipos, t);
+        if constexpr (INC) {
+            if (t < B) {
+#pragma unroll
+                for (int k = 0; k < A; ++k) a[k] = a[k] + x0[k];
+            }
+        }
     }
 
     // the three factors e^{tau/2 C} e^{tau S} e^{tau/2 C}, the skew one wrapped in psi and conj(psi)

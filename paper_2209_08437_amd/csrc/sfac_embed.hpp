@@ -247,14 +247,26 @@ struct EmbedLine {
     // natural position of register (i, k) at pass 0
     static __device__ __forceinline__ int nat(int t, int i, int k) { return embed_pos<LOG2M, LE, 0>(t, i, k); }
 
-    // one exponential factor: forward transform, spectrum, inverse transform, truncation
+    // one exponential factor: forward transform, spectrum, inverse transform, truncation; in the
+    // increment form (FP32) the spectrum is that of the factor minus the identity and the
+    // factor's input (the registers below M/2 at pass 0: the others hold zero padding) is kept
+    // and added back
     __device__ __forceinline__ void factor(const Spec<T>* __restrict__ g, cplx<T>* line, int t, int n) {
+        constexpr bool INC = increment_form<T>();
+        constexpr int R0 = G::R(0);
+        constexpr int H = R0 >= 2 ? R0 / 2 : 1;   // input registers per pass-0 butterfly
+        cplx<T> x0[INC ? G::E / R0 * H : 1];
+        if constexpr (INC) {
+#pragma unroll
+            for (int i = 0; i < G::E / R0; ++i)
+#pragma unroll
+                for (int k = 0; k < H; ++k) x0[i * H + k] = a[i * R0 + k];
+        }
         Spec<T> gv[G::E];
         load_scale(g, gv, t);
         fwd_from<0>(line, t);
         scale(gv);
         inv_from<G::NST - 1>(line, t);
-        constexpr int R0 = G::R(0);
 #pragma unroll
         for (int i = 0; i < G::E / R0; ++i)
 #pragma unroll
@@ -263,6 +275,8 @@ struct EmbedLine {
                     a[i * R0 + k] = {(T)0, (T)0};           // position >= M/2 >= N
                 else if (nat(t, i, k) >= n)
                     a[i * R0 + k] = {(T)0, (T)0};
+                else if constexpr (INC)
+                    a[i * R0 + k] = a[i * R0 + k] + x0[i * H + k];
             }
     }
 };

@@ -44,6 +44,14 @@ __host__ __device__ inline Spec<double> make_spec<double>(double v) { return mak
 template <>
 __host__ __device__ inline Spec<float> make_spec<float>(double v) { return make_spec_float(v); }
 
+// FP32 passes apply every factor K in increment form, x + (K - I) x, from tables of K - I: the
+// transforms then round the increment, which is small against x wherever the state is smooth
+// (the low frequencies that carry it have eigenvalue factors near one), instead of x itself.
+// FP64 passes apply K directly: their rounding is far below the method's error already, and the
+// kept input would cost the FP64 register kernels a wavefront per SIMD.
+template <typename T>
+constexpr bool increment_form() { return sizeof(T) == sizeof(float); }
+
 // a * g
 __device__ __forceinline__ double spec_mul(double a, Spec<double> g) { return a * g.v; }
 __device__ __forceinline__ float spec_mul(float a, Spec<float> g) { return __builtin_fmaf(a, g.lo, a * g.hi); }

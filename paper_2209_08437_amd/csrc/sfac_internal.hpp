@@ -37,6 +37,9 @@ struct AxisTables {
     // two-step diagonal kernel only: A, B and psi2[b A + a] = psi_{(B a + A b) mod N}
     int d2a = 0, d2b = 0;
     std::vector<double> psi2_re, psi2_im;
+    // increment form: scale_c / scale_s (and their permutations) describe e^{tau/2 C} - I and
+    // e^{tau S} - I (expm1 of the eigenvalue exponents); the kernels add the factor's input back
+    bool increment = false;
 };
 
 // Factor pairs N = A * B handled by the register-resident diagonal kernel (false if none).
@@ -56,8 +59,9 @@ struct AxisParams {
 // Builds the tables for one axis. Returns an empty string on success, else an error message.
 // `method` is SFAC_METHOD_DIAG or SFAC_METHOD_EMBED (AUTO is resolved by the caller); for the
 // embedded method `log2e` (3 or 4) selects the radix-pass schedule the position tables follow.
+// `increment` builds the tables of the factors minus the identity (AxisTables::increment).
 std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e = 4,
-                              bool diag2 = true);
+                              bool diag2 = true, bool increment = false);
 
 // Factorisation of n into the supported radices (largest first); empty if n has a prime
 // factor above kMaxPrimeRadix. n == 1 yields an empty list and returns true.

@@ -162,8 +162,9 @@ __device__ __forceinline__ void publish_stats(double vmax, unsigned int bad, con
     }
 }
 
+// keep: a third LDS buffer of lpb lines, used in the increment form only (the factor's input).
 template <typename T>
-__device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>* buf1) {
+__device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>* buf1, cplx<T>* keep) {
     const int N = d.N, L = d.L, lpb = d.lpb;
     const bool contiguous = d.inner == 1;
     long long first;       // first real line (row) or column of the tile
@@ -221,6 +222,9 @@ __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>*
     for (int f = 0; f < 3; ++f) {
         const Spec<T>* scale = f == 1 ? d.scale_s : d.scale_c;
         const bool skew = f == 1;
+        if constexpr (increment_form<T>()) {   // every thread keeps (and later adds) its own elements
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) keep[idx] = cur[idx];
+        }
         if (diag && skew) {  // x <- psi . x
             for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
                 const int k = idx % L;
@@ -250,6 +254,10 @@ __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>*
                 const int k = idx % L;
                 if (k >= N) cur[idx] = {(T)0, (T)0};
             }
+            __syncthreads();
+        }
+        if constexpr (increment_form<T>()) {   // padding positions hold zero in both
+            for (int idx = threadIdx.x; idx < total; idx += blockDim.x) cur[idx] = cur[idx] + keep[idx];
             __syncthreads();
         }
     }
@@ -545,7 +553,7 @@ __global__ void __launch_bounds__(kBlockThreads) axis_pass_single(PassDesc<T> d)
     cplx<T>* buf1 = buf0 + d.lpb * d.L;
     const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
     if (tile >= d.ntiles) return;
-    run_tile(d, tile, buf0, buf1);
+    run_tile(d, tile, buf0, buf1, buf1 + d.lpb * d.L);
 }
 
 // Block size bound of an embedded-method kernel: 256 threads, or one line when a line has more
@@ -703,7 +711,7 @@ __global__ void __launch_bounds__(kBlockThreads) axis_pass_multi(const GroupArgs
     if (tile >= d.ntiles) return;
     cplx<T>* buf0 = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* buf1 = buf0 + d.lpb * d.L;
-    run_tile(d, tile, buf0, buf1);
+    run_tile(d, tile, buf0, buf1, buf1 + d.lpb * d.L);
 }
 
 // Discrete energy (Sec. 5, Example 5), one axis. A thread block holds lpb line pairs packed as

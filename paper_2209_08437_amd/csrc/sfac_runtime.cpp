@@ -182,7 +182,8 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
         }
         in->ax[a].log2e = log2e;
         sfac::AxisParams p{n[a], alpha[a], eps, tau, h[a]};
-        std::string err = sfac::build_axis_tables(p, m, &in->ax[a].host, log2e, kern != 1);
+        std::string err = sfac::build_axis_tables(p, m, &in->ax[a].host, log2e, kern != 1,
+                                                  dt == SFAC_FP32 /* FP32 kernels use the increment form */);
         if (!err.empty() && kern >= 2 && m == SFAC_METHOD_DIAG) err = "";
         if (kern >= 2 && m == SFAC_METHOD_DIAG && in->ax[a].host.d2a == 0)
             return fail(SFAC_EUNSUPPORTED, "%saxis %d: N = %d is not a product the register-resident diagonal "
@@ -249,8 +250,9 @@ sfac_status build_instance(Instance* in, int dims, const int32_t* n, const doubl
                 in->ax[a].lds = elem * ls * lpb;
             }
         } else {
-            // generic kernel: two LDS buffers per line, as many lines as fit the budget
-            const size_t per_line = 2 * elem * (size_t)L;
+            // generic kernel: two LDS buffers per line (three in the increment form of FP32, which
+            // keeps each factor's input), as many lines as fit the budget
+            const size_t per_line = (dt == SFAC_FP32 ? 3 : 2) * elem * (size_t)L;
             int lpb = (int)std::max<size_t>(1, kLdsBudget / per_line);
             if (opt && opt->lines_per_block[a] > 0) lpb = opt->lines_per_block[a];
             lpb = (int)std::min<long long>(lpb, std::max<long long>(1, (avail + 1) / 2));
@@ -1037,11 +1039,12 @@ sfac_status sfac_axis_tables(int32_t n, double alpha, double eps, double tau, do
     double al[1] = {alpha}, hs[1] = {h};
     sfac_status st = validate_instance(1, ns, al, eps, tau, hs, "");
     if (st != SFAC_OK) return st;
-    int m = method;
+    const bool increment = (method & SFAC_TABLES_INCREMENT) != 0;
+    int m = method & ~SFAC_TABLES_INCREMENT;
     if (m == SFAC_METHOD_AUTO) m = sfac::auto_method(n, SFAC_FP64);
     if (m != SFAC_METHOD_DIAG && m != SFAC_METHOD_EMBED) return fail(SFAC_EUNSUPPORTED, "no method for N = %d", n);
     sfac::AxisTables t;
-    std::string err = sfac::build_axis_tables(sfac::AxisParams{n, alpha, eps, tau, h}, m, &t);
+    std::string err = sfac::build_axis_tables(sfac::AxisParams{n, alpha, eps, tau, h}, m, &t, 4, true, increment);
     if (!err.empty()) return fail(SFAC_EUNSUPPORTED, "%s", err.c_str());
     if (length) *length = t.length;
     if (scale_c) std::copy(t.scale_c.begin(), t.scale_c.end(), scale_c);

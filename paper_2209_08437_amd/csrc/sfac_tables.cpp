@@ -321,7 +321,8 @@ std::string build_energy_tables(const AxisParams& p, int log2e, EnergyTables* ou
     return std::string();
 }
 
-std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e, bool diag2) {
+std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, int log2e, bool diag2,
+                              bool increment) {
     const int N = p.n;
     char msg[256];
     if (N < 1) return "N must be >= 1";
@@ -337,6 +338,7 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, 
     t = AxisTables();
     t.n = N;
     t.method = method;
+    t.increment = increment;
     if (method == SFAC_METHOD_DIAG) {
         if (N > kMaxDiagLength) {
             snprintf(msg, sizeof msg, "N = %d exceeds the diagonal method's limit %d", N, kMaxDiagLength);
@@ -393,11 +395,13 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, 
         lam[j] = sl;
         mu[j] = sm;
     }
+    // eigenvalues of the factors, or of the factors minus the identity (expm1 keeps the small
+    // ones to full relative precision: |tau lambda_j| is small for the low frequencies)
     const ld tau = p.tau;
     std::vector<ld> ec(N), es(N);
     for (int j = 0; j < N; ++j) {
-        ec[j] = expl(0.5L * tau * lam[j]);
-        es[j] = expl(tau * mu[j]);
+        ec[j] = increment ? expm1l(0.5L * tau * lam[j]) : expl(0.5L * tau * lam[j]);
+        es[j] = increment ? expm1l(tau * mu[j]) : expl(tau * mu[j]);
     }
 
     const int L = t.length;
@@ -454,7 +458,9 @@ std::string build_axis_tables(const AxisParams& p, int method, AxisTables* out, 
         // first columns of e^{tau/2 C} (circulant, gamma) and e^{tau S} (skew-circulant, sigma):
         // gamma_k = (1/N) sum_j e^{tau/2 lambda_j} cos(2 pi j k / N),
         // sigma_k = (1/N) sum_j e^{tau mu_j} cos(pi k (2j + 1) / N); both matrices are symmetric
-        // Toeplitz, so entry (p, q) is gamma_{|p-q|} resp. sigma_{|p-q|}.
+        // Toeplitz, so entry (p, q) is gamma_{|p-q|} resp. sigma_{|p-q|}. In the increment form
+        // ec / es hold the eigenvalues minus one and these are the columns of the factors minus
+        // the identity (again symmetric Toeplitz).
         std::vector<ld> gam(N), sig(N);
         for (int k = 0; k < N; ++k) {
             ld sg = 0, ss = 0;

@@ -143,13 +143,17 @@ def _check_state(u, shape, dt):
         raise ValueError("state must be contiguous")
 
 
-def axis_tables(n, alpha, eps, tau, h, method=None):
-    """Host-only: (length, scale_c, scale_s, radices) the library builds for one axis."""
+TABLES_INCREMENT = 0x100
+
+
+def axis_tables(n, alpha, eps, tau, h, method=None, increment=False):
+    """Host-only: (length, scale_c, scale_s, radices) the library builds for one axis;
+    increment=True gives the tables of the factors minus the identity (those FP32 plans use)."""
     import numpy as np
     codes = {None: METHOD_AUTO, "auto": METHOD_AUTO, "diag": METHOD_DIAG, "embed": METHOD_EMBED}
     L = lib()
     length = ctypes.c_int32()
-    m = codes[method]
+    m = codes[method] | (TABLES_INCREMENT if increment else 0)
     _check(L.sfac_axis_tables(int(n), float(alpha), float(eps), float(tau), float(h), m,
                               ctypes.byref(length), None, None, None, None))
     sc = np.zeros(length.value)

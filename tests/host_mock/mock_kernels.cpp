@@ -10,6 +10,8 @@
 [[noreturn]] void mock_die(const char* what);
 bool mock_range_live(const void* p, size_t n);
 void mock_submit(hipStream_t s, std::function<void()> f);
+bool mock_inject();
+hipError_t mock_fail_launch(hipStream_t s);
 
 namespace sfac {
 
@@ -31,6 +33,7 @@ static void check_desc(const PassDesc<T>& d) {
 template <typename T>
 hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds, hipStream_t s) {
     if (lds > 160 * 1024) mock_die("LDS above 160 KiB");
+    if (mock_inject()) return mock_fail_launch(s);
     const PassDesc<T> c = d;
     mock_submit(s, [c] { check_desc(c); });
     return hipSuccess;
@@ -44,6 +47,7 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Grou
     if (lds > 160 * 1024) mock_die("grouped launch above 160 KiB of LDS");
     (void)kind;
     (void)variant;
+    if (mock_inject()) return mock_fail_launch(s);
     const GroupArgs<T> c = args;
     mock_submit(s, [c, threads] {
         for (int i = 0; i < c.n; ++i) {

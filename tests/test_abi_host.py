@@ -157,6 +157,33 @@ def test_host_tables_match_oracle(sfac_lib, n, alpha):
     assert np.allclose(kc[n:M - n + 1], 0, atol=1e-14)
 
 
+@pytest.mark.parametrize("n,alpha", [(2, 1.3), (31, 1.5), (255, 1.7), (300, 1.2)])
+def test_host_increment_tables_match_oracle(sfac_lib, n, alpha):
+    """The increment-form tables FP32 plans use describe the factors minus the identity:
+    expm1 of the eigenvalue exponents (diagonal method), and the first columns of
+    e^{tau/2 C} - I and e^{tau S} - I (embedded method), against the oracle's dense matrices."""
+    eps, tau, h = 0.13, 0.02, 2.0 / (n + 1)
+    ops = O.AxisOperators(n, alpha, eps, h, tau)
+    try:
+        L, sc, ss, _ = sfac.axis_tables(n, alpha, eps, tau, h, "diag", increment=True)
+    except sfac.SfacError:
+        L = None
+    if L is not None:
+        lam = O.circulant_spectrum(ops.C)
+        mu = np.roll(O.skew_spectrum(ops.S), -1)
+        ec, es = 0.5 * tau * lam, tau * mu
+        assert np.abs(sc * n - np.expm1(ec)).max() <= 1e-13 * np.abs(ec).max()
+        assert np.abs(ss * n - np.expm1(es)).max() <= 1e-13 * np.abs(es).max()
+    M, gc, gs, _ = sfac.axis_tables(n, alpha, eps, tau, h, "embed", increment=True)
+    kc = np.fft.ifft(gc).real * M
+    ks = np.fft.ifft(gs).real * M
+    eye0 = np.eye(n)[:, 0]
+    assert np.allclose(kc[:n], ops.EC[:, 0] - eye0, rtol=0, atol=1e-14)
+    assert np.allclose(ks[:n], ops.ES[:, 0] - eye0, rtol=0, atol=1e-14)
+    assert np.allclose(kc[M - n + 1:][::-1], ops.EC[1:, 0], rtol=0, atol=1e-14)
+    assert np.allclose(kc[n:M - n + 1], 0, atol=1e-14)
+
+
 def test_batch_options_are_validated(sfac_lib):
     """Per-instance schedules reach validation: a bad one fails the batch with its index."""
     import ctypes

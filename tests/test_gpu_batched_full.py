@@ -17,10 +17,11 @@ from paper_2209_08437_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
-# FP32 over 500 steps with tau up to 1e-2 (T up to 5): the rounding of the FP32 transforms
-# accumulates every step and the nonlinear flow amplifies it near u = 0 by up to e^T
-# (measured at most 7.5e-4)
-FP32_TOL_BATCH = 1.5e-3
+# FP32 over 500 steps with tau up to 1e-2 (T up to 5): the rounding of the FP32 transforms (of the
+# increments (K - I) x, the kernels' FP32 form) accumulates every step and the nonlinear flow
+# amplifies it near u = 0 by up to e^T (measured at most 1.8e-5 over the instances with n <= 511
+# and 7.0e-6 for the sampled n = 1023 one against the extended-precision reference)
+FP32_TOL_BATCH = 6e-5
 UNIT_ROUNDOFF = 2.0 ** -53
 
 

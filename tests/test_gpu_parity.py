@@ -9,10 +9,13 @@ Tolerances (relative max-norm, max|gpu - reference| / max|reference|):
         flow amplifies near u = 0 by up to e^T (4.5e-12 over the 1000-step 1023^2 run). There the
         bound against the FP64 oracle is twice that measured spread, and the benchmark spec's 1e-12 is
         checked against the oracle's extended-precision evaluation (sampled, tests/golden).
-  FP32: per configuration, from the measured error with a margin of about two: 3e-4 for runs of up
-        to a few hundred steps (measured 2.5e-5 .. 1.0e-4), 5e-4 for the 1000-step 1023^2 run
-        (measured 2.5e-4). The error is the rounding of the FP32 transform arithmetic, accumulated
-        over the steps and amplified by the nonlinear flow.
+  FP32: the kernels apply each factor K in increment form, x + (K - I) x, so the rounding of the
+        FP32 transforms scales with the increment, not with the state; what remains accumulates
+        over the steps and the nonlinear flow amplifies it near u = 0 by up to e^T. Bounds from
+        the measured errors with a margin of about three at the longest run: 5e-5 for runs of up
+        to a few hundred steps (measured 7.4e-7 on the 100-step 63^2 run, 1.8e-6 on the 200-step
+        63^3 run, 2.6e-7 .. 5.1e-7 on the short staged-tile runs, 3.2e-7 after one full 255^3
+        step), 5e-5 for the 1000-step 1023^2 run (measured 1.3e-5 in bench.py's schedule).
 """
 import sys
 
@@ -25,8 +28,8 @@ from paper_2209_08437_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
-FP32_TOL = 3e-4
-FP32_TOL_C2 = 5e-4
+FP32_TOL = 5e-5
+FP32_TOL_C2 = 5e-5
 
 
 def _torch():
@@ -194,7 +197,9 @@ def test_embed_staged_tiles(sfac_lib, ns, lpb, dtype, le):
         p.step(u, 3)
         flags, _ = p.flags()
     torch.cuda.synchronize()
-    assert rel_err(u.double().cpu().numpy(), ref) <= (FP64_TOL if dtype == "f64" else FP32_TOL)
+    e = rel_err(u.double().cpu().numpy(), ref)
+    _say(f"  rel err {e:.3e}")
+    assert e <= (FP64_TOL if dtype == "f64" else FP32_TOL)
     assert flags == 0
 
 
@@ -269,8 +274,9 @@ def test_special_parameters(sfac_lib):
                          ids=["20x13-embed", "35x63-diag2", "255x15-diag2"])
 def test_eps0_closed_form_fp32(sfac_lib, ns, method):
     """FP32 against the Bernoulli closed form (eps = 0, Sec. 3): pins the FP32 NL half-step of the
-    register-resident kernels. The linear step is the identity up to the rounding of its
-    transforms; a few ulp per step, amplified by at most e^T near u = 0, bound the error."""
+    register-resident kernels. At eps = 0 the increment-form tables are exactly zero, so the
+    linear step is exactly the identity and the error is the NL's: about one ulp per half-step,
+    amplified by at most e^T near u = 0 (measured 3.8e-7 .. 6.1e-7)."""
     hs = W.mesh_widths(ns)
     u0 = W.uniform_field(tuple(reversed(ns)), -0.99, 0.99, seed=5).astype(np.float32).astype(np.float64)
     steps, tau = 25, 0.03
@@ -280,7 +286,7 @@ def test_eps0_closed_form_fp32(sfac_lib, ns, method):
     closed = u0 / np.sqrt(u0 ** 2 + (1 - u0 ** 2) * np.exp(-2 * T))
     err = np.abs(got - closed).max()
     _say(f"  max abs err {err:.3e}")
-    assert err <= 2e-5
+    assert err <= 2e-6
     assert vmax <= 1.0
 
 
@@ -439,7 +445,9 @@ def test_batch_with_schedules_matches_lone_plans(sfac_lib):
             torch.cuda.synchronize()
             assert torch.equal(u, states[i]), (dt, i)
             ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps)
-            assert rel_err(states[i].double().cpu().numpy(), ref) <= (FP64_TOL if dt == "f64" else FP32_TOL), (dt, i)
+            e = rel_err(states[i].double().cpu().numpy(), ref)
+            _say(f"  {dt} instance {i} rel err {e:.3e}")
+            assert e <= (FP64_TOL if dt == "f64" else FP32_TOL), (dt, i)
         b.close()
 
 

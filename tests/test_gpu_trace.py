@@ -100,4 +100,6 @@ def test_trace_fp32(sfac_lib):
         p.step(u, inst.steps)
         vals, n = p.read_trace()
     assert n == inst.steps
-    assert np.abs(vals - ref).max() <= 3e-4 * np.abs(ref).max()
+    e = float(np.abs(vals - ref).max() / np.abs(ref).max())
+    print(f"  fp32 per-step max|u| rel err {e:.3e}", flush=True)
+    assert e <= 5e-5   # the FP32 parity bound of the state (increment form)

@@ -3,7 +3,8 @@ allocation-free solve's bookkeeping) built for the CPU with AddressSanitizer and
 UndefinedBehaviorSanitizer against a HIP stand-in that checks every API use
 (tests/host_mock), then driven through served streams of the kind the GPU server runs: long
 streams whose active set changes at almost every tick (thousands of distinct grouped steps), and
-one that fills the server. No sanitizer report, no API misuse, nothing left allocated."""
+one that fills the server. No sanitizer report, no API misuse, nothing left allocated; the same
+with every k-th fallible runtime call failing (the library's error paths)."""
 import os
 import shutil
 import subprocess
@@ -52,4 +53,27 @@ def test_served_streams_under_sanitizers(sanitized_lib):
     for spec, line in zip(streams, lines):
         count = spec.split(":")[0]
         assert f"completed {count} " in line, line
+        assert line.endswith("allocations 0 streams 0 graphs 0"), line
+
+
+@pytest.mark.parametrize("every", [7, 29])
+def test_served_streams_with_failing_runtime_calls(sanitized_lib, every):
+    """Every k-th allocation, stream or event creation, copy, capture, instantiation, launch or
+    synchronisation fails: each failure comes back as a library error, the server goes on, and the
+    error paths leave no sanitizer report, no API misuse and nothing allocated."""
+    lib, preload = sanitized_lib
+    env = dict(os.environ, LD_PRELOAD=preload, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", MOCK_FAIL_EVERY=str(every))
+    streams = ["120:20:50", "150:200:5"]
+    r = subprocess.run([sys.executable, os.path.join(MOCK, "replay_served.py"), lib] + streams,
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env, timeout=900)
+    assert r.returncode == 0, r.stdout[-6000:]
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("stream ")]
+    assert len(lines) == len(streams), r.stdout[-3000:]
+    for spec, line in zip(streams, lines):
+        count = spec.split(":")[0]
+        assert f"completed {count} " in line, line
+        injected = int(line.split(" injected ")[1].split()[0])
+        errors = int(line.split(" errors ")[1].split()[0])
+        assert injected > 0 and errors > 0, line
         assert line.endswith("allocations 0 streams 0 graphs 0"), line
