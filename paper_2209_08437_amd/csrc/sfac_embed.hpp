@@ -225,9 +225,8 @@ struct EmbedLine {
         if constexpr (S > 0) inv_from<S - 1>(line, t);
     }
 
-    // multiply by the kernel spectrum, stored in last-pass position order
-    // spectrum values at this thread's last-pass positions; loaded before the forward transform
-    // so that the load latency is hidden behind it
+    // multiply by the kernel spectrum, stored in last-pass position order: the spectrum values at
+    // this thread's last-pass positions
     __device__ __forceinline__ void load_scale(const Spec<T>* __restrict__ g, Spec<T>* gv, int t) {
         constexpr int S = G::NST - 1;
         constexpr int R = G::R(S);
@@ -262,9 +261,12 @@ struct EmbedLine {
 #pragma unroll
                 for (int k = 0; k < H; ++k) x0[i * H + k] = a[i * R0 + k];
         }
+        // FP32 loads the spectrum after the forward transform: held across it, it would take the
+        // kernels that also keep the input past 128 VGPRs; FP64 loads it first and hides the latency
         Spec<T> gv[G::E];
-        load_scale(g, gv, t);
+        if constexpr (!INC) load_scale(g, gv, t);
         fwd_from<0>(line, t);
+        if constexpr (INC) load_scale(g, gv, t);
         scale(gv);
         inv_from<G::NST - 1>(line, t);
 #pragma unroll

@@ -564,9 +564,15 @@ constexpr int embed_max_block(int log2m, int le, bool stage) {
     const int t = 1 << (log2m - embed_log2e(log2m, le));
     return stage ? embed_stage_block(t) : (t > kBlockThreads ? t : kBlockThreads);
 }
+// FP32 blocks above 256 threads with at most 8 elements per thread ask for four wavefronts per
+// SIMD (at most 128 VGPRs), so that two 512-thread blocks share a CU: a batched launch of many
+// lines then keeps twice the wavefronts in flight.
+template <typename T>
+constexpr int embed_min_waves(int log2m, int le, bool stage) {
+    return embed_max_block(log2m, le, stage) > kBlockThreads ? (sizeof(T) == 4 && le <= 3 ? 4 : 2) : 1;
+}
 #define SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE)                   \
-    __launch_bounds__(embed_max_block(LOG2M, LE, STAGE),     \
-                      embed_max_block(LOG2M, LE, STAGE) > kBlockThreads ? 2 : 1)
+    __launch_bounds__(embed_max_block(LOG2M, LE, STAGE), (embed_min_waves<T>(LOG2M, LE, STAGE)))
 
 template <typename T, int LOG2M, int LE, bool STAGE>
 __global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_single(PassDesc<T> d) {

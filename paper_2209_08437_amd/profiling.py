@@ -374,6 +374,74 @@ def _schedules(err_log):
     return out
 
 
+BATCH_TRACE_COMMAND = ("rocprofv3 --kernel-trace --stats --output-format csv -d $O/trace_batched_2d -o run -- "
+                       "python3 $R/bench.py --workload batched_2d --no-cpu")
+
+
+def busy_intervals(intervals):
+    """Total length of the union of (start, end) intervals."""
+    busy, cur_s, cur_e = 0, None, None
+    for s, e in sorted(intervals):
+        if cur_e is None or s > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = s, e
+        else:
+            cur_e = max(cur_e, e)
+    if cur_e is not None:
+        busy += cur_e - cur_s
+    return busy
+
+
+def grouped_gaps(trace_csv):
+    """Per arithmetic type, over the window of the grouped (multi-instance) pass dispatches of a
+    kernel trace: wall time, the time at least one kernel runs, the idle remainder (what a
+    single persistent launch could at most take back), and the sum of kernel durations over the
+    busy time (how many launches overlap on average)."""
+    rows = []
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    out = {}
+    for tag, name in (("<float", "f32"), ("<double", "f64")):
+        multi = [k for k in rows if "_multi" in k[2] and tag in k[2]]
+        if not multi:
+            continue
+        t0, t1 = min(k[0] for k in multi), max(k[1] for k in multi)
+        win = [k for k in rows if k[0] >= t0 and k[1] <= t1]
+        busy = busy_intervals([(s, e) for s, e, _ in win])
+        total = sum(e - s for s, e, _ in win)
+        out[name] = {"dispatches": len(multi), "others": len(win) - len(multi), "wall_ms": (t1 - t0) / 1e6,
+                     "busy_ms": busy / 1e6, "idle_ms": (t1 - t0 - busy) / 1e6,
+                     "idle_frac": (t1 - t0 - busy) / (t1 - t0), "overlap": total / busy}
+    return out
+
+
+def batch_trace_markdown(directory):
+    """Markdown summary of the kernel trace of the batched workload."""
+    d = os.path.join(directory, "trace_batched_2d")
+    bench = json.load(open(os.path.join(directory, "bench_batched_2d.json")))
+    steps = bench["steps"] + bench["warmup"]
+    lines = ["# Grouped launches, workload batched_2d", "",
+             "Command (run from /tmp on one MI355X; `$R` is the repository root, `$O` the output directory):", "",
+             "```", BATCH_TRACE_COMMAND, "```", "", "## Kernel trace (`--kernel-trace --stats`)", "",
+             stats_markdown(os.path.join(d, "run_kernel_stats.csv"), top=12), "",
+             "## Idle time between grouped launches", "",
+             f"Over the window of each arithmetic's grouped pass dispatches ({steps} steps of all 64 instances: "
+             "warm-up and timed region), the time during which no kernel runs is the most that one persistent "
+             "launch per step could take back; the sum of kernel durations over the busy time is the mean number "
+             "of launches running at once (the step graph fans a pass's launches out over several streams).", "",
+             "| dtype | grouped dispatches | wall ms | busy ms | idle ms | idle share | us idle per step | "
+             "launches at once |", "|---|---|---|---|---|---|---|---|"]
+    for dt, g in grouped_gaps(os.path.join(d, "run_kernel_trace.csv")).items():
+        lines.append(f"| {dt} | {g['dispatches']} | {g['wall_ms']:.2f} | {g['busy_ms']:.2f} | {g['idle_ms']:.2f} | "
+                     f"{g['idle_frac']:.3f} | {g['idle_ms'] * 1e3 / steps:.1f} | {g['overlap']:.2f} |")
+    lines += ["", f"bench.py in the same session (under the profiler): FP32 {bench['ms_per_step'] * 1e3:.1f} us per step "
+              f"of all 64 instances, FP64 {bench['config']['points'] / bench['batched_f64'] * 1e6:.1f} us.", "",
+              f"Device-code source hash: `{source_hash()}`.", ""]
+    return "\n".join(lines)
+
+
 def _main():
     """Write the markdown summary of one workload's profiles and update the traffic record."""
     import argparse
@@ -386,7 +454,13 @@ def _main():
     ap.add_argument("--sq", help="write the SQ counter summary (SQ_SETS runs) to this file instead")
     ap.add_argument("--mfma", help="write the matrix-core counter summary of the exact products (MFMA_COMMAND runs of "
                                    "large_2d_1023 and large_3d_255 under --dir) to this file instead")
+    ap.add_argument("--batch-trace", help="write the summary of the batched workload's kernel trace "
+                                          "(BATCH_TRACE_COMMAND under --dir) to this file instead")
     a = ap.parse_args()
+    if a.batch_trace:
+        with open(a.batch_trace, "w") as f:
+            f.write(batch_trace_markdown(a.dir))
+        return
     if a.mfma:
         with open(a.mfma, "w") as f:
             f.write(mfma_markdown(a.dir, [("large_2d_1023", 2), ("large_3d_255", 3)]))
