@@ -265,7 +265,9 @@ const char* sfac_last_error(void);
  * launch), instead of one launch per plan. Used for batched solves and by the solve server's
  * continuous batching. A launch carries its plans in its kernel arguments, so a group holds no
  * device memory; the captured step graphs are kept per set of (plan, state) pairs (the 32 most
- * recently used), so repeated calls with the same plans and states replay them. */
+ * recently used), so repeated calls with the same plans and states replay them. A stretch of at
+ * least 64 steps with a fixed set of plans replays a graph of 8 steps, the rest one step at a
+ * time. */
 typedef struct sfac_group_s* sfac_group;
 
 /* sfac_group_create - a launch workspace ordered on hip_stream (NULL = legacy default stream).

@@ -1089,9 +1089,16 @@ struct GroupLaunch {
 // One cached step graph: the (plan id, state) pairs of a phase, in call order.
 struct GroupGraph {
     std::vector<std::pair<unsigned long long, void*>> key;
+    int steps = 1;   // steps captured in the graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
+
+// A phase of at least kLongPhase steps replays a graph of kPhaseChunk steps (the remainder one
+// step at a time): fewer graph launches, and so fewer gaps between them, on long batched runs;
+// a served tick is shorter and keeps to the one-step graph.
+constexpr int kPhaseChunk = 8;
+constexpr int64_t kLongPhase = 64;
 
 }  // namespace
 
@@ -1229,12 +1236,13 @@ hipError_t group_launch(const GroupLaunch& l, hipStream_t s) {
 // Captures one step of a phase: pass after pass; the launches of one pass (different kernel
 // variants and arithmetic, disjoint plans) fan out over the auxiliary streams and join before
 // the next pass, so every plan still sees its passes in order.
-sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch>& launches, hipGraph_t* graph) {
+sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch>& launches, int steps, hipGraph_t* graph) {
     *graph = nullptr;
     hipError_t e = hipStreamBeginCapture(g->capture, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     hipError_t le = hipSuccess;
-    for (int pass = 0; pass < 3 && le == hipSuccess; ++pass) {
+    for (int it = 0; it < 3 * steps && le == hipSuccess; ++it) {
+        const int pass = it % 3;
         std::vector<const GroupLaunch*> ls;
         for (const GroupLaunch& l : launches)
             if (l.pass == pass) ls.push_back(&l);
@@ -1262,12 +1270,12 @@ sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch>& launches,
 
 // The step graph of a phase: from the cache, or captured and instantiated (the least recently
 // used graph is dropped once the cache is full, after the stream has finished with it).
-sfac_status phase_graph(sfac_group g, const std::vector<PhaseEntry>& entries, hipGraphExec_t* exec) {
+sfac_status phase_graph(sfac_group g, const std::vector<PhaseEntry>& entries, int steps, hipGraphExec_t* exec) {
     std::vector<std::pair<unsigned long long, void*>> key;
     key.reserve(entries.size());
     for (const PhaseEntry& e : entries) key.emplace_back(e.plan->id, e.u);
     for (auto it = g->cache.begin(); it != g->cache.end(); ++it)
-        if (it->key == key) {
+        if (it->key == key && it->steps == steps) {
             g->cache.splice(g->cache.begin(), g->cache, it);
             *exec = g->cache.front().exec;
             return SFAC_OK;
@@ -1286,7 +1294,8 @@ sfac_status phase_graph(sfac_group g, const std::vector<PhaseEntry>& entries, hi
     if (e != hipSuccess) return hip_fail(e, "group streams and events");
     GroupGraph gg;
     gg.key = std::move(key);
-    sfac_status st = capture_step(g, launches, &gg.graph);
+    gg.steps = steps;
+    sfac_status st = capture_step(g, launches, steps, &gg.graph);
     if (st != SFAC_OK) return st;
     e = hipGraphInstantiate(&gg.exec, gg.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -1336,12 +1345,24 @@ sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void*
         std::vector<PhaseEntry> active;
         for (size_t i = 0; i < all.size(); ++i)
             if (steps[i] >= bound) active.push_back(all[i]);
-        hipGraphExec_t exec = nullptr;
-        const sfac_status st = phase_graph(g, active, &exec);
-        if (st != SFAC_OK) return st;
-        for (int64_t r = done; r < bound; ++r) {
-            const hipError_t e = hipGraphLaunch(exec, g->stream);
-            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        int64_t left = bound - done;
+        if (left >= kLongPhase) {
+            hipGraphExec_t chunk = nullptr;
+            const sfac_status st = phase_graph(g, active, kPhaseChunk, &chunk);
+            if (st != SFAC_OK) return st;
+            for (; left >= kPhaseChunk; left -= kPhaseChunk) {
+                const hipError_t e = hipGraphLaunch(chunk, g->stream);
+                if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            }
+        }
+        if (left > 0) {
+            hipGraphExec_t exec = nullptr;
+            const sfac_status st = phase_graph(g, active, 1, &exec);
+            if (st != SFAC_OK) return st;
+            for (; left > 0; --left) {
+                const hipError_t e = hipGraphLaunch(exec, g->stream);
+                if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            }
         }
         done = bound;
     }

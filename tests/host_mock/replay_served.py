@@ -1,7 +1,7 @@
 """Replays served streams through serve.Server against a host build of the library (mock HIP
 runtime, sanitizers): the call sequence of the device executor (a plan per request, grouped
 steps with cached step graphs, flags, destroy), with a simulated clock. Usage:
-    replay_served.py LIBRARY COUNT:RATE:SEED ...
+    replay_served.py LIBRARY COUNT:RATE:SEED[:TICK_STEPS] ...
 Prints one line per stream; exits non-zero (the mock or a sanitizer aborts) on misuse. When the
 mock injects failures (MOCK_FAIL_EVERY), the executor counts the library's errors and goes on:
 plan creation is retried, a failed grouped step or status read is skipped."""
@@ -111,11 +111,13 @@ def main():
     for name in ("mock_live_allocations", "mock_live_streams", "mock_live_graphs", "mock_injected_failures"):
         getattr(L, name).restype = ctypes.c_size_t
     for spec in sys.argv[2:]:
-        count, rate, seed = spec.split(":")
+        fields = spec.split(":")
+        count, rate, seed = fields[:3]
+        tick = int(fields[3]) if len(fields) > 3 else 50
         clock = Clock()
         ex = HostExecutor(L, clock)
         reqs = W.served_stream(count=int(count), rate=float(rate), seed=int(seed), materialize=False)
-        srv = serve.Server(ex, budget_bytes=16 << 30, tick_steps=50, clock=clock, sleep=clock.sleep)
+        srv = serve.Server(ex, budget_bytes=16 << 30, tick_steps=tick, clock=clock, sleep=clock.sleep)
         _, summ = srv.run(reqs)
         ex.close()
         print(f"stream {spec}: completed {summ['completed']} ticks {summ['ticks']} peak_active "

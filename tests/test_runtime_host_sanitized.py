@@ -44,7 +44,7 @@ def test_served_streams_under_sanitizers(sanitized_lib):
     lib, preload = sanitized_lib
     env = dict(os.environ, LD_PRELOAD=preload, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
-    streams = ["150:6.32:51", "120:20:50", "200:200:5"]
+    streams = ["150:6.32:51", "120:20:50", "200:200:5", "60:20:7:200"]   # the last: ticks of 8-step graphs
     r = subprocess.run([sys.executable, os.path.join(MOCK, "replay_served.py"), lib] + streams,
                        stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env, timeout=900)
     assert r.returncode == 0, r.stdout[-6000:]
