@@ -305,22 +305,25 @@ def composed_operators(ops):
     return [op.EC @ op.ES @ op.EC for op in ops]
 
 
-def two_level_solve_composed(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, reverse_axes=True):
+def two_level_solve_composed(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, reverse_axes=True, observe=None):
     """The scheme of two_level_solve evaluated in another FP64 order: each step applies the
     composed per-axis operators P_l (one dense product per axis), the last axis first when
     `reverse_axes` is set. Equal to two_level_solve in exact arithmetic; the two differ only by
-    rounding, which measures how reproducible an FP64 evaluation of a long run is at all."""
+    rounding, which measures how reproducible an FP64 evaluation of a long run is at all.
+    `observe`, if given, is called as observe(step, u) after every step."""
     u = np.array(u0, dtype=np.float64, copy=True)
     if ops is None:
         ops = axis_operators(ns, alphas, eps, hs, tau)
     P = composed_operators(ops)
     d = u.ndim
     order = range(d, 0, -1) if reverse_axes else range(1, d + 1)
-    for _ in range(nsteps):
+    for n in range(nsteps):
         u = nonlinear_flow(u, 0.5 * tau)
         for ax in order:
             u = apply_along_axis(P[ax - 1], u, ax)
         u = nonlinear_flow(u, 0.5 * tau)
+        if observe is not None:
+            observe(n + 1, u)
     return u
 
 
@@ -359,14 +362,15 @@ def apply_exp_skew_fft(x, mu, t, axis):
     return (np.conj(psi) * fft(e * y, axis=ax)).real
 
 
-def two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, dtype=np.float64):
+def two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, dtype=np.float64, observe=None):
     """The scheme of two_level_solve evaluated through Remark 1's diagonalisation with a library
     FFT instead of dense products, in the paper's factor order. In float64 it is a third
     evaluation order (used beside two_level_solve_composed to measure how far FP64 evaluations
     of a long run spread). With dtype=numpy.longdouble every table (g, omega, B, C, S, the
     spectra, Psi) and every operation is carried in extended precision (64-bit significand on
     x86, unit roundoff 2^-64): the reference the FP64 results are measured against, about 2000
-    times more precise than any FP64 evaluation. Returns an array of `dtype`."""
+    times more precise than any FP64 evaluation. Returns an array of `dtype`. `observe`, if given,
+    is called as observe(step, u) after every step."""
     u = np.array(u0, dtype=dtype, copy=True)
     if ops is None or ops[0].dtype != dtype:
         ops = axis_operators(ns, alphas, eps, hs, tau, dtype)
@@ -374,7 +378,7 @@ def two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, dtype=np
     mus = [skew_spectrum(op.S) for op in ops]
     d = u.ndim
     half = dtype(tau) / 2
-    for _ in range(nsteps):
+    for n in range(nsteps):
         u = nonlinear_flow(u, half)
         for ax in range(1, d + 1):
             u = apply_exp_circulant_fft(u, lams[ax - 1], half, ax)
@@ -383,24 +387,27 @@ def two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=None, dtype=np
         for ax in range(1, d + 1):
             u = apply_exp_circulant_fft(u, lams[ax - 1], half, ax)
         u = nonlinear_flow(u, half)
+        if observe is not None:
+            observe(n + 1, u)
     return u
 
 
-def extended_solve(u0, ns, alphas, eps, hs, tau, nsteps):
+def extended_solve(u0, ns, alphas, eps, hs, tau, nsteps, observe=None):
     """two_level_solve_fft in numpy's longdouble: the extended-precision reference."""
-    return two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, dtype=np.longdouble)
+    return two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, dtype=np.longdouble, observe=observe)
 
 
-def rounding_spread(u0, ns, alphas, eps, hs, tau, nsteps, ref, ops=None):
+def rounding_spread(u0, ns, alphas, eps, hs, tau, nsteps, ref, ops=None, observe=None):
     """Largest relative max-norm distance of the two other FP64 evaluation orders
     (two_level_solve_composed, two_level_solve_fft) from `ref`, the result of two_level_solve on
-    the same input: the spread below which FP64 evaluations of this run are not reproducible."""
+    the same input: the spread below which FP64 evaluations of this run are not reproducible.
+    `observe` is passed to both solves."""
     if ops is None:
         ops = axis_operators(ns, alphas, eps, hs, tau)
     scale = max(float(np.abs(ref).max()), 1e-300)
     out = 0.0
-    for alt in (two_level_solve_composed(u0, ns, alphas, eps, hs, tau, nsteps, ops=ops),
-                two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=ops)):
+    for alt in (two_level_solve_composed(u0, ns, alphas, eps, hs, tau, nsteps, ops=ops, observe=observe),
+                two_level_solve_fft(u0, ns, alphas, eps, hs, tau, nsteps, ops=ops, observe=observe)):
         out = max(out, float(np.abs(alt - ref).max()) / scale)
     return out
 

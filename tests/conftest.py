@@ -8,9 +8,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+_CAPTURE = None
+
+
 def pytest_configure(config):
+    global _CAPTURE
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: CPU test that takes tens of seconds")
+    _CAPTURE = config.pluginmanager.getplugin("capturemanager")
+
+
+def progress(msg):
+    """Print a line past pytest's output capture: long GPU tests (minutes of oracle work on the
+    host) report that they are alive as they go, also in a quiet run."""
+    if _CAPTURE is not None:
+        with _CAPTURE.global_and_fixture_disabled():
+            print(msg, flush=True)
+    else:
+        print(msg, flush=True)
 
 
 def _gpu_available():

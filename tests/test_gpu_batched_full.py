@@ -10,6 +10,7 @@ import sys
 
 import numpy as np
 import pytest
+from conftest import progress
 
 from oracle import sfac_oracle as O
 from paper_2209_08437_amd import workloads as W
@@ -33,8 +34,7 @@ def fp64_bound(inst):
 
 
 def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+    progress(msg)   # past the output capture: long tests show they are alive
 
 
 def rel_err(a, ref):
@@ -50,9 +50,14 @@ def _oracle(i, inst):
     if i not in _ORACLE:
         ops = O.axis_operators(inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau)
         _say(f"    oracle for instance {i} (n = {inst.ns[0]}, {inst.steps} steps, three evaluation orders)")
-        ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps, ops=ops)
+
+        def observe(k, _):
+            if inst.ns[0] >= 511 and k % 100 == 0:
+                _say(f"      step {k}")
+        ref = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps, ops=ops,
+                                observe=observe)
         spread = O.rounding_spread(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau, inst.steps, ref,
-                                   ops=ops)
+                                   ops=ops, observe=observe)
         _ORACLE[i] = (ref, spread)
     return _ORACLE[i]
 

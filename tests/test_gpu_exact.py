@@ -15,6 +15,7 @@ import os
 
 import numpy as np
 import pytest
+from conftest import progress
 
 from oracle import sfac_oracle as O
 from paper_2209_08437_amd import workloads as W
@@ -26,7 +27,7 @@ FP64_TOL = 1e-12     # relative to max|u|, as for the two-level FP64 path
 
 
 def _say(msg):
-    print(msg, flush=True)
+    progress(msg)   # past the output capture: long tests show they are alive
 
 
 def _golden(name):

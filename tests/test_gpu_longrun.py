@@ -18,6 +18,7 @@ checks are the properties the paper states for them.
 """
 import numpy as np
 import pytest
+from conftest import progress
 
 from paper_2209_08437_amd import workloads as W
 
@@ -27,7 +28,7 @@ ROUND = 1e-13     # |u| may exceed 1 by the rounding of the last digit
 
 
 def _say(msg):
-    print(msg, flush=True)
+    progress(msg)   # past the output capture: long tests show they are alive
 
 
 def _run(inst, checkpoints=1):

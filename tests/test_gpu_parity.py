@@ -21,6 +21,7 @@ import sys
 
 import numpy as np
 import pytest
+from conftest import progress
 
 from oracle import sfac_oracle as O
 from paper_2209_08437_amd import workloads as W
@@ -38,8 +39,7 @@ def _torch():
 
 
 def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+    progress(msg)   # past the output capture: long tests show they are alive
 
 
 def gpu_solve(u0, ns, alphas, eps, hs, tau, steps, dtype="f64", method=None, use_graph=True, chunk=32, sched=None):
@@ -473,6 +473,11 @@ class _extended:
         return float(np.abs(np.asarray(state).reshape(-1)[self.index] - self.value).max() / self.scale)
 
 
+def progress_every_250(k, _):
+    if k % 250 == 0:
+        _say(f"    oracle step {k}")
+
+
 def _c2_oracle():
     """The 1023^2 workload over all 1000 steps by the oracle, and the spread of its three FP64
     evaluation orders (dense factors in the paper's order, per-axis operators multiplied out,
@@ -481,13 +486,11 @@ def _c2_oracle():
         inst = W.large_2d_1023()
         _say("  oracle, 1023^2 x 1000 steps, three evaluation orders (a minute or two on the host)")
         ops = O.axis_operators(inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau)
-        def progress(k, _):
-            if k % 250 == 0:
-                _say(f"    oracle step {k}")
         _C2_ORACLE["ref"] = O.two_level_solve(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau,
-                                              inst.steps, ops=ops, observe=progress)
+                                              inst.steps, ops=ops, observe=progress_every_250)
+        _say("  oracle, the two other evaluation orders")
         _C2_ORACLE["floor"] = O.rounding_spread(inst.u0, inst.ns, inst.alphas, inst.eps, inst.hs, inst.tau,
-                                                inst.steps, _C2_ORACLE["ref"], ops=ops)
+                                                inst.steps, _C2_ORACLE["ref"], ops=ops, observe=progress_every_250)
         _say(f"  oracle rounding floor (spread of its FP64 evaluation orders) {_C2_ORACLE['floor']:.3e}")
     return _C2_ORACLE["ref"], _C2_ORACLE["floor"]
 

@@ -11,6 +11,7 @@ import os
 
 import numpy as np
 import pytest
+from conftest import progress
 
 from paper_2209_08437_amd import workloads as W
 
@@ -29,7 +30,7 @@ def _rel_ok(got, printed):
 
 
 def _say(msg):
-    print(msg, flush=True)
+    progress(msg)   # past the output capture: long tests show they are alive
 
 
 def _solve(u0, ns, alphas, eps, hs, tau, steps, method=None):

@@ -8,6 +8,7 @@ chunks or single steps.
 """
 import numpy as np
 import pytest
+from conftest import progress
 
 from oracle import sfac_oracle as O
 from paper_2209_08437_amd import workloads as W
@@ -16,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _say(msg):
-    print(msg, flush=True)
+    progress(msg)   # past the output capture: long tests show they are alive
 
 
 def _oracle_maxes(u0, ns, alphas, eps, hs, tau, steps):

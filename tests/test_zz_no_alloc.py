@@ -5,6 +5,7 @@ import sys
 
 import numpy as np
 import pytest
+from conftest import progress
 
 from paper_2209_08437_amd import workloads as W
 
@@ -12,8 +13,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
+    progress(msg)   # past the output capture: long tests show they are alive
 
 
 def _instance(ns, seed):
