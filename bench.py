@@ -6,7 +6,9 @@ the largest single-GPU instance: 3D, N = 255 per axis (16.6 M points), alpha = (
 eps = 0.08, tau = 5e-3, FP64, and the default K = 200 timed steps is its full run. The state is
 resident in HBM before the timed region starts; the timed region is one sfac_step call of K
 steps (HIP graph replays: K / 32 replays of a 32-step graph and one replay per set bit of the
-rest) bracketed by device synchronizations.
+rest, all captured beforehand by untimed runs of K steps from a copy of the initial state, kept
+up for a quarter of a second so that the device's clocks are up) bracketed by device
+synchronizations.
 
 Each axis pass runs the schedule (method, kernel, elements per thread, lines per block) that
 the autotuner picked on an MI355X for this shape, read from the table that ships with the
@@ -103,6 +105,18 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None, 
     warm_ms = (time.perf_counter() - tp) * 1e3
     log(f"[bench] {dtype}: plan created in {plan_ms:.2f} ms; {warmup} warm-up steps (graph capture included) "
         f"{warm_ms:.2f} ms")
+    # the step graphs the timed call replays (a 32-step chunk and one graph per set bit of the
+    # rest) are captured before it by untimed runs of the same step count from the same state
+    # buffer (graphs belong to a state address), which is then reset; the runs go on for a
+    # quarter of a second, so that the device's clocks have ramped up under load when the timed
+    # region starts (after idling, a short timed call otherwise runs up to 20% slow)
+    t_prime = time.perf_counter() + 0.25
+    for _ in range(1000):
+        u.copy_(u0)
+        plan.step(u, steps)
+        torch.cuda.synchronize()
+        if time.perf_counter() > t_prime:
+            break
     u.copy_(u0)
     plan.reset_flags()
     torch.cuda.synchronize()
@@ -296,8 +310,15 @@ def batched_run(args):
         states = [torch.tensor(i.u0, dtype=tdt, device="cuda") for i in insts]
         b = sfac.Batch(insts, dt, schedules=sched)
         b.step(states, min(args.warmup, steps))
+        # the step graphs of the timed call (they belong to the states' addresses) are captured by
+        # an untimed run of the same steps on the same buffers, which are then reset
+        for u, i in zip(states, insts):
+            u.copy_(torch.tensor(i.u0, dtype=tdt, device="cuda"))
+        b.step(states, steps)
         torch.cuda.synchronize()
-        states = [torch.tensor(i.u0, dtype=tdt, device="cuda") for i in insts]
+        for u, i in zip(states, insts):
+            u.copy_(torch.tensor(i.u0, dtype=tdt, device="cuda"))
+        b.reset_flags()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.step(states, steps)
@@ -316,8 +337,10 @@ def batched_run(args):
     states = [torch.tensor(i.u0, dtype=torch.float64, device="cuda") for i in insts]
     for p, u in zip(plans, states):
         p.step(u, min(args.warmup, steps))
-    torch.cuda.synchronize()
-    states = [torch.tensor(i.u0, dtype=torch.float64, device="cuda") for i in insts]
+    for p, u, i in zip(plans, states, insts):     # graphs of the timed call, captured untimed
+        u.copy_(torch.tensor(i.u0, dtype=torch.float64, device="cuda"))
+        p.step(u, steps)
+        u.copy_(torch.tensor(i.u0, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for p, u in zip(plans, states):

@@ -411,6 +411,11 @@ class Batch:
         _check(lib().sfac_batch_step(self._h, ptrs, steps))
         return states
 
+    def reset_flags(self):
+        """Clear every instance's sticky status (sfac_plan_reset_flags on each plan of the batch)."""
+        for i in range(self.count):
+            _check(lib().sfac_plan_reset_flags(lib().sfac_batch_plan(self._h, i)))
+
     def flags(self, i):
         """(flags, max_abs) of instance i; synchronizes the batch's stream."""
         h = lib().sfac_batch_plan(self._h, int(i))
