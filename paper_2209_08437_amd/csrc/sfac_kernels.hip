@@ -1067,6 +1067,19 @@ template <int AXIS>
 __global__ void __launch_bounds__(64) pass_timing_mark() {}
 }  // namespace
 
+namespace {
+__global__ void __launch_bounds__(64) zero_words(unsigned int* p, int words) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < words) p[i] = 0u;
+}
+}  // namespace
+
+hipError_t launch_zero_words(unsigned int* p, int words, hipStream_t stream) {
+    if (words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_words, dim3((words + 63) / 64), dim3(64), 0, stream, p, words);
+    return hipGetLastError();
+}
+
 hipError_t launch_timing_mark(int axis, hipStream_t stream) {
     switch (axis) {
         case 0: hipLaunchKernelGGL(pass_timing_mark<0>, dim3(1), dim3(64), 0, stream); break;

@@ -110,6 +110,10 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Grou
 hipError_t launch_trace_collect(unsigned long long* parts, long long nparts, unsigned long long* rec, long long* step,
                                 long long cap, hipStream_t stream);
 
+// Clears `words` 32-bit words at p on `stream` with a kernel (not a memset node, so that a caller
+// may capture the call into a graph and replay it).
+hipError_t launch_zero_words(unsigned int* p, int words, hipStream_t stream);
+
 // An empty kernel named for `axis` (1..3, or 0 after the last): sfac_plan_time_passes launches
 // one before each axis' timed launches, so that profiles attribute those dispatches to their axis.
 hipError_t launch_timing_mark(int axis, hipStream_t stream);

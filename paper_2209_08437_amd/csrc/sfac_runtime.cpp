@@ -601,7 +601,7 @@ sfac_status energy_setup(sfac_plan p) {
 
 template <typename T>
 hipError_t energy_launch(sfac_plan p, T* u) {
-    hipError_t e = hipMemsetAsync(p->energy_dev, 0, 2 * sizeof(double), p->stream);
+    hipError_t e = sfac::launch_zero_words(reinterpret_cast<unsigned int*>(p->energy_dev), 4, p->stream);
     for (int a = 0; a < p->in.dims && e == hipSuccess; ++a)
         e = sfac::launch_energy_pass<T>(energy_desc<T>(p->in, a, p->eax[a], p->energy_dev, u), p->eax[a].lds,
                                         p->stream);
@@ -1018,8 +1018,8 @@ sfac_status sfac_plan_flags(sfac_plan p, uint32_t* flags, double* max_abs) {
 sfac_status sfac_plan_reset_flags(sfac_plan p) {
     g_error.clear();
     if (!p) return fail(SFAC_EINVAL, "NULL plan");
-    hipError_t e = hipMemsetAsync(p->dev + p->off_stat, 0, 16, p->stream);
-    return e == hipSuccess ? SFAC_OK : hip_fail(e, "hipMemsetAsync");
+    hipError_t e = sfac::launch_zero_words(reinterpret_cast<unsigned int*>(p->dev + p->off_stat), 4, p->stream);
+    return e == hipSuccess ? SFAC_OK : hip_fail(e, "status clear");
 }
 
 sfac_status sfac_plan_method(sfac_plan p, int32_t axis, int32_t* method, int32_t* length) {

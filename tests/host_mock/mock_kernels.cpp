@@ -76,6 +76,16 @@ hipError_t launch_exact_nl(double*, const double*, long long, double, bool, cons
     mock_submit(s, [] {});
     return hipSuccess;
 }
+hipError_t launch_zero_words(unsigned int* p, int words, hipStream_t s) {
+    if (words <= 0) return hipSuccess;
+    if (!mock_range_live(p, sizeof(unsigned int) * (size_t)words)) mock_die("zero_words outside live memory");
+    if (mock_inject()) return mock_fail_launch(s);
+    mock_submit(s, [p, words] {
+        if (!mock_range_live(p, sizeof(unsigned int) * (size_t)words)) mock_die("zero_words outside live memory");
+        for (int i = 0; i < words; ++i) p[i] = 0u;
+    });
+    return hipSuccess;
+}
 hipError_t launch_timing_mark(int, hipStream_t s) {
     mock_submit(s, [] {});
     return hipSuccess;

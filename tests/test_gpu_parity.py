@@ -390,6 +390,49 @@ def test_flags_report_nonfinite_and_above_one(sfac_lib):
         assert f & sfac.FLAG_ABOVE_ONE and m > 1
 
 
+def test_status_clear_and_steps_inside_a_caller_graph(sfac_lib):
+    """A caller captures sfac_plan_reset_flags and plain-launch steps into a graph of its own (the
+    status is cleared by a kernel, not a memset node): every replay, with eager work and
+    synchronisations between them, ends bitwise equal to the same work done eagerly, and the
+    status read after each replay is that replay's own."""
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    ns = (63, 40)
+    hs = W.mesh_widths(ns)
+    u0 = torch.tensor(W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=9), device="cuda")
+    big = torch.tensor(W.uniform_field(tuple(reversed(ns)), -1.4, 1.4, seed=9), device="cuda")
+    _say("case status clear and steps in a caller graph")
+    s = torch.cuda.Stream()
+    with sfac.Plan(ns, (1.4, 1.7), 0.1, 0.01, hs, "f64", stream=s, use_graph=False) as p:
+        u_eager = u0.clone()
+        with torch.cuda.stream(s):
+            p.reset_flags()
+            p.step(u_eager, 4)
+        torch.cuda.synchronize()
+        f_eager, m_eager = p.flags()
+        u = u0.clone()
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            p.reset_flags()
+            p.step(u, 4)
+        for r in range(3):
+            with torch.cuda.stream(s):
+                u.copy_(big)                    # eager work between replays: the status goes above one
+                p.step(u, 1)
+            torch.cuda.synchronize()
+            assert p.flags()[0] & sfac.FLAG_ABOVE_ONE
+            with torch.cuda.stream(s):
+                u.copy_(u0)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            f, m = p.flags()
+            assert torch.equal(u, u_eager), r
+            assert f == f_eager == 0 and m == m_eager, (r, f, m)
+        del g
+
+
 # -------------------------------------------------------------------------- batch
 def test_batch_matches_single_bitwise_and_oracle(sfac_lib):
     torch = _torch()
