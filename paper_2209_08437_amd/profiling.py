@@ -290,7 +290,7 @@ def sq_markdown(directory, workload, dims):
 MFMA_COUNTERS = ("SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU_MFMA_F64 SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_LDS "
                  "SQ_LDS_BANK_CONFLICT SQ_INSTS_VMEM_RD")
 MFMA_COMMAND = ("timeout -s KILL 120 rocprofv3 --pmc " + MFMA_COUNTERS + " --output-format csv -d $O/$W -o run -- "
-                "python3 $R/bench.py --workload $W --no-cpu --no-fp32 --steps 10 --warmup 2 --pass-reps 2")
+                "python3 $R/bench.py --workload $W --no-cpu --no-fp32 --no-sub --steps 10 --warmup 2 --pass-reps 2")
 SIMDS = 1024                      # MI355X: 256 CUs of 4 SIMDs
 CLOCK_MHZ = 2400.0
 
