@@ -21,18 +21,23 @@ against it (the 63^3 subsample of the 3D instance over all its steps, and the 10
 over all its steps), and the one-level scheme with the exact exponential that the paper
 compares the two-level scheme with, run on the GPU over the same steps.
 
-Roofline. Each axis pass reads and writes the state once (2 x points x element bytes) and does
-the conventional FFT count of flops on every point: 6 transforms of 5 L log2 L flops per complex
-line of 2 real lines, i.e. 15 log2 N flops per point, plus 9 for the three spectrum scalings and
-the two psi twiddles, plus the nonlinear half-steps (about 20 flops per point per step, split
-over the d passes). Whichever of the two takes longer at the published peaks (8 TB/s HBM; 78.6
-FP64 / 157.3 FP32 TFLOP/s vector) bounds the pass: 3D N = 255 in FP64 moves 16 B per point for
-136 flops (8.5 flop/B, below the 9.8 flop/B ridge), so it is bound by HBM; 2D N = 1023 does 169
-flops on the same bytes (10.6 flop/B), bound by arithmetic. `achieved` is the algorithmic bytes
-(or flops) per launch over the kernel's mean launch duration, measured here with HIP events
-around a graph of back-to-back launches of that pass on the plan's stream. `traffic` is the HBM
-bytes per launch measured with hardware counters (rocprofv3 FETCH_SIZE and WRITE_SIZE,
-calibrated on a plain copy kernel) when the committed record matches the current kernel sources.
+Roofline. Each axis pass does the conventional FFT count of flops on every point: 6 transforms
+of 5 L log2 L flops per complex line of 2 real lines, i.e. 15 log2 N flops per point, plus 9 for
+the three spectrum scalings and the two psi twiddles, plus the nonlinear half-steps (about 20
+flops per point per step, split over the d passes). Steps alternate their axis order (1..d, then
+d..1), so at every step boundary one launch covers the same axis twice: it reads and writes the
+state once (2 x points x element bytes) for two passes' flops. In steady state two steps of the
+3D instance launch axis 2 twice, axis 3 once (two passes) and axis 1 once (two passes); two steps
+of a 2D instance launch each axis once (two passes). The roofline object describes the launch
+that takes the largest share of that time. Whichever of its algorithmic bytes and flops takes
+longer at the published peaks (8 TB/s HBM; 78.6 FP64 / 157.3 FP32 TFLOP/s vector) bounds it: a
+single 3D N = 255 FP64 pass moves 16 B per point for 136 flops (8.5 flop/B, below the 9.8 flop/B
+ridge), bound by HBM; a fused one does 272 flops on the same bytes, and a fused 2D N = 1023 one
+338, bound by arithmetic. `achieved` is the algorithmic flops (or bytes) per launch over the
+launch's mean duration, measured here with HIP events around a graph of back-to-back launches of
+that kind on the plan's stream. `traffic` is the HBM bytes per launch measured with hardware
+counters (rocprofv3 FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy kernel) when the
+committed record matches the current kernel sources.
 """
 import argparse
 import json
@@ -149,13 +154,16 @@ def gpu_rate(inst, dtype, steps, warmup, pass_reps, tune=True, tune_cache=None, 
     # captured graph, HIP events around the replay on the plan's stream (on a scratch copy)
     uu = u0.clone()
     pass_ms = plan.time_passes(uu, pass_reps)
+    # the launches that cover axis 1 and axis d twice (a step's last pass and the next one's
+    # first, as the steps run them at every step boundary)
+    fused_ms = plan.time_fused(uu, pass_reps)
     del uu
     torch.cuda.synchronize()
     state = u.double().cpu().numpy()
     diag = diagnostics(plan, u0, u, min(steps, 200)) if with_diagnostics else None
     result = {
         "wall_s": wall, "gpu_ms": gpu_ms, "flags": flags, "max_abs": vmax,
-        "pass_ms": pass_ms, "methods": methods, "state": state, "schedule": sched,
+        "pass_ms": pass_ms, "fused_ms": fused_ms, "methods": methods, "state": state, "schedule": sched,
         "plan_create_ms": plan_ms, "warmup_ms": warm_ms, "diagnostics": diag, "repeat_ms_per_step": reps,
     }
     plan.close()
@@ -198,19 +206,46 @@ def diagnostics(plan, u0, u, k):
         return {"unavailable": str(err)}
 
 
+def step_launches(dims, fused_ms):
+    """The launches of two consecutive steps in steady state, as (axis 0-based, passes per launch,
+    launches per two steps): the step boundaries fuse the last pass of a step with the first of
+    the next (axis d after a step in the order 1..d, axis 1 after one in the order d..1); an axis
+    whose kernel does not fuse (fused time 0) runs its two passes as two launches."""
+    if dims == 1:
+        return [(0, 2, 1)] if fused_ms[0] > 0 else [(0, 1, 2)]
+    out = []
+    for a in range(dims):
+        end = 0 if a == 0 else (1 if a == dims - 1 else None)
+        if end is not None and fused_ms[end] > 0:
+            out.append((a, 2, 1))
+        else:
+            out.append((a, 1, 2))
+    return out
+
+
 def pass_roofline(inst, dtype, r, workload_name):
-    """Roofline of the axis pass with the longest mean launch duration of one gpu_rate result.
-    The bound is whichever of the pass's algorithmic bytes (one read and one write of the state)
-    and algorithmic flops takes longer at the published peaks; `achieved` is that quantity per
-    launch over the mean launch duration. The other figure is reported beside it, and `traffic`
-    is the counter-measured HBM bytes per launch when the committed record matches."""
+    """Roofline of the dominant launch of the step: of the launches two steps make in steady
+    state (step_launches), the one that takes the largest share of their time. A launch reads
+    and writes the state once; a fused launch does two passes' flops on those bytes. The bound
+    is whichever of its algorithmic bytes and algorithmic flops takes longer at the published
+    peaks; `achieved` is that quantity per launch over the mean launch duration. The other
+    figure is reported beside it, and `traffic` is the counter-measured HBM bytes per launch when
+    the committed record matches."""
     from paper_2209_08437_amd import profiling
     esize = 8 if dtype == "f64" else 4
     pass_ms = r["pass_ms"]
-    a = max(range(len(pass_ms)), key=lambda i: pass_ms[i])
-    fl = pass_flops(inst, a)
+    fused_ms = r["fused_ms"]
+    mix = step_launches(inst.dims, fused_ms)
+
+    def launch_ms(a, passes):
+        return (fused_ms[0 if a == 0 else 1] if passes == 2 else pass_ms[a])
+
+    a, passes, _ = max(mix, key=lambda m: m[2] * launch_ms(m[0], m[1]))
+    ms = launch_ms(a, passes)
+    step_ms = sum(m[2] * launch_ms(m[0], m[1]) for m in mix) / 2.0
+    fl = passes * pass_flops(inst, a)
     byt = 2 * inst.points * esize
-    sec = pass_ms[a] * 1e-3
+    sec = ms * 1e-3
     peak_tf = VALU_PEAK_TFLOPS[dtype]
     tf = fl / sec / 1e12
     gbps = byt / sec / 1e9
@@ -221,14 +256,21 @@ def pass_roofline(inst, dtype, r, workload_name):
     hbm_bound = byt / (HBM_PEAK_GBS * 1e9) >= fl / (peak_tf * 1e12)
     out = dict(hbm if hbm_bound else alu)
     rec = profiling.load_traffic(TRAFFIC_RECORD, workload_name, dtype, r["schedule"] or None)
+    traffic = None
+    if rec:
+        hit = [x for x in rec["per_axis"] if x["axis"] == a + 1 and x.get("twice", False) == (passes == 2)]
+        traffic = hit[0]["bytes"] if hit else None
     meth, length = r["methods"][a]
     out.update({
-        "traffic": rec["per_axis"][a]["bytes"] if rec else None,
+        "traffic": traffic,
         "kernel": f"{meth} axis pass ({'double' if esize == 8 else 'float'}, transform length {length}), "
-                  f"axis {a + 1}",
+                  f"axis {a + 1}" + (", two passes per launch (a step boundary between)" if passes == 2 else ""),
         "algorithmic_bytes_per_launch": byt, "flops_per_launch": round(fl),
-        "mean_launch_ms": round(pass_ms[a], 5), "pass_ms": [round(x, 5) for x in pass_ms],
-        "timing": "HIP events around a graph of back-to-back launches of each pass on the plan's stream",
+        "mean_launch_ms": round(ms, 5), "pass_ms": [round(x, 5) for x in pass_ms],
+        "fused_ms": [round(x, 5) for x in fused_ms],
+        "launches_per_two_steps": [{"axis": m[0] + 1, "passes": m[1], "launches": m[2]} for m in mix],
+        "step_ms_from_launches": round(step_ms, 5),
+        "timing": "HIP events around a graph of back-to-back launches of each launch kind on the plan's stream",
         "alu" if hbm_bound else "hbm": alu if hbm_bound else hbm,
         "traffic_record": (f"profiles/traffic.json ({rec['profile']})" if rec else
                            "none for the current kernel sources"),

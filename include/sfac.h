@@ -145,8 +145,15 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
  *   u_dev  : device pointer to prod(N_l) values of the plan's dtype, C-order (N_d, .., N_1),
  *            aligned to the element size.
  *   nsteps : >= 0; 0 returns at once.
- * Asynchronous on the plan's stream: it returns once the work is queued. Splitting a run
- * into several calls gives bitwise the same result (no step is fused across calls or steps).
+ * Asynchronous on the plan's stream: it returns once the work is queued.
+ * Axis order: the per-axis factors commute (C_a and S_a are Kronecker sums over the axes, Sec.
+ * 2.2), so the passes of a step may run in any axis order. Steps alternate between the orders
+ * 1..d and d..1 by the parity of the number of steps the plan has queued (through sfac_step
+ * and groups alike), which makes the last pass of a step and the first of the next cover the
+ * same axis; one launch does both, the step boundary (closing J^Q_{tau/2}, statistics, opening
+ * J^Q_{tau/2}) applied in registers, bitwise as the two launches would give it. Splitting a run
+ * into several calls, graph chunks or plain launches, and stepping through a group, give
+ * bitwise the same result as one call.
  * Errors: SFAC_EINVAL (NULL plan or pointer, misaligned pointer, nsteps < 0), SFAC_EDEVICE.
  */
 sfac_status sfac_step(sfac_plan p, void* u_dev, int64_t nsteps);
@@ -180,6 +187,19 @@ sfac_status sfac_plan_reset_flags(sfac_plan p);
  * steps. Errors: SFAC_EINVAL, SFAC_EDEVICE.
  */
 sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float* ms);
+
+/*
+ * sfac_plan_time_fused - measure the launches that cover an axis twice (the last pass of one
+ * step and the first of the next, eq. (finalstrang) applied twice with the step boundary in
+ * between; see sfac_step): `reps` >= 1 such launches on u_dev, captured into a graph and
+ * replayed once between a pair of HIP events on the plan's stream. ms[0] receives the mean
+ * duration per launch over axis 1 (a step in the order d..1 followed by one in the order 1..d),
+ * ms[1] over axis d (the other way round), in milliseconds; 0 for an axis whose kernel does not
+ * fuse (the generic diagonal kernel) and for plans of SFAC_METHOD_EXACT. For one axis both
+ * entries are the same launch. u_dev is overwritten with intermediate values. Synchronizes the
+ * plan's stream. Errors: SFAC_EINVAL, SFAC_EDEVICE.
+ */
+sfac_status sfac_plan_time_fused(sfac_plan p, void* u_dev, int32_t reps, float* ms);
 
 /*
  * sfac_plan_energy - the discrete free energy of Sec. 5, Example 5 (the discretisation of the

@@ -162,6 +162,48 @@ __device__ __forceinline__ void publish_stats(double vmax, unsigned int bad, con
     }
 }
 
+// Statistics of one stored pair: the largest finite |u| and the non-finite flag (the second
+// value counts only when the pair holds two real lines).
+template <typename T>
+__device__ __forceinline__ void track_stats(const cplx<T>& z, bool two, double& vmax, unsigned int& bad) {
+    const double ax = fabs((double)z.x), ay = two ? fabs((double)z.y) : 0.0;
+    if (!(ax <= 1.7976931348623157e308) || !(ay <= 1.7976931348623157e308))
+        bad |= SFAC_FLAG_NONFINITE;
+    else
+        vmax = fmax(vmax, fmax(ax, ay));
+}
+
+// The step boundary inside a pass that covers its axis twice (eq. (finalstrang) applied twice,
+// the last pass of one step and the first of the next on the same axis): the closing half-step
+// J^Q_{tau/2} of the first step, its statistics, and the opening half-step of the next. The
+// values are exactly those the two separate passes would store and load again; a pair that
+// holds one real line keeps zero in its second slot, as a fresh load gives it.
+//
+// Every half-step's input and result pass through an empty asm statement (as_stored), here and
+// where the passes load and store: the compiler may otherwise fuse a product on one side of a
+// half-step into the sums on the other (the transform's last product into 1 - v, the half-step's
+// final product into the transform's first sums) wherever the two meet in one kernel, which
+// would skip a rounding that a store and a load between two launches make.
+template <typename T>
+__device__ __forceinline__ T as_stored(T x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+template <typename T>
+__device__ __forceinline__ T nl_isolated(T v, T decay, T decay_lo) {
+    return as_stored(nonlinear_half_step_fast(as_stored(v), decay, decay_lo));
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> step_boundary(cplx<T> z, bool two, T decay, T decay_lo, double& vmax,
+                                                 unsigned int& bad) {
+    z.x = nl_isolated(z.x, decay, decay_lo);
+    z.y = two ? nl_isolated(z.y, decay, decay_lo) : (T)0;
+    track_stats(z, two, vmax, bad);
+    z.x = nl_isolated(z.x, decay, decay_lo);
+    z.y = nl_isolated(z.y, decay, decay_lo);
+    return z;
+}
+
 // keep: a third LDS buffer of lpb lines, used in the increment form only (the factor's input).
 template <typename T>
 __device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>* buf1, cplx<T>* keep) {
@@ -365,7 +407,8 @@ __device__ __forceinline__ void embed_stage(const PassDesc<T>& d, const TileGeom
 }
 
 // Embedded method, register-resident transforms of length 2^LOG2M; STAGE: tile I/O through LDS.
-template <typename T, int LOG2M, int LE, bool STAGE>
+// TWICE: the pass covers its axis twice with a step boundary between (nl_mid).
+template <typename T, int LOG2M, int LE, bool STAGE, bool TWICE = false>
 __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     using G = EmbedGeom<LOG2M, LE>;
     using Line = EmbedLine<T, LOG2M, LE>;
@@ -397,18 +440,33 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
                 } else {
                     load_pair(own + (long long)n * tg.kstride, tg.lstride, two, z.x, z.y);
                     if (d.nl_in) {
-                        z.x = nonlinear_half_step_fast(z.x, decay, decay_lo);
-                        z.y = nonlinear_half_step_fast(z.y, decay, decay_lo);
+                        z.x = nl_isolated(z.x, decay, decay_lo);
+                        z.y = nl_isolated(z.y, decay, decay_lo);
                     }
                 }
             }
             L.a[i * R0 + k] = z;
         }
-    L.factor(d.gpos_c, ln, t, N);
-    L.factor(d.gpos_s, ln, t, N);
-    L.factor(d.gpos_c, ln, t, N);
     double vmax = 0.0;
     unsigned int bad = 0;
+    // Unrolled: the second pass must see the same compile-time zeros (the padding registers) as
+    // a pass that loads its tile, so that the compiler simplifies and fuses its arithmetic the
+    // same way and the values stay bitwise those of two launches.
+    constexpr int reps = TWICE ? 2 : 1;
+#pragma unroll
+    for (int r = 0; r < reps; ++r) {
+        if (r == 1) {
+#pragma unroll
+            for (int i = 0; i < G::E / R0; ++i)
+#pragma unroll
+                for (int k = 0; k < R0; ++k)
+                    if ((R0 < 2 || k < R0 / 2) && act && Line::nat(t, i, k) < N)
+                        L.a[i * R0 + k] = step_boundary(L.a[i * R0 + k], two, decay, decay_lo, vmax, bad);
+        }
+        L.factor(d.gpos_c, ln, t, N);
+        L.factor(d.gpos_s, ln, t, N);
+        L.factor(d.gpos_c, ln, t, N);
+    }
     if constexpr (STAGE) __syncthreads();   // the last exchange's reads are done before the staging writes
 #pragma unroll
     for (int i = 0; i < G::E / R0; ++i)
@@ -418,13 +476,9 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
             if ((R0 < 2 || k < R0 / 2) && act && n < N) {
                 cplx<T> z = L.a[i * R0 + k];
                 if (d.nl_out) {
-                    z.x = nonlinear_half_step_fast(z.x, decay, decay_lo);
-                    z.y = nonlinear_half_step_fast(z.y, decay, decay_lo);
-                    const double ax = fabs((double)z.x), ay = two ? fabs((double)z.y) : 0.0;
-                    if (!(ax <= 1.7976931348623157e308) || !(ay <= 1.7976931348623157e308))
-                        bad |= SFAC_FLAG_NONFINITE;
-                    else
-                        vmax = fmax(vmax, fmax(ax, ay));
+                    z.x = nl_isolated(z.x, decay, decay_lo);
+                    z.y = nl_isolated(z.y, decay, decay_lo);
+                    track_stats(z, two, vmax, bad);
                 }
                 if constexpr (STAGE)
                     ln[embed_swz<T, LOG2M>(n)] = z;
@@ -436,7 +490,7 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
         __syncthreads();
         embed_stage<T, LOG2M, LE, false>(d, tg, lds);
     }
-    if (d.nl_out) publish_stats(vmax, bad, d);
+    if (d.nl_out || TWICE) publish_stats(vmax, bad, d);
 }
 
 template <typename T, int A, int B, bool LOAD>
@@ -478,7 +532,8 @@ __device__ __forceinline__ void stage_tile(const TileGeom<T>& tg, int lpb, cplx<
 
 // Diagonal method, register-resident two-step transforms of length N = A B. The tile goes
 // through LDS on the way in and out (the prime-factor layout scatters a thread's positions).
-template <typename T, int A, int B, bool WA>
+// TWICE: the pass covers its axis twice with a step boundary between (nl_mid).
+template <typename T, int A, int B, bool WA, bool TWICE = false>
 __device__ __forceinline__ void run_diag2_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     using G = Diag2Geom<A, B>;
     using Line = Diag2Line<T, A, B, WA>;
@@ -507,36 +562,40 @@ __device__ __forceinline__ void run_diag2_tile(const PassDesc<T>& d, int tile, c
             if (act) {
                 z = ln[G::pos(t, k)];
                 if (d.nl_in) {
-                    z.x = nonlinear_half_step_fast(z.x, decay, decay_lo);
-                    z.y = nonlinear_half_step_fast(z.y, decay, decay_lo);
+                    z.x = nl_isolated(z.x, decay, decay_lo);
+                    z.y = nl_isolated(z.y, decay, decay_lo);
                 }
             }
             L.a[k] = z;
         }
     }
-    L.factors(d.gpos_c, d.gpos_s, d.psi2, ln, t);
     double vmax = 0.0;
     unsigned int bad = 0;
+    constexpr int reps = TWICE ? 2 : 1;
+#pragma unroll 1
+    for (int r = 0; r < reps; ++r) {
+        if (r == 1 && t < B && act) {
+#pragma unroll
+            for (int k = 0; k < A; ++k) L.a[k] = step_boundary(L.a[k], two, decay, decay_lo, vmax, bad);
+        }
+        L.factors(d.gpos_c, d.gpos_s, d.psi2, ln, t);
+    }
     __syncthreads();   // the last exchange's reads are done before the staging writes
     if (t < B && act) {
 #pragma unroll
         for (int k = 0; k < A; ++k) {
             cplx<T> z = L.a[k];
             if (d.nl_out) {
-                z.x = nonlinear_half_step_fast(z.x, decay, decay_lo);
-                z.y = nonlinear_half_step_fast(z.y, decay, decay_lo);
-                const double ax = fabs((double)z.x), ay = two ? fabs((double)z.y) : 0.0;
-                if (!(ax <= 1.7976931348623157e308) || !(ay <= 1.7976931348623157e308))
-                    bad |= SFAC_FLAG_NONFINITE;
-                else
-                    vmax = fmax(vmax, fmax(ax, ay));
+                z.x = nl_isolated(z.x, decay, decay_lo);
+                z.y = nl_isolated(z.y, decay, decay_lo);
+                track_stats(z, two, vmax, bad);
             }
             ln[G::pos(t, k)] = z;
         }
     }
     __syncthreads();
     stage_tile<T, A, B, false>(tg, d.lpb, lds);
-    if (d.nl_out) publish_stats(vmax, bad, d);
+    if (d.nl_out || TWICE) publish_stats(vmax, bad, d);
 }
 
 // blockIdx -> tile, grouping neighbouring tiles on one XCD (blocks are dealt round-robin to
@@ -574,12 +633,14 @@ constexpr int embed_min_waves(int log2m, int le, bool stage) {
 #define SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE)                   \
     __launch_bounds__(embed_max_block(LOG2M, LE, STAGE), (embed_min_waves<T>(LOG2M, LE, STAGE)))
 
-template <typename T, int LOG2M, int LE, bool STAGE>
+// TWICE: two passes over the axis in one launch (descriptors with nl_mid), a distinct kernel so
+// that the single passes keep their register allocation.
+template <typename T, int LOG2M, int LE, bool STAGE, bool TWICE>
 __global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_single(PassDesc<T> d) {
     extern __shared__ unsigned char smem_raw[];
     const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
     if (tile >= d.ntiles) return;
-    run_embed_tile<T, LOG2M, LE, STAGE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_embed_tile<T, LOG2M, LE, STAGE, TWICE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
 // The instance of a grouped launch that owns block b (the last entry whose first block is at
@@ -622,12 +683,12 @@ constexpr int diag2_min_waves() {
     return 3;
 }
 
-template <typename T, int A, int B, bool WA>
+template <typename T, int A, int B, bool WA, bool TWICE>
 __global__ void __launch_bounds__(kBlockThreads, (diag2_min_waves<T, A, B, WA>())) diag2_pass_single(PassDesc<T> d) {
     extern __shared__ unsigned char smem_raw[];
     const int tile = d.xcd_remap ? xcd_tile(blockIdx.x, d.ntiles) : (int)blockIdx.x;
     if (tile >= d.ntiles) return;
-    run_diag2_tile<T, A, B, WA>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_diag2_tile<T, A, B, WA, TWICE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
 template <typename T, int A, int B, bool WA>
@@ -640,70 +701,75 @@ __global__ void __launch_bounds__(kBlockThreads, (diag2_min_waves<T, A, B, WA>()
     run_diag2_tile<T, A, B, WA>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
+template <typename T, int A, int B, bool WA>
+const void* diag2_fn_w(bool multi, bool twice) {
+    if (multi) return twice ? nullptr : reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B, WA>);
+    return twice ? reinterpret_cast<const void*>(&diag2_pass_single<T, A, B, WA, true>)
+                 : reinterpret_cast<const void*>(&diag2_pass_single<T, A, B, WA, false>);
+}
 template <typename T, int A, int B>
-const void* diag2_fn_ab(bool multi, bool wave) {
-    if (wave)
-        return multi ? reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B, true>)
-                     : reinterpret_cast<const void*>(&diag2_pass_single<T, A, B, true>);
-    return multi ? reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B, false>)
-                 : reinterpret_cast<const void*>(&diag2_pass_single<T, A, B, false>);
+const void* diag2_fn_ab(bool multi, bool wave, bool twice) {
+    return wave ? diag2_fn_w<T, A, B, true>(multi, twice) : diag2_fn_w<T, A, B, false>(multi, twice);
 }
 
 // the (A, B) pairs the host may plan (see diag2_pair); wave: the wavefront-aligned layout
 template <typename T>
-const void* diag2_fn(int a, int b, bool multi, bool wave) {
+const void* diag2_fn(int a, int b, bool multi, bool wave, bool twice) {
     switch (a * 64 + b) {
-        case 3 * 64 + 5: return diag2_fn_ab<T, 3, 5>(multi, wave);
-        case 5 * 64 + 7: return diag2_fn_ab<T, 5, 7>(multi, wave);
-        case 7 * 64 + 9: return diag2_fn_ab<T, 7, 9>(multi, wave);
-        case 9 * 64 + 11: return diag2_fn_ab<T, 9, 11>(multi, wave);
-        case 11 * 64 + 13: return diag2_fn_ab<T, 11, 13>(multi, wave);
-        case 13 * 64 + 15: return diag2_fn_ab<T, 13, 15>(multi, wave);
-        case 15 * 64 + 17: return diag2_fn_ab<T, 15, 17>(multi, wave);
-        case 5 * 64 + 9: return diag2_fn_ab<T, 5, 9>(multi, wave);
-        case 7 * 64 + 11: return diag2_fn_ab<T, 7, 11>(multi, wave);
+        case 3 * 64 + 5: return diag2_fn_ab<T, 3, 5>(multi, wave, twice);
+        case 5 * 64 + 7: return diag2_fn_ab<T, 5, 7>(multi, wave, twice);
+        case 7 * 64 + 9: return diag2_fn_ab<T, 7, 9>(multi, wave, twice);
+        case 9 * 64 + 11: return diag2_fn_ab<T, 9, 11>(multi, wave, twice);
+        case 11 * 64 + 13: return diag2_fn_ab<T, 11, 13>(multi, wave, twice);
+        case 13 * 64 + 15: return diag2_fn_ab<T, 13, 15>(multi, wave, twice);
+        case 15 * 64 + 17: return diag2_fn_ab<T, 15, 17>(multi, wave, twice);
+        case 5 * 64 + 9: return diag2_fn_ab<T, 5, 9>(multi, wave, twice);
+        case 7 * 64 + 11: return diag2_fn_ab<T, 7, 11>(multi, wave, twice);
         default: return nullptr;
     }
 }
 
 // kernel of one (transform length, elements per thread, staging); LE = 2 (M = 64 to 2048), 3 or 4
+// (the runtime fuses the embedded passes in FP32 only, so the FP64 two-pass kernels are not built)
 template <typename T, int LOG2M, int LE, bool STAGE>
-const void* embed_fn_k(bool multi) {
-    return multi ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, LE, STAGE>)
-                 : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE>);
+const void* embed_fn_k(bool multi, bool twice) {
+    if (multi) return twice ? nullptr : reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, LE, STAGE>);
+    if (!twice) return reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE, false>);
+    if constexpr (sizeof(T) == 4) return reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE, true>);
+    return nullptr;
 }
 template <typename T, int LOG2M, bool STAGE>
-const void* embed_fn_le(int le, bool multi) {
+const void* embed_fn_le(int le, bool multi, bool twice) {
     if (le == 2) {
-        if constexpr (LOG2M >= 6 && LOG2M <= 11) return embed_fn_k<T, LOG2M, 2, STAGE>(multi);
+        if constexpr (LOG2M >= 6 && LOG2M <= 11) return embed_fn_k<T, LOG2M, 2, STAGE>(multi, twice);
         return nullptr;
     }
-    if (le == 3) return embed_fn_k<T, LOG2M, 3, STAGE>(multi);
-    return embed_fn_k<T, LOG2M, 4, STAGE>(multi);
+    if (le == 3) return embed_fn_k<T, LOG2M, 3, STAGE>(multi, twice);
+    return embed_fn_k<T, LOG2M, 4, STAGE>(multi, twice);
 }
 // staged kernels exist for M >= 64 (lines of at least 32 points)
 template <typename T, int LOG2M>
-const void* embed_fn_lm(int le, bool multi, bool stage) {
-    if (!stage) return embed_fn_le<T, LOG2M, false>(le, multi);
-    if constexpr (LOG2M >= 6) return embed_fn_le<T, LOG2M, true>(le, multi);
+const void* embed_fn_lm(int le, bool multi, bool stage, bool twice) {
+    if (!stage) return embed_fn_le<T, LOG2M, false>(le, multi, twice);
+    if constexpr (LOG2M >= 6) return embed_fn_le<T, LOG2M, true>(le, multi, twice);
     return nullptr;
 }
 
 template <typename T>
-const void* embed_fn(int log2m, int le, bool multi, bool stage) {
+const void* embed_fn(int log2m, int le, bool multi, bool stage, bool twice) {
     switch (log2m) {
-        case 1: return embed_fn_lm<T, 1>(le, multi, stage);
-        case 2: return embed_fn_lm<T, 2>(le, multi, stage);
-        case 3: return embed_fn_lm<T, 3>(le, multi, stage);
-        case 4: return embed_fn_lm<T, 4>(le, multi, stage);
-        case 5: return embed_fn_lm<T, 5>(le, multi, stage);
-        case 6: return embed_fn_lm<T, 6>(le, multi, stage);
-        case 7: return embed_fn_lm<T, 7>(le, multi, stage);
-        case 8: return embed_fn_lm<T, 8>(le, multi, stage);
-        case 9: return embed_fn_lm<T, 9>(le, multi, stage);
-        case 10: return embed_fn_lm<T, 10>(le, multi, stage);
-        case 11: return embed_fn_lm<T, 11>(le, multi, stage);
-        case 12: return embed_fn_lm<T, 12>(le, multi, stage);
+        case 1: return embed_fn_lm<T, 1>(le, multi, stage, twice);
+        case 2: return embed_fn_lm<T, 2>(le, multi, stage, twice);
+        case 3: return embed_fn_lm<T, 3>(le, multi, stage, twice);
+        case 4: return embed_fn_lm<T, 4>(le, multi, stage, twice);
+        case 5: return embed_fn_lm<T, 5>(le, multi, stage, twice);
+        case 6: return embed_fn_lm<T, 6>(le, multi, stage, twice);
+        case 7: return embed_fn_lm<T, 7>(le, multi, stage, twice);
+        case 8: return embed_fn_lm<T, 8>(le, multi, stage, twice);
+        case 9: return embed_fn_lm<T, 9>(le, multi, stage, twice);
+        case 10: return embed_fn_lm<T, 10>(le, multi, stage, twice);
+        case 11: return embed_fn_lm<T, 11>(le, multi, stage, twice);
+        case 12: return embed_fn_lm<T, 12>(le, multi, stage, twice);
         default: return nullptr;
     }
 }
@@ -819,8 +885,9 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
     const int blocks = pass_blocks(d);
     if (blocks <= 0) return hipSuccess;
     if (d.method == 2 || (d.method == 1 && d.d2a > 0)) {
-        const void* fn = d.method == 2 ? embed_fn<T>(d.log2m, d.log2e, false, d.stage != 0)
-                                       : diag2_fn<T>(d.d2a, d.d2b, false, d.d2wave != 0);
+        const bool twice = d.nl_mid != 0;
+        const void* fn = d.method == 2 ? embed_fn<T>(d.log2m, d.log2e, false, d.stage != 0, twice)
+                                       : diag2_fn<T>(d.d2a, d.d2b, false, d.d2wave != 0, twice);
         if (!fn) return hipErrorInvalidValue;
         void* args[] = {const_cast<PassDesc<T>*>(&d)};
         return hipLaunchKernel(fn, dim3(blocks), dim3(d.threads), args, lds_bytes, stream);
@@ -836,8 +903,8 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Grou
     const int total_blocks = args.start[args.n];
     if (total_blocks <= 0) return hipSuccess;
     if (kind == 1 || kind == 2) {
-        const void* fn = kind == 1 ? embed_fn<T>((variant % 128) / 8, variant % 8, true, variant >= 128)
-                                   : diag2_fn<T>((variant % 4096) / 64, variant % 64, true, variant >= 4096);
+        const void* fn = kind == 1 ? embed_fn<T>((variant % 128) / 8, variant % 8, true, variant >= 128, false)
+                                   : diag2_fn<T>((variant % 4096) / 64, variant % 64, true, variant >= 4096, false);
         if (!fn) return hipErrorInvalidValue;
         void* kargs[] = {const_cast<GroupArgs<T>*>(&args)};
         return hipLaunchKernel(fn, dim3(total_blocks), dim3(threads), kargs, lds_bytes, stream);
@@ -1061,8 +1128,9 @@ hipError_t launch_trace_collect(unsigned long long* parts, long long nparts, uns
 
 namespace {
 // An empty one-wavefront kernel whose name carries a number: launched around the timed launches
-// of sfac_plan_time_passes, it tells a kernel trace or counter record which axis the pass
-// dispatches that follow belong to (0: the timed launches are over).
+// of sfac_plan_time_passes (the axis, 1..3) and sfac_plan_time_fused (kFusedMark + the axis),
+// it tells a kernel trace or counter record which launches the dispatches that follow are
+// (0: the timed launches are over).
 template <int AXIS>
 __global__ void __launch_bounds__(64) pass_timing_mark() {}
 }  // namespace
@@ -1086,6 +1154,9 @@ hipError_t launch_timing_mark(int axis, hipStream_t stream) {
         case 1: hipLaunchKernelGGL(pass_timing_mark<1>, dim3(1), dim3(64), 0, stream); break;
         case 2: hipLaunchKernelGGL(pass_timing_mark<2>, dim3(1), dim3(64), 0, stream); break;
         case 3: hipLaunchKernelGGL(pass_timing_mark<3>, dim3(1), dim3(64), 0, stream); break;
+        case kFusedMark + 1: hipLaunchKernelGGL(pass_timing_mark<kFusedMark + 1>, dim3(1), dim3(64), 0, stream); break;
+        case kFusedMark + 2: hipLaunchKernelGGL(pass_timing_mark<kFusedMark + 2>, dim3(1), dim3(64), 0, stream); break;
+        case kFusedMark + 3: hipLaunchKernelGGL(pass_timing_mark<kFusedMark + 3>, dim3(1), dim3(64), 0, stream); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1115,12 +1186,13 @@ hipError_t allow_lds(size_t lds_bytes) {
     for (int lg = 1; lg <= 12; ++lg)
         for (int le = 2; le <= 4; ++le)
             for (int multi = 0; multi < 2; ++multi)
-                for (int stage = 0; stage < 2; ++stage) {
-                    const void* fn = embed_fn<T>(lg, le, multi, stage);
-                    if (!fn) continue;
-                    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-                    if (e != hipSuccess) return e;
-                }
+                for (int stage = 0; stage < 2; ++stage)
+                    for (int twice = 0; twice < 2 - multi; ++twice) {
+                        const void* fn = embed_fn<T>(lg, le, multi, stage, twice);
+                        if (!fn) continue;
+                        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+                        if (e != hipSuccess) return e;
+                    }
     for (int lg = 1; lg <= 12; ++lg) {
         e = hipFuncSetAttribute(energy_fn<T>(lg), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
@@ -1128,12 +1200,13 @@ hipError_t allow_lds(size_t lds_bytes) {
     for (int a = 3; a <= 17; ++a)
         for (int b = a; b <= 17; ++b)
             for (int multi = 0; multi < 2; ++multi)
-                for (int wave = 0; wave < 2; ++wave) {
-                    const void* fn = diag2_fn<T>(a, b, multi, wave);
-                    if (!fn) continue;
-                    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-                    if (e != hipSuccess) return e;
-                }
+                for (int wave = 0; wave < 2; ++wave)
+                    for (int twice = 0; twice < 2 - multi; ++twice) {
+                        const void* fn = diag2_fn<T>(a, b, multi, wave, twice);
+                        if (!fn) continue;
+                        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+                        if (e != hipSuccess) return e;
+                    }
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&axis_pass_multi<T>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e == hipSuccess) granted = lds_bytes;

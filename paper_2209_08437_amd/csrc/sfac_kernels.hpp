@@ -67,6 +67,8 @@ struct PassDesc {
     int tiles_per_outer;             // strided passes: ceil(inner / (2 lpb))
     int ntiles;                      // tiles in this pass
     int nl_in, nl_out;               // apply J^Q_{tau/2} on load / on store (+ statistics)
+    int nl_mid;                      // the pass covers its axis twice, a step boundary between the two
+                                     // (closing J^Q_{tau/2}, statistics, opening J^Q_{tau/2}, in registers)
     int xcd_remap;                   // group neighbouring tiles per XCD
     int d2wave;                      // two-step diagonal kernel: wavefront-aligned line layout
     int log2m;                       // embed: log2 of the transform length
@@ -116,6 +118,9 @@ hipError_t launch_zero_words(unsigned int* p, int words, hipStream_t stream);
 
 // An empty kernel named for `axis` (1..3, or 0 after the last): sfac_plan_time_passes launches
 // one before each axis' timed launches, so that profiles attribute those dispatches to their axis.
+// Marker values: the axis (1..3) before the timed single-pass launches, kFusedMark + the axis
+// before the timed launches that cover an axis twice, 0 after the last.
+constexpr int kFusedMark = 10;
 hipError_t launch_timing_mark(int axis, hipStream_t stream);
 
 // The one-level scheme with the exact exponential (eq. (strang)), FP64.

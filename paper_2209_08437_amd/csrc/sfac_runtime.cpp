@@ -326,6 +326,73 @@ hipError_t launch_pass(const sfac::PassDesc<T>& d, size_t lds, hipStream_t s) {
     return sfac::launch_axis_pass<T>(d, lds, s);
 }
 
+// The descriptor of axis a in a step that runs the axes in reverse order (d..1): the opening
+// half-step moves to the pass of the last axis, the closing one (with the statistics) to the
+// pass of the first. The factors of different axes commute (C_a and S_a are Kronecker sums), so
+// every order applies the same operator; steps alternate between the two orders with the
+// parity of the step count, which puts two passes over one axis next to each other at every
+// step boundary.
+template <typename T>
+sfac::PassDesc<T> reversed_desc(sfac::PassDesc<T> d, int a, int dims) {
+    d.nl_in = a == dims - 1;
+    d.nl_out = a == 0;
+    return d;
+}
+
+// Kernels that cover their axis twice in one launch (nl_mid) with values bitwise those of two
+// launches: the two-step diagonal ones (FP64 and FP32) and the FP32 embedded ones. The FP64
+// embedded kernel's fused form was measured to differ from two launches in the last bits (cause
+// not identified), so its passes keep one launch each.
+template <typename T>
+bool can_fuse(const sfac::PassDesc<T>& d) {
+    if (d.method == SFAC_METHOD_DIAG) return d.d2a > 0;
+    return d.method == SFAC_METHOD_EMBED && std::is_same<T, float>::value;
+}
+
+// The launch that covers axis a twice: the last pass of a step (`cur`, from the step's
+// descriptors) and the first pass of the next step (`next`, from the other order's).
+template <typename T>
+sfac::PassDesc<T> fused_desc(const sfac::PassDesc<T>& cur, const sfac::PassDesc<T>& next) {
+    sfac::PassDesc<T> x = cur;
+    x.nl_mid = 1;
+    x.nl_out = next.nl_out;   // one axis: the next step's pass is also its last
+    return x;
+}
+
+// Launches `nsteps` steps from step parity `parity0` (even: axes 1..d; odd: d..1), the passes
+// of axis a taking fwd[a] or rev[a]. With `fuse`, the last pass of a step and the first of the
+// next (the same axis) are one launch that covers the axis twice, the step boundary applied in
+// registers: the state makes one trip through HBM instead of two and the values are bitwise
+// those of the two launches. `after_step` (or null) runs after each step's last launch.
+template <typename T, typename AfterStep>
+hipError_t launch_sequence(const sfac::PassDesc<T>* fwd, const sfac::PassDesc<T>* rev, const Instance& in,
+                           int parity0, int64_t nsteps, bool fuse, hipStream_t s, AfterStep after_step) {
+    const int dims = in.dims;
+    bool carried = false;   // this step's first pass was done by the previous launch
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const bool odd = ((parity0 + k) & 1) != 0;
+        const sfac::PassDesc<T>* D = odd ? rev : fwd;
+        const sfac::PassDesc<T>* next = odd ? fwd : rev;
+        for (int pos = 0; pos < dims; ++pos) {
+            const int a = odd ? dims - 1 - pos : pos;
+            if (pos == 0 && carried) {
+                carried = false;
+                continue;
+            }
+            sfac::PassDesc<T> x = D[a];
+            if (pos == dims - 1 && fuse && k + 1 < nsteps && can_fuse(x)) {
+                x = fused_desc(x, next[a]);
+                carried = true;
+            }
+            const hipError_t e = launch_pass(x, in.ax[a].lds, s);
+            if (e != hipSuccess) return e;
+        }
+        const hipError_t e = after_step(s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 // ===================================================================== plans
@@ -340,6 +407,7 @@ namespace {
 // A captured sequence of `steps` whole steps of a plan, replayed by sfac_step.
 struct StepGraph {
     int64_t steps;
+    int parity;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -356,12 +424,16 @@ struct sfac_plan_s {
     size_t dev_bytes = 0;
     size_t off_stat = 0;
     size_t off_desc = 0;               // device copies of d64 (FP64) or d32 (FP32), state pointer unset
-    sfac::PassDesc<double> d64[3];
+    sfac::PassDesc<double> d64[3];     // axes in the order 1..d (even steps)
     sfac::PassDesc<float> d32[3];
+    sfac::PassDesc<double> r64[3];     // axes in the order d..1 (odd steps)
+    sfac::PassDesc<float> r32[3];
+    int parity = 0;                    // parity of the steps queued so far (the next step's axis order)
     int use_graph = 1;
     int chunk = 32;
     void* graph_u = nullptr;           // state pointer the graphs were captured for
-    // graphs of `chunk` steps and of powers of two below it, each captured on first use
+    // graphs of `chunk` steps and of powers of two below it, per starting parity, each captured
+    // on first use
     std::vector<StepGraph> graphs;
     unsigned char* energy_dev = nullptr;  // [0, 16): the two energy sums; then per-axis tables
     size_t energy_bytes = 0;
@@ -370,7 +442,7 @@ struct sfac_plan_s {
     // wavefront of the last pass
     unsigned char* trace_dev = nullptr;
     long long trace_cap = 0, trace_parts = 0;
-    int trace_wpb = 0;
+    int trace_wpb_last = 0, trace_wpb_first = 0;   // wavefronts per block of the passes of axis d and axis 1
     // one-level scheme with the exact exponential (SFAC_METHOD_EXACT): e^{tau B} per axis and a
     // state-sized scratch buffer in dev
     int exact = 0;
@@ -381,13 +453,16 @@ struct sfac_plan_s {
     unsigned long long* trace_slots() { return trace_rec() + trace_cap; }
     void set_trace() {
         for (int a = 0; a < in.dims; ++a) {
-            d64[a].trace_part = d32[a].trace_part = nullptr;
-            d64[a].trace_wpb = d32[a].trace_wpb = 0;
+            d64[a].trace_part = d32[a].trace_part = r64[a].trace_part = r32[a].trace_part = nullptr;
+            d64[a].trace_wpb = d32[a].trace_wpb = r64[a].trace_wpb = r32[a].trace_wpb = 0;
         }
         if (trace_dev) {
-            const int a = in.dims - 1;            // the pass that stores (and folds) the statistics
-            d64[a].trace_part = d32[a].trace_part = trace_slots();
-            d64[a].trace_wpb = d32[a].trace_wpb = trace_wpb;
+            // the passes that store (and fold) the statistics: the last axis in even steps, the
+            // first in odd ones
+            const int a = in.dims - 1;
+            d64[a].trace_part = d32[a].trace_part = r64[0].trace_part = r32[0].trace_part = trace_slots();
+            d64[a].trace_wpb = d32[a].trace_wpb = trace_wpb_last;
+            r64[0].trace_wpb = r32[0].trace_wpb = trace_wpb_first;
         }
     }
 
@@ -403,9 +478,10 @@ struct sfac_plan_s {
         graph_u = nullptr;
     }
 
+    // device copy of axis a's descriptor for steps in the order 1..d (rev = 0) or d..1 (rev = 1)
     template <typename T>
-    const sfac::PassDesc<T>* device_desc(int a) const {
-        return reinterpret_cast<const sfac::PassDesc<T>*>(dev + off_desc) + a;
+    const sfac::PassDesc<T>* device_desc(int a, int rev) const {
+        return reinterpret_cast<const sfac::PassDesc<T>*>(dev + off_desc) + 3 * rev + a;
     }
 
     // eq. (strang): J^Q_{tau/2} e^{tau A} J^Q_{tau/2}, e^{tau A} one dense product per axis, alternating
@@ -439,34 +515,32 @@ struct sfac_plan_s {
         return e;
     }
 
-    hipError_t launch_steps(hipStream_t s, int64_t nsteps) {
-        for (int64_t k = 0; k < nsteps; ++k) {
-            if (exact) {
+    // `nsteps` steps from step parity `parity0`. The per-step record folds the statistics after
+    // every step, so with a record the passes are not fused across step boundaries (the values
+    // are the same either way).
+    hipError_t launch_steps(hipStream_t s, int64_t nsteps, int parity0) {
+        auto collect = [this](hipStream_t st) -> hipError_t {
+            return trace_dev ? sfac::launch_trace_collect(trace_slots(), trace_parts, trace_rec(), trace_step(),
+                                                          trace_cap, st)
+                             : hipSuccess;
+        };
+        if (exact) {
+            for (int64_t k = 0; k < nsteps; ++k) {
                 hipError_t e = exact_step(s, d64[in.dims - 1]);
-                if (e != hipSuccess) return e;
-                if (trace_dev) e = sfac::launch_trace_collect(trace_slots(), trace_parts, trace_rec(), trace_step(),
-                                                               trace_cap, s);
-                if (e != hipSuccess) return e;
-                continue;
-            }
-            for (int a = 0; a < in.dims; ++a) {
-                hipError_t e = in.dt == SFAC_FP64 ? launch_pass(d64[a], in.ax[a].lds, s)
-                                                  : launch_pass(d32[a], in.ax[a].lds, s);
+                if (e == hipSuccess) e = collect(s);
                 if (e != hipSuccess) return e;
             }
-            if (trace_dev) {
-                hipError_t e = sfac::launch_trace_collect(trace_slots(), trace_parts, trace_rec(), trace_step(),
-                                                          trace_cap, s);
-                if (e != hipSuccess) return e;
-            }
+            return hipSuccess;
         }
-        return hipSuccess;
+        const bool fuse = trace_dev == nullptr;
+        return in.dt == SFAC_FP64 ? launch_sequence(d64, r64, in, parity0, nsteps, fuse, s, collect)
+                                  : launch_sequence(d32, r32, in, parity0, nsteps, fuse, s, collect);
     }
 
     void set_u(void* u) {
         for (int a = 0; a < in.dims; ++a) {
-            d64[a].u = static_cast<double*>(u);
-            d32[a].u = static_cast<float*>(u);
+            d64[a].u = r64[a].u = static_cast<double*>(u);
+            d32[a].u = r32[a].u = static_cast<float*>(u);
         }
     }
 
@@ -476,14 +550,14 @@ struct sfac_plan_s {
         return capture ? hipSuccess : hipStreamCreateWithFlags(&capture, hipStreamNonBlocking);
     }
 
-    sfac_status capture_graph(int64_t steps, hipGraph_t* g, hipGraphExec_t* x) {
+    sfac_status capture_graph(int64_t steps, int parity0, hipGraph_t* g, hipGraphExec_t* x) {
         *g = nullptr;
         *x = nullptr;
         hipError_t e = capture_stream();
         if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
         e = hipStreamBeginCapture(capture, hipStreamCaptureModeRelaxed);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = launch_steps(capture, steps);
+        hipError_t le = launch_steps(capture, steps, parity0);
         e = hipStreamEndCapture(capture, g);
         if (le != hipSuccess || e != hipSuccess) {
             if (e == hipSuccess && *g) (void)hipGraphDestroy(*g);
@@ -500,15 +574,16 @@ struct sfac_plan_s {
         return SFAC_OK;
     }
 
-    // the graph of `steps` steps for the current state pointer, captured on first use
-    sfac_status graph_for(int64_t steps, hipGraphExec_t* x) {
+    // the graph of `steps` steps from step parity `parity0` for the current state pointer,
+    // captured on first use
+    sfac_status graph_for(int64_t steps, int parity0, hipGraphExec_t* x) {
         for (const auto& sg : graphs)
-            if (sg.steps == steps) {
+            if (sg.steps == steps && sg.parity == parity0) {
                 *x = sg.exec;
                 return SFAC_OK;
             }
-        StepGraph sg{steps, nullptr, nullptr};
-        const sfac_status st = capture_graph(steps, &sg.graph, &sg.exec);
+        StepGraph sg{steps, parity0, nullptr, nullptr};
+        const sfac_status st = capture_graph(steps, parity0, &sg.graph, &sg.exec);
         if (st != SFAC_OK) return st;
         graphs.push_back(sg);
         *x = sg.exec;
@@ -742,7 +817,7 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
     p->off_stat = align_up(p->in.table_bytes, 256);
     p->off_desc = p->off_stat + 256;
     const size_t desc_bytes = dt == SFAC_FP64 ? sizeof(sfac::PassDesc<double>) : sizeof(sfac::PassDesc<float>);
-    p->dev_bytes = align_up(p->off_desc + 3 * desc_bytes, 256);
+    p->dev_bytes = align_up(p->off_desc + 6 * desc_bytes, 256);   // three axes, two orders
     std::vector<unsigned char> host(p->dev_bytes, 0);
     for (int a = 0; a < p->in.dims; ++a) {
         if (dt == SFAC_FP64)
@@ -759,12 +834,18 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
     for (int a = 0; a < p->in.dims; ++a) {
         p->d64[a] = make_desc<double>(p->in, a, p->dev, nullptr, p->stat_max(), p->stat_flags());
         p->d32[a] = make_desc<float>(p->in, a, p->dev, nullptr, p->stat_max(), p->stat_flags());
+        p->r64[a] = reversed_desc(p->d64[a], a, p->in.dims);
+        p->r32[a] = reversed_desc(p->d32[a], a, p->in.dims);
     }
-    // the descriptors grouped launches read (the state pointer comes with each launch)
-    if (dt == SFAC_FP64)
+    // the descriptors grouped launches read (the state pointer comes with each launch): the
+    // three axes in the order 1..d, then in the order d..1
+    if (dt == SFAC_FP64) {
         memcpy(host.data() + p->off_desc, p->d64, sizeof(sfac::PassDesc<double>) * p->in.dims);
-    else
+        memcpy(host.data() + p->off_desc + 3 * desc_bytes, p->r64, sizeof(sfac::PassDesc<double>) * p->in.dims);
+    } else {
         memcpy(host.data() + p->off_desc, p->d32, sizeof(sfac::PassDesc<float>) * p->in.dims);
+        memcpy(host.data() + p->off_desc + 3 * desc_bytes, p->r32, sizeof(sfac::PassDesc<float>) * p->in.dims);
+    }
     e = hipMemcpy(p->dev, host.data(), p->dev_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(p->dev);
@@ -791,8 +872,10 @@ sfac_status sfac_step(sfac_plan p, void* u_dev, int64_t nsteps) {
     if (nsteps == 0) return SFAC_OK;
     if (!p->use_graph) {
         p->set_u(u_dev);
-        hipError_t e = p->launch_steps(p->stream, nsteps);
-        return e == hipSuccess ? SFAC_OK : hip_fail(e, "kernel launch");
+        hipError_t e = p->launch_steps(p->stream, nsteps, p->parity);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        p->parity ^= (int)(nsteps & 1);
+        return SFAC_OK;
     }
     if (p->graph_u != u_dev) {
         p->drop_graphs();
@@ -803,21 +886,22 @@ sfac_status sfac_step(sfac_plan p, void* u_dev, int64_t nsteps) {
     // a call of fewer than chunk steps costs at most log2(chunk) + 1 graph launches
     const int64_t full = nsteps / p->chunk, rest = nsteps % p->chunk;
     hipGraphExec_t x = nullptr;
-    if (full > 0) {
-        const sfac_status st = p->graph_for(p->chunk, &x);
+    // (an odd chunk alternates between the graphs of its two starting parities)
+    for (int64_t k = 0; k < full; ++k) {
+        const sfac_status st = p->graph_for(p->chunk, p->parity, &x);
         if (st != SFAC_OK) return st;
-        for (int64_t k = 0; k < full; ++k) {
-            hipError_t e = hipGraphLaunch(x, p->stream);
-            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-        }
+        hipError_t e = hipGraphLaunch(x, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        p->parity ^= p->chunk & 1;
     }
     for (int b = 62; b >= 0; --b) {
         const int64_t part = int64_t(1) << b;
         if (!(rest & part)) continue;
-        const sfac_status st = p->graph_for(part, &x);
+        const sfac_status st = p->graph_for(part, p->parity, &x);
         if (st != SFAC_OK) return st;
         hipError_t e = hipGraphLaunch(x, p->stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        p->parity ^= (int)(part & 1);
     }
     return SFAC_OK;
 }
@@ -896,6 +980,65 @@ sfac_status sfac_plan_time_passes(sfac_plan p, void* u_dev, int32_t reps, float*
     return e == hipSuccess ? SFAC_OK : hip_fail(e, "timed pass launches");
 }
 
+sfac_status sfac_plan_time_fused(sfac_plan p, void* u_dev, int32_t reps, float* ms) {
+    g_error.clear();
+    if (!p) return fail(SFAC_EINVAL, "NULL plan");
+    if (!u_dev || !ms || reps < 1) return fail(SFAC_EINVAL, "NULL state or output, or reps < 1");
+    const size_t es = p->in.dt == SFAC_FP64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(u_dev) % es) return fail(SFAC_EINVAL, "state pointer not aligned to %zu bytes", es);
+    ms[0] = ms[1] = 0.0f;
+    if (p->exact) return SFAC_OK;
+    const int d = p->in.dims;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    void* keep = p->graph_u;
+    p->set_u(u_dev);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess) e = p->capture_stream();
+    // [0]: axis 1, the last pass of a step in the order d..1 with the first of the next; [1]: axis d,
+    // the last pass of a step in the order 1..d with the first of the next (as sfac_step fuses them)
+    const int axes[2] = {0, d - 1};
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        const int a = axes[i];
+        sfac::PassDesc<double> d64 = i == 0 ? fused_desc(p->r64[a], p->d64[a]) : fused_desc(p->d64[a], p->r64[a]);
+        sfac::PassDesc<float> d32 = i == 0 ? fused_desc(p->r32[a], p->d32[a]) : fused_desc(p->d32[a], p->r32[a]);
+        if (p->in.dt == SFAC_FP64 ? !can_fuse(d64) : !can_fuse(d32)) continue;
+        d64.trace_part = nullptr;
+        d32.trace_part = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) break;
+        hipError_t le = hipSuccess;
+        for (int r = 0; r < reps && le == hipSuccess; ++r)
+            le = p->in.dt == SFAC_FP64 ? launch_pass(d64, p->in.ax[a].lds, p->capture)
+                                       : launch_pass(d32, p->in.ax[a].lds, p->capture);
+        e = hipStreamEndCapture(p->capture, &graph);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = sfac::launch_timing_mark(sfac::kFusedMark + a + 1, p->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[0], p->stream);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, p->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        float t = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+        if (e == hipSuccess) ms[i] = t / reps;
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (d == 1) {
+            ms[1] = ms[0];
+            break;
+        }
+    }
+    if (e == hipSuccess) e = sfac::launch_timing_mark(0, p->stream);
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (keep) p->set_u(keep);
+    return e == hipSuccess ? SFAC_OK : hip_fail(e, "timed fused launches");
+}
+
 sfac_status sfac_plan_destroy(sfac_plan p) {
     g_error.clear();
     if (!p) return SFAC_OK;
@@ -945,16 +1088,19 @@ sfac_status sfac_plan_trace(sfac_plan p, int64_t capacity) {
     p->trace_cap = 0;
     p->trace_parts = 0;
     if (capacity > 0) {
-        // one slot per wavefront of the last pass's launch
-        const int a = p->in.dims - 1;
-        long long blocks = p->in.dt == SFAC_FP64 ? sfac::pass_blocks(p->d64[a]) : sfac::pass_blocks(p->d32[a]);
-        int threads = p->in.dt == SFAC_FP64 ? p->d64[a].threads : p->d32[a].threads;
-        if (p->exact) {   // the closing nonlinear half-step kernel stores the statistics
-            threads = sfac::kExactNlThreads;
-            blocks = (p->in.points() + threads - 1) / threads;
-        }
-        p->trace_wpb = (threads + 63) / 64;
-        p->trace_parts = (long long)blocks * p->trace_wpb;
+        // one slot per wavefront of the launch that stores the statistics: the pass of axis d in
+        // steps of the order 1..d, of axis 1 in steps of the order d..1
+        auto slots = [p](int a, int* wpb) {
+            long long blocks = p->in.dt == SFAC_FP64 ? sfac::pass_blocks(p->d64[a]) : sfac::pass_blocks(p->d32[a]);
+            int threads = p->in.dt == SFAC_FP64 ? p->d64[a].threads : p->d32[a].threads;
+            if (p->exact) {   // the closing nonlinear half-step kernel stores the statistics
+                threads = sfac::kExactNlThreads;
+                blocks = (p->in.points() + threads - 1) / threads;
+            }
+            *wpb = (threads + 63) / 64;
+            return blocks * *wpb;
+        };
+        p->trace_parts = std::max(slots(p->in.dims - 1, &p->trace_wpb_last), slots(0, &p->trace_wpb_first));
         const size_t bytes = 8 + 8 * (size_t)capacity + 8 * (size_t)p->trace_parts;
         e = hipMalloc(&p->trace_dev, bytes);
         if (e != hipSuccess) {
@@ -1141,10 +1287,12 @@ struct sfac_group_s {
 
 namespace {
 
-// The plans of a phase that step (in call order), with their states.
+// The plans of a phase that step (in call order), with their states and the parity of the
+// steps each plan had queued when the phase began (its first step's axis order).
 struct PhaseEntry {
     sfac_plan plan;
     void* u;
+    int parity;
 };
 
 template <typename T>
@@ -1162,19 +1310,24 @@ sfac::GroupArgs<T>& launch_args(GroupLaunch& l) {
         return l.a32;
 }
 
-// The launches of one step of a phase for the plans of arithmetic T: for pass 0, 1, 2 in turn,
-// one launch per kernel variant (at most kGroupSlots instances each), so every plan sees the
-// launch sequence a lone sfac_step gives it.
+// The launches of step j of a phase for the plans of arithmetic T: for pass position 0, 1, 2 in
+// turn, one launch per kernel variant (at most kGroupSlots instances each), each plan taking the
+// axis its step's order puts at that position, so every plan sees the passes a lone sfac_step
+// gives it (grouped launches are never fused across step boundaries; the values are the same).
 template <typename T>
-void phase_launches(const std::vector<PhaseEntry>& entries, std::vector<GroupLaunch>* out) {
+void phase_launches(const std::vector<PhaseEntry>& entries, int j, std::vector<GroupLaunch>* out) {
     constexpr bool f64 = std::is_same<T, double>::value;
+    auto axis_of = [j](const PhaseEntry& e, int pass) {
+        const int dims = e.plan->in.dims;
+        return ((e.parity + j) & 1) ? dims - 1 - pass : pass;
+    };
     for (int pass = 0; pass < 3; ++pass) {
         std::vector<std::pair<int, int>> keys;   // (kernel kind, variant): see launch_axis_pass_multi
         std::vector<std::vector<const PhaseEntry*>> members;
         for (const PhaseEntry& e : entries) {
             sfac_plan p = e.plan;
             if ((p->in.dt == SFAC_FP64) != f64 || pass >= p->in.dims) continue;
-            const sfac::PassDesc<T>& d = host_desc<T>(p, pass);
+            const sfac::PassDesc<T>& d = host_desc<T>(p, axis_of(e, pass));
             const int kind = d.method == SFAC_METHOD_EMBED ? 1 : (d.d2a > 0 ? 2 : 0);
             const int variant = kind == 1 ? d.log2m * 8 + d.log2e + (d.stage ? 128 : 0)
                                           : (kind == 2 ? d.d2a * 64 + d.d2b + (d.d2wave ? 4096 : 0) : 0);
@@ -1200,13 +1353,15 @@ void phase_launches(const std::vector<PhaseEntry>& entries, std::vector<GroupLau
                 size_t lds = 0;
                 int threads = l.kind == 0 ? sfac::kBlockThreads : 0;
                 for (size_t i = first; i < last; ++i) {
-                    sfac_plan p = members[g][i]->plan;
-                    const sfac::PassDesc<T>& d = host_desc<T>(p, pass);
+                    const PhaseEntry& e = *members[g][i];
+                    sfac_plan p = e.plan;
+                    const int a = axis_of(e, pass);
+                    const sfac::PassDesc<T>& d = host_desc<T>(p, a);
                     const int k = (int)(i - first);
-                    args.desc[k] = p->template device_desc<T>(pass);
-                    args.u[k] = static_cast<T*>(members[g][i]->u);
+                    args.desc[k] = p->template device_desc<T>(a, (e.parity + j) & 1);
+                    args.u[k] = static_cast<T*>(e.u);
                     args.start[k + 1] = args.start[k] + sfac::pass_blocks(d);
-                    lds = std::max(lds, p->in.ax[pass].lds);
+                    lds = std::max(lds, p->in.ax[a].lds);
                     if (l.kind != 0) threads = std::max(threads, d.threads);
                 }
                 if (l.kind == 1) {
@@ -1233,10 +1388,11 @@ hipError_t group_launch(const GroupLaunch& l, hipStream_t s) {
                   : sfac::launch_axis_pass_multi<float>(l.kind, l.variant, l.threads, l.a32, l.lds, s);
 }
 
-// Captures one step of a phase: pass after pass; the launches of one pass (different kernel
-// variants and arithmetic, disjoint plans) fan out over the auxiliary streams and join before
-// the next pass, so every plan still sees its passes in order.
-sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch>& launches, int steps, hipGraph_t* graph) {
+// Captures `steps` steps of a phase: pass after pass; the launches of one pass (different
+// kernel variants and arithmetic, disjoint plans) fan out over the auxiliary streams and join
+// before the next pass, so every plan still sees its passes in order. launches[j] are those of
+// the phase's even (j = 0) and odd (j = 1) steps.
+sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch> (&launches)[2], int steps, hipGraph_t* graph) {
     *graph = nullptr;
     hipError_t e = hipStreamBeginCapture(g->capture, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
@@ -1244,7 +1400,7 @@ sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch>& launches,
     for (int it = 0; it < 3 * steps && le == hipSuccess; ++it) {
         const int pass = it % 3;
         std::vector<const GroupLaunch*> ls;
-        for (const GroupLaunch& l : launches)
+        for (const GroupLaunch& l : launches[(it / 3) & 1])
             if (l.pass == pass) ls.push_back(&l);
         if (ls.empty()) continue;
         if (ls.size() == 1) {
@@ -1273,18 +1429,21 @@ sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch>& launches,
 sfac_status phase_graph(sfac_group g, const std::vector<PhaseEntry>& entries, int steps, hipGraphExec_t* exec) {
     std::vector<std::pair<unsigned long long, void*>> key;
     key.reserve(entries.size());
-    for (const PhaseEntry& e : entries) key.emplace_back(e.plan->id, e.u);
+    for (const PhaseEntry& e : entries) key.emplace_back(2 * e.plan->id + (unsigned long long)e.parity, e.u);
     for (auto it = g->cache.begin(); it != g->cache.end(); ++it)
         if (it->key == key && it->steps == steps) {
             g->cache.splice(g->cache.begin(), g->cache, it);
             *exec = g->cache.front().exec;
             return SFAC_OK;
         }
-    std::vector<GroupLaunch> launches;
-    phase_launches<double>(entries, &launches);
-    phase_launches<float>(entries, &launches);
+    std::vector<GroupLaunch> launches[2];
+    for (int j = 0; j < 2; ++j) {
+        phase_launches<double>(entries, j, &launches[j]);
+        phase_launches<float>(entries, j, &launches[j]);
+    }
     size_t lds_need = 0;
-    for (const auto& l : launches) lds_need = std::max(lds_need, l.lds);
+    for (const auto& ls : launches)
+        for (const auto& l : ls) lds_need = std::max(lds_need, l.lds);
     if (lds_need > 64 * 1024) {
         hipError_t e = sfac::allow_lds<double>(lds_need);
         if (e == hipSuccess) e = sfac::allow_lds<float>(lds_need);
@@ -1331,39 +1490,45 @@ sfac_status group_run(sfac_group g, int32_t count, const sfac_plan* plans, void*
         if (reinterpret_cast<uintptr_t>(u_dev[i]) % es) return fail(SFAC_EINVAL, "plan %d: misaligned state", i);
         for (int32_t j = 0; j < i; ++j)
             if (plans[j] == p && nsteps[j] > 0) return fail(SFAC_EINVAL, "plan %d appears twice", i);
-        all.push_back(PhaseEntry{p, u_dev[i]});
+        all.push_back(PhaseEntry{p, u_dev[i], 0});
         steps.push_back(nsteps[i]);
         bounds.push_back(nsteps[i]);
     }
     if (bounds.empty()) return SFAC_OK;
     std::sort(bounds.begin(), bounds.end());
     bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
-    // phase after phase (the maximal step ranges with a fixed set of active plans); one step
-    // graph per phase, replayed for the phase's steps
+    // phase after phase (the maximal step ranges with a fixed set of active plans): graphs of
+    // kPhaseChunk steps on long phases, then of two steps, then of one (an even number of steps
+    // leaves every plan's axis order where it was)
     int64_t done = 0;
     for (const int64_t bound : bounds) {
         std::vector<PhaseEntry> active;
         for (size_t i = 0; i < all.size(); ++i)
-            if (steps[i] >= bound) active.push_back(all[i]);
-        int64_t left = bound - done;
-        if (left >= kLongPhase) {
-            hipGraphExec_t chunk = nullptr;
-            const sfac_status st = phase_graph(g, active, kPhaseChunk, &chunk);
-            if (st != SFAC_OK) return st;
-            for (; left >= kPhaseChunk; left -= kPhaseChunk) {
-                const hipError_t e = hipGraphLaunch(chunk, g->stream);
-                if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            if (steps[i] >= bound) {
+                active.push_back(all[i]);
+                active.back().parity = all[i].plan->parity;
             }
-        }
-        if (left > 0) {
+        int64_t left = bound - done;
+        auto replay = [&](int graph_steps, int64_t times) -> sfac_status {
+            if (times <= 0) return SFAC_OK;
             hipGraphExec_t exec = nullptr;
-            const sfac_status st = phase_graph(g, active, 1, &exec);
+            const sfac_status st = phase_graph(g, active, graph_steps, &exec);
             if (st != SFAC_OK) return st;
-            for (; left > 0; --left) {
+            for (int64_t r = 0; r < times; ++r) {
                 const hipError_t e = hipGraphLaunch(exec, g->stream);
                 if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
             }
+            return SFAC_OK;
+        };
+        sfac_status st = SFAC_OK;
+        if (left >= kLongPhase) {
+            st = replay(kPhaseChunk, left / kPhaseChunk);
+            left %= kPhaseChunk;
         }
+        if (st == SFAC_OK) st = replay(2, left / 2);
+        if (st == SFAC_OK) st = replay(1, left % 2);
+        if (st != SFAC_OK) return st;
+        for (PhaseEntry& e : active) e.plan->parity ^= (int)((bound - done) & 1);
         done = bound;
     }
     return SFAC_OK;
@@ -1516,16 +1681,16 @@ sfac_status scratch_address(void** out) {
 template <typename T>
 sfac_status noalloc_run(const Instance& in, unsigned char* base, size_t off_stat, T* u, int64_t nsteps,
                         hipStream_t s) {
-    sfac::PassDesc<T> d[3];
+    sfac::PassDesc<T> d[3], r[3];
     auto* smax = reinterpret_cast<unsigned long long*>(base + off_stat);
     auto* sflags = reinterpret_cast<unsigned int*>(base + off_stat + 8);
-    for (int a = 0; a < in.dims; ++a) d[a] = make_desc<T>(in, a, base, u, smax, sflags);
-    for (int64_t k = 0; k < nsteps; ++k)
-        for (int a = 0; a < in.dims; ++a) {
-            const hipError_t e = launch_pass(d[a], in.ax[a].lds, s);
-            if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        }
-    return SFAC_OK;
+    for (int a = 0; a < in.dims; ++a) {
+        d[a] = make_desc<T>(in, a, base, u, smax, sflags);
+        r[a] = reversed_desc(d[a], a, in.dims);
+    }
+    // the kernels and axis orders of a new plan's sfac_step
+    const hipError_t e = launch_sequence(d, r, in, 0, nsteps, true, s, [](hipStream_t) { return hipSuccess; });
+    return e == hipSuccess ? SFAC_OK : hip_fail(e, "kernel launch");
 }
 }  // namespace
 

@@ -10,9 +10,12 @@
 * `exact_axis_means()` and `mfma_markdown()` summarise the dense products' trace and their
   matrix-core counters.
 
-The axis of a pass-kernel dispatch is recovered from the dispatch order: every step launches
-the passes of axes 1..d in order, and the profiled command launches nothing else with the
-pass kernels' names.
+The launches a summary describes are the timed ones of sfac_plan_time_passes (one pass of one
+axis per launch) and sfac_plan_time_fused (two passes over axis 1 or axis d per launch, as the
+steps run them at every step boundary): each block of them follows a marker kernel
+pass_timing_mark<k> whose number names it (the axis for single passes, FUSED_MARK + the axis
+for the fused launches, 0 after the last). Dispatches outside the marked blocks (the steps,
+whose axis order alternates from step to step) are not attributed.
 """
 import csv
 import hashlib
@@ -67,38 +70,60 @@ def short_name(name):
 
 
 MARK_TAG = "pass_timing_mark<"
+FUSED_MARK = 10          # marker number of the fused launches of axis a: FUSED_MARK + a
 
 
-def axis_labels(names, dims, tags=PASS_KERNEL_TAGS):
-    """Axis (0-based) of every dispatch named by `tags` in a time-ordered list of kernel names,
-    None for the others. Steps launch the passes of axes 1..d in turn (the d-periodic order); the
-    timed launches of sfac_plan_time_passes run one axis at a time, each block preceded by a
-    marker kernel named pass_timing_mark<axis> and the last followed by pass_timing_mark<0>.
-    Counts of the periodic order are kept per element type."""
+def slot_of(axis, twice, dims):
+    """Label of the launches of `axis` (0-based): one pass (twice False) or two (twice True)."""
+    return axis + (dims if twice else 0)
+
+
+def slot_axis(slot, dims):
+    """(axis 0-based, twice) of a label."""
+    return (slot - dims, True) if slot >= dims else (slot, False)
+
+
+def axis_labels(names, dims, tags=PASS_KERNEL_TAGS, periodic=False):
+    """Label (slot_of) of every dispatch named by `tags` in a time-ordered list of kernel names
+    that lies in a marked block of timed launches, None for the others: a marker
+    pass_timing_mark<k> opens the block of single passes of axis k (1..3) or of the fused
+    launches of axis k - FUSED_MARK, pass_timing_mark<0> closes the last. With `periodic`
+    (the one-level scheme's dense products, one per axis in the order 1..d every step), the
+    dispatches outside the blocks take their place in that order, counted per element type."""
     out = []
-    periodic = {}
+    count = {}
     timing = None
     for nm in names:
         if MARK_TAG in nm:
-            a = int(nm.split(MARK_TAG, 1)[1].split(">", 1)[0])
-            timing = a - 1 if a > 0 else None
+            k = int(nm.split(MARK_TAG, 1)[1].split(">", 1)[0])
+            if k == 0:
+                timing = None
+            elif k > FUSED_MARK:
+                timing = slot_of(k - FUSED_MARK - 1, True, dims)
+            else:
+                timing = slot_of(k - 1, False, dims)
             out.append(None)
         elif any(t in nm for t in tags):
-            if timing is not None:
-                out.append(timing)
-            else:
+            if timing is None and periodic:
                 et = "double" if "<double" in nm else "float"
-                k = periodic.get(et, 0)
+                k = count.get(et, 0)
                 out.append(k % dims)
-                periodic[et] = k + 1
+                count[et] = k + 1
+            else:
+                out.append(timing)
         else:
             out.append(None)
     return out
 
 
+def slot_name(slot, dims):
+    a, twice = slot_axis(slot, dims)
+    return f"{a + 1}{' (two passes)' if twice else ''}"
+
+
 def trace_axis_means(trace_csv, dims):
-    """Mean duration (us) per (kernel, axis) of the pass-kernel dispatches in a kernel trace, one
-    list per element type; the axis comes from axis_labels."""
+    """Mean duration (us) per (kernel, axis, one or two passes) of the timed pass-kernel dispatches
+    in a kernel trace, one list per element type; the label comes from axis_labels."""
     rows = sorted(_rows(trace_csv), key=lambda r: int(r["Start_Timestamp"]))
     labels = axis_labels([r["Kernel_Name"] for r in rows], dims)
     seq = {}
@@ -107,16 +132,17 @@ def trace_axis_means(trace_csv, dims):
             continue
         k = r["Kernel_Name"]
         et = "double" if "<double" in k else "float"
-        seq.setdefault(et, [[] for _ in range(dims)])[a].append(
+        seq.setdefault(et, [[] for _ in range(2 * dims)])[a].append(
             (int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), short_name(k)))
     out = {}
     for et, per in seq.items():
         res = []
-        for a in range(dims):
-            xs = [x for x, _ in per[a]]
+        for sl in range(2 * dims):
+            xs = [x for x, _ in per[sl]]
             if not xs:
                 continue
-            res.append({"axis": a + 1, "kernel": per[a][0][1], "dispatches": len(xs),
+            a, twice = slot_axis(sl, dims)
+            res.append({"axis": a + 1, "twice": twice, "kernel": per[sl][0][1], "dispatches": len(xs),
                         "mean_us": sum(xs) / len(xs) / 1e3, "min_us": min(xs) / 1e3, "max_us": max(xs) / 1e3})
         out[et] = res
     return out
@@ -157,8 +183,8 @@ EXACT_KERNEL_TAGS = ("exact_gemm",)
 
 
 def _pass_counters(pmc_csv, counter, dims, tags=PASS_KERNEL_TAGS):
-    """Mean counter value (KiB) per axis over the dispatches of the kernels named by `tags`
-    (the axis passes by default) in one --pmc run; the axis is the place in the d-periodic order."""
+    """Mean counter value (KiB) per label (slot_of) over the timed dispatches of the kernels
+    named by `tags` (the axis passes by default) in one --pmc run."""
     rows = [r for r in _rows(pmc_csv) if r["Counter_Name"] == counter]
     per_dispatch = {}
     names = {}
@@ -169,10 +195,10 @@ def _pass_counters(pmc_csv, counter, dims, tags=PASS_KERNEL_TAGS):
         per_dispatch[d] = per_dispatch.get(d, 0.0) + float(r["Counter_Value"])
         names[d] = r["Kernel_Name"]
     order = sorted(per_dispatch)
-    labels = axis_labels([names[d] for d in order], dims, tags)
-    sums = [0.0] * dims
-    counts = [0] * dims
-    kern = [None] * dims
+    labels = axis_labels([names[d] for d in order], dims, tags, periodic=tags == EXACT_KERNEL_TAGS)
+    sums = [0.0] * (2 * dims)
+    counts = [0] * (2 * dims)
+    kern = [None] * (2 * dims)
     for d, a in zip(order, labels):
         if a is None:
             continue
@@ -205,11 +231,14 @@ def traffic_from_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_
     scale_f = copy_bytes / cf
     scale_w = copy_bytes / cw
     per_axis = []
-    for a in range(dims):
-        fb = f[a] * 1024.0 * scale_f
-        wb = w[a] * 1024.0 * scale_w
-        per_axis.append({"axis": a + 1, "kernel": kf[a], "dispatches": nf[a],
-                         "fetch_kib_raw": round(f[a], 1), "write_kib_raw": round(w[a], 1),
+    for sl in range(2 * dims):
+        if f[sl] is None or w[sl] is None:
+            continue
+        a, twice = slot_axis(sl, dims)
+        fb = f[sl] * 1024.0 * scale_f
+        wb = w[sl] * 1024.0 * scale_w
+        per_axis.append({"axis": a + 1, "twice": twice, "kernel": kf[sl], "dispatches": nf[sl],
+                         "fetch_kib_raw": round(f[sl], 1), "write_kib_raw": round(w[sl], 1),
                          "fetch_bytes": round(fb), "write_bytes": round(wb), "bytes": round(fb + wb)})
     return {"copy_bytes": copy_bytes, "copy_fetch_kib_raw": round(cf / 1024.0, 1),
             "copy_write_kib_raw": round(cw / 1024.0, 1), "fetch_scale": scale_f, "write_scale": scale_w,
@@ -230,9 +259,9 @@ VALU_WAVE_INSTR_PER_US = 256 * 4 / 4 * 2400.0
 
 
 def sq_axis_means(csv_path, dims, tags=PASS_KERNEL_TAGS):
-    """Mean value per axis of every counter in one --pmc run, over the dispatches of the kernels
-    named by `tags` (the pass kernels by default; a dispatch's rows are summed), with the kernel
-    name of each axis."""
+    """Mean value per label (slot_of) of every counter in one --pmc run, over the timed dispatches
+    of the kernels named by `tags` (the pass kernels by default; a dispatch's rows are summed),
+    with the kernel name of each; labels without dispatches are left out."""
     per, names = {}, {}
     for r in _rows(csv_path):
         if not (any(t in r["Kernel_Name"] for t in tags) or MARK_TAG in r["Kernel_Name"]):
@@ -242,14 +271,16 @@ def sq_axis_means(csv_path, dims, tags=PASS_KERNEL_TAGS):
         c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
         names[d] = r["Kernel_Name"]
     order = sorted(per)
-    labels = axis_labels([names[d] for d in order], dims, tags)
+    labels = axis_labels([names[d] for d in order], dims, tags, periodic=tags == EXACT_KERNEL_TAGS)
     names = {d: short_name(n) for d, n in names.items()}
-    out = []
-    for a in range(dims):
-        ds = [d for d, lab in zip(order, labels) if lab == a]
-        keys = set().union(*(per[d] for d in ds)) if ds else set()
-        out.append({"kernel": names[ds[0]] if ds else None, "dispatches": len(ds),
-                    **{k: sum(per[d].get(k, 0.0) for d in ds) / len(ds) for k in keys}})
+    out = {}
+    for sl in range(2 * dims):
+        ds = [d for d, lab in zip(order, labels) if lab == sl]
+        if not ds:
+            continue
+        keys = set().union(*(per[d] for d in ds))
+        out[sl] = {"kernel": names[ds[0]], "dispatches": len(ds),
+                   **{k: sum(per[d].get(k, 0.0) for d in ds) / len(ds) for k in keys}}
     return out
 
 
@@ -257,24 +288,25 @@ def sq_markdown(directory, workload, dims):
     """Markdown summary of the SQ_SETS runs of one workload."""
     runs = [sq_axis_means(os.path.join(directory, f"{name}_{workload}", "run_counter_collection.csv"), dims)
             for name, _ in SQ_SETS]
-    axes = [{**runs[0][a], **runs[1][a]} for a in range(dims)]
+    axes = [(sl, {**runs[0][sl], **runs[1].get(sl, {})}) for sl in sorted(runs[0])]
     lines = [f"# Shader-sequencer counters, workload {workload} (FP64)", "",
              "Commands (run from /tmp on one MI355X; `$R` is the repository root, `$O` the output directory):", "",
              "```"]
     for name, counters in SQ_SETS:
         lines.append(SQ_COMMAND.replace("$COUNTERS", counters).replace("$SET", name).replace("$W", workload))
     lines += ["```", "",
-              "Per axis, means over the pass-kernel dispatches of a run (graph replays and per-pass timing). "
+              "Per axis, means over the timed launches of a run (sfac_plan_time_passes: one pass per launch; "
+              "sfac_plan_time_fused: two passes over the axis per launch, as the steps run them). "
               "Wave-cycle counters are accumulated per wavefront in the same units, so their ratios are shares "
               "of a wavefront's lifetime. VALU issue time: the VALU instructions at one wavefront instruction "
               "per SIMD every 4 cycles on 1024 SIMDs at 2.4 GHz.", "",
               "| axis | kernel | waves | VALU instr. | VALU issue us | FMA / ADD F64 | VALU share | LDS-wait share | "
               "any-wait share | LDS instr. | bank conflicts | VMEM rd / wr |",
               "|---|---|---|---|---|---|---|---|---|---|---|---|"]
-    for a, c in enumerate(axes):
+    for sl, c in axes:
         wc = c.get("SQ_WAVE_CYCLES", 0.0) or float("nan")
         lines.append(
-            f"| {a + 1} | `{c['kernel']}` | {c.get('SQ_WAVES', 0):.0f} | {c.get('SQ_INSTS_VALU', 0):.3g} | "
+            f"| {slot_name(sl, dims)} | `{c['kernel']}` | {c.get('SQ_WAVES', 0):.0f} | {c.get('SQ_INSTS_VALU', 0):.3g} | "
             f"{c.get('SQ_INSTS_VALU', 0) / VALU_WAVE_INSTR_PER_US:.1f} | "
             f"{c.get('SQ_INSTS_VALU_FMA_F64', 0):.3g} / {c.get('SQ_INSTS_VALU_ADD_F64', 0):.3g} | "
             f"{c.get('SQ_ACTIVE_INST_VALU', 0) / wc:.3f} | {c.get('SQ_WAIT_INST_LDS', 0) / wc:.3f} | "
@@ -320,7 +352,8 @@ def mfma_markdown(directory, workloads):
             if any(t in r["Kernel_Name"] for t in EXACT_KERNEL_TAGS):
                 spans[int(r["Dispatch_Id"])] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
         order = sorted(spans)
-        for a, c in enumerate(means):
+        for a in range(dims):
+            c = means.get(a, {"kernel": None})
             ds = order[a::dims]
             us = sum(spans[d] for d in ds) / len(ds) / 1e3 if ds else float("nan")
             n = c.get("SQ_INSTS_VALU_MFMA_F64", 0.0)
@@ -480,12 +513,13 @@ def _main():
     lines += ["## Kernel trace (`--kernel-trace --stats`)", "",
               stats_markdown(os.path.join(d, f"trace_{w}", "run_kernel_stats.csv")), ""]
     means = trace_axis_means(os.path.join(d, f"trace_{w}", "run_kernel_trace.csv"), a.dims)
-    lines += ["Per axis (dispatch order; graph replays of warm-up and timed steps plus the per-pass timing):", "",
+    lines += ["Per axis, the timed launches (sfac_plan_time_passes: one pass per launch; sfac_plan_time_fused: "
+              "two passes over the axis per launch, the step boundary in between, as the steps run them):", "",
               "| element | axis | kernel | dispatches | mean us | min us | max us |", "|---|---|---|---|---|---|---|"]
     for et, res in means.items():
         for r in res:
-            lines.append(f"| {et} | {r['axis']} | `{r['kernel']}` | {r['dispatches']} | {r['mean_us']:.2f} | "
-                         f"{r['min_us']:.2f} | {r['max_us']:.2f} |")
+            lines.append(f"| {et} | {r['axis']}{' (two passes)' if r['twice'] else ''} | `{r['kernel']}` | "
+                         f"{r['dispatches']} | {r['mean_us']:.2f} | {r['min_us']:.2f} | {r['max_us']:.2f} |")
     ex = exact_axis_means(os.path.join(d, f"trace_{w}", "run_kernel_trace.csv"), bench["config"]["grid"])
     if ex:
         lines += ["", "One-level scheme with the exact exponential (`exact_gemm`, FP64 matrix cores; "
@@ -523,8 +557,8 @@ def _main():
             pts *= n
         alg = 2 * pts * es
         for r in t["per_axis"]:
-            lines.append(f"| {dt} | {r['axis']} | `{r['kernel']}` | {r['fetch_kib_raw']} | {r['write_kib_raw']} | "
-                         f"{r['bytes']} | {alg} | {r['bytes'] / alg:.3f} |")
+            lines.append(f"| {dt} | {r['axis']}{' (two passes)' if r['twice'] else ''} | `{r['kernel']}` | "
+                         f"{r['fetch_kib_raw']} | {r['write_kib_raw']} | {r['bytes']} | {alg} | {r['bytes'] / alg:.3f} |")
         rec_all[f"{w}:{dt}"] = {"source_hash": source_hash(), "profile": os.path.basename(a.out),
                                 "algorithmic_bytes": alg, "schedule": scheds.get(dt), **t}
     ex_t = None

@@ -23,6 +23,7 @@ EXPORTS = [
     "sfac_axis_tables", "sfac_plan_time_passes", "sfac_group_create", "sfac_group_step",
     "sfac_group_destroy", "sfac_group_device_bytes", "sfac_batch_plan", "sfac_plan_energy",
     "sfac_plan_trace", "sfac_plan_read_trace", "sfac_exact_exponential", "sfac_solve_noalloc",
+    "sfac_plan_time_fused",
 ]
 
 
@@ -75,6 +76,7 @@ def lib():
     L.sfac_axis_tables.argtypes = [i32, dbl, dbl, dbl, dbl, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl),
                                    ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.sfac_plan_time_passes.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_float)]
+    L.sfac_plan_time_fused.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_float)]
     L.sfac_plan_energy.argtypes = [vp, vp, ctypes.POINTER(dbl)]
     L.sfac_plan_trace.argtypes = [vp, i64]
     L.sfac_exact_exponential.argtypes = [i32, dbl, dbl, dbl, dbl, ctypes.POINTER(dbl)]
@@ -90,7 +92,7 @@ def lib():
                                      ctypes.c_int, vp, i64, vp, ctypes.POINTER(Options),
                                      ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(dbl)]
     L.sfac_solve_noalloc.restype = ctypes.c_int
-    for name in ["sfac_group_create", "sfac_group_step", "sfac_group_destroy", "sfac_plan_time_passes", "sfac_axis_tables", "sfac_plan_create", "sfac_step", "sfac_plan_destroy", "sfac_plan_flags",
+    for name in ["sfac_group_create", "sfac_group_step", "sfac_group_destroy", "sfac_plan_time_passes", "sfac_plan_time_fused", "sfac_axis_tables", "sfac_plan_create", "sfac_step", "sfac_plan_destroy", "sfac_plan_flags",
                  "sfac_plan_reset_flags", "sfac_plan_method", "sfac_batch_create",
                  "sfac_batch_step", "sfac_batch_destroy", "sfac_plan_energy",
                  "sfac_plan_trace", "sfac_plan_read_trace", "sfac_exact_exponential"]:
@@ -261,6 +263,15 @@ class Plan:
         _check_state(u, self.shape, self.dt)
         ms = (ctypes.c_float * self.dims)()
         _check(lib().sfac_plan_time_passes(self._h, ctypes.c_void_p(u.data_ptr()), int(reps), ms))
+        return list(ms)
+
+    def time_fused(self, u, reps):
+        """Mean duration (ms) of the launches that cover axis 1 and axis d twice (the last pass of
+        a step with the first of the next), [axis 1, axis d]; 0 where the kernel does not fuse
+        (advances u)."""
+        _check_state(u, self.shape, self.dt)
+        ms = (ctypes.c_float * 2)()
+        _check(lib().sfac_plan_time_fused(self._h, ctypes.c_void_p(u.data_ptr()), int(reps), ms))
         return list(ms)
 
     def energy(self, u):

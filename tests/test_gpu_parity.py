@@ -367,6 +367,61 @@ def test_odd_symmetry_and_resumability_bitwise(sfac_lib):
     assert np.array_equal(u.cpu().numpy(), a)
 
 
+FUSE_CASES = [
+    # (ns, dtype, schedule): embedded and two-step diagonal kernels, contiguous and strided axes,
+    # tiles whose last pair holds one real line (odd line counts), one and several steps
+    ((63, 41), "f64", None),
+    ((63, 41), "f32", None),
+    ((45, 21), "f64", {"method": ("diag", "diag")}),
+    ((35, 15, 21), "f64", {"method": ("diag", "diag", "diag")}),
+    ((35, 15, 21), "f32", {"method": ("diag", "diag", "diag")}),
+    ((31, 17, 9), "f64", {"method": ("embed", "diag", "embed")}),
+    ((255, 9, 7), "f64", {"method": ("diag", "embed", "embed"), "kernel": (3, 0, 0), "lines_per_block": (3, 1, 1)}),
+    ((127, 33), "f64", {"kernel": (4, 4)}),
+    ((127, 33, 5), "f32", {"kernel": (4, 4, 0)}),
+    ((63, 63), "f64", {"method": "embed", "elems_log2": (2, 2), "lines_per_block": (2, 2)}),
+    ((63, 63), "f32", {"method": "embed", "elems_log2": (2, 3), "lines_per_block": (1, 0)}),
+    ((63, 63, 5), "f64", {"method": ("embed", "diag", "embed"), "elems_log2": (3, 0, 0)}),
+]
+
+
+@pytest.mark.parametrize("ns,dtype,sched", FUSE_CASES)
+def test_fused_passes_equal_separate_passes_bitwise(sfac_lib, ns, dtype, sched):
+    """Consecutive steps run their axes in alternating order (1..d, then d..1), so a step's last
+    pass and the next step's first cover the same axis and one launch does both, with the step
+    boundary (closing half-step, statistics, opening half-step) in registers. A plan that keeps
+    the per-step record launches them separately: states, flags and max|u| must be bitwise
+    equal, and the record's values must match the fused run's sticky maximum."""
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    hs = W.mesh_widths(ns)
+    alphas = (1.3, 1.7, 1.5)[:len(ns)]
+    u0 = W.uniform_field(tuple(reversed(ns)), -0.95, 0.95, seed=31)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    _say(f"case fused vs separate {ns} {dtype} {sched}")
+    out = []
+    for traced in (False, True):
+        for use_graph in (True, False):
+            u = torch.tensor(u0, dtype=tdt, device="cuda")
+            with sfac.Plan(ns, alphas, 0.2, 0.01, hs, dtype, use_graph=use_graph, **(sched or {})) as p:
+                if traced:
+                    p.trace(64)
+                p.step(u, 1)
+                p.step(u, 6)
+                p.step(u, 5)
+                flags = p.flags()
+                rec = p.read_trace()[0] if traced else None
+            torch.cuda.synchronize()
+            out.append((u.cpu().numpy(), flags, rec))
+    ref = out[0]
+    for got in out[1:]:
+        assert np.array_equal(got[0], ref[0])
+        assert got[1] == ref[1]
+    assert out[2][2].max() == ref[1][1]
+    ref64 = O.two_level_solve(u0, ns, alphas, 0.2, hs, 0.01, 12)
+    assert rel_err(ref[0].astype(np.float64), ref64) <= (FP64_TOL if dtype == "f64" else FP32_TOL)
+
+
 def test_flags_report_nonfinite_and_above_one(sfac_lib):
     torch = _torch()
     from paper_2209_08437_amd import sfac

@@ -8,8 +8,13 @@ import pytest
 
 from paper_2209_08437_amd import profiling as P
 
-PASS = "void sfac::(anonymous namespace)::embed_pass_single<double, 11, 3>(sfac::PassDesc<double>)"
+PASS = "void sfac::(anonymous namespace)::embed_pass_single<double, 11, 3, false, false>(sfac::PassDesc<double>)"
+TWICE = "void sfac::(anonymous namespace)::embed_pass_single<double, 11, 3, false, true>(sfac::PassDesc<double>)"
 COPY = "__amd_rocclr_copyBuffer"
+
+
+def MARK(k):
+    return f"void sfac::(anonymous namespace)::pass_timing_mark<{k}>()"
 
 
 def _sources():
@@ -48,17 +53,25 @@ def _write_pmc(path, rows):
             w.writerow(dict(zip(fields, r)))
 
 
+def _timed_2d(counter, vals, extra=()):
+    """Counter rows of a 2D run: step dispatches (not attributed), then the timed blocks of
+    sfac_plan_time_passes (axis 1, axis 2) and sfac_plan_time_fused (axis 1, axis 2), two
+    launches each, behind their markers; `vals` holds the eight launches' values."""
+    rows = [(1, PASS, counter, 5000.0), (2, TWICE, counter, 5000.0)]          # steps: ignored
+    names = [MARK(1), PASS, PASS, MARK(2), PASS, PASS, MARK(11), TWICE, TWICE, MARK(12), TWICE, TWICE, MARK(0)]
+    it = iter(vals)
+    for i, nm in enumerate(names, start=3):
+        rows.append((i, nm, counter, 0.0 if "mark" in nm else next(it)))
+    return rows + list(extra)
+
+
 def test_traffic_calibration_and_axis_attribution(tmp_path):
-    # two steps of a 2D run: dispatches alternate axis 1, axis 2; each dispatch's counter is
-    # reported in two parts (as per-XCD rows) that must be summed; a copy kernel in between is
-    # not a pass kernel and must be ignored
-    fetch = [(1, PASS, "FETCH_SIZE", 60.0), (1, PASS, "FETCH_SIZE", 40.0),   # axis 1: 100
-             (2, PASS, "FETCH_SIZE", 150.0), (2, PASS, "FETCH_SIZE", 50.0),  # axis 2: 200
-             (3, COPY, "FETCH_SIZE", 9999.0),
-             (4, PASS, "FETCH_SIZE", 110.0),                                 # axis 1: 110
-             (5, PASS, "FETCH_SIZE", 210.0)]                                 # axis 2: 210
-    write = [(1, PASS, "WRITE_SIZE", 300.0), (2, PASS, "WRITE_SIZE", 400.0),
-             (4, PASS, "WRITE_SIZE", 320.0), (5, PASS, "WRITE_SIZE", 420.0)]
+    # a 2D run: each dispatch's counter may be reported in several parts (as per-XCD rows) that
+    # must be summed; a copy kernel is not a pass kernel; only the marked blocks count
+    # the first timed launch (dispatch 4) comes in two rows: 60 + 40
+    fetch = _timed_2d("FETCH_SIZE", [60.0, 110.0, 200.0, 210.0, 300.0, 300.0, 400.0, 400.0],
+                      extra=[(4, PASS, "FETCH_SIZE", 40.0), (99, COPY, "FETCH_SIZE", 9999.0)])
+    write = _timed_2d("WRITE_SIZE", [300.0, 320.0, 400.0, 420.0, 500.0, 500.0, 600.0, 600.0])
     copy_bytes = 1 << 20
     # the copy probe: 20 large copies whose FETCH counter reads half the copied bytes and whose
     # WRITE counter reads all of them, plus one small unrelated dispatch
@@ -70,44 +83,53 @@ def test_traffic_calibration_and_axis_attribution(tmp_path):
         _write_pmc(paths[key], rows)
     t = P.traffic_from_pmc(paths["f"], paths["w"], paths["cf"], paths["cw"], copy_bytes, 2)
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
-    a1, a2 = t["per_axis"]
-    assert (a1["dispatches"], a2["dispatches"]) == (2, 2)
-    assert a1["fetch_kib_raw"] == 105.0 and a2["fetch_kib_raw"] == 205.0
-    assert a1["write_kib_raw"] == 310.0 and a2["write_kib_raw"] == 410.0
+    a1, a2, f1, f2 = t["per_axis"]
+    assert [(r["axis"], r["twice"]) for r in t["per_axis"]] == [(1, False), (2, False), (1, True), (2, True)]
+    assert (a1["dispatches"], a2["dispatches"], f1["dispatches"]) == (2, 2, 2)
+    assert a1["fetch_kib_raw"] == 105.0 and a2["fetch_kib_raw"] == 205.0 and f2["fetch_kib_raw"] == 400.0
+    assert a1["write_kib_raw"] == 310.0 and a2["write_kib_raw"] == 410.0 and f1["write_kib_raw"] == 500.0
     assert a1["bytes"] == round(105.0 * 1024 * 2 + 310.0 * 1024)
     assert a2["bytes"] == round(205.0 * 1024 * 2 + 410.0 * 1024)
-    assert a1["kernel"] == "embed_pass_single<double, 11, 3>"
+    assert a1["kernel"] == "embed_pass_single<double, 11, 3, false, false>"
+    assert f1["kernel"] == "embed_pass_single<double, 11, 3, false, true>"
 
 
 def test_trace_axis_means(tmp_path):
     path = str(tmp_path / "trace.csv")
     fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp"]
-    rows = [(PASS, 1000, 3000), (PASS, 3000, 7000), (COPY, 7000, 9000), (PASS, 9000, 12000), (PASS, 12000, 17000)]
+    rows = [(PASS, 0, 900), (MARK(1), 900, 1000), (PASS, 1000, 3000), (PASS, 3000, 7000), (COPY, 7000, 9000),
+            (MARK(2), 8990, 9000), (PASS, 9000, 12000), (PASS, 12000, 17000),
+            (MARK(12), 16990, 17000), (TWICE, 17000, 25000), (MARK(0), 24990, 25000), (PASS, 25000, 26000)]
     with open(path, "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=fields)
         w.writeheader()
         for r in reversed(rows):     # unordered on disk: sorted by start time
             w.writerow(dict(zip(fields, r)))
     m = P.trace_axis_means(path, 2)["double"]
-    assert [r["dispatches"] for r in m] == [2, 2]
-    assert m[0]["mean_us"] == pytest.approx(2.5) and m[1]["mean_us"] == pytest.approx(4.5)
+    assert [(r["axis"], r["twice"], r["dispatches"]) for r in m] == [(1, False, 2), (2, False, 2), (2, True, 1)]
+    assert m[0]["mean_us"] == pytest.approx(3.0) and m[1]["mean_us"] == pytest.approx(4.0)
     assert m[0]["min_us"] == pytest.approx(2.0) and m[1]["max_us"] == pytest.approx(5.0)
+    assert m[2]["mean_us"] == pytest.approx(8.0)
 
 
 def test_axis_labels_follow_timing_marks():
-    """Steps give the d-periodic order; the timed launches of sfac_plan_time_passes come in
-    blocks, one axis each, announced by pass_timing_mark<axis> and closed by pass_timing_mark<0>."""
-    A = "void sfac::(anonymous namespace)::diag2_pass_single<double, 15, 17, true>(sfac::PassDesc<double>)"
-    B = "void sfac::(anonymous namespace)::diag2_pass_single<double, 15, 17, false>(sfac::PassDesc<double>)"
-    F = "void sfac::(anonymous namespace)::diag2_pass_single<float, 15, 17, false>(sfac::PassDesc<float>)"
-    mark = lambda a: f"void sfac::(anonymous namespace)::pass_timing_mark<{a}>()"
-    names = [A, B, B, F, A, B, B, COPY, F,
-             mark(1), A, A, mark(2), B, B, mark(3), B, B, mark(0),
-             F, A, B, B]
+    """Only the timed launches are attributed: blocks announced by pass_timing_mark<axis> (one pass
+    per launch) or pass_timing_mark<FUSED_MARK + axis> (two passes over the axis per launch), the
+    last closed by pass_timing_mark<0>; step dispatches, whose axis order alternates, get None.
+    The one-level scheme's products (periodic) take the d-periodic order outside the blocks."""
+    A = "void sfac::(anonymous namespace)::diag2_pass_single<double, 15, 17, true, false>(sfac::PassDesc<double>)"
+    B = "void sfac::(anonymous namespace)::diag2_pass_single<double, 15, 17, false, false>(sfac::PassDesc<double>)"
+    T = "void sfac::(anonymous namespace)::diag2_pass_single<double, 15, 17, true, true>(sfac::PassDesc<double>)"
+    names = [A, B, T, COPY,
+             MARK(1), A, A, MARK(2), B, B, MARK(3), B, B, MARK(11), T, MARK(13), T, T, MARK(0),
+             A, T, B]
     got = P.axis_labels(names, 3)
-    assert got == [0, 1, 2, 0, 0, 1, 2, None, 1,
-                   None, 0, 0, None, 1, 1, None, 2, 2, None,
-                   2, 0, 1, 2]
+    assert got == [None, None, None, None,
+                   None, 0, 0, None, 1, 1, None, 2, 2, None, 3, None, 5, 5, None,
+                   None, None, None]
+    assert [P.slot_axis(s, 3) for s in (0, 2, 3, 5)] == [(0, False), (2, False), (0, True), (2, True)]
+    G = "void sfac::(anonymous namespace)::exact_gemm<2, 16>(double const*)"
+    assert P.axis_labels([G, G, G, G, G], 2, tags=P.EXACT_KERNEL_TAGS, periodic=True) == [0, 1, 0, 1, 0]
 
 
 def test_trace_axis_means_with_timed_blocks(tmp_path):
@@ -117,14 +139,14 @@ def test_trace_axis_means_with_timed_blocks(tmp_path):
     rows = [(PASS, 0, 2000), (PASS, 2000, 6000),                                    # one step
             (mark(1), 6000, 6100), (PASS, 6100, 8100), (PASS, 8100, 10100),       # axis 1 timed
             (mark(2), 10100, 10200), (PASS, 10200, 14200), (mark(0), 14200, 14300),
-            (PASS, 14300, 16300), (PASS, 16300, 20300)]                          # one more step
+            (PASS, 14300, 16300), (PASS, 16300, 20300)]                          # one more step: ignored
     with open(path, "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=fields)
         w.writeheader()
         for r in rows:
             w.writerow(dict(zip(fields, r)))
     m = P.trace_axis_means(path, 2)["double"]
-    assert [r["dispatches"] for r in m] == [4, 3]
+    assert [r["dispatches"] for r in m] == [2, 1]
     assert m[0]["mean_us"] == pytest.approx(2.0) and m[1]["mean_us"] == pytest.approx(4.0)
 
 
@@ -144,19 +166,23 @@ def test_traffic_record_used_only_for_current_code_and_schedule(tmp_path):
 
 
 def test_sq_axis_means(tmp_path):
-    # a 2D run: dispatches alternate axes; per-XCD rows of a dispatch are summed, other kernels skipped
-    rows = [(1, PASS, "SQ_WAVES", 1000.0), (1, PASS, "SQ_WAVES", 1048.0), (1, PASS, "SQ_INSTS_VALU", 10.0),
-            (2, PASS, "SQ_WAVES", 2048.0), (2, PASS, "SQ_INSTS_VALU", 30.0),
-            (3, COPY, "SQ_WAVES", 5.0),
+    # a 2D run: per-XCD rows of a dispatch are summed, other kernels and step dispatches skipped,
+    # labels without timed dispatches left out
+    rows = [(1, PASS, "SQ_WAVES", 7.0), (2, MARK(1), "SQ_WAVES", 1.0),
+            (3, PASS, "SQ_WAVES", 1000.0), (3, PASS, "SQ_WAVES", 1048.0), (3, PASS, "SQ_INSTS_VALU", 10.0),
             (4, PASS, "SQ_WAVES", 2048.0), (4, PASS, "SQ_INSTS_VALU", 20.0),
-            (5, PASS, "SQ_WAVES", 2048.0), (5, PASS, "SQ_INSTS_VALU", 50.0)]
+            (5, COPY, "SQ_WAVES", 5.0), (6, MARK(12), "SQ_WAVES", 1.0),
+            (7, TWICE, "SQ_WAVES", 2048.0), (7, TWICE, "SQ_INSTS_VALU", 30.0),
+            (8, TWICE, "SQ_WAVES", 2048.0), (8, TWICE, "SQ_INSTS_VALU", 50.0), (9, MARK(0), "SQ_WAVES", 1.0)]
     path = str(tmp_path / "sq.csv")
     _write_pmc(path, rows)
-    a1, a2 = P.sq_axis_means(path, 2)
-    assert a1["dispatches"] == a2["dispatches"] == 2
-    assert a1["SQ_WAVES"] == 2048.0 and a2["SQ_WAVES"] == 2048.0
-    assert a1["SQ_INSTS_VALU"] == 15.0 and a2["SQ_INSTS_VALU"] == 40.0
-    assert a1["kernel"] == "embed_pass_single<double, 11, 3>"
+    m = P.sq_axis_means(path, 2)
+    assert sorted(m) == [0, 3]
+    a1, f2 = m[0], m[3]
+    assert a1["dispatches"] == f2["dispatches"] == 2
+    assert a1["SQ_WAVES"] == 2048.0 and f2["SQ_WAVES"] == 2048.0
+    assert a1["SQ_INSTS_VALU"] == 15.0 and f2["SQ_INSTS_VALU"] == 40.0
+    assert a1["kernel"] == "embed_pass_single<double, 11, 3, false, false>"
 
 
 def test_exact_axis_means(tmp_path):
@@ -203,7 +229,7 @@ def test_exact_traffic_attribution(tmp_path):
     assert a1["write_kib_raw"] == 30.0 and a2["write_kib_raw"] == 40.0
     assert a1["kernel"] == "exact_gemm<1, 32>"
     ps = P.traffic_from_pmc(paths["f"], paths["w"], paths["cf"], paths["cw"], copy_bytes, 2)
-    assert [r["fetch_kib_raw"] for r in ps["per_axis"]] == [100.0, 200.0]
+    assert ps["per_axis"] == []           # pass dispatches outside the timed blocks are not attributed
 
 
 def test_mfma_markdown(tmp_path):
