@@ -318,7 +318,7 @@ def one_level_exact(inst, steps, two_level_state, two_level_ms, workload_name, p
     rec = profiling.load_traffic(TRAFFIC_RECORD, workload_name, "exact")
     roof = {"bound": "mfma", "achieved": round(tf, 3), "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tf / MFMA_F64_PEAK_TFLOPS, 4),
-            "traffic": rec["per_axis"][a]["bytes"] if rec else None,
+            "traffic": rec["per_axis"][a]["bytes"] if rec and len(rec["per_axis"]) > a else None,
             "kernel": f"exact_gemm (FP64 matrix cores), axis {a + 1}", "flops_per_launch": fl,
             "algorithmic_bytes_per_launch": 8 * (2 * inst.points + inst.ns[a] ** 2),
             "product_ms": [round(x, 5) for x in prod_ms]}

@@ -387,8 +387,8 @@ def load_traffic(path, workload, dtype, schedule=None):
 COMMANDS = """\
 python3 -m paper_2209_08437_amd.autotune --fresh --out $R/paper_2209_08437_amd/tuned_mi355x.json large_2d_1023 large_3d_255 plain_2d_63 batched_2d   # the packaged schedule table, tuned on an MI355X beforehand; every run below uses it
 rocprofv3 --kernel-trace --stats --output-format csv -d $O/trace_$W -o run -- python3 $R/bench.py --workload $W --no-cpu --no-sub
-rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --steps 20 --warmup 2 --pass-reps 2
-rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --no-exact --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --no-exact --steps 20 --warmup 2 --pass-reps 2
 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/copy_FETCH_SIZE -o run -- python3 $R/bench.py --copy-probe
 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/copy_WRITE_SIZE -o run -- python3 $R/bench.py --copy-probe"""
 
@@ -532,10 +532,12 @@ def _main():
         if "ms_per_step" in one:
             lines += ["", f"bench.py in the same session: {one['ms_per_step'] * 1e3:.1f} us per one-level step "
                       f"({one['product_TFLOPs']} TFLOP/s over the step), plan creation {one['plan_create_ms']:.0f} ms."]
+    def launches(roof):
+        return (f"pass us {[round(x * 1e3, 2) for x in roof['pass_ms']]}, two-pass launches (axis 1, axis d) us "
+                f"{[round(x * 1e3, 2) for x in roof.get('fused_ms', [])]}")
     lines += ["", f"bench.py in the same session (no profiler): FP64 {bench['ms_per_step'] * 1e3:.2f} us/step, "
-              f"pass us {[round(x * 1e3, 2) for x in bench['roofline']['pass_ms']]}; FP32 "
-              f"{bench['fp32']['ms_per_step'] * 1e3:.2f} us/step, pass us "
-              f"{[round(x * 1e3, 2) for x in bench['fp32']['roofline']['pass_ms']]}.", ""]
+              f"{launches(bench['roofline'])}; FP32 {bench['fp32']['ms_per_step'] * 1e3:.2f} us/step, "
+              f"{launches(bench['fp32']['roofline'])} (0: that axis' kernel does not fuse).", ""]
     scheds = _schedules(os.path.join(d, f"bench_{w}.err"))
     rec_all = {}
     try:
@@ -570,7 +572,7 @@ def _main():
                                 tags=EXACT_KERNEL_TAGS)
     except (TypeError, ZeroDivisionError, OSError):
         ex_t = None
-    if ex_t and all(r["dispatches"] for r in ex_t["per_axis"]):
+    if ex_t and ex_t["per_axis"] and all(r["dispatches"] for r in ex_t["per_axis"]):
         grid = bench["config"]["grid"]
         pts = 1
         for n in grid:
