@@ -452,7 +452,10 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     // Unrolled: the second pass must see the same compile-time zeros (the padding registers) as
     // a pass that loads its tile, so that the compiler simplifies and fuses its arithmetic the
     // same way and the values stay bitwise those of two launches.
+    // FP64 also seals the three factors: every register enters and leaves them through as_stored,
+    // so that the block is compiled from the same opaque inputs in a single and a two-pass kernel.
     constexpr int reps = TWICE ? 2 : 1;
+    constexpr bool SEAL = sizeof(T) == 8;
 #pragma unroll
     for (int r = 0; r < reps; ++r) {
         if (r == 1) {
@@ -463,9 +466,23 @@ __device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
                     if ((R0 < 2 || k < R0 / 2) && act && Line::nat(t, i, k) < N)
                         L.a[i * R0 + k] = step_boundary(L.a[i * R0 + k], two, decay, decay_lo, vmax, bad);
         }
+        if constexpr (SEAL) {
+#pragma unroll
+            for (int e = 0; e < G::E; ++e) {
+                L.a[e].x = as_stored(L.a[e].x);
+                L.a[e].y = as_stored(L.a[e].y);
+            }
+        }
         L.factor(d.gpos_c, ln, t, N);
         L.factor(d.gpos_s, ln, t, N);
         L.factor(d.gpos_c, ln, t, N);
+        if constexpr (SEAL) {
+#pragma unroll
+            for (int e = 0; e < G::E; ++e) {
+                L.a[e].x = as_stored(L.a[e].x);
+                L.a[e].y = as_stored(L.a[e].y);
+            }
+        }
     }
     if constexpr (STAGE) __syncthreads();   // the last exchange's reads are done before the staging writes
 #pragma unroll
@@ -730,13 +747,11 @@ const void* diag2_fn(int a, int b, bool multi, bool wave, bool twice) {
 }
 
 // kernel of one (transform length, elements per thread, staging); LE = 2 (M = 64 to 2048), 3 or 4
-// (the runtime fuses the embedded passes in FP32 only, so the FP64 two-pass kernels are not built)
 template <typename T, int LOG2M, int LE, bool STAGE>
 const void* embed_fn_k(bool multi, bool twice) {
     if (multi) return twice ? nullptr : reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, LE, STAGE>);
-    if (!twice) return reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE, false>);
-    if constexpr (sizeof(T) == 4) return reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE, true>);
-    return nullptr;
+    return twice ? reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE, true>)
+                 : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE, false>);
 }
 template <typename T, int LOG2M, bool STAGE>
 const void* embed_fn_le(int le, bool multi, bool twice) {

@@ -340,13 +340,11 @@ sfac::PassDesc<T> reversed_desc(sfac::PassDesc<T> d, int a, int dims) {
 }
 
 // Kernels that cover their axis twice in one launch (nl_mid) with values bitwise those of two
-// launches: the two-step diagonal ones (FP64 and FP32) and the FP32 embedded ones. The FP64
-// embedded kernel's fused form was measured to differ from two launches in the last bits (cause
-// not identified), so its passes keep one launch each.
+// launches: the two-step diagonal ones and the embedded ones.
 template <typename T>
 bool can_fuse(const sfac::PassDesc<T>& d) {
     if (d.method == SFAC_METHOD_DIAG) return d.d2a > 0;
-    return d.method == SFAC_METHOD_EMBED && std::is_same<T, float>::value;
+    return d.method == SFAC_METHOD_EMBED;
 }
 
 // The launch that covers axis a twice: the last pass of a step (`cur`, from the step's
