@@ -299,9 +299,9 @@ sfac_status sfac_group_create(sfac_group* out, void* hip_stream);
  * sfac_group_step - advance plans[i]'s state u_dev[i] by nsteps[i] >= 0 steps, i < count. A plan
  * may appear once. Plans of both arithmetics may be mixed. Each state ends bitwise equal to
  * stepping its plan alone with sfac_step: its passes run in the axis orders its step count
- * gives them (see sfac_step), one launch per pass (grouped launches are not fused across step
- * boundaries, which gives the same values), and each plan's step count advances by its
- * nsteps[i]. Asynchronous on the group's stream: it returns once the
+ * gives them (see sfac_step), the step boundaries inside each of the group's step graphs as
+ * one launch where the plan's kernel fuses (the same values as two launches), and each plan's
+ * step count advances by its nsteps[i]. Asynchronous on the group's stream: it returns once the
  * work is queued and does not wait for earlier calls (dropping a cached graph when the cache is
  * full waits for the stream). The plans must stay alive until the work has run.
  * Errors: SFAC_EINVAL (NULL arguments, a repeated plan, negative steps, misaligned state),

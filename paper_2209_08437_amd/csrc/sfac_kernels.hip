@@ -680,7 +680,7 @@ __device__ __forceinline__ PassDesc<T> group_desc(const GroupArgs<T>& g, int b, 
 }
 
 // Several instances with the same transform length in one launch (batched form).
-template <typename T, int LOG2M, int LE, bool STAGE>
+template <typename T, int LOG2M, int LE, bool STAGE, bool TWICE>
 __global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_multi(const GroupArgs<T> g) {
     extern __shared__ unsigned char smem_raw[];
     int local;
@@ -689,7 +689,7 @@ __global__ void SFAC_EMBED_BOUNDS(LOG2M, LE, STAGE) embed_pass_multi(const Group
     if (tile >= d.ntiles) return;
     // the block has the group's largest size; threads beyond d.lpb lines hold no line (their
     // LDS rows lie inside the block's allocation) and only take part in the barriers
-    run_embed_tile<T, LOG2M, LE, STAGE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_embed_tile<T, LOG2M, LE, STAGE, TWICE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
 // Waves per SIMD the register budget is cut for: three (at most 168 VGPRs). Every pair fits
@@ -708,19 +708,21 @@ __global__ void __launch_bounds__(kBlockThreads, (diag2_min_waves<T, A, B, WA>()
     run_diag2_tile<T, A, B, WA, TWICE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
-template <typename T, int A, int B, bool WA>
+template <typename T, int A, int B, bool WA, bool TWICE>
 __global__ void __launch_bounds__(kBlockThreads, (diag2_min_waves<T, A, B, WA>())) diag2_pass_multi(const GroupArgs<T> g) {
     extern __shared__ unsigned char smem_raw[];
     int local;
     const PassDesc<T> d = group_desc(g, blockIdx.x, &local);
     const int tile = d.xcd_remap ? xcd_tile(local, d.ntiles) : local;
     if (tile >= d.ntiles) return;
-    run_diag2_tile<T, A, B, WA>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
+    run_diag2_tile<T, A, B, WA, TWICE>(d, tile, reinterpret_cast<cplx<T>*>(smem_raw));
 }
 
 template <typename T, int A, int B, bool WA>
 const void* diag2_fn_w(bool multi, bool twice) {
-    if (multi) return twice ? nullptr : reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B, WA>);
+    if (multi)
+        return twice ? reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B, WA, true>)
+                     : reinterpret_cast<const void*>(&diag2_pass_multi<T, A, B, WA, false>);
     return twice ? reinterpret_cast<const void*>(&diag2_pass_single<T, A, B, WA, true>)
                  : reinterpret_cast<const void*>(&diag2_pass_single<T, A, B, WA, false>);
 }
@@ -749,7 +751,9 @@ const void* diag2_fn(int a, int b, bool multi, bool wave, bool twice) {
 // kernel of one (transform length, elements per thread, staging); LE = 2 (M = 64 to 2048), 3 or 4
 template <typename T, int LOG2M, int LE, bool STAGE>
 const void* embed_fn_k(bool multi, bool twice) {
-    if (multi) return twice ? nullptr : reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, LE, STAGE>);
+    if (multi)
+        return twice ? reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, LE, STAGE, true>)
+                     : reinterpret_cast<const void*>(&embed_pass_multi<T, LOG2M, LE, STAGE, false>);
     return twice ? reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE, true>)
                  : reinterpret_cast<const void*>(&embed_pass_single<T, LOG2M, LE, STAGE, false>);
 }
@@ -918,8 +922,10 @@ hipError_t launch_axis_pass_multi(int kind, int variant, int threads, const Grou
     const int total_blocks = args.start[args.n];
     if (total_blocks <= 0) return hipSuccess;
     if (kind == 1 || kind == 2) {
-        const void* fn = kind == 1 ? embed_fn<T>((variant % 128) / 8, variant % 8, true, variant >= 128, false)
-                                   : diag2_fn<T>((variant % 4096) / 64, variant % 64, true, variant >= 4096, false);
+        const bool twice = variant >= kTwiceVariant;
+        const int v = variant % kTwiceVariant;
+        const void* fn = kind == 1 ? embed_fn<T>((v % 128) / 8, v % 8, true, v >= 128, twice)
+                                   : diag2_fn<T>((v % 4096) / 64, v % 64, true, v >= 4096, twice);
         if (!fn) return hipErrorInvalidValue;
         void* kargs[] = {const_cast<GroupArgs<T>*>(&args)};
         return hipLaunchKernel(fn, dim3(total_blocks), dim3(threads), kargs, lds_bytes, stream);
@@ -1202,7 +1208,7 @@ hipError_t allow_lds(size_t lds_bytes) {
         for (int le = 2; le <= 4; ++le)
             for (int multi = 0; multi < 2; ++multi)
                 for (int stage = 0; stage < 2; ++stage)
-                    for (int twice = 0; twice < 2 - multi; ++twice) {
+                    for (int twice = 0; twice < 2; ++twice) {
                         const void* fn = embed_fn<T>(lg, le, multi, stage, twice);
                         if (!fn) continue;
                         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
@@ -1216,7 +1222,7 @@ hipError_t allow_lds(size_t lds_bytes) {
         for (int b = a; b <= 17; ++b)
             for (int multi = 0; multi < 2; ++multi)
                 for (int wave = 0; wave < 2; ++wave)
-                    for (int twice = 0; twice < 2 - multi; ++twice) {
+                    for (int twice = 0; twice < 2; ++twice) {
                         const void* fn = diag2_fn<T>(a, b, multi, wave, twice);
                         if (!fn) continue;
                         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);

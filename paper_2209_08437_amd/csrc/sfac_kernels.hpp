@@ -91,6 +91,7 @@ hipError_t launch_axis_pass(const PassDesc<T>& d, size_t lds_bytes, hipStream_t 
 // steps, and its first block; start[n] is the launch's block count. A launch holds at most
 // kGroupSlots instances (about 1.3 KB of kernel arguments); larger sets take several launches.
 constexpr int kGroupSlots = 64;
+constexpr int kTwiceVariant = 1 << 20;
 template <typename T>
 struct GroupArgs {
     const PassDesc<T>* desc[kGroupSlots];
@@ -99,7 +100,8 @@ struct GroupArgs {
     int n;
 };
 
-// One launch over several instances' tiles of one pass; every descriptor of the launch uses the
+// One launch over several instances' tiles of one pass (or of two passes over one axis, when
+// variant >= kTwiceVariant: descriptors with nl_mid); every descriptor of the launch uses the
 // same kernel variant; `threads` is the block size (the group's largest).
 // kind: 0 generic, 1 embedded (variant = log2m * 8 + log2e, plus 128 for the LDS-staged tile),
 // 2 two-step diagonal (variant = a * 64 + b, plus 4096 for the wavefront-aligned line layout)

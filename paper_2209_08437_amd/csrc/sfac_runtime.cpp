@@ -481,6 +481,12 @@ struct sfac_plan_s {
     const sfac::PassDesc<T>* device_desc(int a, int rev) const {
         return reinterpret_cast<const sfac::PassDesc<T>*>(dev + off_desc) + 3 * rev + a;
     }
+    // device copy of the descriptor of two passes in one launch: over axis 1 after a step in the
+    // order d..1 (which = 0), over axis d after a step in the order 1..d (which = 1)
+    template <typename T>
+    const sfac::PassDesc<T>* fused_device_desc(int which) const {
+        return reinterpret_cast<const sfac::PassDesc<T>*>(dev + off_desc) + 6 + which;
+    }
 
     // eq. (strang): J^Q_{tau/2} e^{tau A} J^Q_{tau/2}, e^{tau A} one dense product per axis, alternating
     // between the state and the scratch buffer; the closing half-step writes the state and the
@@ -815,7 +821,7 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
     p->off_stat = align_up(p->in.table_bytes, 256);
     p->off_desc = p->off_stat + 256;
     const size_t desc_bytes = dt == SFAC_FP64 ? sizeof(sfac::PassDesc<double>) : sizeof(sfac::PassDesc<float>);
-    p->dev_bytes = align_up(p->off_desc + 6 * desc_bytes, 256);   // three axes, two orders
+    p->dev_bytes = align_up(p->off_desc + 8 * desc_bytes, 256);   // three axes, two orders; two fused
     std::vector<unsigned char> host(p->dev_bytes, 0);
     for (int a = 0; a < p->in.dims; ++a) {
         if (dt == SFAC_FP64)
@@ -836,13 +842,18 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
         p->r32[a] = reversed_desc(p->d32[a], a, p->in.dims);
     }
     // the descriptors grouped launches read (the state pointer comes with each launch): the
-    // three axes in the order 1..d, then in the order d..1
+    // three axes in the order 1..d, three in the order d..1, then the two fused launches
+    const int dl = p->in.dims - 1;
     if (dt == SFAC_FP64) {
+        const sfac::PassDesc<double> f[2] = {fused_desc(p->r64[0], p->d64[0]), fused_desc(p->d64[dl], p->r64[dl])};
         memcpy(host.data() + p->off_desc, p->d64, sizeof(sfac::PassDesc<double>) * p->in.dims);
         memcpy(host.data() + p->off_desc + 3 * desc_bytes, p->r64, sizeof(sfac::PassDesc<double>) * p->in.dims);
+        memcpy(host.data() + p->off_desc + 6 * desc_bytes, f, sizeof f);
     } else {
+        const sfac::PassDesc<float> f[2] = {fused_desc(p->r32[0], p->d32[0]), fused_desc(p->d32[dl], p->r32[dl])};
         memcpy(host.data() + p->off_desc, p->d32, sizeof(sfac::PassDesc<float>) * p->in.dims);
         memcpy(host.data() + p->off_desc + 3 * desc_bytes, p->r32, sizeof(sfac::PassDesc<float>) * p->in.dims);
+        memcpy(host.data() + p->off_desc + 6 * desc_bytes, f, sizeof f);
     }
     e = hipMemcpy(p->dev, host.data(), p->dev_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -1308,75 +1319,112 @@ sfac::GroupArgs<T>& launch_args(GroupLaunch& l) {
         return l.a32;
 }
 
-// The launches of step j of a phase for the plans of arithmetic T: for pass position 0, 1, 2 in
-// turn, one launch per kernel variant (at most kGroupSlots instances each), each plan taking the
-// axis its step's order puts at that position, so every plan sees the passes a lone sfac_step
-// gives it (grouped launches are never fused across step boundaries; the values are the same).
-template <typename T>
-void phase_launches(const std::vector<PhaseEntry>& entries, int j, std::vector<GroupLaunch>* out) {
-    constexpr bool f64 = std::is_same<T, double>::value;
-    auto axis_of = [j](const PhaseEntry& e, int pass) {
-        const int dims = e.plan->in.dims;
-        return ((e.parity + j) & 1) ? dims - 1 - pass : pass;
-    };
-    for (int pass = 0; pass < 3; ++pass) {
-        std::vector<std::pair<int, int>> keys;   // (kernel kind, variant): see launch_axis_pass_multi
-        std::vector<std::vector<const PhaseEntry*>> members;
-        for (const PhaseEntry& e : entries) {
-            sfac_plan p = e.plan;
-            if ((p->in.dt == SFAC_FP64) != f64 || pass >= p->in.dims) continue;
-            const sfac::PassDesc<T>& d = host_desc<T>(p, axis_of(e, pass));
-            const int kind = d.method == SFAC_METHOD_EMBED ? 1 : (d.d2a > 0 ? 2 : 0);
-            const int variant = kind == 1 ? d.log2m * 8 + d.log2e + (d.stage ? 128 : 0)
-                                          : (kind == 2 ? d.d2a * 64 + d.d2b + (d.d2wave ? 4096 : 0) : 0);
-            const std::pair<int, int> key(kind, variant);
-            const size_t g = std::find(keys.begin(), keys.end(), key) - keys.begin();
-            if (g == keys.size()) {
-                keys.push_back(key);
-                members.emplace_back();
+// One launch of one plan in a grouped graph: the pass over `axis` (`which` 0: the descriptor for
+// steps in the order 1..d, 1: in the order d..1) or, `which` 2 and 3, the two passes over axis 1
+// (after a step in the order d..1) or axis d (after one in the order 1..d) in one launch.
+struct PlanLaunch {
+    const PhaseEntry* e;
+    int axis;
+    int which;
+};
+
+// The launches each plan of a phase makes in `steps` steps, as a lone sfac_step makes them inside
+// one graph: its passes in its step orders, a step boundary inside the graph fused where the
+// plan's kernel fuses. out[i] holds every plan's i-th launch; plans are independent, so the
+// launches of one index may run in any order among themselves.
+void phase_slots(const std::vector<PhaseEntry>& entries, int steps, std::vector<std::vector<PlanLaunch>>* out) {
+    out->clear();
+    for (const PhaseEntry& e : entries) {
+        const sfac_plan p = e.plan;
+        const int dims = p->in.dims;
+        size_t idx = 0;
+        bool carried = false;
+        auto push = [&](PlanLaunch l) {
+            if (out->size() <= idx) out->resize(idx + 1);
+            (*out)[idx++].push_back(l);
+        };
+        for (int j = 0; j < steps; ++j) {
+            const int odd = (e.parity + j) & 1;
+            for (int pos = 0; pos < dims; ++pos) {
+                const int a = odd ? dims - 1 - pos : pos;
+                if (pos == 0 && carried) {
+                    carried = false;
+                    continue;
+                }
+                const bool fusable = p->in.dt == SFAC_FP64 ? can_fuse(p->d64[a]) : can_fuse(p->d32[a]);
+                if (pos == dims - 1 && j + 1 < steps && fusable) {
+                    push(PlanLaunch{&e, a, odd ? 2 : 3});
+                    carried = true;
+                } else {
+                    push(PlanLaunch{&e, a, odd});
+                }
             }
-            members[g].push_back(&e);
         }
-        for (size_t g = 0; g < keys.size(); ++g) {
-            for (size_t first = 0; first < members[g].size(); first += sfac::kGroupSlots) {
-                const size_t last = std::min(members[g].size(), first + sfac::kGroupSlots);
-                GroupLaunch l;
-                l.pass = pass;
-                l.fp64 = f64;
-                l.kind = keys[g].first;
-                l.variant = keys[g].second;
-                sfac::GroupArgs<T>& args = launch_args<T>(l);
-                args.n = (int)(last - first);
-                args.start[0] = 0;
-                size_t lds = 0;
-                int threads = l.kind == 0 ? sfac::kBlockThreads : 0;
-                for (size_t i = first; i < last; ++i) {
-                    const PhaseEntry& e = *members[g][i];
-                    sfac_plan p = e.plan;
-                    const int a = axis_of(e, pass);
-                    const sfac::PassDesc<T>& d = host_desc<T>(p, a);
-                    const int k = (int)(i - first);
-                    args.desc[k] = p->template device_desc<T>(a, (e.parity + j) & 1);
-                    args.u[k] = static_cast<T*>(e.u);
-                    args.start[k + 1] = args.start[k] + sfac::pass_blocks(d);
-                    lds = std::max(lds, p->in.ax[a].lds);
-                    if (l.kind != 0) threads = std::max(threads, d.threads);
-                }
-                if (l.kind == 1) {
-                    const int E = 1 << sfac::embed_log2e((l.variant % 128) / 8, l.variant % 8);
-                    lds = (size_t)threads * E * sizeof(sfac::cplx<T>);
-                } else if (l.kind == 2) {
-                    // a full block of P-thread lines (or of wavefronts of 64/P lines); lines beyond
-                    // a descriptor's lpb idle
-                    const int v = l.variant % 4096;
-                    const int A = v / 64, B = v % 64, P = std::max(A, B);
-                    const int lines = l.variant >= 4096 ? (threads / 64) * (64 / P) : threads / P;
-                    lds = (size_t)lines * sfac::diag2_line_stride(A, B, sizeof(sfac::cplx<T>)) * sizeof(sfac::cplx<T>);
-                }
-                l.threads = threads;
-                l.lds = lds;
-                out->push_back(l);
+    }
+}
+
+// The grouped launches of one slot for the plans of arithmetic T: one launch per kernel variant
+// (single or two-pass), at most kGroupSlots instances each.
+template <typename T>
+void slot_launches(const std::vector<PlanLaunch>& slot, int index, std::vector<GroupLaunch>* out) {
+    constexpr bool f64 = std::is_same<T, double>::value;
+    std::vector<std::pair<int, int>> keys;   // (kernel kind, variant): see launch_axis_pass_multi
+    std::vector<std::vector<const PlanLaunch*>> members;
+    for (const PlanLaunch& pl : slot) {
+        sfac_plan p = pl.e->plan;
+        if ((p->in.dt == SFAC_FP64) != f64) continue;
+        const sfac::PassDesc<T>& d = host_desc<T>(p, pl.axis);
+        const int kind = d.method == SFAC_METHOD_EMBED ? 1 : (d.d2a > 0 ? 2 : 0);
+        const int variant = (kind == 1 ? d.log2m * 8 + d.log2e + (d.stage ? 128 : 0)
+                                       : (kind == 2 ? d.d2a * 64 + d.d2b + (d.d2wave ? 4096 : 0) : 0)) +
+                            (pl.which >= 2 ? sfac::kTwiceVariant : 0);
+        const std::pair<int, int> key(kind, variant);
+        const size_t g = std::find(keys.begin(), keys.end(), key) - keys.begin();
+        if (g == keys.size()) {
+            keys.push_back(key);
+            members.emplace_back();
+        }
+        members[g].push_back(&pl);
+    }
+    for (size_t g = 0; g < keys.size(); ++g) {
+        for (size_t first = 0; first < members[g].size(); first += sfac::kGroupSlots) {
+            const size_t last = std::min(members[g].size(), first + sfac::kGroupSlots);
+            GroupLaunch l;
+            l.pass = index;
+            l.fp64 = f64;
+            l.kind = keys[g].first;
+            l.variant = keys[g].second;
+            sfac::GroupArgs<T>& args = launch_args<T>(l);
+            args.n = (int)(last - first);
+            args.start[0] = 0;
+            size_t lds = 0;
+            int threads = l.kind == 0 ? sfac::kBlockThreads : 0;
+            for (size_t i = first; i < last; ++i) {
+                const PlanLaunch& pl = *members[g][i];
+                sfac_plan p = pl.e->plan;
+                const sfac::PassDesc<T>& d = host_desc<T>(p, pl.axis);
+                const int k = (int)(i - first);
+                args.desc[k] = pl.which >= 2 ? p->template fused_device_desc<T>(pl.which - 2)
+                                             : p->template device_desc<T>(pl.axis, pl.which);
+                args.u[k] = static_cast<T*>(pl.e->u);
+                args.start[k + 1] = args.start[k] + sfac::pass_blocks(d);
+                lds = std::max(lds, p->in.ax[pl.axis].lds);
+                if (l.kind != 0) threads = std::max(threads, d.threads);
             }
+            const int v = l.variant % sfac::kTwiceVariant;
+            if (l.kind == 1) {
+                const int E = 1 << sfac::embed_log2e((v % 128) / 8, v % 8);
+                lds = (size_t)threads * E * sizeof(sfac::cplx<T>);
+            } else if (l.kind == 2) {
+                // a full block of P-thread lines (or of wavefronts of 64/P lines); lines beyond
+                // a descriptor's lpb idle
+                const int A = (v % 4096) / 64, B = v % 64, P = std::max(A, B);
+                const int lines = v >= 4096 ? (threads / 64) * (64 / P) : threads / P;
+                lds = (size_t)lines * sfac::diag2_line_stride(A, B, sizeof(sfac::cplx<T>)) * sizeof(sfac::cplx<T>);
+            }
+            l.threads = threads;
+            l.lds = lds;
+            out->push_back(l);
         }
     }
 }
@@ -1386,20 +1434,18 @@ hipError_t group_launch(const GroupLaunch& l, hipStream_t s) {
                   : sfac::launch_axis_pass_multi<float>(l.kind, l.variant, l.threads, l.a32, l.lds, s);
 }
 
-// Captures `steps` steps of a phase: pass after pass; the launches of one pass (different
+// Captures the launches of a phase's graph slot after slot; the launches of one slot (different
 // kernel variants and arithmetic, disjoint plans) fan out over the auxiliary streams and join
-// before the next pass, so every plan still sees its passes in order. launches[j] are those of
-// the phase's even (j = 0) and odd (j = 1) steps.
-sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch> (&launches)[2], int steps, hipGraph_t* graph) {
+// before the next slot, so every plan still sees its launches in order.
+sfac_status capture_step(sfac_group g, const std::vector<GroupLaunch>& launches, int slots, hipGraph_t* graph) {
     *graph = nullptr;
     hipError_t e = hipStreamBeginCapture(g->capture, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     hipError_t le = hipSuccess;
-    for (int it = 0; it < 3 * steps && le == hipSuccess; ++it) {
-        const int pass = it % 3;
+    for (int slot = 0; slot < slots && le == hipSuccess; ++slot) {
         std::vector<const GroupLaunch*> ls;
-        for (const GroupLaunch& l : launches[(it / 3) & 1])
-            if (l.pass == pass) ls.push_back(&l);
+        for (const GroupLaunch& l : launches)
+            if (l.pass == slot) ls.push_back(&l);
         if (ls.empty()) continue;
         if (ls.size() == 1) {
             le = group_launch(*ls[0], g->capture);
@@ -1434,14 +1480,15 @@ sfac_status phase_graph(sfac_group g, const std::vector<PhaseEntry>& entries, in
             *exec = g->cache.front().exec;
             return SFAC_OK;
         }
-    std::vector<GroupLaunch> launches[2];
-    for (int j = 0; j < 2; ++j) {
-        phase_launches<double>(entries, j, &launches[j]);
-        phase_launches<float>(entries, j, &launches[j]);
+    std::vector<std::vector<PlanLaunch>> slots;
+    phase_slots(entries, steps, &slots);
+    std::vector<GroupLaunch> launches;
+    for (size_t i = 0; i < slots.size(); ++i) {
+        slot_launches<double>(slots[i], (int)i, &launches);
+        slot_launches<float>(slots[i], (int)i, &launches);
     }
     size_t lds_need = 0;
-    for (const auto& ls : launches)
-        for (const auto& l : ls) lds_need = std::max(lds_need, l.lds);
+    for (const auto& l : launches) lds_need = std::max(lds_need, l.lds);
     if (lds_need > 64 * 1024) {
         hipError_t e = sfac::allow_lds<double>(lds_need);
         if (e == hipSuccess) e = sfac::allow_lds<float>(lds_need);
@@ -1452,7 +1499,7 @@ sfac_status phase_graph(sfac_group g, const std::vector<PhaseEntry>& entries, in
     GroupGraph gg;
     gg.key = std::move(key);
     gg.steps = steps;
-    sfac_status st = capture_step(g, launches, steps, &gg.graph);
+    sfac_status st = capture_step(g, launches, (int)slots.size(), &gg.graph);
     if (st != SFAC_OK) return st;
     e = hipGraphInstantiate(&gg.exec, gg.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
