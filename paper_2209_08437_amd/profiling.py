@@ -387,8 +387,8 @@ def load_traffic(path, workload, dtype, schedule=None):
 COMMANDS = """\
 python3 -m paper_2209_08437_amd.autotune --fresh --out $R/paper_2209_08437_amd/tuned_mi355x.json large_2d_1023 large_3d_255 plain_2d_63 batched_2d   # the packaged schedule table, tuned on an MI355X beforehand; every run below uses it
 rocprofv3 --kernel-trace --stats --output-format csv -d $O/trace_$W -o run -- python3 $R/bench.py --workload $W --no-cpu --no-sub
-rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --no-exact --steps 20 --warmup 2 --pass-reps 2
-rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --no-exact --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/FETCH_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --steps 20 --warmup 2 --pass-reps 2
+rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/WRITE_SIZE_$W_$DT -o run -- python3 $R/bench.py --workload $W --dtype $DT --no-cpu --no-fp32 --no-sub --steps 20 --warmup 2 --pass-reps 2
 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $O/copy_FETCH_SIZE -o run -- python3 $R/bench.py --copy-probe
 rocprofv3 --pmc WRITE_SIZE --output-format csv -d $O/copy_WRITE_SIZE -o run -- python3 $R/bench.py --copy-probe"""
 
