@@ -382,6 +382,8 @@ FUSE_CASES = [
     ((63, 63), "f64", {"method": "embed", "elems_log2": (2, 2), "lines_per_block": (2, 2)}),
     ((63, 63), "f32", {"method": "embed", "elems_log2": (2, 3), "lines_per_block": (1, 0)}),
     ((63, 63, 5), "f64", {"method": ("embed", "diag", "embed"), "elems_log2": (3, 0, 0)}),
+    ((255,), "f64", {"method": "diag"}),          # one axis: every pass is the first and the last of its step
+    ((63,), "f32", None),
 ]
 
 
@@ -632,6 +634,46 @@ def test_large_2d_1023_all_steps_fp32(sfac_lib):
          f"max|u| {vmax:.6f}")
     assert e <= FP32_TOL_C2 and e_ext <= FP32_TOL_C2
     assert flags == 0 and vmax <= 1.0
+
+
+def test_axis_order_parity_across_lone_and_grouped_calls(sfac_lib):
+    """A plan's step count fixes each step's axis order, whichever path queued the earlier steps:
+    plans of one, two and three axes (diagonal, embedded and generic kernels, both arithmetics)
+    stepped by odd counts through sfac_step and groups in turn, with long grouped phases (8-step
+    graphs) among them, end bitwise equal to one sfac_step call of the total."""
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    cases = [((255,), "f64", {"method": "diag"}), ((63, 41), "f64", None), ((35, 15, 21), "f32", {"method": "diag"}),
+             ((45, 33), "f64", {"method": "diag"}), ((31, 17, 9), "f64", {"method": ("embed", "diag", "embed")}),
+             ((127, 33), "f32", {"kernel": (4, 4)})]
+    _say("case axis-order parity across lone and grouped calls")
+    plans, states, refs = [], [], []
+    for ns, dt, sch in cases:
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        hs = W.mesh_widths(ns)
+        alphas = (1.3, 1.7, 1.5)[:len(ns)]
+        u0 = W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=len(ns) + ns[0])
+        with sfac.Plan(ns, alphas, 0.15, 0.01, hs, dt, **(sch or {})) as p:
+            u = torch.tensor(u0, dtype=tdt, device="cuda")
+            p.step(u, 3 + 7 + 71 + 5 + 2)
+            torch.cuda.synchronize()
+            refs.append(u)
+        plans.append(sfac.Plan(ns, alphas, 0.15, 0.01, hs, dt, **(sch or {})))
+        states.append(torch.tensor(u0, dtype=tdt, device="cuda"))
+    g = sfac.Group()
+    for p, u in zip(plans, states):
+        p.step(u, 3)
+    g.step(plans, states, [7] * len(plans))
+    g.step(plans, states, [71] * len(plans))      # a long phase: 8-step graphs, then 2 and 1
+    for k, (p, u) in enumerate(zip(plans, states)):
+        p.step(u, 5 if k % 2 else 2)
+    g.step(plans, states, [2 if k % 2 else 5 for k in range(len(plans))])
+    torch.cuda.synchronize()
+    for (ns, dt, _), u, ref in zip(cases, states, refs):
+        assert torch.equal(u, ref), (ns, dt)
+    g.close()
+    for p in plans:
+        p.close()
 
 
 def test_group_graph_cache_and_plan_churn(sfac_lib):
