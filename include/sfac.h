@@ -226,7 +226,8 @@ sfac_status sfac_plan_energy(sfac_plan p, const void* u_dev, double* energy);
  * steps are counted but not recorded. capacity = 0 stops recording and frees the record. The
  * value is the same largest |u| the last pass of the step folds into sfac_plan_flags. Only
  * sfac_step records (not sfac_plan_time_passes, groups or batches). Each recorded step adds one
- * one-thread kernel to the step graphs, which this call has re-captured on the next sfac_step.
+ * one-thread kernel to the step graphs, which this call has re-captured on the next sfac_step; a
+ * plan of one axis that keeps the record launches its step boundaries unfused.
  * Synchronizes the plan's stream. Errors: SFAC_EINVAL, SFAC_ENOMEM, SFAC_EDEVICE.
  */
 sfac_status sfac_plan_trace(sfac_plan p, int64_t capacity);

@@ -519,9 +519,11 @@ struct sfac_plan_s {
         return e;
     }
 
-    // `nsteps` steps from step parity `parity0`. The per-step record folds the statistics after
-    // every step, so with a record the passes are not fused across step boundaries (the values
-    // are the same either way).
+    // `nsteps` steps from step parity `parity0`. The per-step record is folded after every step:
+    // with two or more axes a fused launch stores the statistics of the step it closes (its
+    // second pass opens the next step and closes none); with one axis both of its passes close a
+    // step, so a plan of one axis that keeps the record does not fuse (the values are the same
+    // either way).
     hipError_t launch_steps(hipStream_t s, int64_t nsteps, int parity0) {
         auto collect = [this](hipStream_t st) -> hipError_t {
             return trace_dev ? sfac::launch_trace_collect(trace_slots(), trace_parts, trace_rec(), trace_step(),
@@ -536,7 +538,7 @@ struct sfac_plan_s {
             }
             return hipSuccess;
         }
-        const bool fuse = trace_dev == nullptr;
+        const bool fuse = trace_dev == nullptr || in.dims >= 2;
         return in.dt == SFAC_FP64 ? launch_sequence(d64, r64, in, parity0, nsteps, fuse, s, collect)
                                   : launch_sequence(d32, r32, in, parity0, nsteps, fuse, s, collect);
     }

@@ -391,9 +391,10 @@ FUSE_CASES = [
 def test_fused_passes_equal_separate_passes_bitwise(sfac_lib, ns, dtype, sched):
     """Consecutive steps run their axes in alternating order (1..d, then d..1), so a step's last
     pass and the next step's first cover the same axis and one launch does both, with the step
-    boundary (closing half-step, statistics, opening half-step) in registers. A plan that keeps
-    the per-step record launches them separately: states, flags and max|u| must be bitwise
-    equal, and the record's values must match the fused run's sticky maximum."""
+    boundary (closing half-step, statistics, opening half-step) in registers. Graphs of one step
+    (graph_chunk 1) launch every pass separately: states, flags and max|u| must be bitwise equal
+    across fused and separate runs, plain launches and graphs, with and without the per-step
+    record, and the record's values must match the sticky maximum."""
     torch = _torch()
     from paper_2209_08437_amd import sfac
     hs = W.mesh_widths(ns)
@@ -403,9 +404,10 @@ def test_fused_passes_equal_separate_passes_bitwise(sfac_lib, ns, dtype, sched):
     _say(f"case fused vs separate {ns} {dtype} {sched}")
     out = []
     for traced in (False, True):
-        for use_graph in (True, False):
+        for use_graph, chunk in ((True, 32), (False, 32), (True, 1)):
             u = torch.tensor(u0, dtype=tdt, device="cuda")
-            with sfac.Plan(ns, alphas, 0.2, 0.01, hs, dtype, use_graph=use_graph, **(sched or {})) as p:
+            with sfac.Plan(ns, alphas, 0.2, 0.01, hs, dtype, use_graph=use_graph, graph_chunk=chunk,
+                           **(sched or {})) as p:
                 if traced:
                     p.trace(64)
                 p.step(u, 1)
@@ -419,7 +421,9 @@ def test_fused_passes_equal_separate_passes_bitwise(sfac_lib, ns, dtype, sched):
     for got in out[1:]:
         assert np.array_equal(got[0], ref[0])
         assert got[1] == ref[1]
-    assert out[2][2].max() == ref[1][1]
+    for got in out[3:]:
+        assert np.array_equal(got[2], out[3][2])     # the record: fused or not
+        assert got[2].max() == ref[1][1]
     ref64 = O.two_level_solve(u0, ns, alphas, 0.2, hs, 0.01, 12)
     assert rel_err(ref[0].astype(np.float64), ref64) <= (FP64_TOL if dtype == "f64" else FP32_TOL)
 
