@@ -384,6 +384,8 @@ FUSE_CASES = [
     ((63, 63, 5), "f64", {"method": ("embed", "diag", "embed"), "elems_log2": (3, 0, 0)}),
     ((255,), "f64", {"method": "diag"}),          # one axis: every pass is the first and the last of its step
     ((63,), "f32", None),
+    ((1024, 5), "f64", {"method": ("embed", "embed"), "elems_log2": (4, 0)}),   # the longest transform (2048)
+    ((5, 1024), "f32", {"method": ("embed", "embed"), "kernel": (0, 4)}),        # strided, staged, length 2048
 ]
 
 
