@@ -1234,8 +1234,10 @@ sfac_status sfac_exact_exponential(int32_t n, double alpha, double eps, double t
 }  // extern "C"
 
 // ===================================================================== groups
-// A group steps any set of plans together, with one launch per (pass, arithmetic, kernel
-// variant) covering every plan that needs it. A launch's instances travel in its kernel
+// A group steps any set of plans together: each plan makes the launches a lone sfac_step would
+// make inside one step graph (its passes in its step orders, step boundaries fused where its
+// kernel fuses), and the plans' i-th launches share one launch per (arithmetic, kernel variant)
+// covering every plan that needs it. A launch's instances travel in its kernel
 // arguments (sfac::GroupArgs: the device copy of each plan's pass descriptor and its state), so
 // a group owns no device memory, a call never waits for the previous one, and a captured step
 // graph stays valid for as long as its plans live. Step graphs are cached per set of (plan,
@@ -1257,9 +1259,9 @@ struct GroupGraph {
     hipGraphExec_t exec = nullptr;
 };
 
-// A phase of at least kLongPhase steps replays a graph of kPhaseChunk steps (the remainder one
-// step at a time): fewer graph launches, and so fewer gaps between them, on long batched runs;
-// a served tick is shorter and keeps to the one-step graph.
+// A phase of at least kLongPhase steps replays a graph of kPhaseChunk steps first: fewer graph
+// launches, and so fewer gaps between them, on long batched runs; shorter phases (a served
+// tick) and the remainder replay a graph of two steps, then one of one step if the count is odd.
 constexpr int kPhaseChunk = 8;
 constexpr int64_t kLongPhase = 64;
 

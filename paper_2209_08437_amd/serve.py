@@ -4,7 +4,7 @@ Requests (an instance of the fractional Allen-Cahn problem, a step count and an 
 type) arrive over time. The server admits queued requests first-come first-served while their
 device memory (state + tables) fits a budget, keeps every admitted state on the device, and in
 each tick advances all admitted requests together by up to `tick_steps` steps with one grouped
-step (sfac_group_step: one launch per pass and kernel variant for all of them, FP64 and FP32
+step (sfac_group_step: the launches of all of them shared per kernel variant, FP64 and FP32
 mixed). Finished requests are read back and retired at the tick boundary, which frees memory
 for queued ones; requests that arrive while others run join at the next tick. A request larger
 than the whole budget is rejected.
