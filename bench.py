@@ -15,8 +15,9 @@ the autotuner picked on an MI355X for this shape, read from the table that ships
 package (`--tune-cache none` tunes afresh on the device at hand).
 
 Besides the headline value the JSON line carries: the FP32 rate of the same workload, the 2D
-1023^2 instance (FP64 and FP32) as a sub-object, the roofline of the dominant axis-pass kernel
-of each, the CPU oracle timed on a bounded sample with the max-norm error of the GPU results
+1023^2 instance (FP64 and FP32) and the 64-instance batched workload (FP32 and FP64 grouped
+launches against the same instances on plain FP64 plans one after another) as sub-objects, the
+roofline of the dominant launch of each single instance, the CPU oracle timed on a bounded sample with the max-norm error of the GPU results
 against it (the 63^3 subsample of the 3D instance over all its steps, and the 1023^2 instance
 over all its steps), and the one-level scheme with the exact exponential that the paper
 compares the two-level scheme with, run on the GPU over the same steps.
@@ -397,7 +398,7 @@ def batched_run(args):
         "metric": METRIC, "value": round(res["f32"]["value"], 1), "unit": "grid-point-steps/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": round(res["f32"]["wall_s"] * 1e3 / steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batched one-launch-per-pass solve: {len(insts)} independent 2D instances, n from "
+        "config": {"workload": f"batched grouped solve (shared launches per kernel variant): {len(insts)} independent 2D instances, n from "
                                f"{sizes}, alpha_l ~ U(1.1,1.9), eps ~ U(0.02,0.2), tau ~ U(1e-3,1e-2), {steps} steps",
                    "points": pts},
         "batched_f64": round(res["f64"]["value"], 1),
@@ -627,7 +628,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-sub", action="store_true", help="skip the 1023^2 sub-object of the 3D line")
+    ap.add_argument("--no-sub", action="store_true", help="skip the 1023^2 and batched sub-objects of the 3D line")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched sub-object of the 3D line")
     ap.add_argument("--no-oracle-checks", action="store_true",
                     help="skip the oracle runs behind the error figures (the 1023^2 one takes about a minute)")
     ap.add_argument("--no-exact", action="store_true", help="skip the one-level exact-exponential comparison")
@@ -725,6 +727,12 @@ def main():
     if args.workload == "large_3d_255" and not args.no_sub:
         c2_inst, out["large_2d_1023"], c2_states = sub_workload("large_2d_1023", None, args)
         checks.append(("large_2d_1023", c2_inst, c2_states))
+    if args.workload == "large_3d_255" and not args.no_sub and not args.no_batched:
+        b = batched_run(args)
+        out["batched_2d"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "dtype", "batched_f64",
+                                               "plain_f64_sequential", "speedup_f32_batched_vs_plain_f64",
+                                               "f32_rel_err_vs_f64_gpu_max", "max_abs", "flags", "schedules")}
+        out["batched_2d"]["workload"] = b["config"]["workload"]
     if args.dtype == "f64" and not args.no_exact:
         out["one_level_exact"] = one_level_exact(inst, steps, main_r["state"], main_r["wall_s"] * 1e3 / steps,
                                                  args.workload, args.pass_reps)
