@@ -1260,9 +1260,10 @@ struct GroupGraph {
 };
 
 // A phase of at least kLongPhase steps replays a graph of kPhaseChunk steps first: fewer graph
-// launches, and so fewer gaps between them, on long batched runs; shorter phases (a served
-// tick) and the remainder replay a graph of two steps, then one of one step if the count is odd.
-constexpr int kPhaseChunk = 8;
+// launches, and so fewer gaps between them, and more fused step boundaries on long batched runs;
+// shorter phases (a served tick) and the remainder replay a graph of two steps, then one of one
+// step if the count is odd.
+constexpr int kPhaseChunk = 32;
 constexpr int64_t kLongPhase = 64;
 
 }  // namespace
