@@ -642,6 +642,33 @@ def test_large_2d_1023_all_steps_fp32(sfac_lib):
     assert flags == 0 and vmax <= 1.0
 
 
+def test_time_fused_reports_the_fused_launches(sfac_lib):
+    """sfac_plan_time_fused times the launches that cover axis 1 and axis d twice: positive where
+    the axis' kernel fuses, 0 where it does not (the generic diagonal kernel), 0 for plans of the
+    exact exponential; it is not part of the per-step record."""
+    torch = _torch()
+    from paper_2209_08437_amd import sfac
+    _say("case time_fused")
+    cases = [((63, 41), None, (True, True)),
+             ((21, 15, 35), {"method": "diag"}, (False, True)),      # 21 = 3 x 7: generic kernel on axis 1
+             ((255,), {"method": "diag"}, (True, True))]             # one axis: both entries the same launch
+    for ns, sch, fuses in cases:
+        hs = W.mesh_widths(ns)
+        u = torch.tensor(W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=2), device="cuda")
+        with sfac.Plan(ns, (1.3, 1.7, 1.5)[:len(ns)], 0.1, 0.01, hs, "f64", **(sch or {})) as p:
+            p.trace(4)
+            ms = p.time_fused(u, 3)
+            assert [t > 0 for t in ms] == list(fuses), (ns, ms)
+            if len(ns) == 1:
+                assert ms[0] == ms[1]
+            assert p.read_trace()[1] == 0
+    ns = (31, 17)
+    hs = W.mesh_widths(ns)
+    u = torch.tensor(W.uniform_field((17, 31), -0.9, 0.9, seed=2), device="cuda")
+    with sfac.Plan(ns, (1.3, 1.7), 0.1, 0.01, hs, "f64", method="exact") as p:
+        assert p.time_fused(u, 2) == [0.0, 0.0]
+
+
 def test_axis_order_parity_across_lone_and_grouped_calls(sfac_lib):
     """A plan's step count fixes each step's axis order, whichever path queued the earlier steps:
     plans of one, two and three axes (diagonal, embedded and generic kernels, both arithmetics)
