@@ -1050,19 +1050,22 @@ __global__ void __launch_bounds__(kGemmThreads) exact_gemm(const double* __restr
     }
 }
 
+// With `halves` = 2 the launch is a step boundary: the closing half-step (whose values the
+// statistics see), then the next step's opening half-step on the value as stored.
 __global__ void __launch_bounds__(kExactNlThreads) exact_nl(double* dst, const double* src, long long n, double decay,
-                                                            int stats, PassDesc<double> d) {
+                                                            int stats, int halves, PassDesc<double> d) {
     const long long i = (long long)blockIdx.x * kExactNlThreads + threadIdx.x;
     double vmax = 0.0;
     unsigned int bad = 0;
     if (i < n) {
-        const double z = nonlinear_half_step(src[i], decay, 0.0);
-        dst[i] = z;
+        double z = nonlinear_half_step(src[i], decay, 0.0);
         const double az = fabs(z);
         if (!(az <= 1.7976931348623157e308))
             bad |= SFAC_FLAG_NONFINITE;
         else
             vmax = az;
+        if (halves == 2) z = nonlinear_half_step(as_stored(z), decay, 0.0);
+        dst[i] = z;
     }
     if (stats) publish_stats(vmax, bad, d);
 }
@@ -1106,12 +1109,13 @@ hipError_t launch_exact_gemm(const double* X, const double* Y, double* C, int M,
     return hipGetLastError();
 }
 
-hipError_t launch_exact_nl(double* dst, const double* src, long long n, double decay, bool stats,
+hipError_t launch_exact_nl(double* dst, const double* src, long long n, double decay, bool stats, int halves,
                            const PassDesc<double>& d, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
+    if (halves != 1 && halves != 2) return hipErrorInvalidValue;
     const long long blocks = (n + kExactNlThreads - 1) / kExactNlThreads;
     hipLaunchKernelGGL(exact_nl, dim3((unsigned)blocks), dim3(kExactNlThreads), 0, stream, dst, src, n, decay,
-                       stats ? 1 : 0, d);
+                       stats ? 1 : 0, halves, d);
     return hipGetLastError();
 }
 

@@ -133,9 +133,11 @@ hipError_t launch_exact_gemm(const double* X, const double* Y, double* C, int M,
                              hipStream_t stream);
 // dst[i] = J^Q_{tau/2}(src[i]) for i < n (dst may be src); with `stats`, the largest |u| and the
 // non-finite flag are folded into d.stat_max / d.stat_flags (and d.trace_part) as by the last pass
-// of the two-level scheme. Blocks of 256 threads.
+// of the two-level scheme. `halves` = 2 applies the half-step twice, the statistics taken after
+// the first (a step boundary: one step's closing half-step, the next one's opening), with the
+// values of two launches of one half-step each. Blocks of 256 threads.
 constexpr int kExactNlThreads = 256;
-hipError_t launch_exact_nl(double* dst, const double* src, long long n, double decay, bool stats,
+hipError_t launch_exact_nl(double* dst, const double* src, long long n, double decay, bool stats, int halves,
                            const PassDesc<double>& d, hipStream_t stream);
 
 // Elements per thread (log2) of the energy kernel for a transform of length 2^log2m: 8, or 16 at

@@ -497,12 +497,16 @@ struct sfac_plan_s {
     // eq. (strang): J^Q_{tau/2} e^{tau A} J^Q_{tau/2}, e^{tau A} one dense product per axis, alternating
     // between the state and the scratch buffer; the closing half-step writes the state and the
     // statistics of `stats`. With `ev` (2 per axis), each product is bracketed by an event pair.
-    hipError_t exact_step(hipStream_t s, const sfac::PassDesc<double>& stats, hipEvent_t* ev = nullptr) {
+    // Within a run of steps the closing launch of one step also applies the next one's opening
+    // half-step (`open` false for that next step, `chain` true for this one), with the values of
+    // separate launches.
+    hipError_t exact_step(hipStream_t s, const sfac::PassDesc<double>& stats, hipEvent_t* ev = nullptr,
+                          bool open = true, bool chain = false) {
         double* u = d64[0].u;
         double* scratch = reinterpret_cast<double*>(dev + off_scratch);
         const long long pts = in.points();
         const double decay = std::exp(-in.tau);
-        hipError_t e = sfac::launch_exact_nl(u, u, pts, decay, false, stats, s);
+        hipError_t e = open ? sfac::launch_exact_nl(u, u, pts, decay, false, 1, stats, s) : hipSuccess;
         double* cur = u;
         double* other = scratch;
         for (int a = 0; a < in.dims && e == hipSuccess; ++a) {
@@ -521,7 +525,7 @@ struct sfac_plan_s {
             if (ev && e == hipSuccess) e = hipEventRecord(ev[2 * a + 1], s);
             std::swap(cur, other);
         }
-        if (e == hipSuccess) e = sfac::launch_exact_nl(u, cur, pts, decay, true, stats, s);
+        if (e == hipSuccess) e = sfac::launch_exact_nl(u, cur, pts, decay, true, chain ? 2 : 1, stats, s);
         return e;
     }
 
@@ -538,7 +542,7 @@ struct sfac_plan_s {
         };
         if (exact) {
             for (int64_t k = 0; k < nsteps; ++k) {
-                hipError_t e = exact_step(s, d64[in.dims - 1]);
+                hipError_t e = exact_step(s, d64[in.dims - 1], nullptr, k == 0, k + 1 < nsteps);
                 if (e == hipSuccess) e = collect(s);
                 if (e != hipSuccess) return e;
             }

@@ -72,7 +72,7 @@ hipError_t launch_exact_gemm(const double*, const double*, double*, int, int, in
     mock_submit(s, [] {});
     return hipSuccess;
 }
-hipError_t launch_exact_nl(double*, const double*, long long, double, bool, const PassDesc<double>&, hipStream_t s) {
+hipError_t launch_exact_nl(double*, const double*, long long, double, bool, int, const PassDesc<double>&, hipStream_t s) {
     mock_submit(s, [] {});
     return hipSuccess;
 }
