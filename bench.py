@@ -655,7 +655,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design note, not part of this build)", flush=True)
+              "(the slab decomposition over several GPUs is designed, not implemented)", flush=True)
         sys.exit(2)
     from paper_2209_08437_amd import sfac, build_lib
     if not os.path.exists(sfac.LIB_PATH):

@@ -38,7 +38,7 @@ extern "C" {
 typedef enum {
     SFAC_OK = 0,
     SFAC_EINVAL = 1,       /* an argument is outside its documented range */
-    SFAC_EUNSUPPORTED = 2, /* valid, but beyond what this build implements (e.g. N too large) */
+    SFAC_EUNSUPPORTED = 2, /* valid, but beyond what this library implements (e.g. N too large) */
     SFAC_ENOMEM = 3,       /* a device or host allocation failed */
     SFAC_EDEVICE = 4,      /* a HIP runtime call failed; the message carries its text */
     SFAC_EBUDGET = 5       /* a request does not fit the caller's device-memory budget */
