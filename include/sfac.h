@@ -151,9 +151,10 @@ sfac_status sfac_plan_create(sfac_plan* out, int32_t dims, const int32_t* n_axis
  * 1..d and d..1 by the parity of the number of steps the plan has queued (through sfac_step
  * and groups alike), which makes the last pass of a step and the first of the next cover the
  * same axis; one launch does both, the step boundary (closing J^Q_{tau/2}, statistics, opening
- * J^Q_{tau/2}) applied in registers, bitwise as the two launches would give it. Splitting a run
- * into several calls, graph chunks or plain launches, and stepping through a group, give
- * bitwise the same result as one call.
+ * J^Q_{tau/2}) applied in registers, bitwise as the two launches would give it (a plan of
+ * SFAC_METHOD_EXACT likewise applies one step's closing half-step and the next one's opening
+ * half-step in one launch). Splitting a run into several calls, graph chunks or plain launches,
+ * and stepping through a group, give bitwise the same result as one call.
  * Errors: SFAC_EINVAL (NULL plan or pointer, misaligned pointer, nsteps < 0), SFAC_EDEVICE.
  */
 sfac_status sfac_step(sfac_plan p, void* u_dev, int64_t nsteps);
