@@ -408,8 +408,11 @@ __device__ __forceinline__ void embed_stage(const PassDesc<T>& d, const TileGeom
 
 // Embedded method, register-resident transforms of length 2^LOG2M; STAGE: tile I/O through LDS.
 // TWICE: the pass covers its axis twice with a step boundary between (nl_mid).
+// Always inlined: called out of line (as the compiler chose for the two-pass kernels with 16
+// elements per thread in three radix passes), the two-pass kernel differed from two launches in
+// the last bits, and its LDS exchanges go through generic pointers.
 template <typename T, int LOG2M, int LE, bool STAGE, bool TWICE = false>
-__device__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
+__device__ __forceinline__ void run_embed_tile(const PassDesc<T>& d, int tile, cplx<T>* lds) {
     using G = EmbedGeom<LOG2M, LE>;
     using Line = EmbedLine<T, LOG2M, LE>;
     const int line = threadIdx.x >> G::LOG2T;

@@ -341,16 +341,12 @@ sfac::PassDesc<T> reversed_desc(sfac::PassDesc<T> d, int a, int dims) {
 
 // Kernels that cover their axis twice in one launch (nl_mid) with values bitwise those of two
 // launches, as measured against two launches for every transform length up to 2048 and every
-// elements-per-thread choice: the two-step diagonal ones, and the embedded ones with 4 or 8
-// elements per thread, or 16 in at most two radix passes. The embedded kernel with 16 elements
-// per thread in three radix passes (lengths 512 to 2048) differed from two launches in the last
-// bits (cause not identified) and, like lengths above 2048 (not measured), keeps one launch per
-// pass.
+// elements-per-thread choice: the two-step diagonal ones and the embedded ones. Lengths above
+// 2048 (not measured) keep one launch per pass, as does the generic kernel.
 template <typename T>
 bool can_fuse(const sfac::PassDesc<T>& d) {
     if (d.method == SFAC_METHOD_DIAG) return d.d2a > 0;
-    if (d.method != SFAC_METHOD_EMBED || d.log2m > 11) return false;
-    return d.log2e <= 3 || sfac::embed_stages(d.log2m, d.log2e) <= 2;
+    return d.method == SFAC_METHOD_EMBED && d.log2m <= 11;
 }
 
 // The launch that covers axis a twice: the last pass of a step (`cur`, from the step's

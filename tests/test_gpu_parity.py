@@ -385,6 +385,8 @@ FUSE_CASES = [
     ((255,), "f64", {"method": "diag"}),          # one axis: every pass is the first and the last of its step
     ((63,), "f32", None),
     ((1024, 5), "f64", {"method": ("embed", "embed"), "elems_log2": (4, 0)}),   # the longest transform (2048)
+    ((200, 9), "f64", {"method": ("embed", "embed"), "elems_log2": (4, 0)}),    # 16 per thread, three radix passes
+    ((7, 300), "f32", {"method": ("embed", "embed"), "elems_log2": (0, 4), "kernel": (0, 4)}),   # same, staged
     ((5, 1024), "f32", {"method": ("embed", "embed"), "kernel": (0, 4)}),        # strided, staged, length 2048
 ]
 
@@ -651,7 +653,9 @@ def test_time_fused_reports_the_fused_launches(sfac_lib):
     _say("case time_fused")
     cases = [((63, 41), None, (True, True)),
              ((21, 15, 35), {"method": "diag"}, (False, True)),      # 21 = 3 x 7: generic kernel on axis 1
-             ((255,), {"method": "diag"}, (True, True))]             # one axis: both entries the same launch
+             ((255,), {"method": "diag"}, (True, True)),             # one axis: both entries the same launch
+             ((200, 9), {"method": "embed", "elems_log2": (4, 0)}, (True, True)),      # 16 per thread, three radix
+             ((1024, 5), {"method": "embed", "elems_log2": (4, 0)}, (True, True))]     # passes (lengths 512, 2048)
     for ns, sch, fuses in cases:
         hs = W.mesh_widths(ns)
         u = torch.tensor(W.uniform_field(tuple(reversed(ns)), -0.9, 0.9, seed=2), device="cuda")
