@@ -206,7 +206,7 @@ __device__ __forceinline__ cplx<T> step_boundary(cplx<T> z, bool two, T decay, T
 
 // keep: a third LDS buffer of lpb lines, used in the increment form only (the factor's input).
 template <typename T>
-__device__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>* buf1, cplx<T>* keep) {
+__device__ __forceinline__ void run_tile(const PassDesc<T>& d, int tile, cplx<T>* buf0, cplx<T>* buf1, cplx<T>* keep) {
     const int N = d.N, L = d.L, lpb = d.lpb;
     const bool contiguous = d.inner == 1;
     long long first;       // first real line (row) or column of the tile
